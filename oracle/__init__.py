@@ -1,0 +1,172 @@
+"""Mojette transform oracle: a plain CPU implementation used to check the GPU path.
+
+TEST INFRASTRUCTURE ONLY.  The product package never imports this module; only
+the test suite, ``__graft_entry__.smoke()`` and the benchmark's CPU-baseline leg
+do.  The arithmetic lives in ``mojette_oracle.c`` (plain C, one loop per line of
+the definitions); this file only builds it with gcc and marshals numpy arrays.
+
+Paper: Pertin et al., arXiv 1504.07038.
+  - ``proj_size``    Section 2.1, Eq. 2.
+  - ``bin_min``      Section 2.1, Eq. 1 (smallest line position over the image).
+  - ``katz``         Section 2.2, Eq. 3.
+  - ``forward``      Section 2.1, Eq. 1, over a pluggable group ("any addition").
+  - ``inverse``      Section 2.2, the peeling reconstruction.
+  - ``encode_blocks`` / ``decode_blocks``  Section 2.3 and Section 3: the XOR
+    erasure code with q_i = 1, one call per block.
+
+Group: ``kind=0`` XOR on uint64 words; ``kind=1`` integers modulo ``mod``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "mojette_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+OK = 0
+EINVAL = -1
+ENOTRECON = -2
+ENOMEM = -4
+EINCONSISTENT = -5
+
+XOR = 0
+MODN = 1
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc into ``oracle/liboracle.so``."""
+    if force or not os.path.exists(LIB):
+        tmp = LIB + ".tmp"
+        subprocess.run(
+            ["gcc", "-O2", "-std=c99", "-Wall", "-Wextra", "-fPIC", "-shared", SRC, "-o", tmp],
+            check=True,
+        )
+        os.replace(tmp, LIB)
+    return LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB):
+        build(force=False)
+    lib = ctypes.CDLL(LIB)
+    i32, i64, u64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
+    vp = ctypes.c_void_p
+    lib.orc_proj_size.argtypes = [i32, i32, i32, i32]
+    lib.orc_proj_size.restype = i64
+    lib.orc_bin_min.argtypes = [i32, i32, i32, i32]
+    lib.orc_bin_min.restype = i64
+    lib.orc_katz.argtypes = [i32, i32, vp, vp, i32]
+    lib.orc_katz.restype = i32
+    lib.orc_forward.argtypes = [i32, u64, vp, i32, i32, vp, vp, i32, vp, vp]
+    lib.orc_forward.restype = i32
+    lib.orc_inverse.argtypes = [i32, u64, vp, vp, vp, vp, i32, i32, i32, vp, i32, vp]
+    lib.orc_inverse.restype = i32
+    lib.orc_encode_blocks.argtypes = [vp, i64, i32, i32, vp, i32, vp]
+    lib.orc_encode_blocks.restype = i32
+    lib.orc_decode_blocks.argtypes = [vp, vp, i64, i32, i32, vp, i32, vp]
+    lib.orc_decode_blocks.restype = i32
+    _lib = lib
+    return lib
+
+
+def _ptr(a: np.ndarray) -> int:
+    return a.ctypes.data
+
+
+def proj_size(p: int, q: int, P: int, Q: int) -> int:
+    return int(_load().orc_proj_size(p, q, P, Q))
+
+
+def bin_min(p: int, q: int, P: int, Q: int) -> int:
+    return int(_load().orc_bin_min(p, q, P, Q))
+
+
+def katz(P: int, Q: int, dirs) -> bool:
+    p = np.ascontiguousarray([d[0] for d in dirs], dtype=np.int32)
+    q = np.ascontiguousarray([d[1] for d in dirs], dtype=np.int32)
+    return bool(_load().orc_katz(P, Q, _ptr(p), _ptr(q), len(dirs)))
+
+
+def _dir_arrays(dirs):
+    p = np.ascontiguousarray([int(d[0]) for d in dirs], dtype=np.int32)
+    q = np.ascontiguousarray([int(d[1]) for d in dirs], dtype=np.int32)
+    return p, q
+
+
+def forward(image: np.ndarray, dirs, kind: int = XOR, mod: int = 0) -> list[np.ndarray]:
+    """Eq. 1 for every direction (p, q) in ``dirs``; ``image`` is (Q, P) uint64."""
+    img = np.ascontiguousarray(image, dtype=np.uint64)
+    Q, P = img.shape
+    p, q = _dir_arrays(dirs)
+    sizes = [proj_size(int(a), int(b), P, Q) for a, b in zip(p, q)]
+    off = np.zeros(len(sizes), dtype=np.int64)
+    if sizes:
+        off[1:] = np.cumsum(sizes)[:-1]
+    flat = np.zeros(max(1, sum(sizes)), dtype=np.uint64)
+    rc = _load().orc_forward(kind, mod, _ptr(img), P, Q, _ptr(p), _ptr(q), len(sizes),
+                             _ptr(flat), _ptr(off))
+    if rc != OK:
+        raise ValueError(f"orc_forward failed: {rc}")
+    return [flat[o:o + s].copy() for o, s in zip(off, sizes)]
+
+
+def inverse(projs, dirs, P: int, Q: int, kind: int = XOR, mod: int = 0,
+            verify: bool = False, return_ops: bool = False):
+    """Peeling reconstruction (Section 2.2) from ``projs[i]`` along ``dirs[i]``.
+
+    Returns ``(rc, image)`` (and the subtraction count when ``return_ops``);
+    ``image`` is (Q, P) uint64 and meaningful only when ``rc == OK``.
+    """
+    p, q = _dir_arrays(dirs)
+    sizes = [len(x) for x in projs]
+    for a, b, s in zip(p, q, sizes):
+        if s != proj_size(int(a), int(b), P, Q):
+            raise ValueError("projection length does not match Eq. 2")
+    off = np.zeros(len(sizes), dtype=np.int64)
+    if sizes:
+        off[1:] = np.cumsum(sizes)[:-1]
+    flat = np.ascontiguousarray(np.concatenate(projs) if projs else np.zeros(1), dtype=np.uint64)
+    img = np.zeros((Q, P), dtype=np.uint64)
+    ops = ctypes.c_int64(0)
+    rc = _load().orc_inverse(kind, mod, _ptr(flat), _ptr(off), _ptr(p), _ptr(q), len(sizes),
+                             P, Q, _ptr(img), int(verify), ctypes.addressof(ops))
+    if return_ops:
+        return int(rc), img, int(ops.value)
+    return int(rc), img
+
+
+def block_stride(P: int, Q: int, p_list) -> int:
+    return sum(proj_size(int(p), 1, P, Q) for p in p_list)
+
+
+def encode_blocks(images: np.ndarray, P: int, Q: int, p_list) -> np.ndarray:
+    """XOR code, q_i = 1: ``images`` (nblocks, Q, P) -> projections (nblocks, sum B_i)."""
+    img = np.ascontiguousarray(images, dtype=np.uint64).reshape(-1, Q, P)
+    p = np.ascontiguousarray(p_list, dtype=np.int32)
+    out = np.zeros((img.shape[0], block_stride(P, Q, p_list)), dtype=np.uint64)
+    rc = _load().orc_encode_blocks(_ptr(img), img.shape[0], P, Q, _ptr(p), len(p), _ptr(out))
+    if rc != OK:
+        raise ValueError(f"orc_encode_blocks failed: {rc}")
+    return out
+
+
+def decode_blocks(projs: np.ndarray, erased: np.ndarray, P: int, Q: int, p_list) -> np.ndarray:
+    """Decode each block from its projections not flagged in ``erased`` (uint16 bit masks)."""
+    pr = np.ascontiguousarray(projs, dtype=np.uint64)
+    er = np.ascontiguousarray(erased, dtype=np.uint16).reshape(-1)
+    p = np.ascontiguousarray(p_list, dtype=np.int32)
+    out = np.zeros((er.shape[0], Q, P), dtype=np.uint64)
+    rc = _load().orc_decode_blocks(_ptr(pr), _ptr(er), er.shape[0], P, Q, _ptr(p), len(p), _ptr(out))
+    if rc != OK:
+        raise ValueError(f"orc_decode_blocks failed: {rc}")
+    return out
