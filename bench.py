@@ -1,0 +1,373 @@
+"""Benchmark: Mojette encode + decode of 4 KB blocks on one MI355X.
+
+One step = one batched encode launch over every block of the workload followed
+by one batched decode launch (two erasures per block), inputs resident in HBM.
+The JSON line reports user-data GB/s for the round trip (``value``), encode and
+decode separately, the plain path (one launch per block, 1,024 blocks) against
+the batched path on the same 1,024 blocks, per-call latency percentiles, the
+dominant kernel's position on the HBM roofline, and the CPU oracle timed on a
+bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0  # MI355X published HBM3E bandwidth
+
+WORKLOADS = {
+    # name: (P, Q, n, nblocks, erasures per block)
+    "4k_6_4": (128, 4, 6, 1 << 21, 2),
+    "8k_6_4": (256, 4, 6, 1 << 20, (0, 2)),
+    "8k_12_8": (128, 8, 12, 1 << 19, 4),
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="4k_6_4", choices=sorted(WORKLOADS))
+    ap.add_argument("--plain-blocks", type=int, default=1024)
+    ap.add_argument("--cpu-sample", type=int, default=1 << 19)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    return ap.parse_args()
+
+
+def pct(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    i = min(len(xs) - 1, max(0, int(round(q / 100.0 * (len(xs) - 1)))))
+    return xs[i]
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for fn in ("encode.hip", "decode.hip", "mj_internal.h", "api.hip"):
+        with open(os.path.join(ROOT, "paper_1504_07038_amd", "csrc", fn), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(workload: str, kernel: str):
+    """HBM traffic per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("source_hash") != kernel_source_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(P, Q, dirs, sample_blocks, n_erase):
+    """The oracle as it stands, over the first `sample_blocks` blocks of the
+    workload, one block chunk per host thread."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import numpy as np
+
+    import oracle
+    import synth
+
+    oracle.build(force=False)
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    cores = max(1, min(cores, 64))
+    imgs = synth.block_images(synth.SEED_DATA, 0, sample_blocks, P, Q)
+    masks = synth.erasure_masks(synth.SEED_ERASE, sample_blocks, len(dirs), n_erase)
+    chunks = np.array_split(np.arange(sample_blocks), cores)
+
+    def enc(ix):
+        return oracle.encode_blocks(imgs[ix[0]:ix[-1] + 1], P, Q, dirs)
+
+    with ThreadPoolExecutor(cores) as ex:
+        t0 = time.perf_counter()
+        projs = list(ex.map(enc, chunks))
+        t_enc = time.perf_counter() - t0
+
+        def dec(args):
+            ix, pr = args
+            return oracle.decode_blocks(pr, masks[ix[0]:ix[-1] + 1], P, Q, dirs)
+
+        t0 = time.perf_counter()
+        outs = list(ex.map(dec, zip(chunks, projs)))
+        t_dec = time.perf_counter() - t0
+    ok = all(np.array_equal(o, imgs[ix[0]:ix[-1] + 1]) for o, ix in zip(outs, chunks))
+    user = sample_blocks * P * Q * 8
+    return {
+        "value": round(user / (t_enc + t_dec) / 1e9, 4),
+        "unit": "GB/s",
+        "cores": cores,
+        "kind": "oracle",
+        "sample": (f"first {sample_blocks} blocks of the workload (same seeds): oracle encode "
+                   f"then decode, one block range per thread"),
+        "encode_GBps": round(user / t_enc / 1e9, 4),
+        "decode_GBps": round(user / t_dec / 1e9, 4),
+        "roundtrip_ok": bool(ok),
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1504_07038_amd as mj
+    import synth
+
+    P, Q, n, nblocks, ner = WORKLOADS[args.workload]
+    dirs = synth.centered_dirs(n)
+    words = mj.mojette_block_words(dirs, P, Q)
+    block_bytes = P * Q * 8
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+
+    d_img = torch.empty(nblocks * Q * P, dtype=torch.int64, device=dev)
+    mj.mojette_fill_splitmix64(d_img, d_img.numel(), synth.SEED_DATA)
+    masks = synth.erasure_masks(synth.SEED_ERASE, nblocks, n, ner)
+    d_mask = torch.from_numpy(masks.view(np.int16)).to(dev)
+    d_proj = torch.empty(nblocks * words, dtype=torch.int64, device=dev)
+    d_out = torch.empty_like(d_img)
+    d_status = torch.zeros(1, dtype=torch.int32, device=dev)
+    torch.cuda.synchronize()
+
+    def step(evs=None):
+        if evs:
+            evs[0].record(stream)
+        mj.mojette_encode_batch(d_img, nblocks, P, Q, dirs, d_proj)
+        if evs:
+            evs[1].record(stream)
+        mj.mojette_decode_batch(d_proj, d_mask, nblocks, P, Q, dirs, d_out, d_status)
+        if evs:
+            evs[2].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    enc_ms = [e[0].elapsed_time(e[1]) for e in evs]
+    dec_ms = [e[1].elapsed_time(e[2]) for e in evs]
+    step_ms = [e[0].elapsed_time(e[2]) for e in evs]
+    ms_per_step = wall * 1e3 / args.steps
+
+    # correctness of the timed work (outside the timed region)
+    roundtrip_ok = bool(torch.equal(d_out, d_img)) and int(d_status.item()) == 0
+
+    user_bytes = nblocks * block_bytes
+    enc_avg = sum(enc_ms) / len(enc_ms)
+    dec_avg = sum(dec_ms) / len(dec_ms)
+    enc_alg = 8 * (P * Q + words)          # read the image, write every bin
+    dec_alg = 16 * P * Q                   # read P bins of Q survivors, write the image
+    kernels = {
+        "encode": {"ms": enc_avg, "alg_bytes_per_block": enc_alg},
+        "decode": {"ms": dec_avg, "alg_bytes_per_block": dec_alg},
+    }
+    dom = "encode" if enc_avg >= dec_avg else "decode"
+
+    def roof(name):
+        k = kernels[name]
+        achieved = k["alg_bytes_per_block"] * nblocks / (k["ms"] * 1e-3) / 1e9
+        tr = load_traffic(args.workload, name)
+        return {
+            "kernel": name,
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBPS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBPS, 4),
+            "traffic": tr,
+            "alg_bytes_per_launch": k["alg_bytes_per_block"] * nblocks,
+            "avg_launch_ms": round(k["ms"], 4),
+        }
+
+    # a plain streaming copy of the image pool: the practical HBM ceiling
+    copy_ms = []
+    for k in range(6):
+        ea, eb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ea.record(stream)
+        mj.mojette_copy_words(d_out, d_img, d_img.numel())
+        eb.record(stream)
+        torch.cuda.synchronize()
+        if k:
+            copy_ms.append(ea.elapsed_time(eb))
+    copy_gbps = 2 * d_img.numel() * 8 / (sum(copy_ms) / len(copy_ms) * 1e-3) / 1e9
+
+    # plain path: one launch per block, against the batched path on the same blocks
+    plain = None
+    if not args.no_plain:
+        plain = plain_vs_batched(mj, torch, np, d_img, d_proj, masks, P, Q, dirs, words,
+                                 args.plain_blocks, block_bytes)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(P, Q, dirs, min(args.cpu_sample, nblocks), ner)
+
+    rec = {
+        "metric": "encode/decode GB/s of user data at 4 KB blocks (batched vs plain); p99 latency",
+        "value": round(user_bytes / (ms_per_step * 1e-3) / 1e9, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{args.workload}: {nblocks} blocks of {block_bytes} B, P={P} Q={Q} "
+                        f"n={n} p={dirs[0]}..{dirs[-1]} q=1, XOR, erasures/block={ner}",
+            "blocks": nblocks, "P": P, "Q": Q, "n": n, "erasures": str(ner),
+            "parallelism": "single GPU",
+        },
+        "encode_GBps": round(user_bytes / (enc_avg * 1e-3) / 1e9, 2),
+        "decode_GBps": round(user_bytes / (dec_avg * 1e-3) / 1e9, 2),
+        "step_ms_p50": round(pct(step_ms, 50), 4),
+        "step_ms_p99": round(pct(step_ms, 99), 4),
+        "roundtrip_ok": roundtrip_ok,
+        "copy_GBps": round(copy_gbps, 1),
+        "roofline": roof(dom),
+        "roofline_other": roof("decode" if dom == "encode" else "encode"),
+        "plain_vs_batched": plain,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(rec), flush=True)
+    if not roundtrip_ok:
+        sys.exit(1)
+
+
+def plain_vs_batched(mj, torch, np, d_img, d_proj, masks, P, Q, dirs, words, nb, block_bytes):
+    """Config of 1,024 blocks: one mojette_encode / mojette_decode launch per
+    block (the plain path) against one batched launch over the same blocks."""
+    L = mj.lib()
+    n = len(dirs)
+    stream = torch.cuda.current_stream()
+    sp = stream.cuda_stream
+    dirs_arr = (ctypes.c_int32 * n)(*dirs)
+    sizes = [mj.mojette_proj_size(p, P, Q) for p in dirs]
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    p_out = torch.empty(nb * words, dtype=torch.int64, device=d_img.device)
+    i_out = torch.empty(nb * Q * P, dtype=torch.int64, device=d_img.device)
+    b_proj = torch.empty_like(p_out)
+    b_out = torch.empty_like(i_out)
+    d_mask = torch.from_numpy(masks[:nb].view(np.int16)).to(d_img.device)
+    img0, pout0, iout0 = d_img.data_ptr(), p_out.data_ptr(), i_out.data_ptr()
+    enc_args, dec_args = [], []
+    for b in range(nb):
+        outs = (ctypes.c_void_p * n)(*[pout0 + 8 * (b * words + int(offs[i])) for i in range(n)])
+        enc_args.append((ctypes.c_void_p(img0 + 8 * b * Q * P), outs))
+        keep = [i for i in range(n) if not (int(masks[b]) >> i) & 1]
+        ptrs = (ctypes.c_void_p * len(keep))(*[pout0 + 8 * (b * words + int(offs[i])) for i in keep])
+        ids = (ctypes.c_int32 * len(keep))(*keep)
+        dec_args.append((ptrs, ids, len(keep), ctypes.c_void_p(iout0 + 8 * b * Q * P)))
+
+    def run_plain_enc(sync_each):
+        lat = []
+        for a in enc_args:
+            t = time.perf_counter()
+            rc = L.mojette_encode(a[0], P, Q, dirs_arr, n, a[1], sp)
+            if sync_each:
+                torch.cuda.synchronize()
+                lat.append((time.perf_counter() - t) * 1e6)
+            assert rc == 0
+        return lat
+
+    def run_plain_dec(sync_each):
+        lat = []
+        for a in dec_args:
+            t = time.perf_counter()
+            rc = L.mojette_decode(a[0], a[1], a[2], dirs_arr, n, P, Q, a[3], sp)
+            if sync_each:
+                torch.cuda.synchronize()
+                lat.append((time.perf_counter() - t) * 1e6)
+            assert rc == 0
+        return lat
+
+    def run_batch_enc():
+        mj.mojette_encode_batch(d_img, nb, P, Q, dirs, b_proj)
+
+    def run_batch_dec():
+        mj.mojette_decode_batch(b_proj, d_mask, nb, P, Q, dirs, b_out)
+
+    def timed(fn, reps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / reps
+
+    for _ in range(2):
+        run_plain_enc(False)
+        run_plain_dec(False)
+        run_batch_enc()
+        run_batch_dec()
+    t_pe = timed(lambda: run_plain_enc(False), 3)
+    t_pd = timed(lambda: run_plain_dec(False), 3)
+    t_be = timed(run_batch_enc, 50)
+    t_bd = timed(run_batch_dec, 50)
+    lat_pe = run_plain_enc(True)
+    lat_pd = run_plain_dec(True)
+    lat_be, lat_bd = [], []
+    for _ in range(200):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        run_batch_enc()
+        torch.cuda.synchronize()
+        lat_be.append((time.perf_counter() - t) * 1e6)
+        t = time.perf_counter()
+        run_batch_dec()
+        torch.cuda.synchronize()
+        lat_bd.append((time.perf_counter() - t) * 1e6)
+    same = bool(torch.equal(p_out, b_proj)) and bool(torch.equal(i_out, b_out)) and \
+        bool(torch.equal(i_out, d_img[: nb * Q * P]))
+    user = nb * block_bytes
+    return {
+        "blocks": nb,
+        "plain_encode_GBps": round(user / t_pe / 1e9, 3),
+        "plain_decode_GBps": round(user / t_pd / 1e9, 3),
+        "batched_encode_GBps": round(user / t_be / 1e9, 3),
+        "batched_decode_GBps": round(user / t_bd / 1e9, 3),
+        "batched_over_plain_encode": round(t_pe / t_be, 1),
+        "batched_over_plain_decode": round(t_pd / t_bd, 1),
+        "plain_encode_call_us_p50": round(pct(lat_pe, 50), 1),
+        "plain_encode_call_us_p99": round(pct(lat_pe, 99), 1),
+        "plain_decode_call_us_p50": round(pct(lat_pd, 50), 1),
+        "plain_decode_call_us_p99": round(pct(lat_pd, 99), 1),
+        "batched_encode_call_us_p50": round(pct(lat_be, 50), 1),
+        "batched_encode_call_us_p99": round(pct(lat_be, 99), 1),
+        "batched_decode_call_us_p50": round(pct(lat_bd, 50), 1),
+        "batched_decode_call_us_p99": round(pct(lat_bd, 99), 1),
+        "outputs_identical": same,
+    }
+
+
+if __name__ == "__main__":
+    main()

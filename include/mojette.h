@@ -1,0 +1,133 @@
+/*
+ * mojette.h -- C ABI of the MI355X (gfx950) Mojette erasure-code library.
+ *
+ * The Mojette erasure code of Pertin, Feron, Van Kempen and Parrein
+ * (arXiv 1504.07038): the k data packets of a block are the Q = k rows of a
+ * P x Q image of 64-bit pixels (Section 2.3); encoding is the forward Mojette
+ * transform along n directions (p_i, q_i = 1) (Section 2.1, Eq. 1, with XOR as
+ * the addition, Section 3.1); decoding rebuilds the image from any Q surviving
+ * projections (Katz criterion, Section 2.2, Eq. 3) by peeling pixels along a
+ * reconstruction path fixed before the sweep (Section 2.2).
+ *
+ * Conventions shared by every call:
+ *   - Pixel (k, l), column k in [0, P), row l in [0, Q), of a block is word
+ *     l*P + k of the block's image (row l = data packet l).
+ *   - Directions are given by their p values only (q = 1 for all, as the code
+ *     of Section 2.3 fixes); they must be distinct.  n <= 16, 1 <= Q <= 16.
+ *   - Projection i has B_i = |p_i|(Q-1) + P bins (Eq. 2 with q = 1); bin b
+ *     (the line b = -k + l*p_i of Eq. 1) is stored at index b - b_min(p_i),
+ *     b_min(p) = -(P-1) + min(0, (Q-1)p), in ascending b.
+ *   - In a batch pool, the n projections of a block are contiguous, projection
+ *     i at word offset sum_{i' < i} B_i' of the block's slice; the slice is
+ *     mojette_block_words() long and block b's slice starts at b times that.
+ *   - Pixel and bin buffers are DEVICE pointers owned by the caller; small
+ *     host arrays (dirs, pointer tables, ids) are read before the call
+ *     returns.  No call allocates or frees device memory.  Images must not
+ *     overlap projections.
+ *   - Work is enqueued on `stream` (a hipStream_t; NULL = the default stream)
+ *     and the call returns without waiting.  Argument errors are reported
+ *     before anything is enqueued; a failed launch returns MOJETTE_EHIP.
+ *   - The batch calls allocate nothing and never synchronise, so they may be
+ *     recorded into a HIP graph.
+ *   - Calls on distinct streams may run concurrently.
+ */
+#ifndef MOJETTE_H
+#define MOJETTE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MOJETTE_OK 0
+#define MOJETTE_EINVAL (-1)        /* bad argument */
+#define MOJETTE_ENOTRECON (-2)     /* fewer than Q projections survive (Eq. 3) */
+#define MOJETTE_EHIP (-3)          /* a HIP runtime call failed */
+#define MOJETTE_ENOMEM (-4)        /* host-side bookkeeping could not allocate */
+#define MOJETTE_ENOTSUP (-6)       /* geometry beyond the kernels' LDS limits */
+
+#define MOJETTE_MAX_DIRS 16
+#define MOJETTE_MAX_ROWS 16
+
+/* Human-readable name of a status code. */
+const char *mojette_strerror(int status);
+
+/* Eq. 2 with q = 1: number of bins of the projection along (p, 1) of a
+ * P x Q image, |p|(Q-1) + P.  Returns -1 if P < 1 or Q < 1. */
+int64_t mojette_proj_size(int32_t p, int32_t P, int32_t Q);
+
+/* Smallest line position b = -k + l*p over a P x Q image (Eq. 1): bin b is
+ * stored at index b - mojette_bin_offset(p, P, Q). */
+int64_t mojette_bin_offset(int32_t p, int32_t P, int32_t Q);
+
+/* Words of projection data per block: sum over the n directions of B_i.
+ * Returns -1 on bad arguments. */
+int64_t mojette_block_words(const int32_t *dirs, int32_t n, int32_t P, int32_t Q);
+
+/*
+ * Forward transform of ONE block (Section 2.1, Eq. 1; encoding, Section 2.3).
+ *   image     device, Q*P words, row-major.
+ *   dirs      host, n distinct p values.
+ *   proj_out  host array of n device pointers; proj_out[i] receives the B_i
+ *             bins of direction dirs[i].
+ * Returns MOJETTE_OK, MOJETTE_EINVAL, MOJETTE_ENOTSUP or MOJETTE_EHIP.
+ */
+int mojette_encode(const uint64_t *image, int32_t P, int32_t Q, const int32_t *dirs, int32_t n,
+                   uint64_t *const *proj_out, void *stream);
+
+/*
+ * Inverse transform of ONE block (Section 2.2).
+ *   proj      host array of m device pointers; proj[t] holds the full B bins
+ *             of direction dirs[proj_ids[t]].
+ *   proj_ids  host, m distinct indices into dirs.
+ *   dirs, n   the code's directions, as given to mojette_encode.
+ *   image_out device, Q*P words.
+ * m >= Q is required (Katz with q_i = 1: any Q of the n projections
+ * reconstruct, Section 2.3); with m > Q the Q survivors of smallest p are
+ * used.  Returns MOJETTE_OK, MOJETTE_EINVAL, MOJETTE_ENOTRECON,
+ * MOJETTE_ENOTSUP or MOJETTE_EHIP.
+ */
+int mojette_decode(const uint64_t *const *proj, const int32_t *proj_ids, int32_t m,
+                   const int32_t *dirs, int32_t n, int32_t P, int32_t Q, uint64_t *image_out,
+                   void *stream);
+
+/*
+ * Forward transform of nblocks blocks of one geometry in one launch.
+ *   images  device, nblocks x Q x P words (block b at b*Q*P).
+ *   projs   device, nblocks x mojette_block_words() words (layout above).
+ * nblocks == 0 is a no-op.  Returns as mojette_encode.
+ */
+int mojette_encode_batch(const uint64_t *images, int64_t nblocks, int32_t P, int32_t Q,
+                         const int32_t *dirs, int32_t n, uint64_t *projs, void *stream);
+
+/*
+ * Inverse transform of nblocks blocks of one geometry in one launch.
+ *   projs    device, pool laid out as for mojette_encode_batch.  Bins of
+ *            erased projections are never read.
+ *   erased   device, nblocks uint16 masks; bit i set = projection i of that
+ *            block is lost.  NULL means no erasures.
+ *   images   device, nblocks x Q x P words, written for every decodable
+ *            block.
+ *   status   device int32 or NULL.  A block with fewer than Q survivors is
+ *            left unwritten and MOJETTE_ENOTRECON is stored to *status; the
+ *            call never clears *status, so the caller sets it to 0 first.
+ * Returns as mojette_decode (argument errors only; per-block survivor
+ * shortfalls are reported through status).
+ */
+int mojette_decode_batch(const uint64_t *projs, const uint16_t *erased, int64_t nblocks,
+                         int32_t P, int32_t Q, const int32_t *dirs, int32_t n, uint64_t *images,
+                         int32_t *status, void *stream);
+
+/* Ring length (words per row) the decoder needs for this geometry: the
+ * longest distance, over every choice of Q survivors, between a pixel a row
+ * needs and the newest pixel of that row, rounded up to a power of two and
+ * at least the tile width.  -1 on bad arguments. */
+int32_t mojette_decode_ring(const int32_t *dirs, int32_t n, int32_t P, int32_t Q);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MOJETTE_H */

@@ -1,0 +1,195 @@
+"""Python binding of ``libmojette.so`` (Mojette erasure code on MI355X / gfx950).
+
+Argument marshalling only: every step of encode and decode runs in the HIP
+kernels behind the C ABI declared in ``include/mojette.h``.  PyTorch supplies
+device memory (``torch.int64`` tensors carry the 64-bit pixel and bin words
+bit for bit) and the current HIP stream.  If the library is not built, every
+call raises: there is no CPU fallback.
+
+Paper: Pertin, Feron, Van Kempen, Parrein, arXiv 1504.07038 -- Section 2.1
+(forward transform, Eq. 1-2), Section 2.2 (inverse, Eq. 3), Section 2.3 (the
+erasure code: k data lines, n projections with q_i = 1).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmojette.so")
+
+MOJETTE_OK = 0
+MOJETTE_EINVAL = -1
+MOJETTE_ENOTRECON = -2
+MOJETTE_EHIP = -3
+MOJETTE_ENOMEM = -4
+MOJETTE_ENOTSUP = -6
+MAX_DIRS = 16
+MAX_ROWS = 16
+
+
+class MojetteError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        super().__init__(f"{where}: {strerror(status)} ({status})")
+        self.status = status
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load the in-tree HIP library, raising if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    i32, i64, u64, vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_void_p
+    sig = {
+        "mojette_strerror": ([ctypes.c_int], ctypes.c_char_p),
+        "mojette_proj_size": ([i32, i32, i32], i64),
+        "mojette_bin_offset": ([i32, i32, i32], i64),
+        "mojette_block_words": ([vp, i32, i32, i32], i64),
+        "mojette_decode_ring": ([vp, i32, i32, i32], i32),
+        "mojette_encode": ([vp, i32, i32, vp, i32, vp, vp], ctypes.c_int),
+        "mojette_decode": ([vp, vp, i32, vp, i32, i32, i32, vp, vp], ctypes.c_int),
+        "mojette_encode_batch": ([vp, i64, i32, i32, vp, i32, vp, vp], ctypes.c_int),
+        "mojette_decode_batch": ([vp, vp, i64, i32, i32, vp, i32, vp, vp, vp], ctypes.c_int),
+        "mojette_fill_splitmix64": ([vp, i64, u64, u64, vp], ctypes.c_int),
+        "mojette_copy_words": ([vp, vp, i64, vp], ctypes.c_int),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = L
+    return L
+
+
+def exported_symbols() -> list[str]:
+    return [
+        "mojette_strerror", "mojette_proj_size", "mojette_bin_offset", "mojette_block_words",
+        "mojette_decode_ring", "mojette_encode", "mojette_decode", "mojette_encode_batch",
+        "mojette_decode_batch", "mojette_fill_splitmix64", "mojette_copy_words",
+    ]
+
+
+# ---- marshalling helpers -------------------------------------------------
+
+def _i32_array(values):
+    vals = [int(v) for v in values]
+    return (ctypes.c_int32 * max(1, len(vals)))(*vals), len(vals)
+
+
+def _dev_ptr(t, name: str) -> int:
+    if t is None:
+        return 0
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t.data_ptr()
+
+
+def _word_tensor(t, name: str) -> int:
+    import torch
+
+    if t.dtype not in (torch.int64, torch.uint64):
+        raise ValueError(f"{name} must hold 64-bit words (torch.int64)")
+    return _dev_ptr(t, name)
+
+
+def _stream(stream) -> int:
+    if stream is not None:
+        return int(stream)
+    import torch
+
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _check(rc: int, where: str, check: bool) -> int:
+    if check and rc != MOJETTE_OK:
+        raise MojetteError(rc, where)
+    return rc
+
+
+# ---- the C ABI, name for name -------------------------------------------
+
+def strerror(status: int) -> str:
+    return lib().mojette_strerror(status).decode()
+
+
+mojette_strerror = strerror
+
+
+def mojette_proj_size(p: int, P: int, Q: int) -> int:
+    return int(lib().mojette_proj_size(p, P, Q))
+
+
+def mojette_bin_offset(p: int, P: int, Q: int) -> int:
+    return int(lib().mojette_bin_offset(p, P, Q))
+
+
+def mojette_block_words(dirs, P: int, Q: int) -> int:
+    arr, n = _i32_array(dirs)
+    return int(lib().mojette_block_words(arr, n, P, Q))
+
+
+def mojette_decode_ring(dirs, P: int, Q: int) -> int:
+    arr, n = _i32_array(dirs)
+    return int(lib().mojette_decode_ring(arr, n, P, Q))
+
+
+def mojette_encode(image, P: int, Q: int, dirs, proj_out, stream=None, check: bool = True) -> int:
+    arr, n = _i32_array(dirs)
+    ptrs = (ctypes.c_void_p * max(1, len(proj_out)))(
+        *[_word_tensor(t, "proj_out") for t in proj_out])
+    rc = lib().mojette_encode(_word_tensor(image, "image"), P, Q, arr, n, ptrs, _stream(stream))
+    return _check(rc, "mojette_encode", check)
+
+
+def mojette_decode(proj, proj_ids, dirs, P: int, Q: int, image_out, stream=None,
+                   check: bool = True) -> int:
+    arr, n = _i32_array(dirs)
+    ids, m = _i32_array(proj_ids)
+    ptrs = (ctypes.c_void_p * max(1, len(proj)))(*[_word_tensor(t, "proj") for t in proj])
+    rc = lib().mojette_decode(ptrs, ids, m, arr, n, P, Q, _word_tensor(image_out, "image_out"),
+                              _stream(stream))
+    return _check(rc, "mojette_decode", check)
+
+
+def mojette_encode_batch(images, nblocks: int, P: int, Q: int, dirs, projs, stream=None,
+                         check: bool = True) -> int:
+    arr, n = _i32_array(dirs)
+    rc = lib().mojette_encode_batch(_word_tensor(images, "images"), nblocks, P, Q, arr, n,
+                                    _word_tensor(projs, "projs"), _stream(stream))
+    return _check(rc, "mojette_encode_batch", check)
+
+
+def mojette_decode_batch(projs, erased, nblocks: int, P: int, Q: int, dirs, images,
+                         status=None, stream=None, check: bool = True) -> int:
+    import torch
+
+    arr, n = _i32_array(dirs)
+    if erased is not None and erased.dtype not in (torch.int16, torch.uint16):
+        raise ValueError("erased must be 16-bit masks")
+    if status is not None and status.dtype != torch.int32:
+        raise ValueError("status must be int32")
+    rc = lib().mojette_decode_batch(_word_tensor(projs, "projs"), _dev_ptr(erased, "erased"),
+                                    nblocks, P, Q, arr, n, _word_tensor(images, "images"),
+                                    _dev_ptr(status, "status"), _stream(stream))
+    return _check(rc, "mojette_decode_batch", check)
+
+
+def mojette_fill_splitmix64(dst, nwords: int, seed: int, start: int = 0, stream=None,
+                            check: bool = True) -> int:
+    rc = lib().mojette_fill_splitmix64(_word_tensor(dst, "dst"), nwords,
+                                       seed & 0xFFFFFFFFFFFFFFFF, start, _stream(stream))
+    return _check(rc, "mojette_fill_splitmix64", check)
+
+
+def mojette_copy_words(dst, src, nwords: int, stream=None, check: bool = True) -> int:
+    rc = lib().mojette_copy_words(_word_tensor(dst, "dst"), _word_tensor(src, "src"), nwords,
+                                  _stream(stream))
+    return _check(rc, "mojette_copy_words", check)

@@ -1,0 +1,286 @@
+// C-ABI entry points: argument checking, per-geometry launch parameters and
+// kernel launches.  Nothing here allocates device memory or synchronises.
+#include <algorithm>
+#include <cstdlib>
+#include <map>
+#include <mutex>
+#include <vector>
+
+#include "mj_internal.h"
+
+namespace {
+
+using mj::kMaxDirs;
+using mj::kMaxRows;
+
+constexpr size_t kLdsLimit = 64 * 1024;        // dynamic LDS per workgroup used by the kernels
+constexpr int kMaxP = 1 << 24;                 // keeps every bin index inside int32
+constexpr int kMaxAbsP = 1 << 16;
+constexpr int kEncodeGridCap = 256 * 64;       // workgroups; larger batches loop inside the kernel
+constexpr int kDecodeGridCap = 256 * 128;
+
+bool geometry_ok(const int32_t *dirs, int32_t n, int32_t P, int32_t Q) {
+    if (!dirs || n < 1 || n > kMaxDirs || P < 1 || P > kMaxP || Q < 1 || Q > kMaxRows) return false;
+    if ((int64_t)P * Q > ((int64_t)1 << 30)) return false;
+    for (int i = 0; i < n; ++i) {
+        if (dirs[i] < -kMaxAbsP || dirs[i] > kMaxAbsP) return false;
+        for (int j = 0; j < i; ++j)
+            if (dirs[i] == dirs[j]) return false;
+    }
+    return true;
+}
+
+int status_of(hipError_t e) { return e == hipSuccess ? MOJETTE_OK : MOJETTE_EHIP; }
+
+// Encode tiling: the whole row when it fits, else the widest multiple of 64
+// columns whose tile plus halo fits the LDS budget.  Four waves per
+// workgroup when their four tiles fit (at least min(P, 256) columns each),
+// else two, else one.
+bool encode_tiling(const int32_t *dirs, int32_t n, int32_t P, int32_t Q, mj::EncodeArgs &a) {
+    int maxabs = 0;
+    for (int i = 0; i < n; ++i) maxabs = std::max(maxabs, std::abs(dirs[i]));
+    const int H = (Q - 1) * maxabs;
+    const int want = std::min(P, 256);
+    int waves = mj::kEncodeWaves;
+    size_t cols_fit = 0;
+    for (; waves >= 1; waves /= 2) {
+        cols_fit = kLdsLimit / ((size_t)waves * Q * sizeof(uint64_t));
+        if (cols_fit >= (size_t)(2 * H + want) || (waves == 1 && cols_fit >= (size_t)(2 * H + 64)))
+            break;
+    }
+    if (waves < 1) return false;
+    int W = P;
+    if ((size_t)(P + 2 * H) > cols_fit) W = (int)((cols_fit - 2 * H) / 64 * 64);
+    a.waves = waves;
+    a.W = W;
+    a.H = H;
+    a.S = W + 2 * H;
+    a.ntiles = (P + W - 1) / W;
+    a.P = P;
+    a.Q = Q;
+    a.n = n;
+    for (int i = 0; i < n; ++i) {
+        a.p[i] = dirs[i];
+        a.bmin[i] = mj::bin_offset(dirs[i], P, Q);
+        a.nbins[i] = mj::proj_bins(dirs[i], P, Q);
+    }
+    return true;
+}
+
+// Ring length for the decoder: the largest distance D between the newest
+// pixel of row l and the pixel (k + (l-r)p_r, l) that row r reads, over
+// every Q-subset of the directions, plus one, rounded up to a power of two
+// and to at least the tile width.  D = ceil((A_l - A_r)/2) - 1 - (l-r)p_r is
+// independent of k.  A negative D would mean a pixel is read before it is
+// written; the ordering argument in decode.hip rules that out, and this
+// function re-checks it (returns -1 then).
+struct RingKey {
+    std::vector<int> p;
+    int Q;
+    bool operator<(const RingKey &o) const { return Q != o.Q ? Q < o.Q : p < o.p; }
+};
+
+int ring_length(const std::vector<int> &sorted_p, int Q) {
+    static std::mutex mu;
+    static std::map<RingKey, int> cache;
+    RingKey key{sorted_p, Q};
+    {
+        std::lock_guard<std::mutex> g(mu);
+        auto it = cache.find(key);
+        if (it != cache.end()) return it->second;
+    }
+    const int n = (int)sorted_p.size();
+    int Dmax = 0;
+    bool ok = true;
+    std::vector<int> pick(Q), A(Q);
+    for (int i = 0; i < Q; ++i) pick[i] = i;
+    while (true) {
+        int psum = 0;
+        for (int r = 0; r < Q; ++r) {
+            A[r] = 2 * psum + r;
+            psum += sorted_p[pick[r]];
+        }
+        for (int r = 0; r < Q; ++r) {
+            const int pr = sorted_p[pick[r]];
+            for (int l = 0; l < Q; ++l) {
+                if (l == r) continue;
+                const int diff = A[l] - A[r];
+                const int ceil_half = (diff >= 0) ? (diff + 1) / 2 : -((-diff) / 2);
+                const int D = ceil_half - 1 - (l - r) * pr;
+                if (D < 0) ok = false;
+                Dmax = std::max(Dmax, D);
+            }
+        }
+        int i = Q - 1;
+        while (i >= 0 && pick[i] == n - Q + i) --i;
+        if (i < 0) break;
+        ++pick[i];
+        for (int j = i + 1; j < Q; ++j) pick[j] = pick[j - 1] + 1;
+    }
+    int R = -1;
+    if (ok) {
+        R = mj::kDecodeTile;
+        while (R < Dmax + 1) R <<= 1;
+    }
+    std::lock_guard<std::mutex> g(mu);
+    cache[key] = R;
+    return R;
+}
+
+// Fills the geometry part of the decode arguments.  Returns a status.
+int decode_setup(const int32_t *dirs, int32_t n, int32_t P, int32_t Q, mj::DecodeArgs &a) {
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::sort(order.begin(), order.end(), [&](int x, int y) { return dirs[x] < dirs[y]; });
+    std::vector<int> sp(n);
+    for (int s = 0; s < n; ++s) {
+        a.p_sorted[s] = dirs[order[s]];
+        a.id_sorted[s] = order[s];
+        sp[s] = dirs[order[s]];
+    }
+    if (n < Q) return MOJETTE_ENOTRECON;
+    const int R = ring_length(sp, Q);
+    if (R < 0) return MOJETTE_EINVAL;
+    a.R = R;
+    a.ring_stride = R + 1;  // odd stride spreads the rows over the LDS banks
+    a.nb = mj::kWave / Q;
+    while (a.nb > 0 && mj::decode_lds_bytes(Q, a.nb, a.ring_stride) > kLdsLimit) --a.nb;
+    if (a.nb < 1) return MOJETTE_ENOTSUP;
+    a.P = P;
+    a.n = n;
+    return MOJETTE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *mojette_strerror(int status) {
+    switch (status) {
+        case MOJETTE_OK: return "ok";
+        case MOJETTE_EINVAL: return "invalid argument";
+        case MOJETTE_ENOTRECON: return "fewer than Q projections survive: not reconstructible";
+        case MOJETTE_EHIP: return "HIP runtime error";
+        case MOJETTE_ENOMEM: return "out of host memory";
+        case MOJETTE_ENOTSUP: return "geometry exceeds the kernels' LDS limits";
+        default: return "unknown status";
+    }
+}
+
+int64_t mojette_proj_size(int32_t p, int32_t P, int32_t Q) {
+    if (P < 1 || Q < 1) return -1;
+    return (int64_t)(p < 0 ? -(int64_t)p : p) * (Q - 1) + P;
+}
+
+int64_t mojette_bin_offset(int32_t p, int32_t P, int32_t Q) {
+    const int64_t m = (int64_t)(Q - 1) * p;
+    return -(int64_t)(P - 1) + (m < 0 ? m : 0);
+}
+
+int64_t mojette_block_words(const int32_t *dirs, int32_t n, int32_t P, int32_t Q) {
+    if (!geometry_ok(dirs, n, P, Q)) return -1;
+    int64_t s = 0;
+    for (int i = 0; i < n; ++i) s += mojette_proj_size(dirs[i], P, Q);
+    return s;
+}
+
+int32_t mojette_decode_ring(const int32_t *dirs, int32_t n, int32_t P, int32_t Q) {
+    if (!geometry_ok(dirs, n, P, Q) || n < Q) return -1;
+    std::vector<int> sp(dirs, dirs + n);
+    std::sort(sp.begin(), sp.end());
+    return ring_length(sp, Q);
+}
+
+int mojette_encode(const uint64_t *image, int32_t P, int32_t Q, const int32_t *dirs, int32_t n,
+                   uint64_t *const *proj_out, void *stream) {
+    if (!image || !proj_out || !geometry_ok(dirs, n, P, Q)) return MOJETTE_EINVAL;
+    for (int i = 0; i < n; ++i)
+        if (!proj_out[i]) return MOJETTE_EINVAL;
+    mj::EncodeArgs a{};
+    if (!encode_tiling(dirs, n, P, Q, a)) return MOJETTE_ENOTSUP;
+    a.images = image;
+    a.img_stride = 0;
+    for (int i = 0; i < n; ++i) a.out[i] = proj_out[i];
+    a.proj_stride = 0;
+    a.nblocks = 1;
+    const int grid = (a.ntiles + a.waves - 1) / a.waves;
+    return status_of(mj::launch_encode(a, grid, (hipStream_t)stream));
+}
+
+int mojette_encode_batch(const uint64_t *images, int64_t nblocks, int32_t P, int32_t Q,
+                         const int32_t *dirs, int32_t n, uint64_t *projs, void *stream) {
+    if (nblocks < 0 || !geometry_ok(dirs, n, P, Q)) return MOJETTE_EINVAL;
+    if (nblocks == 0) return MOJETTE_OK;
+    if (!images || !projs) return MOJETTE_EINVAL;
+    mj::EncodeArgs a{};
+    if (!encode_tiling(dirs, n, P, Q, a)) return MOJETTE_ENOTSUP;
+    a.images = images;
+    a.img_stride = (int64_t)P * Q;
+    int64_t off = 0;
+    for (int i = 0; i < n; ++i) {
+        a.out[i] = projs + off;
+        off += a.nbins[i];
+    }
+    a.proj_stride = off;
+    a.nblocks = nblocks;
+    const int64_t items = nblocks * a.ntiles;
+    const int64_t want = (items + a.waves - 1) / a.waves;
+    const int grid = (int)std::min<int64_t>(want, kEncodeGridCap);
+    return status_of(mj::launch_encode(a, grid, (hipStream_t)stream));
+}
+
+int mojette_decode(const uint64_t *const *proj, const int32_t *proj_ids, int32_t m,
+                   const int32_t *dirs, int32_t n, int32_t P, int32_t Q, uint64_t *image_out,
+                   void *stream) {
+    if (!image_out || !geometry_ok(dirs, n, P, Q) || m < 0 || m > n) return MOJETTE_EINVAL;
+    if (m > 0 && (!proj || !proj_ids)) return MOJETTE_EINVAL;
+    mj::DecodeArgs a{};
+    uint32_t have = 0;
+    for (int t = 0; t < m; ++t) {
+        const int id = proj_ids[t];
+        if (id < 0 || id >= n || ((have >> id) & 1u) || !proj[t]) return MOJETTE_EINVAL;
+        have |= 1u << id;
+        a.in[id] = proj[t];
+    }
+    if (m < Q) return MOJETTE_ENOTRECON;
+    a.fallback = proj[0];
+    const int rc = decode_setup(dirs, n, P, Q, a);
+    if (rc != MOJETTE_OK) return rc;
+    a.proj_stride = 0;
+    a.images = image_out;
+    a.img_stride = 0;
+    a.masks = nullptr;
+    a.mask_uniform = ~have & ((1u << n) - 1u);
+    a.status = nullptr;
+    a.nblocks = 1;
+    return status_of(mj::launch_decode(Q, a, 1, (hipStream_t)stream));
+}
+
+int mojette_decode_batch(const uint64_t *projs, const uint16_t *erased, int64_t nblocks,
+                         int32_t P, int32_t Q, const int32_t *dirs, int32_t n, uint64_t *images,
+                         int32_t *status, void *stream) {
+    if (nblocks < 0 || !geometry_ok(dirs, n, P, Q)) return MOJETTE_EINVAL;
+    if (nblocks == 0) return MOJETTE_OK;
+    if (!projs || !images) return MOJETTE_EINVAL;
+    mj::DecodeArgs a{};
+    const int rc = decode_setup(dirs, n, P, Q, a);
+    if (rc != MOJETTE_OK) return rc;
+    int64_t off = 0;
+    for (int i = 0; i < n; ++i) {
+        a.in[i] = projs + off;
+        off += mojette_proj_size(dirs[i], P, Q);
+    }
+    a.fallback = projs;
+    a.proj_stride = off;
+    a.images = images;
+    a.img_stride = (int64_t)P * Q;
+    a.masks = erased;
+    a.mask_uniform = 0;
+    a.status = status;
+    a.nblocks = nblocks;
+    const int64_t batches = (nblocks + a.nb - 1) / a.nb;
+    const int grid = (int)std::min<int64_t>(batches, kDecodeGridCap);
+    return status_of(mj::launch_decode(Q, a, grid, (hipStream_t)stream));
+}
+
+}  // extern "C"

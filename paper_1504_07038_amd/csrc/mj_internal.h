@@ -1,0 +1,84 @@
+// Internal declarations shared by the host API and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/mojette.h"
+
+namespace mj {
+
+constexpr int kMaxDirs = MOJETTE_MAX_DIRS;
+constexpr int kMaxRows = MOJETTE_MAX_ROWS;
+constexpr int kWave = 64;          // CDNA wavefront width
+constexpr int kDecodeTile = 16;    // columns per row per decode tile
+constexpr int kEncodeWaves = 4;    // most waves per encode workgroup
+
+// Orders LDS traffic between the lanes of one wavefront.  The LDS
+// instructions of a wave execute in issue order, so a compiler-level fence at
+// wavefront scope is enough: no wait for the LDS queue to drain.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Smallest line position b = -k + l*p over a P x Q image (q = 1).
+__host__ __device__ inline int32_t bin_offset(int32_t p, int32_t P, int32_t Q) {
+    int32_t m = (Q - 1) * p;
+    return -(P - 1) + (m < 0 ? m : 0);
+}
+
+// Eq. 2 with q = 1.
+__host__ __device__ inline int32_t proj_bins(int32_t p, int32_t P, int32_t Q) {
+    return (p < 0 ? -p : p) * (Q - 1) + P;
+}
+
+// ---- encode --------------------------------------------------------------
+// One work item is (block, column tile).  A tile covers image columns
+// [x0, x0 + W) and produces every bin whose row-0 crossing -b lies in that
+// range (the first and last tiles also take the edge bins outside [0, P)).
+// The wave stages columns [x0 - H, x0 + W + H) of all Q rows into LDS with
+// zeros outside the image, H = (Q-1) * max|p|, so no bin read is bounds
+// checked.
+struct EncodeArgs {
+    const uint64_t *images;
+    int64_t img_stride;              // words between consecutive blocks' images
+    uint64_t *out[kMaxDirs];         // projection i of block b: out[i] + b*proj_stride
+    int64_t proj_stride;
+    int64_t nblocks;
+    int32_t P, Q, n;
+    int32_t W, H, S, ntiles;         // tile width, halo, LDS row stride, tiles per block
+    int32_t waves;                   // waves per workgroup (1, 2 or 4), one LDS tile each
+    int32_t p[kMaxDirs];
+    int32_t bmin[kMaxDirs];
+    int32_t nbins[kMaxDirs];
+};
+
+// ---- decode --------------------------------------------------------------
+// Rows of a block are swept left to right in the order fixed by the sorted
+// directions (see decode.hip).  Each lane owns one row of one block; a wave
+// holds 64/Q blocks.  Each row keeps its last R pixels in an LDS ring.
+struct DecodeArgs {
+    const uint64_t *in[kMaxDirs];    // projection i of block b: in[i] + b*proj_stride
+    const uint64_t *fallback;        // a projection that exists (read by idle lanes, never used)
+    int64_t proj_stride;
+    uint64_t *images;
+    int64_t img_stride;
+    const uint16_t *masks;           // per-block erasure masks, or null
+    uint32_t mask_uniform;           // mask used when masks is null
+    int32_t *status;                 // may be null
+    int64_t nblocks;
+    int32_t P, n;
+    int32_t R, ring_stride;          // ring length (power of two), words per LDS ring row
+    int32_t nb;                      // blocks per wavefront (at most 64/Q, fewer if LDS is short)
+    int32_t p_sorted[kMaxDirs];      // directions in ascending p
+    int32_t id_sorted[kMaxDirs];     // their indices in the caller's dirs
+};
+
+hipError_t launch_encode(const EncodeArgs &a, int grid, hipStream_t s);
+hipError_t launch_decode(int Q, const DecodeArgs &a, int grid, hipStream_t s);
+size_t decode_lds_bytes(int Q, int nb, int ring_stride);
+size_t encode_lds_bytes(int Q, int S, int waves);
+
+}  // namespace mj

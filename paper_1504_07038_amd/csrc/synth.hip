@@ -1,0 +1,74 @@
+// Seeded input generation and a plain streaming copy (measurement reference).
+// Neither touches the Mojette arithmetic.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "../../include/mojette.h"
+#include "../../include/mojette_synth.h"
+
+namespace {
+
+constexpr uint64_t kGamma = 0x9E3779B97F4A7C15ull;
+
+__device__ __forceinline__ uint64_t splitmix_mix(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__global__ void fill_kernel(uint64_t *dst, int64_t nwords, uint64_t seed, uint64_t start) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nwords; i += stride)
+        dst[i] = splitmix_mix(seed + (start + (uint64_t)i + 1) * kGamma);
+}
+
+struct alignas(16) W2 {
+    uint64_t x, y;
+};
+
+__global__ void copy16_kernel(W2 *dst, const W2 *src, int64_t n2) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += stride)
+        dst[i] = src[i];
+}
+
+__global__ void copy8_kernel(uint64_t *dst, const uint64_t *src, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        dst[i] = src[i];
+}
+
+int grid_for(int64_t n, int threads) {
+    return (int)std::max<int64_t>(1, std::min<int64_t>((n + threads - 1) / threads, 256 * 64));
+}
+
+}  // namespace
+
+extern "C" {
+
+int mojette_fill_splitmix64(uint64_t *dst, int64_t nwords, uint64_t seed, uint64_t start,
+                            void *stream) {
+    if (nwords < 0 || (nwords > 0 && !dst)) return MOJETTE_EINVAL;
+    if (nwords == 0) return MOJETTE_OK;
+    hipLaunchKernelGGL(fill_kernel, dim3(grid_for(nwords, 256)), dim3(256), 0, (hipStream_t)stream,
+                       dst, nwords, seed, start);
+    return hipGetLastError() == hipSuccess ? MOJETTE_OK : MOJETTE_EHIP;
+}
+
+int mojette_copy_words(uint64_t *dst, const uint64_t *src, int64_t nwords, void *stream) {
+    if (nwords < 0 || (nwords > 0 && (!dst || !src))) return MOJETTE_EINVAL;
+    if (nwords == 0) return MOJETTE_OK;
+    const bool aligned = ((((uintptr_t)dst) | ((uintptr_t)src)) & 15u) == 0 && (nwords % 2) == 0;
+    if (aligned) {
+        const int64_t n2 = nwords / 2;
+        hipLaunchKernelGGL(copy16_kernel, dim3(grid_for(n2, 256)), dim3(256), 0,
+                           (hipStream_t)stream, (W2 *)dst, (const W2 *)src, n2);
+    } else {
+        hipLaunchKernelGGL(copy8_kernel, dim3(grid_for(nwords, 256)), dim3(256), 0,
+                           (hipStream_t)stream, dst, src, nwords);
+    }
+    return hipGetLastError() == hipSuccess ? MOJETTE_OK : MOJETTE_EHIP;
+}
+
+}  // extern "C"

@@ -1,0 +1,105 @@
+"""C-ABI library checks that need no GPU: it loads, exports every declared
+symbol, and its host-only geometry calls and argument checks behave."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = []
+    for fn in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if not fn.endswith(".h"):
+            continue
+        text = open(os.path.join(ROOT, "include", fn)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names += re.findall(r"\b(mojette_\w+)\s*\(", text)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def mj():
+    import paper_1504_07038_amd as mj
+
+    if not os.path.exists(mj.LIB_PATH):
+        from paper_1504_07038_amd import build
+
+        build.build()
+    return mj
+
+
+def test_every_declared_symbol_is_exported(mj):
+    L = mj.lib()
+    decl = declared_functions()
+    assert len(decl) >= 11
+    for name in decl:
+        assert hasattr(L, name), name
+    assert sorted(mj.exported_symbols()) == decl
+
+
+def test_proj_size_and_offset_match_eq2(mj):
+    for P in (1, 3, 128, 256):
+        for Q in (1, 4, 8, 12):
+            for p in range(-8, 9):
+                assert mj.mojette_proj_size(p, P, Q) == abs(p) * (Q - 1) + P
+                assert mj.mojette_bin_offset(p, P, Q) == min(
+                    -k + l * p for k in (0, P - 1) for l in (0, Q - 1))
+    assert mj.mojette_block_words([-3, -2, -1, 0, 1, 2], 128, 4) == 795
+    assert mj.mojette_block_words([-8 + i for i in range(16)], 128, 12) == 16 * 128 + 11 * 64
+
+
+def test_decode_ring_is_power_of_two_and_covers_every_survivor_set(mj):
+    for dirs, Q in [([-3, -2, -1, 0, 1, 2], 4), (list(range(-6, 6)), 8), (list(range(-4, 5)), 6),
+                    (list(range(-8, 8)), 12), ([5, -1, 3], 2), ([0], 1)]:
+        R = mj.mojette_decode_ring(dirs, 128, Q)
+        assert R >= 16 and R & (R - 1) == 0
+
+
+def test_argument_errors_before_any_launch(mj):
+    """Bad arguments are rejected on the host, before any HIP call."""
+    L = mj.lib()
+    dirs = (ctypes.c_int32 * 3)(-1, 0, 1)
+    dup = (ctypes.c_int32 * 3)(-1, 0, -1)
+    fake = ctypes.c_void_p(0x1000)
+    outs = (ctypes.c_void_p * 3)(0x1000, 0x2000, 0x3000)
+    assert L.mojette_encode(None, 8, 2, dirs, 3, outs, None) == mj.MOJETTE_EINVAL
+    assert L.mojette_encode(fake, 0, 2, dirs, 3, outs, None) == mj.MOJETTE_EINVAL
+    assert L.mojette_encode(fake, 8, 0, dirs, 3, outs, None) == mj.MOJETTE_EINVAL
+    assert L.mojette_encode(fake, 8, 17, dirs, 3, outs, None) == mj.MOJETTE_EINVAL
+    assert L.mojette_encode(fake, 8, 2, dup, 3, outs, None) == mj.MOJETTE_EINVAL
+    assert L.mojette_encode(fake, 8, 2, dirs, 17, outs, None) == mj.MOJETTE_EINVAL
+    ids = (ctypes.c_int32 * 2)(0, 0)
+    projs = (ctypes.c_void_p * 2)(0x1000, 0x2000)
+    assert L.mojette_decode(projs, ids, 2, dirs, 3, 8, 2, fake, None) == mj.MOJETTE_EINVAL
+    ids2 = (ctypes.c_int32 * 2)(0, 3)
+    assert L.mojette_decode(projs, ids2, 2, dirs, 3, 8, 2, fake, None) == mj.MOJETTE_EINVAL
+    ids3 = (ctypes.c_int32 * 1)(1)
+    assert L.mojette_decode(projs, ids3, 1, dirs, 3, 8, 2, fake, None) == mj.MOJETTE_ENOTRECON
+    assert L.mojette_encode_batch(fake, -1, 8, 2, dirs, 3, fake, None) == mj.MOJETTE_EINVAL
+    assert L.mojette_encode_batch(fake, 0, 8, 2, dirs, 3, fake, None) == mj.MOJETTE_OK
+    assert L.mojette_decode_batch(fake, None, 0, 8, 2, dirs, 3, fake, None, None) == mj.MOJETTE_OK
+    assert L.mojette_decode_batch(fake, None, 5, 8, 2, dup, 3, fake, None, None) == mj.MOJETTE_EINVAL
+    assert L.mojette_fill_splitmix64(None, 5, 1, 0, None) == mj.MOJETTE_EINVAL
+    assert mj.strerror(mj.MOJETTE_ENOTRECON).startswith("fewer than Q")
+
+
+def test_binding_refuses_host_tensors(mj):
+    import torch
+
+    img = torch.zeros(8, dtype=torch.int64)
+    with pytest.raises(ValueError):
+        mj.mojette_encode(img, 4, 2, [-1, 0, 1], [img, img, img])
+
+
+def test_package_does_not_import_the_oracle():
+    """The product package has no route to the CPU oracle."""
+    pkg = os.path.join(ROOT, "paper_1504_07038_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for fn in files:
+            if fn.endswith((".py", ".hip", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, fn)).read()
+                assert "import oracle" not in text and "from oracle" not in text, fn
+                assert "mojette_oracle" not in text and "liboracle" not in text, fn
