@@ -117,10 +117,12 @@ int ring_length(const std::vector<int> &sorted_p, int Q) {
         ++pick[i];
         for (int j = i + 1; j < Q; ++j) pick[j] = pick[j - 1] + 1;
     }
+    // A staged bin must not land on a pixel still needed (TW + D + 1) or on
+    // one not yet stored (2 TW).
     int R = -1;
     if (ok) {
-        R = mj::kDecodeTile;
-        while (R < Dmax + 1) R <<= 1;
+        R = 2 * mj::kDecodeTile;
+        while (R < mj::kDecodeTile + Dmax + 1) R <<= 1;
     }
     std::lock_guard<std::mutex> g(mu);
     cache[key] = R;
@@ -143,7 +145,7 @@ int decode_setup(const int32_t *dirs, int32_t n, int32_t P, int32_t Q, mj::Decod
     if (R < 0) return MOJETTE_EINVAL;
     a.R = R;
     a.ring_stride = R + 1;  // odd stride spreads the rows over the LDS banks
-    a.nb = mj::kWave / Q;
+    a.nb = mj::decode_max_blocks_per_wave(Q);
     while (a.nb > 0 && mj::decode_lds_bytes(Q, a.nb, a.ring_stride) > kLdsLimit) --a.nb;
     if (a.nb < 1) return MOJETTE_ENOTSUP;
     a.P = P;
@@ -243,17 +245,17 @@ int mojette_decode(const uint64_t *const *proj, const int32_t *proj_ids, int32_t
         a.in[id] = proj[t];
     }
     if (m < Q) return MOJETTE_ENOTRECON;
-    a.fallback = proj[0];
     const int rc = decode_setup(dirs, n, P, Q, a);
     if (rc != MOJETTE_OK) return rc;
+    a.pool = nullptr;
     a.proj_stride = 0;
     a.images = image_out;
-    a.img_stride = 0;
+    a.img_stride = (int64_t)P * Q;
     a.masks = nullptr;
     a.mask_uniform = ~have & ((1u << n) - 1u);
     a.status = nullptr;
     a.nblocks = 1;
-    return status_of(mj::launch_decode(Q, a, 1, (hipStream_t)stream));
+    return status_of(mj::launch_decode(Q, false, a, 1, (hipStream_t)stream));
 }
 
 int mojette_decode_batch(const uint64_t *projs, const uint16_t *erased, int64_t nblocks,
@@ -267,10 +269,15 @@ int mojette_decode_batch(const uint64_t *projs, const uint16_t *erased, int64_t 
     if (rc != MOJETTE_OK) return rc;
     int64_t off = 0;
     for (int i = 0; i < n; ++i) {
-        a.in[i] = projs + off;
+        a.off[i] = (int32_t)off;
         off += mojette_proj_size(dirs[i], P, Q);
     }
-    a.fallback = projs;
+    // A wave's slice of the pool and of the images must be addressable with
+    // 32-bit byte offsets.
+    if ((int64_t)a.nb * off * 8 >= ((int64_t)1 << 31) ||
+        (int64_t)a.nb * P * Q * 8 >= ((int64_t)1 << 31))
+        return MOJETTE_ENOTSUP;
+    a.pool = projs;
     a.proj_stride = off;
     a.images = images;
     a.img_stride = (int64_t)P * Q;
@@ -280,7 +287,7 @@ int mojette_decode_batch(const uint64_t *projs, const uint16_t *erased, int64_t 
     a.nblocks = nblocks;
     const int64_t batches = (nblocks + a.nb - 1) / a.nb;
     const int grid = (int)std::min<int64_t>(batches, kDecodeGridCap);
-    return status_of(mj::launch_decode(Q, a, grid, (hipStream_t)stream));
+    return status_of(mj::launch_decode(Q, true, a, grid, (hipStream_t)stream));
 }
 
 }  // extern "C"

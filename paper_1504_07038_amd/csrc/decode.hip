@@ -15,17 +15,36 @@
 // + (l - r) > 0, and for l < r the distinct sorted p give p_r - p_j >= r - j,
 // so the gap is at least (r - l)^2 > 0.  Rows therefore sweep their columns
 // left to right in lockstep (the left-to-right reconstruction of Section
-// 3.1), row r active on half-steps of parity A_r.
+// 3.1).  Row r is active on half-steps of the parity of A_r, which is the
+// parity of r, so rows 2j and 2j+1 are never active together.
 //
-// Mapping.  One lane per (block, row); a wavefront holds up to 64/Q blocks and one
-// workgroup is one wavefront, so no barrier is ever needed.  A row keeps only
-// its last R pixels, in an LDS ring (slot = column mod R): a pixel is read at
-// most D columns behind its row's newest pixel, D fixed by the survivor set,
-// and R > D is chosen by the host over every survivor set.  Columns outside
-// the image are written as zero, and rings start zeroed, so dependency reads
-// are never bounds checked.  Each lane streams its own row's P used bins
-// from HBM one tile of TW columns ahead; after each tile the wave stores the
-// tile's pixels of all its rows, eight lanes per 128-byte row segment.
+// Mapping.  One lane owns the row pair (2j, 2j+1) of one block and works on
+// every half-step, alternately on each row; a wavefront holds up to
+// 64 / ceil(Q/2) blocks and one workgroup is one wavefront, so no barrier is
+// ever needed.  Every row lives in an LDS ring of R words (slot = column mod
+// R).  A slot first receives the bin of its column, staged one tile ahead;
+// the sweep replaces it by the pixel.  A pixel is read at most D columns
+// behind its row's newest pixel (D fixed by the survivor set), and the host
+// picks R >= max(2 TW, TW + D + 1) over every survivor set, so a staged bin
+// never lands on a pixel that is still needed or not yet stored.  Columns
+// outside the image are written as zero and rings start zeroed, so
+// dependency reads are never bounds checked.  Block slots in LDS are an odd
+// number of words apart, so equal ring positions of different blocks fall on
+// different LDS banks.
+//
+// Memory traffic.  A tile is TW columns per row.  After sweeping tile t the
+// wave (1) stores, for every row, the TW-aligned window of TW pixels that has
+// just been completed (lagging the sweep by less than one tile), (2) writes
+// the bins of tile t+1, loaded one tile earlier, into the rings, and (3)
+// issues the loads for tile t+2.  Loads and stores are cooperative: TW/2
+// consecutive lanes move one row window as 16-byte pieces, so every
+// instruction touches whole cache lines (bins are loaded one 8-byte word per
+// instruction so that every word is bounds checked on its own).  In pool mode
+// (batches) they are raw buffer instructions on the wave's slice of the pool:
+// a disabled lane uses an offset past the slice, which the hardware drops
+// (stores) or answers with zero (loads).  Every memory instruction is therefore issued
+// unconditionally, the compiler knows exactly how many are in flight, and
+// waiting for a tile's bins never waits for the stores issued after them.
 #include <climits>
 
 #include "mj_internal.h"
@@ -38,169 +57,345 @@ __device__ __forceinline__ int wave_max(int v) {
     return __builtin_amdgcn_readfirstlane(v);
 }
 
-// Loads the bins of columns k0 .. k0+TW-1 of one row.  Every load is issued
-// unconditionally from an in-range address (columns clamped to [0, P)), so the
-// results stay in flight until the next tile uses them; values loaded for
-// columns outside the image, or by lanes without a block, are never used.
-template <int TW>
-__device__ __forceinline__ void load_bins(uint64_t (&dst)[TW], const uint64_t *bins, int jbase,
-                                          int k0, int P) {
-#pragma unroll
-    for (int i = 0; i < TW; ++i) {
-        int k = k0 + i;
-        k = k < 0 ? 0 : (k >= P ? P - 1 : k);
-        dst[i] = bins[jbase - k];
-    }
+// gfx9 buffer descriptor word 3: 32-bit data format, raw (stride 0) access.
+constexpr int kBufferWord3 = 0x00020000;
+constexpr uint32_t kOffNone = 0x80000000u;   // past any slice: dropped / reads zero
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ uint64_t lo64(u32x4 v) { return ((uint64_t)v.y << 32) | v.x; }
+__device__ __forceinline__ uint64_t hi64(u32x4 v) { return ((uint64_t)v.w << 32) | v.z; }
+
+// Two consecutive words with one 16-byte store.  The address is only 8-byte
+// aligned; gfx950 global stores accept that (unaligned buffer access).
+struct __attribute__((aligned(8))) WordPair {
+    uint64_t lo, hi;
+};
+__device__ __forceinline__ void store_pair(uint64_t *dst, uint64_t lo, uint64_t hi) {
+    *reinterpret_cast<WordPair *>(dst) = WordPair{lo, hi};
 }
 
+// Sweep state of one row of one lane.
 template <int Q>
+struct RowState {
+    static constexpr int QM = Q > 1 ? Q - 1 : 1;
+    uint64_t *ring;          // this row's ring
+    uint64_t *dep[QM];       // rings of the other rows
+    int delta[QM];           // column offset (l - r) * p_r of each other row
+    int d;                   // first column of tile 0
+    bool on;                 // a real row of a decodable block
+};
+
+// Reconstructs column k0 + i of one row: the bin staged in the row's slot
+// XOR the other rows' pixels on the same line, zero outside the image.
+template <int Q>
+__device__ __forceinline__ void sweep_pixel(const RowState<Q> &s, const int (&o)[RowState<Q>::QM],
+                                            int k0, int i, int Rmask, int P) {
+    if (!s.on) return;
+    const int k = k0 + i;
+    uint64_t v = s.ring[k & Rmask];
+#pragma unroll
+    for (int m = 0; m < Q - 1; ++m) v ^= s.dep[m][(o[m] + i) & Rmask];
+    if ((unsigned)k >= (unsigned)P) v = 0;
+    s.ring[k & Rmask] = v;
+}
+
+// Row window owned by one lane in store/load iteration `it`: segment
+// it*SPI + lane/LPS, words 2q, 2q+1 of the window, q = lane % LPS.
+struct SegParam {
+    int ring;      // LDS word index of the segment's ring row (valid slots only)
+    int gbin;      // pool: word offset (in the wave's pool slice) of column 0's bin
+                   // pointer mode: bin index of column 0 (jbase)
+    int col0;      // column of word 2q of the load window of tile 0
+    int scol0;     // first column stored by this lane at tile 0 (window lag applied)
+    int img;       // word offset (in the wave's image slice) of the segment's row
+    int id;        // projection id of the row (pointer mode)
+    bool on;       // segment belongs to a block slot in use
+};
+
+template <int Q, int TW, bool POOL>
 __global__ __launch_bounds__(kWave) void decode_kernel(DecodeArgs a) {
-    constexpr int NBMAX = kWave / Q;  // blocks per wavefront at most
-    constexpr int TW = kDecodeTile;
-    constexpr int LPS = TW / 2;     // lanes per stored row segment (two words each)
-    constexpr int SPI = kWave / LPS;
+    constexpr int LPB = (Q + 1) / 2;        // lanes per block
+    constexpr int NBMAX = kWave / LPB;      // blocks per wavefront at most
+    constexpr int LPS = TW / 2;             // lanes per row window (two words each)
+    constexpr int SPI = kWave / LPS;        // row windows per iteration
+    constexpr int NIT = (NBMAX * Q + SPI - 1) / SPI;
+    constexpr int QM = RowState<Q>::QM;
 
     extern __shared__ uint64_t lds[];
     const int lane = threadIdx.x;
-    const int slot = lane / Q;
-    const int r = lane - slot * Q;
+    const int slot = lane / LPB;
+    const int j = lane - slot * LPB;
     const int NB = a.nb;
-    const int NSEG = NB * Q;          // ring rows in use
     const bool lane_used = slot < NB;
     const int RS = a.ring_stride;
+    const int SS = Q * RS + 1;              // words per block slot (odd)
     const int Rmask = a.R - 1;
-    uint64_t *zero_row = lds + (size_t)NSEG * RS;
-    for (int c = lane; c < a.R; c += kWave) zero_row[c] = 0;
+    const int P = a.P;
+    uint64_t *slot_base = lds + (size_t)(lane_used ? slot : 0) * SS;
+    const int r0 = 2 * j, r1 = 2 * j + 1;   // this lane's rows
+    const int q = lane % LPS;
+    const int QP = Q * P;
 
     const int64_t nbatches = (a.nblocks + NB - 1) / NB;
     for (int64_t batch = blockIdx.x; batch < nbatches; batch += gridDim.x) {
         const int64_t blk = batch * NB + slot;
-        bool valid = lane_used && blk < a.nblocks;
+        const bool blk_ok = lane_used && blk < a.nblocks;
         uint32_t mask = a.mask_uniform;
-        if (valid && a.masks) mask = a.masks[blk];
+        if (blk_ok && a.masks) mask = a.masks[blk];
 
         // Survivors in ascending p; row r takes the r-th.
-        int my_p = 0, my_id = 0, A_r = 0, A_max = INT_MIN, A_min = INT_MAX, cnt = 0, psum = 0;
+        int p0 = 0, p1 = 0, id0 = 0, id1 = 0, A0 = 0, A1 = 0;
+        int A_max = INT_MIN, A_min = INT_MAX, cnt = 0, psum = 0;
         for (int s = 0; s < a.n; ++s) {
             const int id = a.id_sorted[s];
             const int p = a.p_sorted[s];
             if (!((mask >> id) & 1u) && cnt < Q) {
                 const int A = 2 * psum + cnt;
-                if (cnt == r) {
-                    my_p = p;
-                    my_id = id;
-                    A_r = A;
-                }
+                if (cnt == r0) { p0 = p; id0 = id; A0 = A; }
+                if (cnt == r1) { p1 = p; id1 = id; A1 = A; }
                 A_max = max(A_max, A);
                 A_min = min(A_min, A);
                 psum += p;
                 ++cnt;
             }
         }
+        bool valid = blk_ok;
         if (cnt < Q) {
-            if (valid && r == 0 && a.status) a.status[0] = MOJETTE_ENOTRECON;
+            if (blk_ok && j == 0 && a.status) a.status[0] = MOJETTE_ENOTRECON;
             valid = false;
         }
-        // Tile t of row r covers columns [t*TW + d, t*TW + d + TW); column
-        // t*TW + d + i is handled at sub-step 2i + e.
-        const int d = valid ? -((A_max - A_r) >> 1) : 0;
-        const int e = valid ? 2 * d - (A_r - A_max) : 0;
+        // Half-step of pixel (k, r) within the block: h = 2k - A_r + A_max.
+        // Rows with (r & 1) == (A_max & 1) have even h (row X of a lane),
+        // the others odd h (row Y).  In tile t, half-steps [2TW t, 2TW(t+1)),
+        // row X handles column t*TW + d + i at half-step 2i and row Y column
+        // t*TW + d + i at half-step 2i + 1 (d <= 0 per row).  A row stores
+        // window m = t - L at the end of tile t, L = ceil(-d / TW); the
+        // block is done once its rows have stored the window of column P-1.
+        const int par = A_max & 1;
         const int dmin = valid ? -((A_max - A_min) >> 1) : 0;
-        const int ntiles = valid ? (a.P - dmin + TW - 1) / TW : 0;
+        const int ntiles = valid ? (P - 1) / TW + (-dmin + TW - 1) / TW + 1 : 0;
         const int ntiles_wave = wave_max(ntiles);
 
-        uint64_t *ring = lds + (size_t)(lane_used ? lane : 0) * RS;
-        uint64_t *dep[Q];
-        int delta[Q];
+        RowState<Q> X, Y;
+        const bool r0_is_x = ((r0 & 1) == par);
+        int jb0 = 0, jb1 = 0;   // bin index of column 0 for rows r0 and r1
+        {
+            const int rx = r0_is_x ? r0 : r1, ry = r0_is_x ? r1 : r0;
+            const int px = r0_is_x ? p0 : p1, py = r0_is_x ? p1 : p0;
+            const int Ax = r0_is_x ? A0 : A1, Ay = r0_is_x ? A1 : A0;
+            X.on = valid && rx < Q;
+            Y.on = valid && ry < Q;
+            X.ring = slot_base + (rx < Q ? rx : 0) * RS;
+            Y.ring = slot_base + (ry < Q ? ry : 0) * RS;
 #pragma unroll
-        for (int l = 0; l < Q; ++l) {
-            dep[l] = (l == r || !lane_used) ? zero_row : lds + (size_t)(slot * Q + l) * RS;
-            delta[l] = (l - r) * my_p;
+            for (int m = 0; m < Q - 1; ++m) {
+                const int lx = m + (m >= rx ? 1 : 0), ly = m + (m >= ry ? 1 : 0);
+                X.dep[m] = slot_base + (lx < Q ? lx : 0) * RS;
+                Y.dep[m] = slot_base + (ly < Q ? ly : 0) * RS;
+                X.delta[m] = (lx - rx) * px;
+                Y.delta[m] = (ly - ry) * py;
+            }
+            X.d = X.on ? -((A_max - Ax) >> 1) : 0;       // (Ax - A_max)/2, exact
+            Y.d = Y.on ? -((A_max - Ay - 1) >> 1) : 0;   // (Ay - A_max + 1)/2, exact
+            jb0 = r0 * p0 - bin_offset(p0, P, Q);
+            jb1 = r1 * p1 - bin_offset(p1, P, Q);
         }
-        if (lane_used)
-            for (int c = 0; c < a.R; ++c) ring[c] = 0;
 
-        // Lanes without a block read column bins of a projection that always
-        // exists (p = 0 gives jbase = P - 1, so indices stay in [0, P)).
-        const uint64_t *bins = valid ? a.in[my_id] + blk * a.proj_stride : a.fallback;
-        const int jbase = valid ? r * my_p - bin_offset(my_p, a.P, Q) : a.P - 1;
-        uint64_t cb[TW], nb[TW];
-        load_bins<TW>(cb, bins, jbase, d, a.P);
+        // Per-iteration row windows, from the lanes that own their rows.
+        SegParam sp[NIT];
+        {
+            const int dr0 = r0_is_x ? X.d : Y.d;
+            const int dr1 = r0_is_x ? Y.d : X.d;
+            // pool mode: word offset of column 0's bin within the wave's slice
+            const int g0 = POOL ? slot * (int)a.proj_stride + a.off[id0] + jb0 : jb0;
+            const int g1 = POOL ? slot * (int)a.proj_stride + a.off[id1] + jb1 : jb1;
+            const int own0 = valid ? dr0 : INT_MIN;
+            const int own1 = valid ? dr1 : INT_MIN;
+#pragma unroll
+            for (int it = 0; it < NIT; ++it) {
+                const int seg = it * SPI + lane / LPS;
+                const int sslot = seg / Q;
+                const int srow = seg - sslot * Q;
+                const int owner = sslot * LPB + (srow >> 1);
+                const int src = owner < kWave ? owner : 0;
+                const int od0 = __shfl(own0, src), od1 = __shfl(own1, src);
+                const int og0 = __shfl(g0, src), og1 = __shfl(g1, src);
+                const int oi0 = __shfl(id0, src), oi1 = __shfl(id1, src);
+                const bool odd = srow & 1;
+                const int sd = odd ? od1 : od0;
+                SegParam &s = sp[it];
+                s.on = sslot < NB && sd != INT_MIN;
+                const int dd = s.on ? sd : 0;
+                s.ring = (sslot < NB ? sslot : 0) * SS + srow * RS;
+                s.gbin = odd ? og1 : og0;
+                s.id = odd ? oi1 : oi0;
+                s.col0 = dd + TW - 1 - 2 * q;
+                const int L = (-dd + TW - 1) / TW;
+                s.scol0 = -TW * L + 2 * q;
+                s.img = sslot * QP + srow * P;
+            }
+        }
+
+        // Buffer descriptors of this wave's pool and image slices.
+        const int64_t first = batch * NB;
+        const int64_t nblk = min((int64_t)NB, a.nblocks - first);
+        __amdgpu_buffer_rsrc_t rin, rout;
+        if constexpr (POOL) {
+            rin = __builtin_amdgcn_make_buffer_rsrc(
+                (void *)(a.pool + first * a.proj_stride), 0,
+                (int)(nblk * a.proj_stride * sizeof(uint64_t)), kBufferWord3);
+            rout = __builtin_amdgcn_make_buffer_rsrc(
+                (void *)(a.images + first * a.img_stride), 0,
+                (int)(nblk * a.img_stride * sizeof(uint64_t)), kBufferWord3);
+        }
+
+        // Loads the bins of tile t: words 2q, 2q+1 of each row window are the
+        // bins of columns c and c - 1, c = t*TW + col0.
+        auto load_tile = [&](int t, u32x4 (&buf)[NIT]) {
+#pragma unroll
+            for (int it = 0; it < NIT; ++it) {
+                const SegParam &s = sp[it];
+                const int c = t * TW + s.col0;
+                if constexpr (POOL) {
+                    // one 8-byte load per word, so each word is bounds checked
+                    // on its own (a window may start just before the slice)
+                    const uint32_t off0 = s.on ? (uint32_t)(s.gbin - c) * 8u : kOffNone;
+                    const uint32_t off1 = s.on ? (uint32_t)(s.gbin - c + 1) * 8u : kOffNone;
+                    const u32x2 w0 = __builtin_amdgcn_raw_buffer_load_b64(rin, off0, 0, 0);
+                    const u32x2 w1 = __builtin_amdgcn_raw_buffer_load_b64(rin, off1, 0, 0);
+                    buf[it] = u32x4{w0.x, w0.y, w1.x, w1.y};
+                } else {
+                    const uint64_t *bins = a.in[s.id];
+                    const int c0 = min(max(c, 0), P - 1), c1 = min(max(c - 1, 0), P - 1);
+                    const uint64_t w0 = s.on ? bins[s.gbin - c0] : 0;
+                    const uint64_t w1 = s.on ? bins[s.gbin - c1] : 0;
+                    buf[it] = u32x4{(uint32_t)w0, (uint32_t)(w0 >> 32), (uint32_t)w1,
+                                    (uint32_t)(w1 >> 32)};
+                }
+            }
+        };
+        // Writes loaded bins of tile t into the rings.
+        auto stage_tile = [&](int t, const u32x4 (&buf)[NIT]) {
+#pragma unroll
+            for (int it = 0; it < NIT; ++it) {
+                const SegParam &s = sp[it];
+                if (!s.on) continue;
+                const int c = t * TW + s.col0;
+                uint64_t *row = lds + s.ring;
+                row[c & Rmask] = lo64(buf[it]);
+                row[(c - 1) & Rmask] = hi64(buf[it]);
+            }
+        };
+        // Stores the completed TW-aligned window of every row at the end of
+        // tile t: columns t*TW + scol0 and the next one.
+        auto store_tile = [&](int t) {
+#pragma unroll
+            for (int it = 0; it < NIT; ++it) {
+                const SegParam &s = sp[it];
+                const int c = t * TW + s.scol0;
+                const uint64_t *row = lds + s.ring;
+                const uint64_t w0 = row[c & Rmask], w1 = row[(c + 1) & Rmask];
+                const bool both = s.on && c >= 0 && c + 1 < P;
+                const bool last = s.on && c == P - 1;
+                if constexpr (POOL) {
+                    const uint32_t off2 = both ? (uint32_t)(s.img + c) * 8u : kOffNone;
+                    const uint32_t off1 = last ? (uint32_t)(s.img + c) * 8u : kOffNone;
+                    __builtin_amdgcn_raw_buffer_store_b128(
+                        u32x4{(uint32_t)w0, (uint32_t)(w0 >> 32), (uint32_t)w1,
+                              (uint32_t)(w1 >> 32)},
+                        rout, off2, 0, 0);
+                    if (P & 1)   // only an odd row length leaves a single last word
+                        __builtin_amdgcn_raw_buffer_store_b64(
+                            u32x2{(uint32_t)w0, (uint32_t)(w0 >> 32)}, rout, off1, 0, 0);
+                } else {
+                    uint64_t *dst = a.images + s.img;
+                    if (both) {
+                        store_pair(dst + c, w0, w1);
+                    } else if (last) {
+                        dst[c] = w0;
+                    }
+                }
+            }
+        };
+
+        // Rings start zeroed; then the bins of tile 0 go in.
+        if (lane_used) {
+            for (int c = 0; c < a.R; ++c) {
+                if (r0 < Q) slot_base[r0 * RS + c] = 0;
+                if (r1 < Q) slot_base[r1 * RS + c] = 0;
+            }
+        }
+        u32x4 buf[NIT];
+        load_tile(0, buf);
+        wave_sync();
+        stage_tile(0, buf);
+        load_tile(1, buf);
         wave_sync();
 
         for (int t = 0; t < ntiles_wave; ++t) {
-            const int k0 = t * TW + d;
-            load_bins<TW>(nb, bins, jbase, k0 + TW, a.P);
-            int o[Q];
+            const int kx = t * TW + X.d, ky = t * TW + Y.d;
+            int ox[QM], oy[QM];
 #pragma unroll
-            for (int l = 0; l < Q; ++l) o[l] = k0 + delta[l];
+            for (int m = 0; m < Q - 1; ++m) {
+                ox[m] = kx + X.delta[m];
+                oy[m] = ky + Y.delta[m];
+            }
 #pragma unroll
-            for (int u = 0; u < 2 * TW; ++u) {
-                const int i = u >> 1;
-                if (valid && e == (u & 1)) {
-                    uint64_t v = cb[i];
-#pragma unroll
-                    for (int l = 0; l < Q; ++l) v ^= dep[l][(o[l] + i) & Rmask];
-                    const int k = k0 + i;
-                    if ((unsigned)k >= (unsigned)a.P) v = 0;
-                    ring[k & Rmask] = v;
-                }
+            for (int i = 0; i < TW; ++i) {
+                sweep_pixel<Q>(X, ox, kx, i, Rmask, P);
+                wave_sync();
+                sweep_pixel<Q>(Y, oy, ky, i, Rmask, P);
                 wave_sync();
             }
-            // Store this tile's columns of every row of the wave.
-#pragma unroll
-            for (int it = 0; it < (NBMAX * Q + SPI - 1) / SPI; ++it) {
-                const int seg = it * SPI + lane / LPS;
-                const int pair = lane % LPS;
-                const int od = __shfl(valid ? d : INT_MIN, seg < kWave ? seg : 0);
-                if (seg < NSEG && od != INT_MIN) {
-                    const int sslot = seg / Q;
-                    const int srow = seg - sslot * Q;
-                    const int k = t * TW + od + 2 * pair;
-                    const uint64_t *sring = lds + (size_t)seg * RS;
-                    uint64_t *dst = a.images + (batch * NB + sslot) * a.img_stride +
-                                    (int64_t)srow * a.P;
-                    if ((unsigned)k < (unsigned)a.P) dst[k] = sring[k & Rmask];
-                    if ((unsigned)(k + 1) < (unsigned)a.P) dst[k + 1] = sring[(k + 1) & Rmask];
-                }
-            }
+            store_tile(t);
             wave_sync();
-#pragma unroll
-            for (int i = 0; i < TW; ++i) cb[i] = nb[i];
+            stage_tile(t + 1, buf);
+            load_tile(t + 2, buf);
+            wave_sync();
         }
-        wave_sync();
     }
 }
 
+int decode_tile(int) { return kDecodeTile; }
+
 size_t decode_lds_bytes(int Q, int nb, int ring_stride) {
-    return (size_t)(nb * Q + 1) * ring_stride * sizeof(uint64_t);
+    return (size_t)nb * (Q * ring_stride + 1) * sizeof(uint64_t);
 }
 
+int decode_max_blocks_per_wave(int Q) { return kWave / ((Q + 1) / 2); }
+
 template <int Q>
-static hipError_t launch_q(const DecodeArgs &a, int grid, hipStream_t s) {
-    hipLaunchKernelGGL(decode_kernel<Q>, dim3(grid), dim3(kWave), decode_lds_bytes(Q, a.nb, a.ring_stride),
-                       s, a);
+static hipError_t launch_q(bool pool, const DecodeArgs &a, int grid, hipStream_t s) {
+    const size_t lds = decode_lds_bytes(Q, a.nb, a.ring_stride);
+    if (pool)
+        hipLaunchKernelGGL((decode_kernel<Q, kDecodeTile, true>), dim3(grid), dim3(kWave), lds, s,
+                           a);
+    else
+        hipLaunchKernelGGL((decode_kernel<Q, kDecodeTile, false>), dim3(grid), dim3(kWave), lds, s,
+                           a);
     return hipGetLastError();
 }
 
-hipError_t launch_decode(int Q, const DecodeArgs &a, int grid, hipStream_t s) {
+hipError_t launch_decode(int Q, bool pool, const DecodeArgs &a, int grid, hipStream_t s) {
     switch (Q) {
-        case 1: return launch_q<1>(a, grid, s);
-        case 2: return launch_q<2>(a, grid, s);
-        case 3: return launch_q<3>(a, grid, s);
-        case 4: return launch_q<4>(a, grid, s);
-        case 5: return launch_q<5>(a, grid, s);
-        case 6: return launch_q<6>(a, grid, s);
-        case 7: return launch_q<7>(a, grid, s);
-        case 8: return launch_q<8>(a, grid, s);
-        case 9: return launch_q<9>(a, grid, s);
-        case 10: return launch_q<10>(a, grid, s);
-        case 11: return launch_q<11>(a, grid, s);
-        case 12: return launch_q<12>(a, grid, s);
-        case 13: return launch_q<13>(a, grid, s);
-        case 14: return launch_q<14>(a, grid, s);
-        case 15: return launch_q<15>(a, grid, s);
-        case 16: return launch_q<16>(a, grid, s);
+        case 1: return launch_q<1>(pool, a, grid, s);
+        case 2: return launch_q<2>(pool, a, grid, s);
+        case 3: return launch_q<3>(pool, a, grid, s);
+        case 4: return launch_q<4>(pool, a, grid, s);
+        case 5: return launch_q<5>(pool, a, grid, s);
+        case 6: return launch_q<6>(pool, a, grid, s);
+        case 7: return launch_q<7>(pool, a, grid, s);
+        case 8: return launch_q<8>(pool, a, grid, s);
+        case 9: return launch_q<9>(pool, a, grid, s);
+        case 10: return launch_q<10>(pool, a, grid, s);
+        case 11: return launch_q<11>(pool, a, grid, s);
+        case 12: return launch_q<12>(pool, a, grid, s);
+        case 13: return launch_q<13>(pool, a, grid, s);
+        case 14: return launch_q<14>(pool, a, grid, s);
+        case 15: return launch_q<15>(pool, a, grid, s);
+        case 16: return launch_q<16>(pool, a, grid, s);
         default: return hipErrorInvalidValue;
     }
 }

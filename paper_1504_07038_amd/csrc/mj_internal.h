@@ -57,11 +57,16 @@ struct EncodeArgs {
 
 // ---- decode --------------------------------------------------------------
 // Rows of a block are swept left to right in the order fixed by the sorted
-// directions (see decode.hip).  Each lane owns one row of one block; a wave
-// holds 64/Q blocks.  Each row keeps its last R pixels in an LDS ring.
+// directions (see decode.hip).  Each lane owns two rows of one block; a wave
+// holds up to 64/ceil(Q/2) blocks.  Each row keeps its last R pixels in an
+// LDS ring.
 struct DecodeArgs {
-    const uint64_t *in[kMaxDirs];    // projection i of block b: in[i] + b*proj_stride
-    const uint64_t *fallback;        // a projection that exists (read by idle lanes, never used)
+    // Pool mode (batches): block b's n projections start at word
+    // b*proj_stride of `pool`, projection i at word off[i] of that slice.
+    const uint64_t *pool;
+    int32_t off[kMaxDirs];
+    // Pointer mode (one block): projection i at in[i] (null if not given).
+    const uint64_t *in[kMaxDirs];
     int64_t proj_stride;
     uint64_t *images;
     int64_t img_stride;
@@ -71,14 +76,16 @@ struct DecodeArgs {
     int64_t nblocks;
     int32_t P, n;
     int32_t R, ring_stride;          // ring length (power of two), words per LDS ring row
-    int32_t nb;                      // blocks per wavefront (at most 64/Q, fewer if LDS is short)
+    int32_t nb;                      // blocks per wavefront (at most 64/ceil(Q/2), fewer if LDS is short)
     int32_t p_sorted[kMaxDirs];      // directions in ascending p
     int32_t id_sorted[kMaxDirs];     // their indices in the caller's dirs
 };
 
 hipError_t launch_encode(const EncodeArgs &a, int grid, hipStream_t s);
-hipError_t launch_decode(int Q, const DecodeArgs &a, int grid, hipStream_t s);
+hipError_t launch_decode(int Q, bool pool, const DecodeArgs &a, int grid, hipStream_t s);
 size_t decode_lds_bytes(int Q, int nb, int ring_stride);
+int decode_max_blocks_per_wave(int Q);
+int decode_tile(int Q);
 size_t encode_lds_bytes(int Q, int S, int waves);
 
 }  // namespace mj
