@@ -42,6 +42,9 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=1 << 19)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="summarise two rocprofv3 --pmc runs into profiles/traffic_*.json")
+    ap.add_argument("--pmc-command", default="", help="command recorded with --pmc-summary")
     return ap.parse_args()
 
 
@@ -72,6 +75,57 @@ def load_traffic(workload: str, kernel: str):
     if rec.get("source_hash") != kernel_source_hash():
         return None
     return rec.get("hbm_bytes_per_launch")
+
+
+KERNEL_TAGS = {"encode": "encode_kernel", "decode": "decode_kernel", "copy": "copy16_kernel"}
+
+
+def pmc_summary(workload: str, fetch_csv: str, write_csv: str, command: str) -> None:
+    """Turn two rocprofv3 --pmc runs of this script (FETCH_SIZE, then
+    WRITE_SIZE, KiB per dispatch) into HBM bytes per launch for the encode and
+    decode kernels.  Each counter is scaled by what it reads for the plain
+    copy kernel, which moves a known number of bytes (the image pool read once
+    and written once)."""
+    import csv
+
+    P, Q, n, nblocks, _ = WORKLOADS[workload]
+    copy_bytes = nblocks * P * Q * 8
+
+    def per_kernel(path, counter):
+        vals = {k: [] for k in KERNEL_TAGS}
+        with open(path) as fh:
+            for row in csv.DictReader(fh):
+                if row["Counter_Name"] != counter:
+                    continue
+                for k, tag in KERNEL_TAGS.items():
+                    if tag in row["Kernel_Name"]:
+                        vals[k].append(float(row["Counter_Value"]))
+        return {k: sum(v) / len(v) for k, v in vals.items() if v}
+
+    fetch = per_kernel(fetch_csv, "FETCH_SIZE")
+    write = per_kernel(write_csv, "WRITE_SIZE")
+    f_scale = copy_bytes / (fetch["copy"] * 1024.0)
+    w_scale = copy_bytes / (write["copy"] * 1024.0)
+    for k in ("encode", "decode"):
+        rec = {
+            "kernel": k,
+            "workload": workload,
+            "source_hash": kernel_source_hash(),
+            "fetch_kib_per_launch": fetch[k],
+            "write_kib_per_launch": write[k],
+            "copy_fetch_kib": fetch["copy"],
+            "copy_write_kib": write["copy"],
+            "copy_bytes_each_way": copy_bytes,
+            "fetch_scale": f_scale,
+            "write_scale": w_scale,
+            "hbm_bytes_per_launch": round(fetch[k] * 1024.0 * f_scale + write[k] * 1024.0 * w_scale),
+            "command": command,
+        }
+        path = os.path.join(ROOT, "profiles", f"traffic_{k}_{workload}.json")
+        with open(path, "w") as fh:
+            json.dump(rec, fh, indent=1)
+            fh.write("\n")
+        print(json.dumps(rec))
 
 
 def cpu_baseline(P, Q, dirs, sample_blocks, n_erase):
@@ -123,6 +177,9 @@ def cpu_baseline(P, Q, dirs, sample_blocks, n_erase):
 
 def main():
     args = parse()
+    if args.pmc_summary:
+        pmc_summary(args.workload, args.pmc_summary[0], args.pmc_summary[1], args.pmc_command)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}), flush=True)
