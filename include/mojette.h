@@ -120,6 +120,44 @@ int mojette_decode_batch(const uint64_t *projs, const uint16_t *erased, int64_t 
                          int32_t P, int32_t Q, const int32_t *dirs, int32_t n, uint64_t *images,
                          int32_t *status, void *stream);
 
+/*
+ * Mixed batches: blocks of up to MOJETTE_MAX_CLASSES geometry classes (each
+ * class: nblocks blocks of one P, Q and direction set) encoded or decoded in
+ * ONE launch.  Classes are laid out one after another in each pool, in the
+ * order given: class c's images start at word sum_{c'<c} nblocks*P*Q of the
+ * image pool, its projection slices (layout as for mojette_encode_batch) at
+ * word sum_{c'<c} nblocks*block_words of the projection pool, and its erasure
+ * masks at entry sum_{c'<c} nblocks of the mask array.  The launch walks the
+ * classes' work heaviest first (largest rows first) so that long items start
+ * early.  Directions must satisfy |p| <= 32767.  Same ownership, error and
+ * stream rules as the batch calls; safe to record into a HIP graph.
+ */
+#define MOJETTE_MAX_CLASSES 16
+
+typedef struct mojette_class {
+    int32_t P;                        /* pixels per row */
+    int32_t Q;                        /* rows = data packets, 1..16 */
+    int32_t n;                        /* projections, Q..16 */
+    int32_t dirs[MOJETTE_MAX_DIRS];   /* p of each projection (q = 1), distinct */
+    int64_t nblocks;                  /* blocks of this class, >= 0 */
+} mojette_class;
+
+/* Pool sizes of a mixed batch: *image_words and *proj_words receive the total
+ * words of the image and projection pools.  Returns MOJETTE_OK or
+ * MOJETTE_EINVAL. */
+int mojette_classes_layout(const mojette_class *classes, int32_t nclasses, int64_t *image_words,
+                           int64_t *proj_words);
+
+/* Forward transform (Section 2.1, Eq. 1) of every block of every class. */
+int mojette_encode_classes(const mojette_class *classes, int32_t nclasses,
+                           const uint64_t *images, uint64_t *projs, void *stream);
+
+/* Inverse transform (Section 2.2) of every block of every class; erased,
+ * images and status as for mojette_decode_batch (erased may be NULL). */
+int mojette_decode_classes(const mojette_class *classes, int32_t nclasses,
+                           const uint64_t *projs, const uint16_t *erased, uint64_t *images,
+                           int32_t *status, void *stream);
+
 /* Ring length (words per row) the decoder needs for this geometry: the
  * longest distance, over every choice of Q survivors, between a pixel a row
  * needs and the newest pixel of that row, rounded up to a power of two and

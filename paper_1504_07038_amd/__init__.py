@@ -28,6 +28,27 @@ MAX_DIRS = 16
 MAX_ROWS = 16
 
 
+MAX_CLASSES = 16
+
+
+class MojetteClass(ctypes.Structure):
+    """``mojette_class``: nblocks blocks of one geometry in a mixed batch."""
+
+    _fields_ = [("P", ctypes.c_int32), ("Q", ctypes.c_int32), ("n", ctypes.c_int32),
+                ("dirs", ctypes.c_int32 * MAX_DIRS), ("nblocks", ctypes.c_int64)]
+
+
+def make_classes(classes):
+    """``classes``: iterable of (P, Q, dirs, nblocks) -> ctypes array."""
+    classes = list(classes)
+    arr = (MojetteClass * max(1, len(classes)))()
+    for c, (P, Q, dirs, nb) in enumerate(classes):
+        arr[c].P, arr[c].Q, arr[c].n, arr[c].nblocks = int(P), int(Q), len(dirs), int(nb)
+        for i, p in enumerate(dirs):
+            arr[c].dirs[i] = int(p)
+    return arr, len(classes)
+
+
 class MojetteError(RuntimeError):
     def __init__(self, status: int, where: str):
         super().__init__(f"{where}: {strerror(status)} ({status})")
@@ -56,6 +77,9 @@ def lib() -> ctypes.CDLL:
         "mojette_decode": ([vp, vp, i32, vp, i32, i32, i32, vp, vp], ctypes.c_int),
         "mojette_encode_batch": ([vp, i64, i32, i32, vp, i32, vp, vp], ctypes.c_int),
         "mojette_decode_batch": ([vp, vp, i64, i32, i32, vp, i32, vp, vp, vp], ctypes.c_int),
+        "mojette_classes_layout": ([vp, i32, vp, vp], ctypes.c_int),
+        "mojette_encode_classes": ([vp, i32, vp, vp, vp], ctypes.c_int),
+        "mojette_decode_classes": ([vp, i32, vp, vp, vp, vp, vp], ctypes.c_int),
         "mojette_fill_splitmix64": ([vp, i64, u64, u64, vp], ctypes.c_int),
         "mojette_copy_words": ([vp, vp, i64, vp], ctypes.c_int),
     }
@@ -71,7 +95,8 @@ def exported_symbols() -> list[str]:
     return [
         "mojette_strerror", "mojette_proj_size", "mojette_bin_offset", "mojette_block_words",
         "mojette_decode_ring", "mojette_encode", "mojette_decode", "mojette_encode_batch",
-        "mojette_decode_batch", "mojette_fill_splitmix64", "mojette_copy_words",
+        "mojette_decode_batch", "mojette_classes_layout", "mojette_encode_classes",
+        "mojette_decode_classes", "mojette_fill_splitmix64", "mojette_copy_words",
     ]
 
 
@@ -180,6 +205,37 @@ def mojette_decode_batch(projs, erased, nblocks: int, P: int, Q: int, dirs, imag
                                     nblocks, P, Q, arr, n, _word_tensor(images, "images"),
                                     _dev_ptr(status, "status"), _stream(stream))
     return _check(rc, "mojette_decode_batch", check)
+
+
+def mojette_classes_layout(classes) -> tuple[int, int]:
+    """(image words, projection words) of a mixed batch."""
+    arr, n = make_classes(classes)
+    iw, pw = ctypes.c_int64(0), ctypes.c_int64(0)
+    rc = lib().mojette_classes_layout(arr, n, ctypes.addressof(iw), ctypes.addressof(pw))
+    _check(rc, "mojette_classes_layout", True)
+    return int(iw.value), int(pw.value)
+
+
+def mojette_encode_classes(classes, images, projs, stream=None, check: bool = True) -> int:
+    arr, n = make_classes(classes)
+    rc = lib().mojette_encode_classes(arr, n, _word_tensor(images, "images"),
+                                      _word_tensor(projs, "projs"), _stream(stream))
+    return _check(rc, "mojette_encode_classes", check)
+
+
+def mojette_decode_classes(classes, projs, erased, images, status=None, stream=None,
+                           check: bool = True) -> int:
+    import torch
+
+    arr, n = make_classes(classes)
+    if erased is not None and erased.dtype not in (torch.int16, torch.uint16):
+        raise ValueError("erased must be 16-bit masks")
+    if status is not None and status.dtype != torch.int32:
+        raise ValueError("status must be int32")
+    rc = lib().mojette_decode_classes(arr, n, _word_tensor(projs, "projs"),
+                                      _dev_ptr(erased, "erased"), _word_tensor(images, "images"),
+                                      _dev_ptr(status, "status"), _stream(stream))
+    return _check(rc, "mojette_decode_classes", check)
 
 
 def mojette_fill_splitmix64(dst, nwords: int, seed: int, start: int = 0, stream=None,

@@ -35,13 +35,14 @@ int status_of(hipError_t e) { return e == hipSuccess ? MOJETTE_OK : MOJETTE_EHIP
 // Encode tiling: the whole row when it fits, else the widest multiple of 64
 // columns whose tile plus halo fits the LDS budget.  Four waves per
 // workgroup when their four tiles fit (at least min(P, 256) columns each),
-// else two, else one.
-bool encode_tiling(const int32_t *dirs, int32_t n, int32_t P, int32_t Q, mj::EncodeArgs &a) {
+// else two, else one; `max_waves` caps that choice.
+bool encode_tiling(const int32_t *dirs, int32_t n, int32_t P, int32_t Q, mj::EncodeArgs &a,
+                   int max_waves = mj::kEncodeWaves) {
     int maxabs = 0;
     for (int i = 0; i < n; ++i) maxabs = std::max(maxabs, std::abs(dirs[i]));
     const int H = (Q - 1) * maxabs;
     const int want = std::min(P, 256);
-    int waves = mj::kEncodeWaves;
+    int waves = max_waves;
     size_t cols_fit = 0;
     for (; waves >= 1; waves /= 2) {
         cols_fit = kLdsLimit / ((size_t)waves * Q * sizeof(uint64_t));
@@ -59,11 +60,7 @@ bool encode_tiling(const int32_t *dirs, int32_t n, int32_t P, int32_t Q, mj::Enc
     a.P = P;
     a.Q = Q;
     a.n = n;
-    for (int i = 0; i < n; ++i) {
-        a.p[i] = dirs[i];
-        a.bmin[i] = mj::bin_offset(dirs[i], P, Q);
-        a.nbins[i] = mj::proj_bins(dirs[i], P, Q);
-    }
+    for (int i = 0; i < n; ++i) a.p[i] = dirs[i];
     return true;
 }
 
@@ -129,8 +126,10 @@ int ring_length(const std::vector<int> &sorted_p, int Q) {
     return R;
 }
 
-// Fills the geometry part of the decode arguments.  Returns a status.
-int decode_setup(const int32_t *dirs, int32_t n, int32_t P, int32_t Q, mj::DecodeArgs &a) {
+// Fills the geometry part of decode arguments (DecodeArgs or DecodeClass).
+// Returns a status.
+template <class A>
+int decode_setup(const int32_t *dirs, int32_t n, int32_t P, int32_t Q, A &a) {
     std::vector<int> order(n);
     for (int i = 0; i < n; ++i) order[i] = i;
     std::sort(order.begin(), order.end(), [&](int x, int y) { return dirs[x] < dirs[y]; });
@@ -150,6 +149,33 @@ int decode_setup(const int32_t *dirs, int32_t n, int32_t P, int32_t Q, mj::Decod
     if (a.nb < 1) return MOJETTE_ENOTSUP;
     a.P = P;
     a.n = n;
+    return MOJETTE_OK;
+}
+
+// Checks a class table and returns, per class, block words and pool offsets.
+int classes_check(const mojette_class *cls, int32_t ncls, std::vector<int64_t> &bw,
+                  std::vector<int64_t> &img_off, std::vector<int64_t> &proj_off,
+                  std::vector<int64_t> &mask_off, int64_t &img_total, int64_t &proj_total) {
+    if (!cls || ncls < 1 || ncls > mj::kMaxClasses) return MOJETTE_EINVAL;
+    bw.assign(ncls, 0);
+    img_off.assign(ncls, 0);
+    proj_off.assign(ncls, 0);
+    mask_off.assign(ncls, 0);
+    img_total = proj_total = 0;
+    int64_t masks = 0;
+    for (int c = 0; c < ncls; ++c) {
+        const mojette_class &k = cls[c];
+        if (k.nblocks < 0 || !geometry_ok(k.dirs, k.n, k.P, k.Q)) return MOJETTE_EINVAL;
+        for (int i = 0; i < k.n; ++i)
+            if (k.dirs[i] < -32767 || k.dirs[i] > 32767) return MOJETTE_EINVAL;
+        bw[c] = mojette_block_words(k.dirs, k.n, k.P, k.Q);
+        img_off[c] = img_total;
+        proj_off[c] = proj_total;
+        mask_off[c] = masks;
+        img_total += k.nblocks * (int64_t)k.P * k.Q;
+        proj_total += k.nblocks * bw[c];
+        masks += k.nblocks;
+    }
     return MOJETTE_OK;
 }
 
@@ -201,7 +227,6 @@ int mojette_encode(const uint64_t *image, int32_t P, int32_t Q, const int32_t *d
     mj::EncodeArgs a{};
     if (!encode_tiling(dirs, n, P, Q, a)) return MOJETTE_ENOTSUP;
     a.images = image;
-    a.img_stride = 0;
     for (int i = 0; i < n; ++i) a.out[i] = proj_out[i];
     a.proj_stride = 0;
     a.nblocks = 1;
@@ -217,11 +242,10 @@ int mojette_encode_batch(const uint64_t *images, int64_t nblocks, int32_t P, int
     mj::EncodeArgs a{};
     if (!encode_tiling(dirs, n, P, Q, a)) return MOJETTE_ENOTSUP;
     a.images = images;
-    a.img_stride = (int64_t)P * Q;
     int64_t off = 0;
     for (int i = 0; i < n; ++i) {
         a.out[i] = projs + off;
-        off += a.nbins[i];
+        off += mojette_proj_size(dirs[i], P, Q);
     }
     a.proj_stride = off;
     a.nblocks = nblocks;
@@ -288,6 +312,156 @@ int mojette_decode_batch(const uint64_t *projs, const uint16_t *erased, int64_t 
     const int64_t batches = (nblocks + a.nb - 1) / a.nb;
     const int grid = (int)std::min<int64_t>(batches, kDecodeGridCap);
     return status_of(mj::launch_decode(Q, true, a, grid, (hipStream_t)stream));
+}
+
+int mojette_classes_layout(const mojette_class *classes, int32_t nclasses, int64_t *image_words,
+                           int64_t *proj_words) {
+    std::vector<int64_t> bw, io, po, mo;
+    int64_t it = 0, pt = 0;
+    const int rc = classes_check(classes, nclasses, bw, io, po, mo, it, pt);
+    if (rc != MOJETTE_OK) return rc;
+    if (image_words) *image_words = it;
+    if (proj_words) *proj_words = pt;
+    return MOJETTE_OK;
+}
+
+int mojette_encode_classes(const mojette_class *classes, int32_t nclasses,
+                           const uint64_t *images, uint64_t *projs, void *stream) {
+    std::vector<int64_t> bw, io, po, mo;
+    int64_t it = 0, pt = 0;
+    int rc = classes_check(classes, nclasses, bw, io, po, mo, it, pt);
+    if (rc != MOJETTE_OK) return rc;
+    if (it == 0) return MOJETTE_OK;
+    if (!images || !projs) return MOJETTE_EINVAL;
+    // heaviest items (widest tiles x rows x directions) first
+    std::vector<int> order(nclasses);
+    std::vector<mj::EncodeArgs> geo(nclasses);
+    for (int c = 0; c < nclasses; ++c) {
+        order[c] = c;
+        const mojette_class &k = classes[c];
+        if (!encode_tiling(k.dirs, k.n, k.P, k.Q, geo[c], 1)) return MOJETTE_ENOTSUP;
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        const int64_t wx = (int64_t)geo[x].W * classes[x].Q * classes[x].n;
+        const int64_t wy = (int64_t)geo[y].W * classes[y].Q * classes[y].n;
+        return wx > wy;
+    });
+    mj::EncodeClassTable tab{};
+    size_t lds = 0;
+    int qmax = 1;
+    int64_t items = 0;
+    int k = 0;
+    for (int oc : order) {
+        const mojette_class &cl = classes[oc];
+        if (cl.nblocks == 0) continue;
+        mj::EncodeClass &e = tab.cls[k];
+        e.images = images + io[oc];
+        e.projs = projs + po[oc];
+        e.nblocks = cl.nblocks;
+        e.proj_stride = (int32_t)bw[oc];
+        e.P = cl.P;
+        e.Q = cl.Q;
+        e.n = cl.n;
+        e.W = geo[oc].W;
+        e.H = geo[oc].H;
+        e.S = geo[oc].S;
+        e.ntiles = geo[oc].ntiles;
+        int32_t off = 0;
+        for (int i = 0; i < cl.n; ++i) {
+            e.off[i] = off;
+            e.p[i] = (int16_t)cl.dirs[i];
+            off += (int32_t)mojette_proj_size(cl.dirs[i], cl.P, cl.Q);
+        }
+        tab.first_item[k] = items;
+        items += cl.nblocks * e.ntiles;
+        lds = std::max(lds, mj::encode_lds_bytes(cl.Q, e.S, 1));
+        qmax = std::max(qmax, (int)cl.Q);
+        ++k;
+    }
+    tab.nclasses = k;
+    tab.first_item[k] = items;
+    const int grid = (int)std::min<int64_t>(items, kEncodeGridCap * mj::kEncodeWaves);
+    return status_of(mj::launch_encode_classes(qmax, tab, lds, grid, (hipStream_t)stream));
+}
+
+// One mixed decode launch over the classes listed in `which` (heaviest first).
+int decode_classes_launch(const mojette_class *classes, const std::vector<int> &which,
+                          const std::vector<int64_t> &bw, const std::vector<int64_t> &io,
+                          const std::vector<int64_t> &po, const std::vector<int64_t> &mo,
+                          const uint64_t *projs, const uint16_t *erased, uint64_t *images,
+                          int32_t *status, hipStream_t stream) {
+    mj::DecodeClassTable tab{};
+    size_t lds = 0;
+    unsigned qmask = 0;
+    int64_t items = 0;
+    int k = 0;
+    for (int oc : which) {
+        const mojette_class &cl = classes[oc];
+        if (cl.nblocks == 0) continue;
+        mj::DecodeClass &d = tab.cls[k];
+        const int rc = decode_setup(cl.dirs, cl.n, cl.P, cl.Q, d);
+        if (rc != MOJETTE_OK) return rc;
+        if ((int64_t)d.nb * bw[oc] * 8 >= ((int64_t)1 << 31) ||
+            (int64_t)d.nb * cl.P * cl.Q * 8 >= ((int64_t)1 << 31))
+            return MOJETTE_ENOTSUP;
+        d.Q = cl.Q;
+        d.pool = projs + po[oc];
+        d.images = images + io[oc];
+        d.masks = erased ? erased + mo[oc] : nullptr;
+        d.status = status;
+        d.nblocks = cl.nblocks;
+        d.proj_stride = bw[oc];
+        d.img_stride = (int64_t)cl.P * cl.Q;
+        d.mask_uniform = 0;
+        int32_t off = 0;
+        for (int i = 0; i < cl.n; ++i) {
+            d.off[i] = off;
+            off += (int32_t)mojette_proj_size(cl.dirs[i], cl.P, cl.Q);
+        }
+        tab.first_item[k] = items;
+        items += (cl.nblocks + d.nb - 1) / d.nb;
+        lds = std::max(lds, mj::decode_lds_bytes(cl.Q, d.nb, d.ring_stride));
+        qmask |= 1u << cl.Q;
+        ++k;
+    }
+    if (k == 0) return MOJETTE_OK;
+    tab.nclasses = k;
+    tab.first_item[k] = items;
+    const int grid = (int)std::min<int64_t>(items, kDecodeGridCap);
+    return status_of(mj::launch_decode_classes(qmask, tab, lds, grid, stream));
+}
+
+int mojette_decode_classes(const mojette_class *classes, int32_t nclasses,
+                           const uint64_t *projs, const uint16_t *erased, uint64_t *images,
+                           int32_t *status, void *stream) {
+    std::vector<int64_t> bw, io, po, mo;
+    int64_t it = 0, pt = 0;
+    int rc = classes_check(classes, nclasses, bw, io, po, mo, it, pt);
+    if (rc != MOJETTE_OK) return rc;
+    if (it == 0) return MOJETTE_OK;
+    if (!images || !projs) return MOJETTE_EINVAL;
+    std::vector<int> order(nclasses);
+    for (int c = 0; c < nclasses; ++c) order[c] = c;
+    // longest rows (longest sweeps) first
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int x, int y) { return classes[x].P > classes[y].P; });
+    unsigned qmask = 0;
+    for (int c = 0; c < nclasses; ++c)
+        if (classes[c].nblocks > 0) qmask |= 1u << classes[c].Q;
+    if (mj::decode_classes_supported(qmask))
+        return decode_classes_launch(classes, order, bw, io, po, mo, projs, erased, images, status,
+                                     (hipStream_t)stream);
+    // A mix of row counts without a compiled kernel: one launch per row count.
+    for (int q = 1; q <= mj::kMaxRows; ++q) {
+        if (!((qmask >> q) & 1u)) continue;
+        std::vector<int> sub;
+        for (int oc : order)
+            if (classes[oc].Q == q) sub.push_back(oc);
+        rc = decode_classes_launch(classes, sub, bw, io, po, mo, projs, erased, images, status,
+                                   (hipStream_t)stream);
+        if (rc != MOJETTE_OK) return rc;
+    }
+    return MOJETTE_OK;
 }
 
 }  // extern "C"

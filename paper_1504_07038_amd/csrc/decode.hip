@@ -114,8 +114,12 @@ struct SegParam {
     bool on;       // segment belongs to a block slot in use
 };
 
-template <int Q, int TW, bool POOL>
-__global__ __launch_bounds__(kWave) void decode_kernel(DecodeArgs a) {
+// One batch of up to nb blocks of one geometry, swept by one wavefront.  `A`
+// supplies the geometry and buffers (`Args`: DecodeArgs for one pool or one block,
+// DecodeClass for one class of a mixed launch).
+template <int Q, int TW, bool POOL, class Args>
+__device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch) {
+    extern __shared__ uint64_t lds[];
     constexpr int LPB = (Q + 1) / 2;        // lanes per block
     constexpr int NBMAX = kWave / LPB;      // blocks per wavefront at most
     constexpr int LPS = TW / 2;             // lanes per row window (two words each)
@@ -123,7 +127,6 @@ __global__ __launch_bounds__(kWave) void decode_kernel(DecodeArgs a) {
     constexpr int NIT = (NBMAX * Q + SPI - 1) / SPI;
     constexpr int QM = RowState<Q>::QM;
 
-    extern __shared__ uint64_t lds[];
     const int lane = threadIdx.x;
     const int slot = lane / LPB;
     const int j = lane - slot * LPB;
@@ -138,8 +141,7 @@ __global__ __launch_bounds__(kWave) void decode_kernel(DecodeArgs a) {
     const int q = lane % LPS;
     const int QP = Q * P;
 
-    const int64_t nbatches = (a.nblocks + NB - 1) / NB;
-    for (int64_t batch = blockIdx.x; batch < nbatches; batch += gridDim.x) {
+    {
         const int64_t blk = batch * NB + slot;
         const bool blk_ok = lane_used && blk < a.nblocks;
         uint32_t mask = a.mask_uniform;
@@ -356,6 +358,80 @@ __global__ __launch_bounds__(kWave) void decode_kernel(DecodeArgs a) {
             wave_sync();
         }
     }
+}
+
+template <int Q, int TW, bool POOL>
+__global__ __launch_bounds__(kWave) void decode_kernel(DecodeArgs a) {
+    const int64_t nbatches = (a.nblocks + a.nb - 1) / a.nb;
+    for (int64_t batch = blockIdx.x; batch < nbatches; batch += gridDim.x)
+        decode_batch<Q, TW, POOL>(a, batch);
+}
+
+// A mixed launch: batches of every class, in the order of the class table
+// (heaviest first), one wavefront per workgroup.  QMASK has bit Q set for
+// every row count the launch may meet; only those bodies are compiled in, so
+// the kernel's registers are those of its largest body, not of all sixteen.
+template <unsigned QMASK>
+__global__ __launch_bounds__(kWave) void decode_classes_kernel(DecodeClassTable tab) {
+    const int64_t total = tab.first_item[tab.nclasses];
+    for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
+        int c = 0;
+        while (item >= tab.first_item[c + 1]) ++c;
+        const DecodeClass &a = tab.cls[c];
+        const int64_t batch = item - tab.first_item[c];
+        switch (a.Q) {
+#define MJ_DEC_CASE(QQ)                                                                  \
+    case QQ:                                                                             \
+        if constexpr ((QMASK >> QQ) & 1u) decode_batch<QQ, kDecodeTile, true>(a, batch); \
+        break;
+            MJ_DEC_CASE(1) MJ_DEC_CASE(2) MJ_DEC_CASE(3) MJ_DEC_CASE(4)
+            MJ_DEC_CASE(5) MJ_DEC_CASE(6) MJ_DEC_CASE(7) MJ_DEC_CASE(8)
+            MJ_DEC_CASE(9) MJ_DEC_CASE(10) MJ_DEC_CASE(11) MJ_DEC_CASE(12)
+            MJ_DEC_CASE(13) MJ_DEC_CASE(14) MJ_DEC_CASE(15) MJ_DEC_CASE(16)
+#undef MJ_DEC_CASE
+            default: break;
+        }
+    }
+}
+
+constexpr unsigned qbit(int q) { return 1u << q; }
+
+// Row-count sets with a compiled mixed kernel: every single row count, and
+// the mixes of the (4,2)+(8,4) and (4,2)+(6,3)+(8,4)+(12,4) code families.
+bool decode_classes_supported(unsigned qmask) {
+    if (qmask && !(qmask & (qmask - 1))) return true;
+    return qmask == (qbit(4) | qbit(8)) || qmask == (qbit(4) | qbit(6) | qbit(8) | qbit(12));
+}
+
+hipError_t launch_decode_classes(unsigned qmask, const DecodeClassTable &tab, size_t lds,
+                                 int grid, hipStream_t s) {
+#define MJ_LAUNCH(M) \
+    hipLaunchKernelGGL(decode_classes_kernel<M>, dim3(grid), dim3(kWave), lds, s, tab)
+    switch (qmask) {
+        case qbit(1): MJ_LAUNCH(qbit(1)); break;
+        case qbit(2): MJ_LAUNCH(qbit(2)); break;
+        case qbit(3): MJ_LAUNCH(qbit(3)); break;
+        case qbit(4): MJ_LAUNCH(qbit(4)); break;
+        case qbit(5): MJ_LAUNCH(qbit(5)); break;
+        case qbit(6): MJ_LAUNCH(qbit(6)); break;
+        case qbit(7): MJ_LAUNCH(qbit(7)); break;
+        case qbit(8): MJ_LAUNCH(qbit(8)); break;
+        case qbit(9): MJ_LAUNCH(qbit(9)); break;
+        case qbit(10): MJ_LAUNCH(qbit(10)); break;
+        case qbit(11): MJ_LAUNCH(qbit(11)); break;
+        case qbit(12): MJ_LAUNCH(qbit(12)); break;
+        case qbit(13): MJ_LAUNCH(qbit(13)); break;
+        case qbit(14): MJ_LAUNCH(qbit(14)); break;
+        case qbit(15): MJ_LAUNCH(qbit(15)); break;
+        case qbit(16): MJ_LAUNCH(qbit(16)); break;
+        case qbit(4) | qbit(8): MJ_LAUNCH(qbit(4) | qbit(8)); break;
+        case qbit(4) | qbit(6) | qbit(8) | qbit(12):
+            MJ_LAUNCH(qbit(4) | qbit(6) | qbit(8) | qbit(12));
+            break;
+        default: return hipErrorInvalidValue;
+    }
+#undef MJ_LAUNCH
+    return hipGetLastError();
 }
 
 int decode_tile(int) { return kDecodeTile; }

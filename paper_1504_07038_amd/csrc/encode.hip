@@ -11,6 +11,52 @@
 
 namespace mj {
 
+// One work item: the bins of block `blk` whose row-0 crossing falls in
+// column tile t, computed by one wavefront from its LDS tile.  `A` supplies
+// the geometry (EncodeArgs for one pool, EncodeClass for one class of a mixed
+// launch).
+template <int Q, class A>
+__device__ __forceinline__ void encode_item(const A &a, int64_t blk, int t, uint64_t *tile,
+                                            int lane) {
+    const int P = a.P, W = a.W, H = a.H, S = a.S;
+    const int x0 = t * W;
+    const uint64_t *img = a.images + blk * (int64_t)P * Q;
+
+    // Stage image columns [x0 - H, x0 + W + H) of every row, zeros outside.
+#pragma unroll
+    for (int l = 0; l < Q; ++l) {
+        const uint64_t *row = img + (int64_t)l * P;
+        for (int c = lane; c < S; c += kWave) {
+            const int col = x0 - H + c;
+            uint64_t v = 0;
+            if ((unsigned)col < (unsigned)P) v = row[col];
+            tile[l * S + c] = v;
+        }
+    }
+    wave_sync();
+
+    // The bins whose row-0 crossing -b falls in [x0, x0 + W); the first tile
+    // also takes the edge bins with -b < 0, the last those with -b >= P.
+    const bool first = (t == 0), last = (t == a.ntiles - 1);
+    const int base = H - x0;
+    for (int i = 0; i < a.n; ++i) {
+        const int p = a.dir(i);
+        const int bmin = bin_offset(p, P, Q);
+        const int bmax = bmin + proj_bins(p, P, Q) - 1;
+        const int bh = first ? bmax : min(bmax, -x0);
+        const int bl = last ? bmin : max(bmin, -x0 - W + 1);
+        uint64_t *dst = a.proj(i, blk);
+        const int rstride = S + p;
+        for (int b = bl + lane; b <= bh; b += kWave) {
+            uint64_t v = 0;
+#pragma unroll
+            for (int l = 0; l < Q; ++l) v ^= tile[l * rstride + base - b];
+            dst[b - bmin] = v;
+        }
+    }
+    wave_sync();  // the next item restages this wave's tile
+}
+
 template <int Q>
 __global__ __launch_bounds__(kWave *kEncodeWaves) void encode_kernel(EncodeArgs a) {
     extern __shared__ uint64_t lds[];
@@ -29,44 +75,50 @@ __global__ __launch_bounds__(kWave *kEncodeWaves) void encode_kernel(EncodeArgs 
             blk = item / a.ntiles;
             t = (int)(item - blk * a.ntiles);
         }
-        const int x0 = t * a.W;
-        const uint64_t *img = a.images + blk * a.img_stride;
-
-        // Stage image columns [x0 - H, x0 + W + H) of every row, zeros outside.
-#pragma unroll
-        for (int l = 0; l < Q; ++l) {
-            const uint64_t *row = img + (int64_t)l * a.P;
-            for (int c = lane; c < a.S; c += kWave) {
-                const int col = x0 - a.H + c;
-                uint64_t v = 0;
-                if ((unsigned)col < (unsigned)a.P) v = row[col];
-                tile[l * a.S + c] = v;
-            }
-        }
-        wave_sync();
-
-        // The bins whose row-0 crossing -b falls in [x0, x0 + W); the first
-        // tile also takes the edge bins with -b < 0, the last those with
-        // -b >= P.
-        const bool first = (t == 0), last = (t == a.ntiles - 1);
-        const int base = a.H - x0;
-        for (int i = 0; i < a.n; ++i) {
-            const int p = a.p[i];
-            const int bmin = a.bmin[i];
-            const int bmax = bmin + a.nbins[i] - 1;
-            const int bh = first ? bmax : min(bmax, -x0);
-            const int bl = last ? bmin : max(bmin, -x0 - a.W + 1);
-            uint64_t *dst = a.out[i] + blk * a.proj_stride;
-            const int rstride = a.S + p;
-            for (int b = bl + lane; b <= bh; b += kWave) {
-                uint64_t v = 0;
-#pragma unroll
-                for (int l = 0; l < Q; ++l) v ^= tile[l * rstride + base - b];
-                dst[b - bmin] = v;
-            }
-        }
-        wave_sync();  // the next item restages this wave's tile
+        encode_item<Q>(a, blk, t, tile, lane);
     }
+}
+
+// A mixed launch: items of every class, in the order of the class table
+// (heaviest items first), one wavefront per workgroup.
+template <int QMAX>
+__global__ __launch_bounds__(kWave) void encode_classes_kernel(EncodeClassTable tab) {
+    extern __shared__ uint64_t lds[];
+    const int lane = threadIdx.x;
+    const int64_t total = tab.first_item[tab.nclasses];
+    for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
+        int c = 0;
+        while (item >= tab.first_item[c + 1]) ++c;
+        const EncodeClass &a = tab.cls[c];
+        const int64_t local = item - tab.first_item[c];
+        const int64_t blk = local / a.ntiles;
+        const int t = (int)(local - blk * a.ntiles);
+        switch (a.Q) {
+#define MJ_ENC_CASE(QQ)                                      \
+    case QQ:                                                 \
+        if constexpr (QQ <= QMAX) encode_item<QQ>(a, blk, t, lds, lane); \
+        break;
+            MJ_ENC_CASE(1) MJ_ENC_CASE(2) MJ_ENC_CASE(3) MJ_ENC_CASE(4)
+            MJ_ENC_CASE(5) MJ_ENC_CASE(6) MJ_ENC_CASE(7) MJ_ENC_CASE(8)
+            MJ_ENC_CASE(9) MJ_ENC_CASE(10) MJ_ENC_CASE(11) MJ_ENC_CASE(12)
+            MJ_ENC_CASE(13) MJ_ENC_CASE(14) MJ_ENC_CASE(15) MJ_ENC_CASE(16)
+#undef MJ_ENC_CASE
+            default: break;
+        }
+    }
+}
+
+hipError_t launch_encode_classes(int qmax, const EncodeClassTable &tab, size_t lds, int grid,
+                                 hipStream_t s) {
+    if (qmax <= 4)
+        hipLaunchKernelGGL(encode_classes_kernel<4>, dim3(grid), dim3(kWave), lds, s, tab);
+    else if (qmax <= 8)
+        hipLaunchKernelGGL(encode_classes_kernel<8>, dim3(grid), dim3(kWave), lds, s, tab);
+    else if (qmax <= 12)
+        hipLaunchKernelGGL(encode_classes_kernel<12>, dim3(grid), dim3(kWave), lds, s, tab);
+    else
+        hipLaunchKernelGGL(encode_classes_kernel<16>, dim3(grid), dim3(kWave), lds, s, tab);
+    return hipGetLastError();
 }
 
 size_t encode_lds_bytes(int Q, int S, int waves) { return (size_t)waves * Q * S * sizeof(uint64_t); }

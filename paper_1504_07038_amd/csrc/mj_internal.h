@@ -42,8 +42,7 @@ __host__ __device__ inline int32_t proj_bins(int32_t p, int32_t P, int32_t Q) {
 // zeros outside the image, H = (Q-1) * max|p|, so no bin read is bounds
 // checked.
 struct EncodeArgs {
-    const uint64_t *images;
-    int64_t img_stride;              // words between consecutive blocks' images
+    const uint64_t *images;          // block b's image at images + b*P*Q
     uint64_t *out[kMaxDirs];         // projection i of block b: out[i] + b*proj_stride
     int64_t proj_stride;
     int64_t nblocks;
@@ -51,8 +50,33 @@ struct EncodeArgs {
     int32_t W, H, S, ntiles;         // tile width, halo, LDS row stride, tiles per block
     int32_t waves;                   // waves per workgroup (1, 2 or 4), one LDS tile each
     int32_t p[kMaxDirs];
-    int32_t bmin[kMaxDirs];
-    int32_t nbins[kMaxDirs];
+    __device__ int dir(int i) const { return p[i]; }
+    __device__ uint64_t *proj(int i, int64_t blk) const { return out[i] + blk * proj_stride; }
+};
+
+// One geometry class of a mixed launch: nblocks blocks with the same P, Q and
+// directions, images back to back at `images`, projection slices back to back
+// at `projs`.
+struct EncodeClass {
+    const uint64_t *images;
+    uint64_t *projs;
+    int64_t nblocks;
+    int32_t proj_stride;             // words per block slice
+    int32_t P, Q, n, W, H, S, ntiles;
+    int32_t off[kMaxDirs];           // projection i at off[i] within a slice
+    int16_t p[kMaxDirs];
+    __device__ int dir(int i) const { return p[i]; }
+    __device__ uint64_t *proj(int i, int64_t blk) const {
+        return projs + blk * proj_stride + off[i];
+    }
+};
+
+constexpr int kMaxClasses = MOJETTE_MAX_CLASSES;
+
+struct EncodeClassTable {
+    EncodeClass cls[kMaxClasses];
+    int64_t first_item[kMaxClasses + 1];   // items of class c: [first_item[c], first_item[c+1])
+    int32_t nclasses;
 };
 
 // ---- decode --------------------------------------------------------------
@@ -81,7 +105,35 @@ struct DecodeArgs {
     int32_t id_sorted[kMaxDirs];     // their indices in the caller's dirs
 };
 
+// One geometry class of a mixed decode launch (pool mode only).  Field names
+// match DecodeArgs so that the same per-batch body serves both.
+struct DecodeClass {
+    const uint64_t *pool;            // projection slices of the class, back to back
+    uint64_t *images;                // images of the class, back to back
+    const uint16_t *masks;           // erasure masks of the class, one per block
+    int32_t *status;
+    int64_t nblocks;
+    int64_t proj_stride;
+    int64_t img_stride;
+    int32_t P, Q, n, nb, R, ring_stride;
+    uint32_t mask_uniform;
+    int32_t off[kMaxDirs];
+    int16_t p_sorted[kMaxDirs];
+    int8_t id_sorted[kMaxDirs];
+};
+
+struct DecodeClassTable {
+    DecodeClass cls[kMaxClasses];
+    int64_t first_item[kMaxClasses + 1];   // batches of class c: [first_item[c], first_item[c+1])
+    int32_t nclasses;
+};
+
 hipError_t launch_encode(const EncodeArgs &a, int grid, hipStream_t s);
+hipError_t launch_encode_classes(int qmax, const EncodeClassTable &tab, size_t lds, int grid,
+                                 hipStream_t s);
+hipError_t launch_decode_classes(unsigned qmask, const DecodeClassTable &tab, size_t lds,
+                                 int grid, hipStream_t s);
+bool decode_classes_supported(unsigned qmask);
 hipError_t launch_decode(int Q, bool pool, const DecodeArgs &a, int grid, hipStream_t s);
 size_t decode_lds_bytes(int Q, int nb, int ring_stride);
 int decode_max_blocks_per_wave(int Q);

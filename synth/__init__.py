@@ -94,3 +94,33 @@ def erasure_masks(seed: int, nblocks: int, n: int, n_erase, first_block: int = 0
 def centered_dirs(n: int) -> list[int]:
     """p_i = i - floor(n/2): {-3..2} for n=6, {-6..5} for n=12, {-8..7} for n=16."""
     return [i - n // 2 for i in range(n)]
+
+
+# Mixed batches: four block sizes and four (k, m) codes, each combination a
+# geometry class.  Sizes are drawn so that every size is equally likely (the
+# set read as log-spaced), codes uniformly; P = ceil(size / (8k)), the last
+# row zero-padded when 8k does not divide the size.
+MIXED_SIZES = (4096, 8192, 65536, 1 << 20)
+MIXED_CODES = ((4, 2), (6, 3), (8, 4), (12, 4))
+
+
+def mixed_classes(total_blocks: int, seed: int, sizes=MIXED_SIZES, codes=MIXED_CODES):
+    """[(P, Q, dirs, nblocks, size_bytes)] for a mixed batch of total_blocks,
+    one entry per (size, code) pair, counts drawn from SplitMix64(seed)."""
+    r = splitmix64(seed, 0, total_blocks)
+    cell = _uniform_below(r, len(sizes) * len(codes))
+    counts = np.bincount(cell, minlength=len(sizes) * len(codes))
+    out = []
+    for si, size in enumerate(sizes):
+        for ci, (k, m) in enumerate(codes):
+            cnt = int(counts[si * len(codes) + ci])
+            P = -(-size // (8 * k))
+            out.append((P, k, centered_dirs(k + m), cnt, size))
+    return out
+
+
+def mixed_images(seed: int, P: int, Q: int, nblocks: int, size: int, first_block: int = 0):
+    """Images of one class: seeded words, zero past `size` bytes of each block."""
+    imgs = block_images(seed, first_block, nblocks, P, Q).reshape(nblocks, Q * P)
+    imgs[:, size // 8:] = 0
+    return imgs.reshape(nblocks, Q, P)

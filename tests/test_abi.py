@@ -103,3 +103,29 @@ def test_package_does_not_import_the_oracle():
                 text = open(os.path.join(dirpath, fn)).read()
                 assert "import oracle" not in text and "from oracle" not in text, fn
                 assert "mojette_oracle" not in text and "liboracle" not in text, fn
+
+
+def test_classes_layout_and_argument_errors(mj):
+    spec = [(128, 4, [-3, -2, -1, 0, 1, 2], 10), (256, 8, list(range(-6, 6)), 3)]
+    iw, pw = mj.mojette_classes_layout(spec)
+    assert iw == 10 * 512 + 3 * 2048
+    assert pw == 10 * 795 + 3 * mj.mojette_block_words(list(range(-6, 6)), 256, 8)
+    L = mj.lib()
+    arr, n = mj.make_classes([(128, 4, [-3, -3, 0, 1], 5)])   # duplicate direction
+    assert L.mojette_classes_layout(arr, n, None, None) == mj.MOJETTE_EINVAL
+    arr, n = mj.make_classes([(128, 4, [-3, -2, 0, 1], -1)])  # negative count
+    assert L.mojette_classes_layout(arr, n, None, None) == mj.MOJETTE_EINVAL
+    arr, n = mj.make_classes([(128, 4, [40000, -2, 0, 1], 1)])  # |p| too large for a class
+    assert L.mojette_encode_classes(arr, n, 0x1000, 0x2000, None) == mj.MOJETTE_EINVAL
+    arr, n = mj.make_classes([(8, 2, [0, 1], 1)] * 17)          # too many classes
+    assert L.mojette_classes_layout(arr, 17, None, None) == mj.MOJETTE_EINVAL
+
+
+def test_mixed_classes_recipe():
+    import synth
+
+    cl = synth.mixed_classes(10000, 4)
+    assert len(cl) == 16 and sum(c[3] for c in cl) == 10000
+    for P, Q, dirs, nb, size in cl:
+        assert len(dirs) - Q in (2, 3, 4) and P * Q * 8 >= size > (P - 1) * Q * 8
+        assert 10000 / 16 * 0.8 < nb < 10000 / 16 * 1.2
