@@ -158,6 +158,38 @@ int mojette_decode_classes(const mojette_class *classes, int32_t nclasses,
                            const uint64_t *projs, const uint16_t *erased, uint64_t *images,
                            int32_t *status, void *stream);
 
+/*
+ * Jobs: the general form of a mixed batch, for callers that keep projections
+ * at scattered slots (an object store).  A job is one geometry class with its
+ * own device buffers:
+ *   images   nblocks images back to back (encode reads them, decode writes).
+ *   projs    a region of projection slices, each mojette_block_words() long.
+ *   slots    device int64 array or NULL: block b's slice is slice slots[b] of
+ *            projs (NULL: slice b).  Encode scatters to the slots, decode
+ *            gathers from them.
+ *   erased   decode: device uint16 masks, one per block, or NULL.
+ * Up to MOJETTE_MAX_CLASSES jobs run in one launch.  Decode launches with any
+ * `slots` support row counts 2, 4, ..., 16 alone and the {4, 8} mix
+ * (MOJETTE_ENOTSUP otherwise).  Same ownership, error and stream rules as the
+ * batch calls; safe to record into a HIP graph.
+ */
+typedef struct mojette_job {
+    int32_t P, Q, n;
+    int32_t dirs[MOJETTE_MAX_DIRS];
+    int64_t nblocks;
+    uint64_t *images;
+    uint64_t *projs;
+    const int64_t *slots;
+    const uint16_t *erased;
+} mojette_job;
+
+/* Forward transform (Section 2.1, Eq. 1) of every block of every job. */
+int mojette_encode_jobs(const mojette_job *jobs, int32_t njobs, void *stream);
+
+/* Inverse transform (Section 2.2) of every block of every job; status as for
+ * mojette_decode_batch. */
+int mojette_decode_jobs(const mojette_job *jobs, int32_t njobs, int32_t *status, void *stream);
+
 /* Ring length (words per row) the decoder needs for this geometry: the
  * longest distance, over every choice of Q survivors, between a pixel a row
  * needs and the newest pixel of that row, rounded up to a power of two and

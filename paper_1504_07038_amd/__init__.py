@@ -49,6 +49,38 @@ def make_classes(classes):
     return arr, len(classes)
 
 
+class MojetteJob(ctypes.Structure):
+    """``mojette_job``: one geometry class with its own device buffers."""
+
+    _fields_ = [("P", ctypes.c_int32), ("Q", ctypes.c_int32), ("n", ctypes.c_int32),
+                ("dirs", ctypes.c_int32 * MAX_DIRS), ("nblocks", ctypes.c_int64),
+                ("images", ctypes.c_void_p), ("projs", ctypes.c_void_p),
+                ("slots", ctypes.c_void_p), ("erased", ctypes.c_void_p)]
+
+
+def make_jobs(jobs):
+    """``jobs``: iterable of dicts with P, Q, dirs, nblocks, images, projs and
+    optional slots (int64 device tensor) and erased (int16 device tensor)."""
+    jobs = list(jobs)
+    arr = (MojetteJob * max(1, len(jobs)))()
+    for c, j in enumerate(jobs):
+        a = arr[c]
+        a.P, a.Q, a.n, a.nblocks = int(j["P"]), int(j["Q"]), len(j["dirs"]), int(j["nblocks"])
+        for i, p in enumerate(j["dirs"]):
+            a.dirs[i] = int(p)
+        a.images = _word_tensor(j["images"], "images")
+        a.projs = _word_tensor(j["projs"], "projs")
+        sl = j.get("slots")
+        if sl is not None:
+            import torch
+
+            if sl.dtype != torch.int64:
+                raise ValueError("slots must be int64")
+        a.slots = _dev_ptr(sl, "slots")
+        a.erased = _dev_ptr(j.get("erased"), "erased")
+    return arr, len(jobs)
+
+
 class MojetteError(RuntimeError):
     def __init__(self, status: int, where: str):
         super().__init__(f"{where}: {strerror(status)} ({status})")
@@ -80,6 +112,8 @@ def lib() -> ctypes.CDLL:
         "mojette_classes_layout": ([vp, i32, vp, vp], ctypes.c_int),
         "mojette_encode_classes": ([vp, i32, vp, vp, vp], ctypes.c_int),
         "mojette_decode_classes": ([vp, i32, vp, vp, vp, vp, vp], ctypes.c_int),
+        "mojette_encode_jobs": ([vp, i32, vp], ctypes.c_int),
+        "mojette_decode_jobs": ([vp, i32, vp, vp], ctypes.c_int),
         "mojette_fill_splitmix64": ([vp, i64, u64, u64, vp], ctypes.c_int),
         "mojette_copy_words": ([vp, vp, i64, vp], ctypes.c_int),
     }
@@ -96,7 +130,8 @@ def exported_symbols() -> list[str]:
         "mojette_strerror", "mojette_proj_size", "mojette_bin_offset", "mojette_block_words",
         "mojette_decode_ring", "mojette_encode", "mojette_decode", "mojette_encode_batch",
         "mojette_decode_batch", "mojette_classes_layout", "mojette_encode_classes",
-        "mojette_decode_classes", "mojette_fill_splitmix64", "mojette_copy_words",
+        "mojette_decode_classes", "mojette_encode_jobs", "mojette_decode_jobs",
+        "mojette_fill_splitmix64", "mojette_copy_words",
     ]
 
 
@@ -236,6 +271,22 @@ def mojette_decode_classes(classes, projs, erased, images, status=None, stream=N
                                       _dev_ptr(erased, "erased"), _word_tensor(images, "images"),
                                       _dev_ptr(status, "status"), _stream(stream))
     return _check(rc, "mojette_decode_classes", check)
+
+
+def mojette_encode_jobs(jobs, stream=None, check: bool = True) -> int:
+    arr, n = make_jobs(jobs)
+    rc = lib().mojette_encode_jobs(arr, n, _stream(stream))
+    return _check(rc, "mojette_encode_jobs", check)
+
+
+def mojette_decode_jobs(jobs, status=None, stream=None, check: bool = True) -> int:
+    import torch
+
+    arr, n = make_jobs(jobs)
+    if status is not None and status.dtype != torch.int32:
+        raise ValueError("status must be int32")
+    rc = lib().mojette_decode_jobs(arr, n, _dev_ptr(status, "status"), _stream(stream))
+    return _check(rc, "mojette_decode_jobs", check)
 
 
 def mojette_fill_splitmix64(dst, nwords: int, seed: int, start: int = 0, stream=None,

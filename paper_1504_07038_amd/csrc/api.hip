@@ -325,25 +325,36 @@ int mojette_classes_layout(const mojette_class *classes, int32_t nclasses, int64
     return MOJETTE_OK;
 }
 
-int mojette_encode_classes(const mojette_class *classes, int32_t nclasses,
-                           const uint64_t *images, uint64_t *projs, void *stream) {
-    std::vector<int64_t> bw, io, po, mo;
-    int64_t it = 0, pt = 0;
-    int rc = classes_check(classes, nclasses, bw, io, po, mo, it, pt);
+// Checks jobs; returns per-job block words.
+static int jobs_check(const mojette_job *jobs, int32_t njobs, std::vector<int64_t> &bw) {
+    if (!jobs || njobs < 1 || njobs > mj::kMaxClasses) return MOJETTE_EINVAL;
+    bw.assign(njobs, 0);
+    for (int c = 0; c < njobs; ++c) {
+        const mojette_job &j = jobs[c];
+        if (j.nblocks < 0 || !geometry_ok(j.dirs, j.n, j.P, j.Q)) return MOJETTE_EINVAL;
+        for (int i = 0; i < j.n; ++i)
+            if (j.dirs[i] < -32767 || j.dirs[i] > 32767) return MOJETTE_EINVAL;
+        if (j.nblocks > 0 && (!j.images || !j.projs)) return MOJETTE_EINVAL;
+        bw[c] = mojette_block_words(j.dirs, j.n, j.P, j.Q);
+    }
+    return MOJETTE_OK;
+}
+
+int mojette_encode_jobs(const mojette_job *jobs, int32_t njobs, void *stream) {
+    std::vector<int64_t> bw;
+    int rc = jobs_check(jobs, njobs, bw);
     if (rc != MOJETTE_OK) return rc;
-    if (it == 0) return MOJETTE_OK;
-    if (!images || !projs) return MOJETTE_EINVAL;
     // heaviest items (widest tiles x rows x directions) first
-    std::vector<int> order(nclasses);
-    std::vector<mj::EncodeArgs> geo(nclasses);
-    for (int c = 0; c < nclasses; ++c) {
+    std::vector<int> order(njobs);
+    std::vector<mj::EncodeArgs> geo(njobs);
+    for (int c = 0; c < njobs; ++c) {
         order[c] = c;
-        const mojette_class &k = classes[c];
-        if (!encode_tiling(k.dirs, k.n, k.P, k.Q, geo[c], 1)) return MOJETTE_ENOTSUP;
+        const mojette_job &j = jobs[c];
+        if (!encode_tiling(j.dirs, j.n, j.P, j.Q, geo[c], 1)) return MOJETTE_ENOTSUP;
     }
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
-        const int64_t wx = (int64_t)geo[x].W * classes[x].Q * classes[x].n;
-        const int64_t wy = (int64_t)geo[y].W * classes[y].Q * classes[y].n;
+        const int64_t wx = (int64_t)geo[x].W * jobs[x].Q * jobs[x].n;
+        const int64_t wy = (int64_t)geo[y].W * jobs[y].Q * jobs[y].n;
         return wx > wy;
     });
     mj::EncodeClassTable tab{};
@@ -352,116 +363,161 @@ int mojette_encode_classes(const mojette_class *classes, int32_t nclasses,
     int64_t items = 0;
     int k = 0;
     for (int oc : order) {
-        const mojette_class &cl = classes[oc];
-        if (cl.nblocks == 0) continue;
+        const mojette_job &jb = jobs[oc];
+        if (jb.nblocks == 0) continue;
         mj::EncodeClass &e = tab.cls[k];
-        e.images = images + io[oc];
-        e.projs = projs + po[oc];
-        e.nblocks = cl.nblocks;
+        e.images = jb.images;
+        e.projs = jb.projs;
+        e.slots = jb.slots;
+        e.nblocks = jb.nblocks;
         e.proj_stride = (int32_t)bw[oc];
-        e.P = cl.P;
-        e.Q = cl.Q;
-        e.n = cl.n;
+        e.P = jb.P;
+        e.Q = jb.Q;
+        e.n = jb.n;
         e.W = geo[oc].W;
         e.H = geo[oc].H;
         e.S = geo[oc].S;
         e.ntiles = geo[oc].ntiles;
         int32_t off = 0;
-        for (int i = 0; i < cl.n; ++i) {
+        for (int i = 0; i < jb.n; ++i) {
             e.off[i] = off;
-            e.p[i] = (int16_t)cl.dirs[i];
-            off += (int32_t)mojette_proj_size(cl.dirs[i], cl.P, cl.Q);
+            e.p[i] = (int16_t)jb.dirs[i];
+            off += (int32_t)mojette_proj_size(jb.dirs[i], jb.P, jb.Q);
         }
         tab.first_item[k] = items;
-        items += cl.nblocks * e.ntiles;
-        lds = std::max(lds, mj::encode_lds_bytes(cl.Q, e.S, 1));
-        qmax = std::max(qmax, (int)cl.Q);
+        items += jb.nblocks * e.ntiles;
+        lds = std::max(lds, mj::encode_lds_bytes(jb.Q, e.S, 1));
+        qmax = std::max(qmax, (int)jb.Q);
         ++k;
     }
+    if (k == 0) return MOJETTE_OK;
     tab.nclasses = k;
     tab.first_item[k] = items;
     const int grid = (int)std::min<int64_t>(items, kEncodeGridCap * mj::kEncodeWaves);
     return status_of(mj::launch_encode_classes(qmax, tab, lds, grid, (hipStream_t)stream));
 }
 
-// One mixed decode launch over the classes listed in `which` (heaviest first).
-int decode_classes_launch(const mojette_class *classes, const std::vector<int> &which,
-                          const std::vector<int64_t> &bw, const std::vector<int64_t> &io,
-                          const std::vector<int64_t> &po, const std::vector<int64_t> &mo,
-                          const uint64_t *projs, const uint16_t *erased, uint64_t *images,
-                          int32_t *status, hipStream_t stream) {
+// One mixed decode launch over the jobs listed in `which` (heaviest first).
+static int decode_jobs_launch(const mojette_job *jobs, const std::vector<int> &which,
+                              const std::vector<int64_t> &bw, bool gather, int32_t *status,
+                              hipStream_t stream) {
     mj::DecodeClassTable tab{};
     size_t lds = 0;
     unsigned qmask = 0;
     int64_t items = 0;
     int k = 0;
     for (int oc : which) {
-        const mojette_class &cl = classes[oc];
-        if (cl.nblocks == 0) continue;
+        const mojette_job &jb = jobs[oc];
+        if (jb.nblocks == 0) continue;
         mj::DecodeClass &d = tab.cls[k];
-        const int rc = decode_setup(cl.dirs, cl.n, cl.P, cl.Q, d);
+        const int rc = decode_setup(jb.dirs, jb.n, jb.P, jb.Q, d);
         if (rc != MOJETTE_OK) return rc;
-        if ((int64_t)d.nb * bw[oc] * 8 >= ((int64_t)1 << 31) ||
-            (int64_t)d.nb * cl.P * cl.Q * 8 >= ((int64_t)1 << 31))
+        if (!gather && ((int64_t)d.nb * bw[oc] * 8 >= ((int64_t)1 << 31) ||
+                        (int64_t)d.nb * jb.P * jb.Q * 8 >= ((int64_t)1 << 31)))
             return MOJETTE_ENOTSUP;
-        d.Q = cl.Q;
-        d.pool = projs + po[oc];
-        d.images = images + io[oc];
-        d.masks = erased ? erased + mo[oc] : nullptr;
+        d.Q = jb.Q;
+        d.pool = jb.projs;
+        d.slots = jb.slots;
+        d.images = jb.images;
+        d.masks = jb.erased;
         d.status = status;
-        d.nblocks = cl.nblocks;
+        d.nblocks = jb.nblocks;
         d.proj_stride = bw[oc];
-        d.img_stride = (int64_t)cl.P * cl.Q;
+        d.img_stride = (int64_t)jb.P * jb.Q;
         d.mask_uniform = 0;
         int32_t off = 0;
-        for (int i = 0; i < cl.n; ++i) {
+        for (int i = 0; i < jb.n; ++i) {
             d.off[i] = off;
-            off += (int32_t)mojette_proj_size(cl.dirs[i], cl.P, cl.Q);
+            off += (int32_t)mojette_proj_size(jb.dirs[i], jb.P, jb.Q);
         }
         tab.first_item[k] = items;
-        items += (cl.nblocks + d.nb - 1) / d.nb;
-        lds = std::max(lds, mj::decode_lds_bytes(cl.Q, d.nb, d.ring_stride));
-        qmask |= 1u << cl.Q;
+        items += (jb.nblocks + d.nb - 1) / d.nb;
+        lds = std::max(lds, mj::decode_lds_bytes(jb.Q, d.nb, d.ring_stride));
+        qmask |= 1u << jb.Q;
         ++k;
     }
     if (k == 0) return MOJETTE_OK;
     tab.nclasses = k;
     tab.first_item[k] = items;
     const int grid = (int)std::min<int64_t>(items, kDecodeGridCap);
-    return status_of(mj::launch_decode_classes(qmask, tab, lds, grid, stream));
+    return status_of(mj::launch_decode_classes(qmask, gather, tab, lds, grid, stream));
+}
+
+int mojette_decode_jobs(const mojette_job *jobs, int32_t njobs, int32_t *status, void *stream) {
+    std::vector<int64_t> bw;
+    int rc = jobs_check(jobs, njobs, bw);
+    if (rc != MOJETTE_OK) return rc;
+    std::vector<int> order(njobs);
+    for (int c = 0; c < njobs; ++c) order[c] = c;
+    // longest rows (longest sweeps) first
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int x, int y) { return jobs[x].P > jobs[y].P; });
+    unsigned qmask = 0;
+    bool gather = false;
+    for (int c = 0; c < njobs; ++c)
+        if (jobs[c].nblocks > 0) {
+            qmask |= 1u << jobs[c].Q;
+            gather = gather || jobs[c].slots != nullptr;
+        }
+    if (qmask == 0) return MOJETTE_OK;
+    if (mj::decode_classes_supported(qmask, gather))
+        return decode_jobs_launch(jobs, order, bw, gather, status, (hipStream_t)stream);
+    // A mix of row counts without a compiled kernel: one launch per row count.
+    for (int q = 1; q <= mj::kMaxRows; ++q) {
+        if (!((qmask >> q) & 1u)) continue;
+        if (!mj::decode_classes_supported(1u << q, gather)) return MOJETTE_ENOTSUP;
+    }
+    for (int q = 1; q <= mj::kMaxRows; ++q) {
+        if (!((qmask >> q) & 1u)) continue;
+        std::vector<int> sub;
+        for (int oc : order)
+            if (jobs[oc].Q == q) sub.push_back(oc);
+        rc = decode_jobs_launch(jobs, sub, bw, gather, status, (hipStream_t)stream);
+        if (rc != MOJETTE_OK) return rc;
+    }
+    return MOJETTE_OK;
+}
+
+// The pool layout of the class calls, expressed as jobs.
+static int classes_to_jobs(const mojette_class *classes, int32_t nclasses, const uint64_t *images,
+                           const uint64_t *projs, const uint16_t *erased,
+                           std::vector<mojette_job> &jobs) {
+    std::vector<int64_t> bw, io, po, mo;
+    int64_t it = 0, pt = 0;
+    const int rc = classes_check(classes, nclasses, bw, io, po, mo, it, pt);
+    if (rc != MOJETTE_OK) return rc;
+    if (it > 0 && (!images || !projs)) return MOJETTE_EINVAL;
+    jobs.assign(nclasses, mojette_job{});
+    for (int c = 0; c < nclasses; ++c) {
+        mojette_job &j = jobs[c];
+        j.P = classes[c].P;
+        j.Q = classes[c].Q;
+        j.n = classes[c].n;
+        for (int i = 0; i < j.n; ++i) j.dirs[i] = classes[c].dirs[i];
+        j.nblocks = classes[c].nblocks;
+        j.images = const_cast<uint64_t *>(images) + io[c];
+        j.projs = const_cast<uint64_t *>(projs) + po[c];
+        j.slots = nullptr;
+        j.erased = erased ? erased + mo[c] : nullptr;
+    }
+    return MOJETTE_OK;
+}
+
+int mojette_encode_classes(const mojette_class *classes, int32_t nclasses,
+                           const uint64_t *images, uint64_t *projs, void *stream) {
+    std::vector<mojette_job> jobs;
+    const int rc = classes_to_jobs(classes, nclasses, images, projs, nullptr, jobs);
+    if (rc != MOJETTE_OK) return rc;
+    return mojette_encode_jobs(jobs.data(), nclasses, stream);
 }
 
 int mojette_decode_classes(const mojette_class *classes, int32_t nclasses,
                            const uint64_t *projs, const uint16_t *erased, uint64_t *images,
                            int32_t *status, void *stream) {
-    std::vector<int64_t> bw, io, po, mo;
-    int64_t it = 0, pt = 0;
-    int rc = classes_check(classes, nclasses, bw, io, po, mo, it, pt);
+    std::vector<mojette_job> jobs;
+    const int rc = classes_to_jobs(classes, nclasses, images, projs, erased, jobs);
     if (rc != MOJETTE_OK) return rc;
-    if (it == 0) return MOJETTE_OK;
-    if (!images || !projs) return MOJETTE_EINVAL;
-    std::vector<int> order(nclasses);
-    for (int c = 0; c < nclasses; ++c) order[c] = c;
-    // longest rows (longest sweeps) first
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int x, int y) { return classes[x].P > classes[y].P; });
-    unsigned qmask = 0;
-    for (int c = 0; c < nclasses; ++c)
-        if (classes[c].nblocks > 0) qmask |= 1u << classes[c].Q;
-    if (mj::decode_classes_supported(qmask))
-        return decode_classes_launch(classes, order, bw, io, po, mo, projs, erased, images, status,
-                                     (hipStream_t)stream);
-    // A mix of row counts without a compiled kernel: one launch per row count.
-    for (int q = 1; q <= mj::kMaxRows; ++q) {
-        if (!((qmask >> q) & 1u)) continue;
-        std::vector<int> sub;
-        for (int oc : order)
-            if (classes[oc].Q == q) sub.push_back(oc);
-        rc = decode_classes_launch(classes, sub, bw, io, po, mo, projs, erased, images, status,
-                                   (hipStream_t)stream);
-        if (rc != MOJETTE_OK) return rc;
-    }
-    return MOJETTE_OK;
+    return mojette_decode_jobs(jobs.data(), nclasses, status, stream);
 }
 
 }  // extern "C"

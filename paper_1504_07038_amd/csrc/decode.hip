@@ -110,7 +110,7 @@ struct SegParam {
     int col0;      // column of word 2q of the load window of tile 0
     int scol0;     // first column stored by this lane at tile 0 (window lag applied)
     int img;       // word offset (in the wave's image slice) of the segment's row
-    int id;        // projection id of the row (pointer mode)
+    const uint64_t *bins;   // pointer mode: the row's projection
     bool on;       // segment belongs to a block slot in use
 };
 
@@ -215,6 +215,14 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch)
             const int g1 = POOL ? slot * (int)a.proj_stride + a.off[id1] + jb1 : jb1;
             const int own0 = valid ? dr0 : INT_MIN;
             const int own1 = valid ? dr1 : INT_MIN;
+            // pointer mode: the projections of this lane's two rows
+            uint64_t pb0 = 0, pb1 = 0;
+            if constexpr (!POOL) {
+                if (valid) {
+                    pb0 = (uint64_t)a.proj_base(blk, id0);
+                    pb1 = (uint64_t)a.proj_base(blk, id1);
+                }
+            }
 #pragma unroll
             for (int it = 0; it < NIT; ++it) {
                 const int seg = it * SPI + lane / LPS;
@@ -224,7 +232,6 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch)
                 const int src = owner < kWave ? owner : 0;
                 const int od0 = __shfl(own0, src), od1 = __shfl(own1, src);
                 const int og0 = __shfl(g0, src), og1 = __shfl(g1, src);
-                const int oi0 = __shfl(id0, src), oi1 = __shfl(id1, src);
                 const bool odd = srow & 1;
                 const int sd = odd ? od1 : od0;
                 SegParam &s = sp[it];
@@ -232,7 +239,16 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch)
                 const int dd = s.on ? sd : 0;
                 s.ring = (sslot < NB ? sslot : 0) * SS + srow * RS;
                 s.gbin = odd ? og1 : og0;
-                s.id = odd ? oi1 : oi0;
+                s.bins = nullptr;
+                if constexpr (!POOL) {
+                    // both rows' pointers come over; the requester picks
+                    const uint32_t lo0 = __shfl((uint32_t)pb0, src);
+                    const uint32_t hi0 = __shfl((uint32_t)(pb0 >> 32), src);
+                    const uint32_t lo1 = __shfl((uint32_t)pb1, src);
+                    const uint32_t hi1 = __shfl((uint32_t)(pb1 >> 32), src);
+                    s.bins = (const uint64_t *)(odd ? (((uint64_t)hi1 << 32) | lo1)
+                                                    : (((uint64_t)hi0 << 32) | lo0));
+                }
                 s.col0 = dd + TW - 1 - 2 * q;
                 const int L = (-dd + TW - 1) / TW;
                 s.scol0 = -TW * L + 2 * q;
@@ -269,7 +285,7 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch)
                     const u32x2 w1 = __builtin_amdgcn_raw_buffer_load_b64(rin, off1, 0, 0);
                     buf[it] = u32x4{w0.x, w0.y, w1.x, w1.y};
                 } else {
-                    const uint64_t *bins = a.in[s.id];
+                    const uint64_t *bins = s.bins;
                     const int c0 = min(max(c, 0), P - 1), c1 = min(max(c - 1, 0), P - 1);
                     const uint64_t w0 = s.on ? bins[s.gbin - c0] : 0;
                     const uint64_t w1 = s.on ? bins[s.gbin - c1] : 0;
@@ -312,7 +328,7 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch)
                         __builtin_amdgcn_raw_buffer_store_b64(
                             u32x2{(uint32_t)w0, (uint32_t)(w0 >> 32)}, rout, off1, 0, 0);
                 } else {
-                    uint64_t *dst = a.images + s.img;
+                    uint64_t *dst = a.images + first * a.img_stride + s.img;
                     if (both) {
                         store_pair(dst + c, w0, w1);
                     } else if (last) {
@@ -371,7 +387,7 @@ __global__ __launch_bounds__(kWave) void decode_kernel(DecodeArgs a) {
 // (heaviest first), one wavefront per workgroup.  QMASK has bit Q set for
 // every row count the launch may meet; only those bodies are compiled in, so
 // the kernel's registers are those of its largest body, not of all sixteen.
-template <unsigned QMASK>
+template <unsigned QMASK, bool GATHER>
 __global__ __launch_bounds__(kWave) void decode_classes_kernel(DecodeClassTable tab) {
     const int64_t total = tab.first_item[tab.nclasses];
     for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
@@ -382,7 +398,7 @@ __global__ __launch_bounds__(kWave) void decode_classes_kernel(DecodeClassTable 
         switch (a.Q) {
 #define MJ_DEC_CASE(QQ)                                                                  \
     case QQ:                                                                             \
-        if constexpr ((QMASK >> QQ) & 1u) decode_batch<QQ, kDecodeTile, true>(a, batch); \
+        if constexpr ((QMASK >> QQ) & 1u) decode_batch<QQ, kDecodeTile, !GATHER>(a, batch); \
         break;
             MJ_DEC_CASE(1) MJ_DEC_CASE(2) MJ_DEC_CASE(3) MJ_DEC_CASE(4)
             MJ_DEC_CASE(5) MJ_DEC_CASE(6) MJ_DEC_CASE(7) MJ_DEC_CASE(8)
@@ -398,35 +414,59 @@ constexpr unsigned qbit(int q) { return 1u << q; }
 
 // Row-count sets with a compiled mixed kernel: every single row count, and
 // the mixes of the (4,2)+(8,4) and (4,2)+(6,3)+(8,4)+(12,4) code families.
-bool decode_classes_supported(unsigned qmask) {
+// Gathering launches (blocks at arbitrary projection slots) exist for the
+// even row counts up to 16 and the (4,2)+(8,4) mix.
+bool decode_classes_supported(unsigned qmask, bool gather) {
+    if (gather) {
+        switch (qmask) {
+            case qbit(2): case qbit(4): case qbit(6): case qbit(8): case qbit(10):
+            case qbit(12): case qbit(14): case qbit(16): case qbit(4) | qbit(8): return true;
+            default: return false;
+        }
+    }
     if (qmask && !(qmask & (qmask - 1))) return true;
     return qmask == (qbit(4) | qbit(8)) || qmask == (qbit(4) | qbit(6) | qbit(8) | qbit(12));
 }
 
-hipError_t launch_decode_classes(unsigned qmask, const DecodeClassTable &tab, size_t lds,
-                                 int grid, hipStream_t s) {
-#define MJ_LAUNCH(M) \
-    hipLaunchKernelGGL(decode_classes_kernel<M>, dim3(grid), dim3(kWave), lds, s, tab)
+hipError_t launch_decode_classes(unsigned qmask, bool gather, const DecodeClassTable &tab,
+                                 size_t lds, int grid, hipStream_t s) {
+#define MJ_LAUNCH(M, G) \
+    hipLaunchKernelGGL((decode_classes_kernel<M, G>), dim3(grid), dim3(kWave), lds, s, tab)
+    if (gather) {
+        switch (qmask) {
+            case qbit(2): MJ_LAUNCH(qbit(2), true); break;
+            case qbit(4): MJ_LAUNCH(qbit(4), true); break;
+            case qbit(6): MJ_LAUNCH(qbit(6), true); break;
+            case qbit(8): MJ_LAUNCH(qbit(8), true); break;
+            case qbit(10): MJ_LAUNCH(qbit(10), true); break;
+            case qbit(12): MJ_LAUNCH(qbit(12), true); break;
+            case qbit(14): MJ_LAUNCH(qbit(14), true); break;
+            case qbit(16): MJ_LAUNCH(qbit(16), true); break;
+            case qbit(4) | qbit(8): MJ_LAUNCH(qbit(4) | qbit(8), true); break;
+            default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     switch (qmask) {
-        case qbit(1): MJ_LAUNCH(qbit(1)); break;
-        case qbit(2): MJ_LAUNCH(qbit(2)); break;
-        case qbit(3): MJ_LAUNCH(qbit(3)); break;
-        case qbit(4): MJ_LAUNCH(qbit(4)); break;
-        case qbit(5): MJ_LAUNCH(qbit(5)); break;
-        case qbit(6): MJ_LAUNCH(qbit(6)); break;
-        case qbit(7): MJ_LAUNCH(qbit(7)); break;
-        case qbit(8): MJ_LAUNCH(qbit(8)); break;
-        case qbit(9): MJ_LAUNCH(qbit(9)); break;
-        case qbit(10): MJ_LAUNCH(qbit(10)); break;
-        case qbit(11): MJ_LAUNCH(qbit(11)); break;
-        case qbit(12): MJ_LAUNCH(qbit(12)); break;
-        case qbit(13): MJ_LAUNCH(qbit(13)); break;
-        case qbit(14): MJ_LAUNCH(qbit(14)); break;
-        case qbit(15): MJ_LAUNCH(qbit(15)); break;
-        case qbit(16): MJ_LAUNCH(qbit(16)); break;
-        case qbit(4) | qbit(8): MJ_LAUNCH(qbit(4) | qbit(8)); break;
+        case qbit(1): MJ_LAUNCH(qbit(1), false); break;
+        case qbit(2): MJ_LAUNCH(qbit(2), false); break;
+        case qbit(3): MJ_LAUNCH(qbit(3), false); break;
+        case qbit(4): MJ_LAUNCH(qbit(4), false); break;
+        case qbit(5): MJ_LAUNCH(qbit(5), false); break;
+        case qbit(6): MJ_LAUNCH(qbit(6), false); break;
+        case qbit(7): MJ_LAUNCH(qbit(7), false); break;
+        case qbit(8): MJ_LAUNCH(qbit(8), false); break;
+        case qbit(9): MJ_LAUNCH(qbit(9), false); break;
+        case qbit(10): MJ_LAUNCH(qbit(10), false); break;
+        case qbit(11): MJ_LAUNCH(qbit(11), false); break;
+        case qbit(12): MJ_LAUNCH(qbit(12), false); break;
+        case qbit(13): MJ_LAUNCH(qbit(13), false); break;
+        case qbit(14): MJ_LAUNCH(qbit(14), false); break;
+        case qbit(15): MJ_LAUNCH(qbit(15), false); break;
+        case qbit(16): MJ_LAUNCH(qbit(16), false); break;
+        case qbit(4) | qbit(8): MJ_LAUNCH(qbit(4) | qbit(8), false); break;
         case qbit(4) | qbit(6) | qbit(8) | qbit(12):
-            MJ_LAUNCH(qbit(4) | qbit(6) | qbit(8) | qbit(12));
+            MJ_LAUNCH(qbit(4) | qbit(6) | qbit(8) | qbit(12), false);
             break;
         default: return hipErrorInvalidValue;
     }

@@ -60,6 +60,7 @@ struct EncodeArgs {
 struct EncodeClass {
     const uint64_t *images;
     uint64_t *projs;
+    const int64_t *slots;            // block b's slice is slice slots[b] of projs (null: b)
     int64_t nblocks;
     int32_t proj_stride;             // words per block slice
     int32_t P, Q, n, W, H, S, ntiles;
@@ -67,7 +68,7 @@ struct EncodeClass {
     int16_t p[kMaxDirs];
     __device__ int dir(int i) const { return p[i]; }
     __device__ uint64_t *proj(int i, int64_t blk) const {
-        return projs + blk * proj_stride + off[i];
+        return projs + (slots ? slots[blk] : blk) * proj_stride + off[i];
     }
 };
 
@@ -103,12 +104,14 @@ struct DecodeArgs {
     int32_t nb;                      // blocks per wavefront (at most 64/ceil(Q/2), fewer if LDS is short)
     int32_t p_sorted[kMaxDirs];      // directions in ascending p
     int32_t id_sorted[kMaxDirs];     // their indices in the caller's dirs
+    __device__ const uint64_t *proj_base(int64_t, int id) const { return in[id]; }
 };
 
 // One geometry class of a mixed decode launch (pool mode only).  Field names
 // match DecodeArgs so that the same per-batch body serves both.
 struct DecodeClass {
-    const uint64_t *pool;            // projection slices of the class, back to back
+    const uint64_t *pool;            // projection slices of the class
+    const int64_t *slots;            // block b's slice is slice slots[b] of pool (null: b)
     uint64_t *images;                // images of the class, back to back
     const uint16_t *masks;           // erasure masks of the class, one per block
     int32_t *status;
@@ -120,6 +123,9 @@ struct DecodeClass {
     int32_t off[kMaxDirs];
     int16_t p_sorted[kMaxDirs];
     int8_t id_sorted[kMaxDirs];
+    __device__ const uint64_t *proj_base(int64_t blk, int id) const {
+        return pool + (slots ? slots[blk] : blk) * proj_stride + off[id];
+    }
 };
 
 struct DecodeClassTable {
@@ -131,9 +137,9 @@ struct DecodeClassTable {
 hipError_t launch_encode(const EncodeArgs &a, int grid, hipStream_t s);
 hipError_t launch_encode_classes(int qmax, const EncodeClassTable &tab, size_t lds, int grid,
                                  hipStream_t s);
-hipError_t launch_decode_classes(unsigned qmask, const DecodeClassTable &tab, size_t lds,
-                                 int grid, hipStream_t s);
-bool decode_classes_supported(unsigned qmask);
+hipError_t launch_decode_classes(unsigned qmask, bool gather, const DecodeClassTable &tab,
+                                 size_t lds, int grid, hipStream_t s);
+bool decode_classes_supported(unsigned qmask, bool gather);
 hipError_t launch_decode(int Q, bool pool, const DecodeArgs &a, int grid, hipStream_t s);
 size_t decode_lds_bytes(int Q, int nb, int ring_stride);
 int decode_max_blocks_per_wave(int Q);

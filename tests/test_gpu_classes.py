@@ -141,3 +141,41 @@ def test_mixed_config_sample(mj):
     spec = [(P, Q, d, nb) for P, Q, d, nb, _ in synth.mixed_classes(640, 4)]
     say(f"mixed workload classes: {[(P, Q, nb) for P, Q, _, nb in spec]}")
     check(spec, run_classes(mj, spec, 41), sample=6)
+
+
+def test_jobs_scatter_and_gather_slots(mj):
+    """Encode scatters blocks to arbitrary projection slots of an arena,
+    decode gathers them back, codes (4,2) and (8,4) in one launch each."""
+    rng = np.random.default_rng(5)
+    specs = [(128, 4, synth.centered_dirs(6), 300, 1000), (96, 8, synth.centered_dirs(12), 120, 500),
+             (2048, 4, synth.centered_dirs(6), 20, 64)]
+    arenas, jobs_e, jobs_d, host = [], [], [], []
+    for c, (P, Q, dirs, nb, cap) in enumerate(specs):
+        words = mj.mojette_block_words(dirs, P, Q)
+        imgs = synth.block_images(70 + c, 0, nb, P, Q)
+        slots = rng.permutation(cap)[:nb].astype(np.int64)
+        masks = synth.erasure_masks(80 + c, nb, len(dirs), (0, len(dirs) - Q))
+        arena = torch.full((cap * words,), 7, dtype=torch.int64, device="cuda")
+        d_slots = torch.from_numpy(slots).cuda()
+        d_img = to_dev(imgs)
+        d_out = torch.full_like(d_img, -1)
+        jobs_e.append(dict(P=P, Q=Q, dirs=dirs, nblocks=nb, images=d_img, projs=arena,
+                           slots=d_slots))
+        jobs_d.append(dict(P=P, Q=Q, dirs=dirs, nblocks=nb, images=d_out, projs=arena,
+                           slots=d_slots, erased=masks_to_dev(masks)))
+        arenas.append(arena)
+        host.append((imgs, slots, masks, words, d_out))
+    say("jobs: scatter encode")
+    mj.mojette_encode_jobs(jobs_e)
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    say("jobs: gather decode")
+    mj.mojette_decode_jobs(jobs_d, status=st)
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0
+    for (P, Q, dirs, nb, cap), arena, (imgs, slots, masks, words, d_out) in zip(specs, arenas, host):
+        ar = to_np(arena).reshape(cap, words)
+        want = oracle.encode_blocks(imgs, P, Q, dirs)
+        assert np.array_equal(ar[slots], want)
+        untouched = np.setdiff1d(np.arange(cap), slots)
+        assert (ar[untouched] == 7).all()
+        assert np.array_equal(to_np(d_out).reshape(nb, Q, P), imgs)
