@@ -54,6 +54,13 @@ extern "C" {
 /* Human-readable name of a status code. */
 const char *mojette_strerror(int status);
 
+/* Name of the HIP error behind the calling thread's most recent
+ * MOJETTE_EHIP ("no HIP error" if there was none).  A call clears any error
+ * an earlier HIP call of the thread left pending before it launches, so
+ * MOJETTE_EHIP always reports the library's own launch.  The string is
+ * static; the call never fails. */
+const char *mojette_last_hip_error(void);
+
 /* Eq. 2 with q = 1: number of bins of the projection along (p, 1) of a
  * P x Q image, |p|(Q-1) + P.  Returns -1 if P < 1 or Q < 1. */
 int64_t mojette_proj_size(int32_t p, int32_t P, int32_t Q);

@@ -83,7 +83,10 @@ def make_jobs(jobs):
 
 class MojetteError(RuntimeError):
     def __init__(self, status: int, where: str):
-        super().__init__(f"{where}: {strerror(status)} ({status})")
+        msg = f"{where}: {strerror(status)} ({status})"
+        if status == MOJETTE_EHIP:
+            msg += f": {lib().mojette_last_hip_error().decode()}"
+        super().__init__(msg)
         self.status = status
 
 
@@ -97,10 +100,20 @@ def lib() -> ctypes.CDLL:
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    # torch ships its own HIP runtime under the same soname as the system one.
+    # Loading torch first makes the library's libamdhip64 dependency resolve
+    # to that copy, so the process has ONE runtime and torch's streams and
+    # allocations are valid handles for the library.
+    import torch  # noqa: F401
+
     L = ctypes.CDLL(LIB_PATH)
+    runtimes = _hip_runtimes_mapped()
+    if len(runtimes) > 1:
+        raise RuntimeError("two HIP runtimes are loaded in this process: " + ", ".join(runtimes))
     i32, i64, u64, vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_void_p
     sig = {
         "mojette_strerror": ([ctypes.c_int], ctypes.c_char_p),
+        "mojette_last_hip_error": ([], ctypes.c_char_p),
         "mojette_proj_size": ([i32, i32, i32], i64),
         "mojette_bin_offset": ([i32, i32, i32], i64),
         "mojette_block_words": ([vp, i32, i32, i32], i64),
@@ -125,13 +138,28 @@ def lib() -> ctypes.CDLL:
     return L
 
 
+def _hip_runtimes_mapped() -> list[str]:
+    """Distinct libamdhip64 files mapped into this process (Linux)."""
+    found = set()
+    try:
+        with open("/proc/self/maps") as f:
+            for line in f:
+                path = line.split()[-1]
+                if "libamdhip64.so" in os.path.basename(path):
+                    found.add(os.path.realpath(path))
+    except OSError:
+        pass
+    return sorted(found)
+
+
 def exported_symbols() -> list[str]:
     return [
-        "mojette_strerror", "mojette_proj_size", "mojette_bin_offset", "mojette_block_words",
-        "mojette_decode_ring", "mojette_encode", "mojette_decode", "mojette_encode_batch",
-        "mojette_decode_batch", "mojette_classes_layout", "mojette_encode_classes",
-        "mojette_decode_classes", "mojette_encode_jobs", "mojette_decode_jobs",
-        "mojette_fill_splitmix64", "mojette_copy_words",
+        "mojette_strerror", "mojette_last_hip_error", "mojette_proj_size",
+        "mojette_bin_offset", "mojette_block_words", "mojette_decode_ring", "mojette_encode",
+        "mojette_decode", "mojette_encode_batch", "mojette_decode_batch",
+        "mojette_classes_layout", "mojette_encode_classes", "mojette_decode_classes",
+        "mojette_encode_jobs", "mojette_decode_jobs", "mojette_fill_splitmix64",
+        "mojette_copy_words",
     ]
 
 

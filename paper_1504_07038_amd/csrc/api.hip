@@ -30,7 +30,15 @@ bool geometry_ok(const int32_t *dirs, int32_t n, int32_t P, int32_t Q) {
     return true;
 }
 
-int status_of(hipError_t e) { return e == hipSuccess ? MOJETTE_OK : MOJETTE_EHIP; }
+int status_of(hipError_t e) { return mj::hip_status(e); }
+
+// Kernel launches report through hipGetLastError(), which also returns an
+// error left behind by any earlier HIP call of the thread (the caller's or a
+// framework's).  Such a stale error is cleared before each launch so that a
+// call reports only its own failure.
+void clear_stale_error() { (void)hipGetLastError(); }
+
+thread_local hipError_t g_last_hip = hipSuccess;
 
 // Encode tiling: the whole row when it fits, else the widest multiple of 64
 // columns whose tile plus halo fits the LDS budget.  Four waves per
@@ -181,7 +189,17 @@ int classes_check(const mojette_class *cls, int32_t ncls, std::vector<int64_t> &
 
 }  // namespace
 
+int mj::hip_status(hipError_t e) {
+    if (e == hipSuccess) return MOJETTE_OK;
+    g_last_hip = e;
+    return MOJETTE_EHIP;
+}
+
 extern "C" {
+
+const char *mojette_last_hip_error(void) {
+    return g_last_hip == hipSuccess ? "no HIP error" : hipGetErrorName(g_last_hip);
+}
 
 const char *mojette_strerror(int status) {
     switch (status) {
@@ -231,6 +249,7 @@ int mojette_encode(const uint64_t *image, int32_t P, int32_t Q, const int32_t *d
     a.proj_stride = 0;
     a.nblocks = 1;
     const int grid = (a.ntiles + a.waves - 1) / a.waves;
+    clear_stale_error();
     return status_of(mj::launch_encode(a, grid, (hipStream_t)stream));
 }
 
@@ -252,6 +271,7 @@ int mojette_encode_batch(const uint64_t *images, int64_t nblocks, int32_t P, int
     const int64_t items = nblocks * a.ntiles;
     const int64_t want = (items + a.waves - 1) / a.waves;
     const int grid = (int)std::min<int64_t>(want, kEncodeGridCap);
+    clear_stale_error();
     return status_of(mj::launch_encode(a, grid, (hipStream_t)stream));
 }
 
@@ -279,6 +299,7 @@ int mojette_decode(const uint64_t *const *proj, const int32_t *proj_ids, int32_t
     a.mask_uniform = ~have & ((1u << n) - 1u);
     a.status = nullptr;
     a.nblocks = 1;
+    clear_stale_error();
     return status_of(mj::launch_decode(Q, false, a, 1, (hipStream_t)stream));
 }
 
@@ -311,6 +332,7 @@ int mojette_decode_batch(const uint64_t *projs, const uint16_t *erased, int64_t 
     a.nblocks = nblocks;
     const int64_t batches = (nblocks + a.nb - 1) / a.nb;
     const int grid = (int)std::min<int64_t>(batches, kDecodeGridCap);
+    clear_stale_error();
     return status_of(mj::launch_decode(Q, true, a, grid, (hipStream_t)stream));
 }
 
@@ -394,6 +416,7 @@ int mojette_encode_jobs(const mojette_job *jobs, int32_t njobs, void *stream) {
     tab.nclasses = k;
     tab.first_item[k] = items;
     const int grid = (int)std::min<int64_t>(items, kEncodeGridCap * mj::kEncodeWaves);
+    clear_stale_error();
     return status_of(mj::launch_encode_classes(qmax, tab, lds, grid, (hipStream_t)stream));
 }
 
@@ -440,6 +463,7 @@ static int decode_jobs_launch(const mojette_job *jobs, const std::vector<int> &w
     tab.nclasses = k;
     tab.first_item[k] = items;
     const int grid = (int)std::min<int64_t>(items, kDecodeGridCap);
+    clear_stale_error();
     return status_of(mj::launch_decode_classes(qmask, gather, tab, lds, grid, stream));
 }
 

@@ -134,6 +134,10 @@ struct DecodeClassTable {
     int32_t nclasses;
 };
 
+// Status of a HIP call as a library status code; a failure is remembered for
+// mojette_last_hip_error() on the calling thread.
+int hip_status(hipError_t e);
+
 hipError_t launch_encode(const EncodeArgs &a, int grid, hipStream_t s);
 hipError_t launch_encode_classes(int qmax, const EncodeClassTable &tab, size_t lds, int grid,
                                  hipStream_t s);

@@ -6,6 +6,7 @@
 
 #include "../../include/mojette.h"
 #include "../../include/mojette_synth.h"
+#include "mj_internal.h"
 
 namespace {
 
@@ -51,14 +52,16 @@ int mojette_fill_splitmix64(uint64_t *dst, int64_t nwords, uint64_t seed, uint64
                             void *stream) {
     if (nwords < 0 || (nwords > 0 && !dst)) return MOJETTE_EINVAL;
     if (nwords == 0) return MOJETTE_OK;
+    (void)hipGetLastError();  // report this launch only, not an earlier call's error
     hipLaunchKernelGGL(fill_kernel, dim3(grid_for(nwords, 256)), dim3(256), 0, (hipStream_t)stream,
                        dst, nwords, seed, start);
-    return hipGetLastError() == hipSuccess ? MOJETTE_OK : MOJETTE_EHIP;
+    return mj::hip_status(hipGetLastError());
 }
 
 int mojette_copy_words(uint64_t *dst, const uint64_t *src, int64_t nwords, void *stream) {
     if (nwords < 0 || (nwords > 0 && (!dst || !src))) return MOJETTE_EINVAL;
     if (nwords == 0) return MOJETTE_OK;
+    (void)hipGetLastError();
     const bool aligned = ((((uintptr_t)dst) | ((uintptr_t)src)) & 15u) == 0 && (nwords % 2) == 0;
     if (aligned) {
         const int64_t n2 = nwords / 2;
@@ -68,7 +71,7 @@ int mojette_copy_words(uint64_t *dst, const uint64_t *src, int64_t nwords, void 
         hipLaunchKernelGGL(copy8_kernel, dim3(grid_for(nwords, 256)), dim3(256), 0,
                            (hipStream_t)stream, dst, src, nwords);
     }
-    return hipGetLastError() == hipSuccess ? MOJETTE_OK : MOJETTE_EHIP;
+    return mj::hip_status(hipGetLastError());
 }
 
 }  // extern "C"

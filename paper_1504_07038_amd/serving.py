@@ -1,0 +1,441 @@
+"""Continuous-batching request loop for the Mojette erasure code on one GPU.
+
+Writes (encode an object of k data packets into n projections, Section 2.3)
+and degraded reads (rebuild an object from the projections that survive,
+Section 2.2) arrive as a Poisson stream.  Projections stay resident in HBM in
+per-class arenas; a class is one code (k, m) and one row length P from a
+geometric grid, and an object of S bytes is stored in the smallest class with
+P * k * 8 >= S.
+
+Admission works against a fixed HBM budget, carved at start-up into the
+arenas, a pre-staged payload pool per class (the images writes encode) and
+an output ring per class (where reads land):
+  - a write needs an arena slot: a free one, or the oldest resident object if
+    no in-flight read uses it; otherwise it waits;
+  - a read needs a resident object of its class and a row of the output ring;
+  - an iteration takes at most `cap` requests of each kind per class.
+Every loop turn retires the iterations whose completion event has fired,
+admits what has arrived and fits, and launches ONE scatter-encode and ONE
+gather-decode job launch for every class with work (the job API of
+``mojette.h``; 16 classes per launch), up to `depth` iterations in flight, so
+requests join while earlier ones are still running on the device.
+
+Latency is arrival to the GPU completion event of the request's iteration,
+read on the GPU clock from a start event that had completed before the host
+clock started: never shorter than the true latency.  The host work is
+bookkeeping only (slot rings, masks, timestamps); every pixel and bin is read
+and written by the HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+import time
+from dataclasses import dataclass
+
+import numpy as np
+
+import paper_1504_07038_amd as mj
+
+CODES = ((4, 2), (8, 4))
+READ_FRACTION = 0.7
+LOG2_MIN, LOG2_MAX = 12, 20     # object sizes 4 KB .. 1 MB
+
+
+@dataclass
+class Geometry:
+    k: int
+    m: int
+    P: int
+    dirs: list
+    words: int          # projection words per object (one arena slot)
+
+    @property
+    def Q(self):
+        return self.k
+
+    @property
+    def img_words(self):
+        return self.P * self.k
+
+
+def class_grid(k: int, per_octave: int = 4):
+    """Row lengths of the classes of code k: P_min * 2^(j / per_octave),
+    rounded up, from 4 KB objects to 1 MB objects."""
+    pmin = (1 << LOG2_MIN) // (8 * k)
+    steps = (LOG2_MAX - LOG2_MIN) * per_octave
+    return sorted({int(np.ceil(pmin * 2.0 ** (j / per_octave) - 1e-9)) for j in range(steps + 1)})
+
+
+def geometries(codes=CODES, per_octave: int = 4):
+    out = []
+    for k, m in codes:
+        n = k + m
+        dirs = [i - n // 2 for i in range(n)]
+        for P in class_grid(k, per_octave):
+            out.append(Geometry(k, m, P, dirs, mj.mojette_block_words(dirs, P, k)))
+    return out
+
+
+@dataclass
+class Trace:
+    """A request stream, sorted by arrival."""
+    arrival: np.ndarray     # seconds
+    size: np.ndarray        # object bytes
+    cls: np.ndarray         # class index
+    read: np.ndarray        # 1 = degraded read, 0 = write
+    mask: np.ndarray        # reads: erased projections (bit i = projection i)
+
+
+def make_trace(qps: float, duration: float, geos, seed: int, codes=CODES) -> Trace:
+    """Poisson arrivals at `qps` for `duration` s.  Per request: code uniform
+    over `codes`; size 2^U[12, 20] bytes rounded up to a multiple of 8k; 70%
+    reads, each losing a uniform number 0..m of its n projections (a uniform
+    subset, so every read is decodable, Section 2.3)."""
+    import synth
+
+    rng = np.random.default_rng(seed)
+    N = max(1, int(rng.poisson(qps * duration)))
+    arrival = np.sort(rng.uniform(0.0, duration, N))
+    code = rng.integers(0, len(codes), N)
+    ks = np.array([k for k, _ in codes])[code]
+    raw = 2.0 ** rng.uniform(LOG2_MIN, LOG2_MAX, N)
+    size = (np.ceil(raw / (8 * ks)) * (8 * ks)).astype(np.int64)
+    read = (rng.random(N) < READ_FRACTION).astype(np.int64)
+    cls = np.empty(N, dtype=np.int64)
+    mask = np.zeros(N, dtype=np.uint16)
+    for ci, (k, m) in enumerate(codes):
+        ids = np.array([g for g, geo in enumerate(geos) if (geo.k, geo.m) == (k, m)])
+        Ps = np.array([geos[g].P for g in ids])
+        sel = np.flatnonzero(code == ci)
+        pos = np.searchsorted(Ps, size[sel] // (8 * k), side="left")
+        if (pos >= len(Ps)).any():
+            raise ValueError("object larger than the largest class")
+        cls[sel] = ids[pos]
+        mask[sel] = synth.erasure_masks(seed * 7 + ci, len(sel), k + m, (0, m))
+    return Trace(arrival, size, cls, read, mask)
+
+
+class SlotStore:
+    """Arena slot bookkeeping of one class (host side, no device memory):
+    free slots on a stack, resident objects in a FIFO ring (oldest at head),
+    in-flight read counts per slot, and the payload row each object holds."""
+
+    def __init__(self, slots: int):
+        self.slots = slots
+        self.free = np.arange(slots - 1, -1, -1, dtype=np.int64)
+        self.nfree = slots
+        self.ring = np.zeros(slots, dtype=np.int64)
+        self.head = 0
+        self.count = 0
+        self.refs = np.zeros(slots, dtype=np.int32)
+        self.source = np.full(slots, -1, dtype=np.int64)
+
+    def push_resident(self, slots: np.ndarray, rows: np.ndarray) -> None:
+        k = len(slots)
+        idx = (self.head + self.count + np.arange(k)) % self.slots
+        self.ring[idx] = slots
+        self.count += k
+        self.source[slots] = rows
+
+    def take_write_slots(self, want: int) -> np.ndarray:
+        """Up to `want` slots: free ones first, then the oldest resident
+        objects in ring order up to the first one an in-flight read holds."""
+        take = min(want, self.nfree)
+        got = self.free[self.nfree - take:self.nfree][::-1].copy()
+        self.nfree -= take
+        want -= take
+        if want > 0 and self.count > 0:
+            c = min(want, self.count)
+            idx = (self.head + np.arange(c)) % self.slots
+            cand = self.ring[idx]
+            busy = np.flatnonzero(self.refs[cand] != 0)
+            ev = c if len(busy) == 0 else int(busy[0])
+            if ev:
+                self.head = (self.head + ev) % self.slots
+                self.count -= ev
+                self.source[cand[:ev]] = -1
+                got = np.concatenate([got, cand[:ev]])
+        return got
+
+    def pick_resident(self, k: int, rng) -> np.ndarray:
+        """k resident objects drawn uniformly (with repeats); holds them."""
+        idx = (self.head + rng.integers(0, self.count, k)) % self.slots
+        slots = self.ring[idx]
+        np.add.at(self.refs, slots, 1)
+        return slots
+
+    def release(self, slots: np.ndarray) -> None:
+        np.add.at(self.refs, slots, -1)
+
+    def resident(self) -> np.ndarray:
+        return self.ring[(self.head + np.arange(self.count)) % self.slots]
+
+
+class _Class(SlotStore):
+    """Device buffers of one class on top of its slot bookkeeping."""
+
+    def __init__(self, geo: Geometry, slots: int, cap: int, depth: int, dev, torch):
+        super().__init__(slots)
+        self.geo = geo
+        self.cap = cap
+        self.pay = 2 * cap
+        self.arena = torch.empty(slots * geo.words, dtype=torch.int64, device=dev)
+        self.payload = torch.empty(self.pay * geo.img_words, dtype=torch.int64, device=dev)
+        self.out = torch.empty(depth * cap * geo.img_words, dtype=torch.int64, device=dev)
+        self.arena_ptr = self.arena.data_ptr()
+        self.payload_ptr = self.payload.data_ptr()
+        self.out_ptr = self.out.data_ptr()
+        tmpl = mj.MojetteJob()
+        tmpl.P, tmpl.Q, tmpl.n = geo.P, geo.Q, len(geo.dirs)
+        for i, p in enumerate(geo.dirs):
+            tmpl.dirs[i] = p
+        self.template = tmpl
+
+
+class Server:
+    """The store and the loop.  `budget_bytes` covers the arenas, payload
+    pools, output rings and staging; `per_iter_bytes` bounds one class's
+    image bytes per kind per iteration (sets `cap`)."""
+
+    def __init__(self, budget_bytes: int = 64 << 30, depth: int = 3, seed: int = 1,
+                 geos=None, prefill: float = 0.5, per_iter_bytes: int = 16 << 20):
+        import torch
+
+        self.torch = torch
+        self.dev = torch.device("cuda:0")
+        self.geos = geos if geos is not None else geometries()
+        self.depth = depth
+        self.rng = np.random.default_rng(seed)
+        self.stream = torch.cuda.Stream()
+        self.stream_ptr = self.stream.cuda_stream
+        self.L = mj.lib()
+        caps = [int(max(4, min(4096, per_iter_bytes // (g.img_words * 8)))) for g in self.geos]
+        stage_words = sum(2 * c + c // 4 + 1 for c in caps) + 64
+        fixed = sum((depth + 2) * c * g.img_words * 8 for c, g in zip(caps, self.geos))
+        fixed += 2 * depth * stage_words * 8
+        if fixed >= budget_bytes:
+            raise ValueError("budget too small for the payload pools and output rings")
+        share = (budget_bytes - fixed) // len(self.geos)
+        self.cs = []
+        for c, (g, cap) in enumerate(zip(self.geos, caps)):
+            slots = share // (g.words * 8)
+            if slots < 2 * cap:
+                raise ValueError(f"budget leaves class {c} fewer than {2 * cap} slots")
+            self.cs.append(_Class(g, int(slots), cap, depth, self.dev, torch))
+        for c, st in enumerate(self.cs):
+            mj.mojette_fill_splitmix64(st.payload, st.payload.numel(), seed * 1000 + c,
+                                       stream=self.stream_ptr)
+        self.stage_words = stage_words
+        self.h_stage = torch.empty(depth * stage_words, dtype=torch.int64).pin_memory()
+        self.h_np = self.h_stage.numpy()
+        self.d_stage = torch.empty(depth * stage_words, dtype=torch.int64, device=self.dev)
+        self.d_stage_ptr = self.d_stage.data_ptr()
+        self.status = torch.zeros(1, dtype=torch.int32, device=self.dev)
+        self.jobs = [(mj.MojetteJob * mj.MAX_CLASSES)() for _ in range(2)]
+        self.iter_no = 0
+        self._prefill(prefill)
+        self.stream.synchronize()
+
+    @property
+    def budget_used(self) -> int:
+        b = (self.h_stage.numel() + self.d_stage.numel()) * 8
+        for st in self.cs:
+            b += (st.arena.numel() + st.payload.numel() + st.out.numel()) * 8
+        return b
+
+    # ---- launches -----------------------------------------------------------
+
+    def _run_jobs(self, kind: str, entries) -> None:
+        """entries: (class, nblocks, images ptr, slots ptr, erased ptr)."""
+        arr = self.jobs[0 if kind == "w" else 1]
+        size = ctypes.sizeof(mj.MojetteJob)
+        for s in range(0, len(entries), mj.MAX_CLASSES):
+            chunk = entries[s:s + mj.MAX_CLASSES]
+            for i, (c, nb, img, slots, erased) in enumerate(chunk):
+                st = self.cs[c]
+                ctypes.memmove(ctypes.addressof(arr[i]), ctypes.addressof(st.template), size)
+                a = arr[i]
+                a.nblocks, a.images, a.projs, a.slots, a.erased = nb, img, st.arena_ptr, slots, erased
+            if kind == "w":
+                rc = self.L.mojette_encode_jobs(arr, len(chunk), self.stream_ptr)
+            else:
+                rc = self.L.mojette_decode_jobs(arr, len(chunk), self.status.data_ptr(),
+                                                self.stream_ptr)
+            if rc != mj.MOJETTE_OK:
+                raise mj.MojetteError(rc, f"mojette_{'encode' if kind == 'w' else 'decode'}_jobs")
+
+    def _prefill(self, frac: float) -> None:
+        """Write objects into a fraction of every arena (set-up, untimed)."""
+        torch = self.torch
+        for c, st in enumerate(self.cs):
+            want = int(st.slots * frac)
+            while want > 0:
+                b = min(want, st.pay)
+                slots = st.take_write_slots(b)
+                d = torch.from_numpy(slots).to(self.dev)
+                with torch.cuda.stream(self.stream):
+                    self._run_jobs("w", [(c, b, st.payload_ptr, d.data_ptr(), None)])
+                self.stream.synchronize()
+                st.push_resident(slots, np.arange(b))
+                want -= b
+
+    def _launch(self, writes, reads, trace: Trace):
+        """Stage slot lists and masks, copy them over, launch, record the
+        completion event.  writes: (class, ids, slots, first payload row);
+        reads: (class, ids, slots)."""
+        torch = self.torch
+        ring = self.iter_no % self.depth
+        self.iter_no += 1
+        base = ring * self.stage_words
+        pos = base
+        hs = self.h_np
+        wl, rl = [], []
+        for c, ids, slots, row0 in writes:
+            k = len(slots)
+            st = self.cs[c]
+            hs[pos:pos + k] = slots
+            wl.append((c, k, st.payload_ptr + row0 * st.geo.img_words * 8,
+                       self.d_stage_ptr + pos * 8, None))
+            pos += k
+        for c, ids, slots in reads:
+            k = len(slots)
+            st = self.cs[c]
+            hs[pos:pos + k] = slots
+            nw = (k + 3) // 4
+            hs[pos + k + nw - 1] = 0
+            hs[pos + k:pos + k + nw].view(np.uint16)[:k] = trace.mask[ids]
+            out = st.out_ptr + ring * st.cap * st.geo.img_words * 8
+            rl.append((c, k, out, self.d_stage_ptr + pos * 8, self.d_stage_ptr + (pos + k) * 8))
+            pos += k + nw
+        done = torch.cuda.Event(enable_timing=True)
+        with torch.cuda.stream(self.stream):
+            self.d_stage[base:pos].copy_(self.h_stage[base:pos], non_blocking=True)
+            if wl:
+                self._run_jobs("w", wl)
+            if rl:
+                self._run_jobs("r", rl)
+            done.record(self.stream)
+        return done, ring
+
+    # ---- the loop -----------------------------------------------------------
+
+    def run(self, trace: Trace, track=None, max_wall: float = 120.0):
+        """Serve `trace` in real time.  Returns (completion times on the
+        trace's clock, tracked results, counters).  `track`: request ids whose
+        results are copied out at completion (tests)."""
+        torch = self.torch
+        N = len(trace.arrival)
+        nq = 2 * len(self.cs)
+        qid = trace.cls * 2 + trace.read
+        order = np.argsort(qid, kind="stable")
+        bounds = np.searchsorted(qid[order], np.arange(nq + 1))
+        queues = [order[bounds[q]:bounds[q + 1]] for q in range(nq)]
+        arrived = np.zeros(nq, dtype=np.int64)
+        heads = np.zeros(nq, dtype=np.int64)
+        done_t = np.full(N, np.nan)
+        results = {}
+        inflight = []
+        seen = 0
+        stats = {"iterations": 0, "max_queued": 0, "admitted": 0, "blocked_writes": 0}
+        start = torch.cuda.Event(enable_timing=True)
+        start.record(self.stream)
+        start.synchronize()
+        t0 = time.perf_counter()
+        while True:
+            # retire finished iterations (the oldest regardless, if the window is full)
+            while inflight and (len(inflight) >= self.depth or inflight[0][0].query()):
+                ev, ring, writes, reads = inflight.pop(0)
+                ev.synchronize()
+                self._retire(start.elapsed_time(ev) / 1e3, ring, writes, reads, done_t,
+                             track, results)
+            now = time.perf_counter() - t0
+            n_arr = int(np.searchsorted(trace.arrival, now, side="right"))
+            if n_arr > seen:
+                arrived += np.bincount(qid[seen:n_arr], minlength=nq)
+                seen = n_arr
+            pending = arrived - heads
+            stats["max_queued"] = max(stats["max_queued"], int(pending.sum()))
+            writes, reads = [], []
+            for q in np.flatnonzero(pending):
+                c, is_read = divmod(int(q), 2)
+                st = self.cs[c]
+                h = int(heads[q])
+                if is_read:
+                    if st.count == 0:
+                        continue
+                    k = min(int(pending[q]), st.cap)
+                    slots = st.pick_resident(k, self.rng)
+                    reads.append((c, queues[q][h:h + k], slots))
+                else:
+                    slots = st.take_write_slots(min(int(pending[q]), st.cap))
+                    k = len(slots)
+                    if k == 0:
+                        stats["blocked_writes"] += 1
+                        continue
+                    row0 = int(self.rng.integers(0, st.pay - k + 1))
+                    writes.append((c, queues[q][h:h + k], slots, row0))
+                heads[q] = h + k
+                stats["admitted"] += k
+            if writes or reads:
+                ev, ring = self._launch(writes, reads, trace)
+                inflight.append((ev, ring, writes, reads))
+                stats["iterations"] += 1
+            elif seen == N and not inflight and (heads == arrived).all():
+                break
+            elif inflight:
+                time.sleep(10e-6)
+            else:
+                nxt = trace.arrival[seen] if seen < N else now
+                time.sleep(max(0.0, min(nxt - now, 1e-3)))
+            if time.perf_counter() - t0 > max_wall:
+                raise RuntimeError("serving loop exceeded its wall-clock limit")
+        self.stream.synchronize()
+        return done_t, results, stats
+
+    def _retire(self, t_done, ring, writes, reads, done_t, track, results) -> None:
+        for c, ids, slots, row0 in writes:
+            st = self.cs[c]
+            done_t[ids] = t_done
+            rows = row0 + np.arange(len(slots))
+            st.push_resident(slots, rows)
+            if track:
+                g = st.geo
+                for rid, s, row in zip(ids, slots, rows):
+                    if int(rid) in track:
+                        results[int(rid)] = ("w", c, int(s), int(row),
+                                             st.arena[s * g.words:(s + 1) * g.words].cpu())
+        for c, ids, slots in reads:
+            st = self.cs[c]
+            done_t[ids] = t_done
+            st.release(slots)
+            if track:
+                g = st.geo
+                for j, (rid, s) in enumerate(zip(ids, slots)):
+                    if int(rid) in track:
+                        o = (ring * st.cap + j) * g.img_words
+                        results[int(rid)] = ("r", c, int(s), int(st.source[s]),
+                                             st.out[o:o + g.img_words].cpu())
+
+
+def summarize(trace: Trace, done_t: np.ndarray, stats: dict) -> dict:
+    """p50/p99 latency (arrival to completion), sustained user GB/s."""
+    lat = done_t - trace.arrival
+    ok = np.isfinite(lat)
+    span = float(np.nanmax(done_t)) if ok.any() else float("nan")
+    rd = ok & (trace.read == 1)
+    wr = ok & (trace.read == 0)
+
+    def pct(x, q):
+        return round(float(np.percentile(x, q)) * 1e6, 1) if len(x) else None
+
+    return {
+        "requests": int(len(lat)),
+        "completed": int(ok.sum()),
+        "offered_qps": round(len(lat) / float(trace.arrival[-1]), 1) if len(lat) > 1 else None,
+        "p50_us": pct(lat[ok], 50), "p99_us": pct(lat[ok], 99),
+        "read_p50_us": pct(lat[rd], 50), "read_p99_us": pct(lat[rd], 99),
+        "write_p50_us": pct(lat[wr], 50), "write_p99_us": pct(lat[wr], 99),
+        "GBps": round(float(trace.size[ok].sum()) / span / 1e9, 3) if span > 0 else None,
+        "span_s": round(span, 4),
+        **stats,
+    }

@@ -129,3 +129,18 @@ def test_mixed_classes_recipe():
     for P, Q, dirs, nb, size in cl:
         assert len(dirs) - Q in (2, 3, 4) and P * Q * 8 >= size > (P - 1) * Q * 8
         assert 10000 / 16 * 0.8 < nb < 10000 / 16 * 1.2
+
+
+def test_one_hip_runtime_even_when_the_library_loads_first():
+    """The binding loads torch before the library, so the library's HIP
+    dependency resolves to torch's copy: one runtime per process, whichever
+    of the two the caller touches first."""
+    import subprocess
+    import sys
+
+    code = ("import paper_1504_07038_amd as mj; mj.mojette_block_words([0, 1], 8, 2); "
+            "import torch; torch.zeros(1); print(len(mj._hip_runtimes_mapped()))")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True,
+                         timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip().splitlines()[-1] == "1"
