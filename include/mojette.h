@@ -22,8 +22,8 @@
  *     mojette_block_words() long and block b's slice starts at b times that.
  *   - Pixel and bin buffers are DEVICE pointers owned by the caller; small
  *     host arrays (dirs, pointer tables, ids) are read before the call
- *     returns.  No call allocates or frees device memory.  Images must not
- *     overlap projections.
+ *     returns.  No call allocates or frees device memory except the plan
+ *     calls of the chunked decode.  Images must not overlap projections.
  *   - Work is enqueued on `stream` (a hipStream_t; NULL = the default stream)
  *     and the call returns without waiting.  Argument errors are reported
  *     before anything is enqueued; a failed launch returns MOJETTE_EHIP.
@@ -196,6 +196,57 @@ int mojette_encode_jobs(const mojette_job *jobs, int32_t njobs, void *stream);
 /* Inverse transform (Section 2.2) of every block of every job; status as for
  * mojette_decode_batch. */
 int mojette_decode_jobs(const mojette_job *jobs, int32_t njobs, int32_t *status, void *stream);
+
+/*
+ * Chunked decode of long rows (the inverse of Section 2.2, cut into chunks).
+ * A block's decode is a left-to-right sweep whose length grows with P; for
+ * long rows (large blocks) the sweep of one block is cut into chunks of about
+ * chunk_cols columns that run in parallel: every chunk is swept from a zero
+ * start, a carry pass applies the GF(2) transfer matrix of the block's
+ * survivor set to turn the chunks' end states into exact start states
+ * (XOR is linear), and every chunk is swept again from its exact start.
+ * Results are bit-identical to mojette_decode_batch.
+ *
+ * A plan holds the transfer matrices of every Q-subset of the directions for
+ * one chunk length.  mojette_plan_create computes them on the host and
+ * copies them to the current device: it allocates device memory and
+ * synchronises, so it is not for use under graph capture.  It returns
+ * MOJETTE_ENOTSUP if chunks of that length are shorter than the decode's
+ * own lead-in.  mojette_plan_destroy frees the plan (NULL is a no-op).
+ */
+typedef struct mojette_plan mojette_plan;
+
+int mojette_plan_create(const int32_t *dirs, int32_t n, int32_t Q, int32_t chunk_cols,
+                        mojette_plan **plan);
+int mojette_plan_destroy(mojette_plan *plan);
+
+/* Host only: the state width E (*state_cols) and transfer matrix of one
+ * survivor set, directions p_sorted[0..Q) strictly ascending.  Row i of the
+ * matrix (ceil(Q*E/64) words, bit j of word w = start-state word 64w + j)
+ * lists the start-state words whose XOR is end-state word i when every bin
+ * is zero; state word r*E + e is the pixel of row r at e columns from the
+ * start of the state window.  Writes the rows when cap_words is large
+ * enough and returns the words they take, -1 on bad arguments, -2 if chunks
+ * of chunk_cols columns are too short. */
+int64_t mojette_chunk_matrix(const int32_t *p_sorted, int32_t Q, int32_t chunk_cols,
+                             int32_t *state_cols, uint64_t *rows, int64_t cap_words);
+
+/* Device workspace (words) a chunked decode of nblocks blocks of row length
+ * P needs; 0 when P is too short to cut (the call then decodes whole
+ * blocks).  -1 on bad arguments. */
+int64_t mojette_decode_chunked_workspace(const mojette_plan *plan, int32_t P, int64_t nblocks);
+
+/*
+ * mojette_decode_batch with the plan's directions and row count, the sweep
+ * of every block cut into chunks.  Arguments as for mojette_decode_batch;
+ * workspace: device, mojette_decode_chunked_workspace() words, owned by the
+ * caller, overwritten.  Three launches on `stream` (two when a block has
+ * only two chunks); allocates nothing; safe to record into a HIP graph.
+ */
+int mojette_decode_batch_chunked(const mojette_plan *plan, const uint64_t *projs,
+                                 const uint16_t *erased, int64_t nblocks, int32_t P,
+                                 uint64_t *images, int32_t *status, uint64_t *workspace,
+                                 void *stream);
 
 /* Ring length (words per row) the decoder needs for this geometry: the
  * longest distance, over every choice of Q survivors, between a pixel a row

@@ -127,6 +127,11 @@ def lib() -> ctypes.CDLL:
         "mojette_decode_classes": ([vp, i32, vp, vp, vp, vp, vp], ctypes.c_int),
         "mojette_encode_jobs": ([vp, i32, vp], ctypes.c_int),
         "mojette_decode_jobs": ([vp, i32, vp, vp], ctypes.c_int),
+        "mojette_plan_create": ([vp, i32, i32, i32, vp], ctypes.c_int),
+        "mojette_plan_destroy": ([vp], ctypes.c_int),
+        "mojette_chunk_matrix": ([vp, i32, i32, vp, vp, i64], i64),
+        "mojette_decode_chunked_workspace": ([vp, i32, i64], i64),
+        "mojette_decode_batch_chunked": ([vp, vp, vp, i64, i32, vp, vp, vp, vp], ctypes.c_int),
         "mojette_fill_splitmix64": ([vp, i64, u64, u64, vp], ctypes.c_int),
         "mojette_copy_words": ([vp, vp, i64, vp], ctypes.c_int),
     }
@@ -158,8 +163,9 @@ def exported_symbols() -> list[str]:
         "mojette_bin_offset", "mojette_block_words", "mojette_decode_ring", "mojette_encode",
         "mojette_decode", "mojette_encode_batch", "mojette_decode_batch",
         "mojette_classes_layout", "mojette_encode_classes", "mojette_decode_classes",
-        "mojette_encode_jobs", "mojette_decode_jobs", "mojette_fill_splitmix64",
-        "mojette_copy_words",
+        "mojette_encode_jobs", "mojette_decode_jobs", "mojette_plan_create",
+        "mojette_plan_destroy", "mojette_chunk_matrix", "mojette_decode_chunked_workspace",
+        "mojette_decode_batch_chunked", "mojette_fill_splitmix64", "mojette_copy_words",
     ]
 
 
@@ -315,6 +321,79 @@ def mojette_decode_jobs(jobs, status=None, stream=None, check: bool = True) -> i
         raise ValueError("status must be int32")
     rc = lib().mojette_decode_jobs(arr, n, _dev_ptr(status, "status"), _stream(stream))
     return _check(rc, "mojette_decode_jobs", check)
+
+
+class Plan:
+    """``mojette_plan``: transfer matrices of the chunked decode for one code
+    (directions, Q) and one chunk length.  Creating it allocates device memory
+    and synchronises; ``close()`` (or garbage collection) frees it."""
+
+    def __init__(self, dirs, Q: int, chunk_cols: int):
+        arr, n = _i32_array(dirs)
+        h = ctypes.c_void_p(0)
+        rc = lib().mojette_plan_create(arr, n, Q, chunk_cols, ctypes.addressof(h))
+        _check(rc, "mojette_plan_create", True)
+        self.handle = h.value
+        self.dirs, self.Q, self.chunk_cols = [int(p) for p in dirs], int(Q), int(chunk_cols)
+
+    def close(self) -> None:
+        if self.handle:
+            lib().mojette_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace_words(self, P: int, nblocks: int) -> int:
+        return int(lib().mojette_decode_chunked_workspace(self.handle, P, nblocks))
+
+
+mojette_plan_create = Plan
+
+
+def mojette_chunk_matrix(p_sorted, Q: int, chunk_cols: int):
+    """(E, matrix rows as a (Q*E, ceil(Q*E/64)) uint64 array) of one survivor set."""
+    import numpy as np
+
+    arr, _ = _i32_array(p_sorted)
+    E = ctypes.c_int32(0)
+    need = int(lib().mojette_chunk_matrix(arr, Q, chunk_cols, ctypes.addressof(E), None, 0))
+    if need < 0:
+        raise MojetteError(MOJETTE_EINVAL if need == -1 else MOJETTE_ENOTSUP,
+                           "mojette_chunk_matrix")
+    rows = np.zeros(max(1, need), dtype=np.uint64)
+    lib().mojette_chunk_matrix(arr, Q, chunk_cols, ctypes.addressof(E), rows.ctypes.data, need)
+    d = Q * E.value
+    rw = (d + 63) // 64
+    return E.value, rows[:need].reshape(d, rw) if d else rows[:0].reshape(0, 0)
+
+
+def mojette_decode_chunked_workspace(plan: Plan, P: int, nblocks: int) -> int:
+    return plan.workspace_words(P, nblocks)
+
+
+def mojette_decode_batch_chunked(plan: Plan, projs, erased, nblocks: int, P: int, images,
+                                 workspace, status=None, stream=None, check: bool = True) -> int:
+    import torch
+
+    if erased is not None and erased.dtype not in (torch.int16, torch.uint16):
+        raise ValueError("erased must be 16-bit masks")
+    if status is not None and status.dtype != torch.int32:
+        raise ValueError("status must be int32")
+    need = plan.workspace_words(P, nblocks)
+    ws = 0
+    if need > 0:
+        if workspace is None or workspace.numel() < need:
+            raise ValueError(f"workspace must hold {need} words")
+        ws = _word_tensor(workspace, "workspace")
+    rc = lib().mojette_decode_batch_chunked(plan.handle, _word_tensor(projs, "projs"),
+                                            _dev_ptr(erased, "erased"), nblocks, P,
+                                            _word_tensor(images, "images"),
+                                            _dev_ptr(status, "status"), ws, _stream(stream))
+    return _check(rc, "mojette_decode_batch_chunked", check)
 
 
 def mojette_fill_splitmix64(dst, nwords: int, seed: int, start: int = 0, stream=None,

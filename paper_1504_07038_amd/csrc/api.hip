@@ -1,9 +1,11 @@
 // C-ABI entry points: argument checking, per-geometry launch parameters and
-// kernel launches.  Nothing here allocates device memory or synchronises.
+// kernel launches.  Only the plan calls of the chunked decode allocate device
+// memory or synchronise; every other call does neither.
 #include <algorithm>
 #include <cstdlib>
 #include <map>
 #include <mutex>
+#include <new>
 #include <vector>
 
 #include "mj_internal.h"
@@ -299,8 +301,9 @@ int mojette_decode(const uint64_t *const *proj, const int32_t *proj_ids, int32_t
     a.mask_uniform = ~have & ((1u << n) - 1u);
     a.status = nullptr;
     a.nblocks = 1;
+    a.nb = 1;   // one block: one slot
     clear_stale_error();
-    return status_of(mj::launch_decode(Q, false, a, 1, (hipStream_t)stream));
+    return status_of(mj::launch_decode(Q, mj::kLaunchPointers, a, 1, (hipStream_t)stream));
 }
 
 int mojette_decode_batch(const uint64_t *projs, const uint16_t *erased, int64_t nblocks,
@@ -333,7 +336,192 @@ int mojette_decode_batch(const uint64_t *projs, const uint16_t *erased, int64_t 
     const int64_t batches = (nblocks + a.nb - 1) / a.nb;
     const int grid = (int)std::min<int64_t>(batches, kDecodeGridCap);
     clear_stale_error();
-    return status_of(mj::launch_decode(Q, true, a, grid, (hipStream_t)stream));
+    return status_of(mj::launch_decode(Q, mj::kLaunchPool, a, grid, (hipStream_t)stream));
+}
+
+// ---- chunked decode of long rows -------------------------------------------
+
+struct mojette_plan {
+    int32_t n, Q, tiles, max_cols, R, nsets;
+    int32_t dirs[MOJETTE_MAX_DIRS];
+    int32_t *lut;            // device, 2^n entries
+    int32_t *state_cols;     // device, per set
+    int64_t *tmat_off;       // device, per set
+    uint64_t *tmat;          // device
+};
+
+static void plan_free(mojette_plan *pl) {
+    if (!pl) return;
+    if (pl->lut) (void)hipFree(pl->lut);
+    if (pl->state_cols) (void)hipFree(pl->state_cols);
+    if (pl->tmat_off) (void)hipFree(pl->tmat_off);
+    if (pl->tmat) (void)hipFree(pl->tmat);
+    delete pl;
+}
+
+int mojette_plan_create(const int32_t *dirs, int32_t n, int32_t Q, int32_t chunk_cols,
+                        mojette_plan **plan) {
+    if (!plan) return MOJETTE_EINVAL;
+    *plan = nullptr;
+    if (!geometry_ok(dirs, n, 1, Q) || n < Q || chunk_cols < 1) return MOJETTE_EINVAL;
+    const int TW = mj::kDecodeTile;
+    const int tiles = (chunk_cols + TW - 1) / TW;
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::sort(order.begin(), order.end(), [&](int x, int y) { return dirs[x] < dirs[y]; });
+    std::vector<int> sp(n);
+    for (int i = 0; i < n; ++i) sp[i] = dirs[order[i]];
+    std::vector<int32_t> lut((size_t)1 << n, -1), cols;
+    std::vector<int64_t> toff;
+    std::vector<uint64_t> tmat;
+    std::vector<int> pick(Q);
+    for (int i = 0; i < Q; ++i) pick[i] = i;
+    int max_cols = 0;
+    while (true) {
+        int32_t ps[MOJETTE_MAX_ROWS];
+        uint32_t used = 0;
+        for (int r = 0; r < Q; ++r) {
+            ps[r] = sp[pick[r]];
+            used |= 1u << order[pick[r]];
+        }
+        int E = 0;
+        std::vector<uint64_t> T;
+        if (!mj::chunk_transfer(ps, Q, tiles, E, T)) return MOJETTE_ENOTSUP;
+        lut[used] = (int32_t)cols.size();
+        cols.push_back(E);
+        toff.push_back((int64_t)tmat.size());
+        tmat.insert(tmat.end(), T.begin(), T.end());
+        max_cols = std::max(max_cols, E);
+        int i = Q - 1;
+        while (i >= 0 && pick[i] == n - Q + i) --i;
+        if (i < 0) break;
+        ++pick[i];
+        for (int j = i + 1; j < Q; ++j) pick[j] = pick[j - 1] + 1;
+    }
+    if (Q * max_cols > mj::kCarryMaxState) return MOJETTE_ENOTSUP;
+    int R = ring_length(sp, Q);
+    if (R < 0) return MOJETTE_EINVAL;
+    while (R < max_cols + TW) R <<= 1;   // a chunk's start state and its first tile of bins
+    if (tmat.empty()) tmat.push_back(0);
+    auto *pl = new (std::nothrow) mojette_plan{};
+    if (!pl) return MOJETTE_ENOMEM;
+    pl->n = n;
+    pl->Q = Q;
+    pl->tiles = tiles;
+    pl->max_cols = max_cols;
+    pl->R = R;
+    pl->nsets = (int32_t)cols.size();
+    for (int i = 0; i < n; ++i) pl->dirs[i] = dirs[i];
+    hipError_t e = hipSuccess;
+    auto up = [&](void **dst, const void *src, size_t bytes) {
+        if (e != hipSuccess) return;
+        e = hipMalloc(dst, bytes);
+        if (e == hipSuccess) e = hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
+    };
+    up((void **)&pl->lut, lut.data(), lut.size() * sizeof(int32_t));
+    up((void **)&pl->state_cols, cols.data(), cols.size() * sizeof(int32_t));
+    up((void **)&pl->tmat_off, toff.data(), toff.size() * sizeof(int64_t));
+    up((void **)&pl->tmat, tmat.data(), tmat.size() * sizeof(uint64_t));
+    if (e != hipSuccess) {
+        mj::hip_status(e);
+        plan_free(pl);
+        return MOJETTE_EHIP;
+    }
+    *plan = pl;
+    return MOJETTE_OK;
+}
+
+int64_t mojette_chunk_matrix(const int32_t *p_sorted, int32_t Q, int32_t chunk_cols,
+                             int32_t *state_cols, uint64_t *rows, int64_t cap_words) {
+    if (!p_sorted || Q < 1 || Q > kMaxRows || chunk_cols < 1 || !state_cols) return -1;
+    for (int r = 0; r < Q; ++r) {
+        if (p_sorted[r] < -kMaxAbsP || p_sorted[r] > kMaxAbsP) return -1;
+        if (r > 0 && p_sorted[r] <= p_sorted[r - 1]) return -1;
+    }
+    const int tiles = (chunk_cols + mj::kDecodeTile - 1) / mj::kDecodeTile;
+    int E = 0;
+    std::vector<uint64_t> T;
+    if (!mj::chunk_transfer(p_sorted, Q, tiles, E, T)) return -2;
+    *state_cols = E;
+    if (rows && cap_words >= (int64_t)T.size()) std::copy(T.begin(), T.end(), rows);
+    return (int64_t)T.size();
+}
+
+int mojette_plan_destroy(mojette_plan *plan) {
+    plan_free(plan);
+    return MOJETTE_OK;
+}
+
+static int plan_chunks(const mojette_plan *pl, int32_t P) {
+    return std::max(1, (P / mj::kDecodeTile) / pl->tiles);
+}
+
+int64_t mojette_decode_chunked_workspace(const mojette_plan *plan, int32_t P, int64_t nblocks) {
+    if (!plan || P < 1 || P > kMaxP || nblocks < 0) return -1;
+    const int nchunks = plan_chunks(plan, P);
+    if (nchunks < 2) return 0;
+    return nblocks * (nchunks - 1) * (int64_t)plan->Q * plan->max_cols;
+}
+
+int mojette_decode_batch_chunked(const mojette_plan *plan, const uint64_t *projs,
+                                 const uint16_t *erased, int64_t nblocks, int32_t P,
+                                 uint64_t *images, int32_t *status, uint64_t *workspace,
+                                 void *stream) {
+    if (!plan || nblocks < 0 || P < 1 || P > kMaxP) return MOJETTE_EINVAL;
+    const int nchunks = plan_chunks(plan, P);
+    if (nchunks < 2)
+        return mojette_decode_batch(projs, erased, nblocks, P, plan->Q, plan->dirs, plan->n,
+                                    images, status, stream);
+    const int n = plan->n, Q = plan->Q;
+    if (!geometry_ok(plan->dirs, n, P, Q)) return MOJETTE_EINVAL;
+    if (nblocks == 0) return MOJETTE_OK;
+    if (!projs || !images || !workspace) return MOJETTE_EINVAL;
+    mj::DecodeArgs a{};
+    const int rc = decode_setup(plan->dirs, n, P, Q, a);
+    if (rc != MOJETTE_OK) return rc;
+    a.R = std::max(a.R, plan->R);
+    a.ring_stride = a.R + 1;
+    // chunks are plentiful: half-full waves keep the sweep's registers and
+    // LDS share small
+    a.nb = std::max(1, mj::decode_max_blocks_per_wave(Q) / 2);
+    while (a.nb > 0 && mj::decode_lds_bytes(Q, a.nb, a.ring_stride) > kLdsLimit) --a.nb;
+    if (a.nb < 1) return MOJETTE_ENOTSUP;
+    int64_t off = 0;
+    for (int i = 0; i < n; ++i) {
+        a.off[i] = (int32_t)off;
+        off += mojette_proj_size(plan->dirs[i], P, Q);
+    }
+    if ((int64_t)a.nb * off * 8 >= ((int64_t)1 << 31) ||
+        (int64_t)a.nb * P * Q * 8 >= ((int64_t)1 << 31))
+        return MOJETTE_ENOTSUP;
+    a.pool = projs;
+    a.proj_stride = off;
+    a.images = images;
+    a.img_stride = (int64_t)P * Q;
+    a.masks = erased;
+    a.mask_uniform = 0;
+    a.status = status;
+    a.nblocks = nblocks;
+    a.chunk.ws = workspace;
+    a.chunk.lut = plan->lut;
+    a.chunk.state_cols = plan->state_cols;
+    a.chunk.tmat_off = plan->tmat_off;
+    a.chunk.tmat = plan->tmat;
+    a.chunk.tiles = plan->tiles;
+    a.chunk.nchunks = nchunks;
+    a.chunk.max_cols = plan->max_cols;
+    const int64_t items = nblocks * (nchunks - 1);
+    const int grid = (int)std::min<int64_t>((items + a.nb - 1) / a.nb, kDecodeGridCap);
+    hipStream_t s = (hipStream_t)stream;
+    clear_stale_error();
+    int st = status_of(mj::launch_decode(Q, mj::kLaunchChunkA, a, grid, s));
+    if (st != MOJETTE_OK) return st;
+    if (nchunks > 2) {
+        st = status_of(mj::launch_decode_carry(
+            a, Q, (int)std::min<int64_t>(nblocks, kDecodeGridCap), s));
+        if (st != MOJETTE_OK) return st;
+    }
+    return status_of(mj::launch_decode(Q, mj::kLaunchChunkC, a, grid, s));
 }
 
 int mojette_classes_layout(const mojette_class *classes, int32_t nclasses, int64_t *image_words,

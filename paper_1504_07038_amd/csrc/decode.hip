@@ -45,6 +45,7 @@
 // (stores) or answers with zero (loads).  Every memory instruction is therefore issued
 // unconditionally, the compiler knows exactly how many are in flight, and
 // waiting for a tile's bins never waits for the stores issued after them.
+#include <algorithm>
 #include <climits>
 
 #include "mj_internal.h"
@@ -117,11 +118,25 @@ struct SegParam {
 // One batch of up to nb blocks of one geometry, swept by one wavefront.  `A`
 // supplies the geometry and buffers (`Args`: DecodeArgs for one pool or one block,
 // DecodeClass for one class of a mixed launch).
-template <int Q, int TW, bool POOL, class Args>
+//
+// CHUNK selects what a slot of the wave sweeps (the chunked decode of long
+// rows; the tiles of a block are cut into chunks of a.chunk.tiles tiles):
+//   kWhole   the whole block (every tile), from zeroed rings;
+//   kChunkA  chunk c of the first nchunks-1 chunks of a block, from zeroed
+//            rings; chunk 0 stores its image windows (its start state is the
+//            true one); every chunk saves its end state (the last E pixels
+//            of every row) to the workspace;
+//   kChunkC  chunk c >= 1, from its exact start state read from the
+//            workspace; stores its image windows.
+//
+// NBT is the most block slots the body is compiled for (a.nb <= NBT): the
+// full 64 / ceil(Q/2), or half of it when long rings leave LDS for no more,
+// which saves the registers of the unused row windows.
+template <int Q, int TW, bool POOL, int CHUNK, int NBT, class Args>
 __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch) {
     extern __shared__ uint64_t lds[];
     constexpr int LPB = (Q + 1) / 2;        // lanes per block
-    constexpr int NBMAX = kWave / LPB;      // blocks per wavefront at most
+    constexpr int NBMAX = NBT;              // blocks per wavefront at most
     constexpr int LPS = TW / 2;             // lanes per row window (two words each)
     constexpr int SPI = kWave / LPS;        // row windows per iteration
     constexpr int NIT = (NBMAX * Q + SPI - 1) / SPI;
@@ -132,6 +147,19 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch)
     const int j = lane - slot * LPB;
     const int NB = a.nb;
     const bool lane_used = slot < NB;
+    // Slot -> (block, chunk).  A wave's slots cover consecutive blocks
+    // [blk_lo, blk_hi]; `rel` is the slot's block relative to blk_lo.
+    int per = 1;                             // slots per block
+    if constexpr (CHUNK != kWhole) per = a.chunk.nchunks - 1;
+    const int64_t item = batch * NB + slot;
+    const int64_t blk = item / per;
+    int chunk = 0, shift = 0;                // chunk index, its first column offset
+    if constexpr (CHUNK != kWhole) {
+        chunk = (int)(item - blk * per) + (CHUNK == kChunkC ? 1 : 0);
+        shift = chunk * a.chunk.tiles * TW;
+    }
+    const int64_t blk_lo = batch * NB / per;
+    const int rel = (int)(blk - blk_lo);
     const int RS = a.ring_stride;
     const int SS = Q * RS + 1;              // words per block slot (odd)
     const int Rmask = a.R - 1;
@@ -142,7 +170,6 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch)
     const int QP = Q * P;
 
     {
-        const int64_t blk = batch * NB + slot;
         const bool blk_ok = lane_used && blk < a.nblocks;
         uint32_t mask = a.mask_uniform;
         if (blk_ok && a.masks) mask = a.masks[blk];
@@ -150,6 +177,7 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch)
         // Survivors in ascending p; row r takes the r-th.
         int p0 = 0, p1 = 0, id0 = 0, id1 = 0, A0 = 0, A1 = 0;
         int A_max = INT_MIN, A_min = INT_MAX, cnt = 0, psum = 0;
+        uint32_t used = 0;
         for (int s = 0; s < a.n; ++s) {
             const int id = a.id_sorted[s];
             const int p = a.p_sorted[s];
@@ -160,13 +188,21 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch)
                 A_max = max(A_max, A);
                 A_min = min(A_min, A);
                 psum += p;
+                used |= 1u << id;
                 ++cnt;
             }
         }
         bool valid = blk_ok;
         if (cnt < Q) {
-            if (blk_ok && j == 0 && a.status) a.status[0] = MOJETTE_ENOTRECON;
+            // reported once per block: by its whole sweep or its first chunk
+            if (blk_ok && j == 0 && a.status && (CHUNK == kWhole || (CHUNK == kChunkA && chunk == 0)))
+                a.status[0] = MOJETTE_ENOTRECON;
             valid = false;
+        }
+        // Chunked sweeps: the state width E of this survivor set.
+        int E = 0;
+        if constexpr (CHUNK != kWhole) {
+            if (valid) E = a.chunk.state_cols[a.chunk.lut[used]];
         }
         // Half-step of pixel (k, r) within the block: h = 2k - A_r + A_max.
         // Rows with (r & 1) == (A_max & 1) have even h (row X of a lane),
@@ -177,7 +213,23 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch)
         // block is done once its rows have stored the window of column P-1.
         const int par = A_max & 1;
         const int dmin = valid ? -((A_max - A_min) >> 1) : 0;
-        const int ntiles = valid ? (P - 1) / TW + (-dmin + TW - 1) / TW + 1 : 0;
+        const int ntiles_all = valid ? (P - 1) / TW + (-dmin + TW - 1) / TW + 1 : 0;
+        int ntiles = ntiles_all;                 // tiles this slot sweeps
+        // Chunked sweeps store a window at local tile t < a.chunk.tiles when
+        // bit `it` of store_in is set, at later tiles when bit `it` of
+        // store_past is: the first sweep stores chunk 0 only, the final
+        // sweep every chunk, the last one through its end.
+        int first_last = 0;                      // this slot's chunk is the first (1), last (2)
+        if constexpr (CHUNK == kChunkA) {
+            ntiles = valid ? a.chunk.tiles : 0;
+            first_last = chunk == 0 ? 1 : 0;
+        } else if constexpr (CHUNK == kChunkC) {
+            const int first_tile = chunk * a.chunk.tiles;
+            ntiles = !valid ? 0
+                     : chunk < a.chunk.nchunks - 1 ? a.chunk.tiles
+                                                   : ntiles_all - first_tile;
+            first_last = chunk == a.chunk.nchunks - 1 ? 2 : 0;
+        }
         const int ntiles_wave = wave_max(ntiles);
 
         RowState<Q> X, Y;
@@ -206,13 +258,14 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch)
         }
 
         // Per-iteration row windows, from the lanes that own their rows.
+        const int dr0 = r0_is_x ? X.d : Y.d;     // first column of tile 0, unshifted
+        const int dr1 = r0_is_x ? Y.d : X.d;
         SegParam sp[NIT];
+        uint32_t store_in = 0, store_past = 0;   // chunked sweeps: see first_last
         {
-            const int dr0 = r0_is_x ? X.d : Y.d;
-            const int dr1 = r0_is_x ? Y.d : X.d;
             // pool mode: word offset of column 0's bin within the wave's slice
-            const int g0 = POOL ? slot * (int)a.proj_stride + a.off[id0] + jb0 : jb0;
-            const int g1 = POOL ? slot * (int)a.proj_stride + a.off[id1] + jb1 : jb1;
+            const int g0 = POOL ? rel * (int)a.proj_stride + a.off[id0] + jb0 : jb0;
+            const int g1 = POOL ? rel * (int)a.proj_stride + a.off[id1] + jb1 : jb1;
             const int own0 = valid ? dr0 : INT_MIN;
             const int own1 = valid ? dr1 : INT_MIN;
             // pointer mode: the projections of this lane's two rows
@@ -232,6 +285,15 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch)
                 const int src = owner < kWave ? owner : 0;
                 const int od0 = __shfl(own0, src), od1 = __shfl(own1, src);
                 const int og0 = __shfl(g0, src), og1 = __shfl(g1, src);
+                int orel = sslot, oshift = 0;   // whole blocks: slot = block
+                if constexpr (CHUNK != kWhole) {
+                    orel = __shfl(rel, src);
+                    oshift = __shfl(shift, src);
+                    const int ofl = __shfl(first_last, src);
+                    const bool in = CHUNK == kChunkC || (ofl & 1);
+                    store_in |= (uint32_t)in << it;
+                    store_past |= (uint32_t)((ofl >> 1) & 1) << it;
+                }
                 const bool odd = srow & 1;
                 const int sd = odd ? od1 : od0;
                 SegParam &s = sp[it];
@@ -249,16 +311,21 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch)
                     s.bins = (const uint64_t *)(odd ? (((uint64_t)hi1 << 32) | lo1)
                                                     : (((uint64_t)hi0 << 32) | lo0));
                 }
-                s.col0 = dd + TW - 1 - 2 * q;
+                s.col0 = dd + TW - 1 - 2 * q + oshift;
                 const int L = (-dd + TW - 1) / TW;
-                s.scol0 = -TW * L + 2 * q;
-                s.img = sslot * QP + srow * P;
+                s.scol0 = -TW * L + 2 * q + oshift;
+                s.img = orel * QP + srow * P;
             }
         }
 
+        // The sweep of a chunk starts `shift` columns in.
+        X.d += shift;
+        Y.d += shift;
+
         // Buffer descriptors of this wave's pool and image slices.
-        const int64_t first = batch * NB;
-        const int64_t nblk = min((int64_t)NB, a.nblocks - first);
+        const int64_t first = blk_lo;
+        const int64_t blk_hi = min(a.nblocks, (batch * NB + NB + per - 1) / per);
+        const int64_t nblk = blk_hi - first;
         __amdgpu_buffer_rsrc_t rin, rout;
         if constexpr (POOL) {
             rin = __builtin_amdgcn_make_buffer_rsrc(
@@ -315,8 +382,11 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch)
                 const int c = t * TW + s.scol0;
                 const uint64_t *row = lds + s.ring;
                 const uint64_t w0 = row[c & Rmask], w1 = row[(c + 1) & Rmask];
-                const bool both = s.on && c >= 0 && c + 1 < P;
-                const bool last = s.on && c == P - 1;
+                bool in_chunk = true;
+                if constexpr (CHUNK != kWhole)
+                    in_chunk = ((t < a.chunk.tiles ? store_in : store_past) >> it) & 1u;
+                const bool both = s.on && in_chunk && c >= 0 && c + 1 < P;
+                const bool last = s.on && in_chunk && c == P - 1;
                 if constexpr (POOL) {
                     const uint32_t off2 = both ? (uint32_t)(s.img + c) * 8u : kOffNone;
                     const uint32_t off1 = last ? (uint32_t)(s.img + c) * 8u : kOffNone;
@@ -343,6 +413,18 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch)
             for (int c = 0; c < a.R; ++c) {
                 if (r0 < Q) slot_base[r0 * RS + c] = 0;
                 if (r1 < Q) slot_base[r1 * RS + c] = 0;
+            }
+        }
+        // A chunk after the first starts from the exact state left by the
+        // chunks before it: the last E pixels of every row.
+        if constexpr (CHUNK == kChunkC) {
+            if (valid) {
+                const uint64_t *st =
+                    a.chunk.ws + (blk * per + (chunk - 1)) * (int64_t)(Q * a.chunk.max_cols);
+                for (int e = 0; e < E; ++e) {
+                    if (r0 < Q) slot_base[r0 * RS + ((shift + dr0 - E + e) & Rmask)] = st[r0 * E + e];
+                    if (r1 < Q) slot_base[r1 * RS + ((shift + dr1 - E + e) & Rmask)] = st[r1 * E + e];
+                }
             }
         }
         u32x4 buf[NIT];
@@ -373,14 +455,29 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch)
             load_tile(t + 2, buf);
             wave_sync();
         }
+        // The end state of a chunk: the last E pixels of every row.
+        if constexpr (CHUNK == kChunkA) {
+            if (valid) {
+                uint64_t *st = a.chunk.ws + (blk * per + chunk) * (int64_t)(Q * a.chunk.max_cols);
+                const int end = shift + a.chunk.tiles * TW;
+                for (int e = 0; e < E; ++e) {
+                    if (r0 < Q) st[r0 * E + e] = slot_base[r0 * RS + ((end + dr0 - E + e) & Rmask)];
+                    if (r1 < Q) st[r1 * E + e] = slot_base[r1 * RS + ((end + dr1 - E + e) & Rmask)];
+                }
+            }
+        }
     }
 }
 
-template <int Q, int TW, bool POOL>
+template <int Q>
+constexpr int full_slots() { return kWave / ((Q + 1) / 2); }
+
+template <int Q, int TW, bool POOL, int CHUNK, int NBT>
 __global__ __launch_bounds__(kWave) void decode_kernel(DecodeArgs a) {
-    const int64_t nbatches = (a.nblocks + a.nb - 1) / a.nb;
+    const int64_t per = CHUNK == kWhole ? 1 : a.chunk.nchunks - 1;
+    const int64_t nbatches = (a.nblocks * per + a.nb - 1) / a.nb;
     for (int64_t batch = blockIdx.x; batch < nbatches; batch += gridDim.x)
-        decode_batch<Q, TW, POOL>(a, batch);
+        decode_batch<Q, TW, POOL, CHUNK, NBT>(a, batch);
 }
 
 // A mixed launch: batches of every class, in the order of the class table
@@ -398,7 +495,8 @@ __global__ __launch_bounds__(kWave) void decode_classes_kernel(DecodeClassTable 
         switch (a.Q) {
 #define MJ_DEC_CASE(QQ)                                                                  \
     case QQ:                                                                             \
-        if constexpr ((QMASK >> QQ) & 1u) decode_batch<QQ, kDecodeTile, !GATHER>(a, batch); \
+        if constexpr ((QMASK >> QQ) & 1u)                                               \
+            decode_batch<QQ, kDecodeTile, !GATHER, kWhole, full_slots<QQ>()>(a, batch);   \
         break;
             MJ_DEC_CASE(1) MJ_DEC_CASE(2) MJ_DEC_CASE(3) MJ_DEC_CASE(4)
             MJ_DEC_CASE(5) MJ_DEC_CASE(6) MJ_DEC_CASE(7) MJ_DEC_CASE(8)
@@ -408,6 +506,150 @@ __global__ __launch_bounds__(kWave) void decode_classes_kernel(DecodeClassTable 
             default: break;
         }
     }
+}
+
+// Carry pass of the chunked decode.  For every block, with y_c the end state
+// of chunk c swept from a zero start (saved by the first sweep) and T the
+// transfer matrix of the block's survivor set, the exact start state of
+// chunk c+1 is z_{c+1} = T z_c XOR y_c, z_1 = y_0 (chunk 0 starts from the
+// true, all-zero state).  z_{c+1} overwrites y_c in place.
+//
+// One workgroup per block, up to kCarryWaves wavefronts.  A product T z is
+// taken four state words at a time (the "four Russians" method of Arlazarov,
+// Dinic, Kronrod and Faradzev): for every group g of words 4g..4g+3 of z the
+// 16 XOR combinations are tabulated in LDS, and output word i is the XOR over
+// g of the entry that row i's 4-bit slice of T selects, so an output costs
+// Q*E/4 independent LDS lookups.  Tables are built over as many groups at a
+// time as fit in kCarryTableWords.
+constexpr int kCarryWaves = 8;
+constexpr int kCarryTableWords = 5888;   // 46 KB of tables (a multiple of 256); z up to 16 KB
+constexpr int kCarryOutPerThread = kCarryMaxState / (kWave * kCarryWaves);
+constexpr int kCarryAhead = 4;           // chunks whose end states are loaded ahead
+
+// RWC > 0: every thread owns at most one output word and keeps its matrix row
+// (RW <= RWC words) in registers for all chunks; RWC == 0: rows are read from
+// memory at every chunk.
+template <int RWC>
+__global__ __launch_bounds__(kWave * kCarryWaves) void decode_carry_kernel(DecodeArgs a, int Q) {
+    extern __shared__ uint64_t lds_carry[];
+    constexpr int OPT = RWC > 0 ? 1 : kCarryOutPerThread;   // outputs per thread
+    const int tid = threadIdx.x;
+    const int nthreads = blockDim.x;
+    const int per = a.chunk.nchunks - 1;
+    const int64_t stride = (int64_t)Q * a.chunk.max_cols;
+    const int64_t zwords = stride + 4;                // z, zero past the state
+    uint64_t *z = lds_carry;
+    uint64_t *tab = lds_carry + zwords;               // kCarryTableWords words
+    for (int64_t blk = blockIdx.x; blk < a.nblocks; blk += gridDim.x) {
+        const uint32_t mask = a.masks ? a.masks[blk] : a.mask_uniform;
+        uint32_t used = 0;
+        int cnt = 0;
+        for (int s = 0; s < a.n; ++s) {
+            const int id = a.id_sorted[s];
+            if (!((mask >> id) & 1u) && cnt < Q) {
+                used |= 1u << id;
+                ++cnt;
+            }
+        }
+        if (cnt < Q) continue;   // undecodable: reported by the sweep (uniform per block)
+        const int set = a.chunk.lut[used];
+        const int d = Q * a.chunk.state_cols[set];
+        const int RW = (d + 63) / 64;
+        const int G = (d + 3) / 4;                    // 4-word groups
+        const int GP = kCarryTableWords / 16;         // groups per table pass
+        const uint64_t *T = a.chunk.tmat + a.chunk.tmat_off[set];
+        uint64_t *ws = a.chunk.ws + blk * per * stride;
+        uint64_t trow[RWC > 0 ? RWC : 1];
+        if constexpr (RWC > 0) {
+#pragma unroll
+            for (int w = 0; w < RWC; ++w) trow[w] = (tid < d && w < RW) ? T[(int64_t)tid * RW + w] : 0;
+        }
+        for (int i = tid; i < zwords; i += nthreads) z[i] = i < d ? ws[i] : 0;
+        // y_c of the next kCarryAhead chunks, loaded ahead of their step
+        uint64_t yq[kCarryAhead][OPT];
+#pragma unroll
+        for (int k = 0; k < kCarryAhead; ++k)
+#pragma unroll
+            for (int u = 0; u < OPT; ++u) {
+                const int i = tid + nthreads * u;
+                yq[k][u] = (i < d && 1 + k < per) ? ws[(1 + k) * stride + i] : 0;
+            }
+        __syncthreads();
+        for (int c = 1; c < per; ++c) {
+            uint64_t *y = ws + c * stride;
+            uint64_t acc[OPT];
+#pragma unroll
+            for (int u = 0; u < OPT; ++u) {
+                const int i = tid + nthreads * u;
+                acc[u] = yq[0][u];
+#pragma unroll
+                for (int k = 0; k + 1 < kCarryAhead; ++k) yq[k][u] = yq[k + 1][u];
+                yq[kCarryAhead - 1][u] =
+                    (i < d && c + kCarryAhead < per) ? ws[(c + kCarryAhead) * stride + i] : 0;
+            }
+            for (int g0 = 0; g0 < G; g0 += GP) {
+                const int g1 = min(G, g0 + GP);
+                for (int e = tid; e < (g1 - g0) * 16; e += nthreads) {
+                    const int g = g0 + (e >> 4), m = e & 15;
+                    uint64_t v = 0;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k)
+                        if ((m >> k) & 1) v ^= z[4 * g + k];
+                    tab[e] = v;
+                }
+                __syncthreads();
+                if constexpr (RWC > 0) {
+                    // one pass covers every group (RWC * 16 <= GP)
+                    if (tid < d) {
+#pragma unroll
+                        for (int w = 0; w < RWC; ++w) {
+                            if (w >= RW) break;
+                            const uint64_t bits = trow[w];
+                            const int gn = min(16, G - 16 * w);
+                            for (int q = 0; q < gn; ++q)
+                                acc[0] ^= tab[((16 * w + q) << 4) | (int)((bits >> (4 * q)) & 15)];
+                        }
+                    }
+                } else {
+#pragma unroll
+                    for (int u = 0; u < OPT; ++u) {
+                        const int i = tid + nthreads * u;
+                        if (i >= d) continue;
+                        const uint64_t *row = T + (int64_t)i * RW;
+                        for (int g = g0; g < g1; g += 16) {    // one matrix word: 16 groups
+                            const uint64_t bits = row[g >> 4];
+                            const int gn = min(16, g1 - g);
+                            for (int q = 0; q < gn; ++q)
+                                acc[u] ^= tab[((g - g0 + q) << 4) | (int)((bits >> (4 * q)) & 15)];
+                        }
+                    }
+                }
+                __syncthreads();   // tables are rebuilt or z is overwritten next
+            }
+#pragma unroll
+            for (int u = 0; u < OPT; ++u) {
+                const int i = tid + nthreads * u;
+                if (i < d) {
+                    z[i] = acc[u];
+                    y[i] = acc[u];
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+hipError_t launch_decode_carry(const DecodeArgs &a, int Q, int grid, hipStream_t s) {
+    const int state = Q * a.chunk.max_cols;
+    if (state > kCarryMaxState) return hipErrorInvalidValue;
+    const int waves = std::min(kCarryWaves, std::max(1, (state + kWave - 1) / kWave));
+    const size_t lds = ((size_t)state + 4 + kCarryTableWords) * sizeof(uint64_t);
+    // rows cached in registers while one thread per output word suffices
+    if (state <= kWave * kCarryWaves && state <= 8 * 64)
+        hipLaunchKernelGGL(decode_carry_kernel<8>, dim3(grid), dim3(kWave * waves), lds, s, a, Q);
+    else
+        hipLaunchKernelGGL(decode_carry_kernel<0>, dim3(grid), dim3(kWave * waves), lds, s, a, Q);
+    return hipGetLastError();
 }
 
 constexpr unsigned qbit(int q) { return 1u << q; }
@@ -482,36 +724,58 @@ size_t decode_lds_bytes(int Q, int nb, int ring_stride) {
 
 int decode_max_blocks_per_wave(int Q) { return kWave / ((Q + 1) / 2); }
 
-template <int Q>
-static hipError_t launch_q(bool pool, const DecodeArgs &a, int grid, hipStream_t s) {
+template <int Q, int NBT>
+static hipError_t launch_qn(int mode, const DecodeArgs &a, int grid, hipStream_t s) {
     const size_t lds = decode_lds_bytes(Q, a.nb, a.ring_stride);
-    if (pool)
-        hipLaunchKernelGGL((decode_kernel<Q, kDecodeTile, true>), dim3(grid), dim3(kWave), lds, s,
-                           a);
-    else
-        hipLaunchKernelGGL((decode_kernel<Q, kDecodeTile, false>), dim3(grid), dim3(kWave), lds, s,
-                           a);
+    switch (mode) {
+        case kLaunchPool:
+            hipLaunchKernelGGL((decode_kernel<Q, kDecodeTile, true, kWhole, NBT>), dim3(grid),
+                               dim3(kWave), lds, s, a);
+            break;
+        case kLaunchPointers:
+            hipLaunchKernelGGL((decode_kernel<Q, kDecodeTile, false, kWhole, NBT>), dim3(grid),
+                               dim3(kWave), lds, s, a);
+            break;
+        case kLaunchChunkA:
+            hipLaunchKernelGGL((decode_kernel<Q, kDecodeTile, true, kChunkA, NBT>), dim3(grid),
+                               dim3(kWave), lds, s, a);
+            break;
+        case kLaunchChunkC:
+            hipLaunchKernelGGL((decode_kernel<Q, kDecodeTile, true, kChunkC, NBT>), dim3(grid),
+                               dim3(kWave), lds, s, a);
+            break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_decode(int Q, bool pool, const DecodeArgs &a, int grid, hipStream_t s) {
+// The body compiled for half the slots serves launches whose LDS allows no
+// more (one block alone in pointer mode included).
+template <int Q>
+static hipError_t launch_q(int mode, const DecodeArgs &a, int grid, hipStream_t s) {
+    constexpr int full = full_slots<Q>();
+    if (full >= 2 && a.nb <= full / 2) return launch_qn<Q, (full >= 2 ? full / 2 : 1)>(mode, a, grid, s);
+    return launch_qn<Q, full>(mode, a, grid, s);
+}
+
+hipError_t launch_decode(int Q, int mode, const DecodeArgs &a, int grid, hipStream_t s) {
     switch (Q) {
-        case 1: return launch_q<1>(pool, a, grid, s);
-        case 2: return launch_q<2>(pool, a, grid, s);
-        case 3: return launch_q<3>(pool, a, grid, s);
-        case 4: return launch_q<4>(pool, a, grid, s);
-        case 5: return launch_q<5>(pool, a, grid, s);
-        case 6: return launch_q<6>(pool, a, grid, s);
-        case 7: return launch_q<7>(pool, a, grid, s);
-        case 8: return launch_q<8>(pool, a, grid, s);
-        case 9: return launch_q<9>(pool, a, grid, s);
-        case 10: return launch_q<10>(pool, a, grid, s);
-        case 11: return launch_q<11>(pool, a, grid, s);
-        case 12: return launch_q<12>(pool, a, grid, s);
-        case 13: return launch_q<13>(pool, a, grid, s);
-        case 14: return launch_q<14>(pool, a, grid, s);
-        case 15: return launch_q<15>(pool, a, grid, s);
-        case 16: return launch_q<16>(pool, a, grid, s);
+        case 1: return launch_q<1>(mode, a, grid, s);
+        case 2: return launch_q<2>(mode, a, grid, s);
+        case 3: return launch_q<3>(mode, a, grid, s);
+        case 4: return launch_q<4>(mode, a, grid, s);
+        case 5: return launch_q<5>(mode, a, grid, s);
+        case 6: return launch_q<6>(mode, a, grid, s);
+        case 7: return launch_q<7>(mode, a, grid, s);
+        case 8: return launch_q<8>(mode, a, grid, s);
+        case 9: return launch_q<9>(mode, a, grid, s);
+        case 10: return launch_q<10>(mode, a, grid, s);
+        case 11: return launch_q<11>(mode, a, grid, s);
+        case 12: return launch_q<12>(mode, a, grid, s);
+        case 13: return launch_q<13>(mode, a, grid, s);
+        case 14: return launch_q<14>(mode, a, grid, s);
+        case 15: return launch_q<15>(mode, a, grid, s);
+        case 16: return launch_q<16>(mode, a, grid, s);
         default: return hipErrorInvalidValue;
     }
 }

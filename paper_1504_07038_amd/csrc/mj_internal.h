@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "../../include/mojette.h"
 
 namespace mj {
@@ -85,6 +87,38 @@ struct EncodeClassTable {
 // directions (see decode.hip).  Each lane owns two rows of one block; a wave
 // holds up to 64/ceil(Q/2) blocks.  Each row keeps its last R pixels in an
 // LDS ring.
+// Chunked decode of long rows.  The tiles of a block are cut into nchunks
+// chunks of `tiles` tiles (the last one takes the rest).  Chunks 0..nchunks-2
+// are first swept from zeroed rings, each saving its end state (the last E
+// pixels of every row, E fixed by the survivor set); a carry pass turns those
+// into the exact start states of chunks 1..nchunks-1 with the GF(2) transfer
+// matrix of the survivor set; the chunks are then swept again from their
+// exact states.  The decode is linear over GF(2) (XOR), so a chunk's end
+// state is its end state from a zero start XOR the transfer matrix applied
+// to its true start state.
+constexpr int kWhole = 0;     // sweep whole blocks
+constexpr int kChunkA = 1;    // sweep chunks from zero states, save end states
+constexpr int kChunkC = 2;    // sweep chunks from exact start states
+
+constexpr int kCarryMaxState = 2048;   // most state words (Q * E) the carry pass handles
+
+struct ChunkInfo {
+    uint64_t *ws;                    // per (block, chunk boundary): Q * max_cols words
+    const int32_t *lut;              // survivor id mask -> set index (-1: none)
+    const int32_t *state_cols;       // per set: E
+    const int64_t *tmat_off;         // per set: word offset of its matrix in tmat
+    const uint64_t *tmat;            // per set: Q*E rows of ceil(Q*E/64) words
+    int32_t tiles;                   // tiles per chunk
+    int32_t nchunks;                 // chunks per block (>= 2 in chunked launches)
+    int32_t max_cols;                // largest E over the sets
+};
+
+// Launch modes of launch_decode.
+constexpr int kLaunchPool = 0;       // whole blocks from a projection pool
+constexpr int kLaunchPointers = 1;   // one whole block from projection pointers
+constexpr int kLaunchChunkA = 2;     // pool, first chunk sweep
+constexpr int kLaunchChunkC = 3;     // pool, final chunk sweep
+
 struct DecodeArgs {
     // Pool mode (batches): block b's n projections start at word
     // b*proj_stride of `pool`, projection i at word off[i] of that slice.
@@ -104,6 +138,7 @@ struct DecodeArgs {
     int32_t nb;                      // blocks per wavefront (at most 64/ceil(Q/2), fewer if LDS is short)
     int32_t p_sorted[kMaxDirs];      // directions in ascending p
     int32_t id_sorted[kMaxDirs];     // their indices in the caller's dirs
+    ChunkInfo chunk;                 // chunked launches only
     __device__ const uint64_t *proj_base(int64_t, int id) const { return in[id]; }
 };
 
@@ -144,7 +179,12 @@ hipError_t launch_encode_classes(int qmax, const EncodeClassTable &tab, size_t l
 hipError_t launch_decode_classes(unsigned qmask, bool gather, const DecodeClassTable &tab,
                                  size_t lds, int grid, hipStream_t s);
 bool decode_classes_supported(unsigned qmask, bool gather);
-hipError_t launch_decode(int Q, bool pool, const DecodeArgs &a, int grid, hipStream_t s);
+hipError_t launch_decode(int Q, int mode, const DecodeArgs &a, int grid, hipStream_t s);
+// State width E and transfer matrix (Q*E rows of ceil(Q*E/64) words) of an
+// interior chunk of `tiles` tiles for the survivor directions ps[0..Q) in
+// ascending order.  False if chunks that short cannot be interior.
+bool chunk_transfer(const int32_t *ps, int Q, int tiles, int &E, std::vector<uint64_t> &T);
+hipError_t launch_decode_carry(const DecodeArgs &a, int Q, int grid, hipStream_t s);
 size_t decode_lds_bytes(int Q, int nb, int ring_stride);
 int decode_max_blocks_per_wave(int Q);
 int decode_tile(int Q);

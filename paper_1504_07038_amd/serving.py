@@ -307,15 +307,17 @@ class Server:
             out = st.out_ptr + ring * st.cap * st.geo.img_words * 8
             rl.append((c, k, out, self.d_stage_ptr + pos * 8, self.d_stage_ptr + (pos + k) * 8))
             pos += k + nw
+        begin = torch.cuda.Event(enable_timing=True)
         done = torch.cuda.Event(enable_timing=True)
         with torch.cuda.stream(self.stream):
+            begin.record(self.stream)
             self.d_stage[base:pos].copy_(self.h_stage[base:pos], non_blocking=True)
             if wl:
                 self._run_jobs("w", wl)
             if rl:
                 self._run_jobs("r", rl)
             done.record(self.stream)
-        return done, ring
+        return begin, done, ring
 
     # ---- the loop -----------------------------------------------------------
 
@@ -337,6 +339,7 @@ class Server:
         inflight = []
         seen = 0
         stats = {"iterations": 0, "max_queued": 0, "admitted": 0, "blocked_writes": 0}
+        gpu_ms = 0.0
         start = torch.cuda.Event(enable_timing=True)
         start.record(self.stream)
         start.synchronize()
@@ -344,8 +347,9 @@ class Server:
         while True:
             # retire finished iterations (the oldest regardless, if the window is full)
             while inflight and (len(inflight) >= self.depth or inflight[0][0].query()):
-                ev, ring, writes, reads = inflight.pop(0)
+                begin, ev, ring, writes, reads = inflight.pop(0)
                 ev.synchronize()
+                gpu_ms += begin.elapsed_time(ev)
                 self._retire(start.elapsed_time(ev) / 1e3, ring, writes, reads, done_t,
                              track, results)
             now = time.perf_counter() - t0
@@ -377,8 +381,7 @@ class Server:
                 heads[q] = h + k
                 stats["admitted"] += k
             if writes or reads:
-                ev, ring = self._launch(writes, reads, trace)
-                inflight.append((ev, ring, writes, reads))
+                inflight.append((*self._launch(writes, reads, trace), writes, reads))
                 stats["iterations"] += 1
             elif seen == N and not inflight and (heads == arrived).all():
                 break
@@ -390,6 +393,8 @@ class Server:
             if time.perf_counter() - t0 > max_wall:
                 raise RuntimeError("serving loop exceeded its wall-clock limit")
         self.stream.synchronize()
+        stats["gpu_busy_s"] = round(gpu_ms / 1e3, 4)
+        stats["wall_s"] = round(time.perf_counter() - t0, 4)
         return done_t, results, stats
 
     def _retire(self, t_done, ring, writes, reads, done_t, track, results) -> None:

@@ -1,0 +1,135 @@
+"""Chunked decode of long rows on the GPU: bit-identical to the oracle's
+decode and to the whole-block decode, for several codes, chunk lengths,
+erasure patterns and 1 MB blocks; undecodable blocks; graph replay."""
+import numpy as np
+import pytest
+
+import synth
+from tests.gpuutil import masks_to_dev, say, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+POISON = np.uint64(0xDEADBEEFCAFEF00D)
+
+
+@pytest.fixture(scope="module")
+def mj():
+    import paper_1504_07038_amd as mj
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    mj.lib()
+    return mj
+
+
+def poisoned(orc, enc, masks, P, Q, dirs):
+    src = enc.copy()
+    sizes = np.cumsum([0] + [orc.proj_size(p, 1, P, Q) for p in dirs])
+    for i in range(len(dirs)):
+        rows = np.flatnonzero((masks >> i) & 1)
+        src[rows, sizes[i]:sizes[i + 1]] = POISON
+    return src
+
+
+CASES = [
+    # (P, Q, dirs, nblocks, chunk_cols)
+    (2000, 4, synth.centered_dirs(6), 24, 64),
+    (2000, 4, synth.centered_dirs(6), 24, 256),
+    (4096, 8, synth.centered_dirs(12), 12, 128),
+    (1531, 6, synth.centered_dirs(9), 10, 96),
+    (777, 2, [5, -1, 3], 40, 32),
+    (3000, 12, list(range(-8, 8)), 4, 512),
+    (32768, 4, synth.centered_dirs(6), 3, 512),     # 1 MB blocks of the (4,2) code
+    (16384, 8, synth.centered_dirs(12), 2, 1024),   # 1 MB blocks of the (8,4) code
+]
+
+
+@pytest.mark.parametrize("P,Q,dirs,nb,cols", CASES)
+def test_chunked_decode_matches_oracle(mj, orc, P, Q, dirs, nb, cols):
+    n = len(dirs)
+    say(f"chunked: P={P} Q={Q} n={n} blocks={nb} chunk={cols}")
+    imgs = synth.block_images(31 + P, 0, nb, P, Q)
+    masks = synth.erasure_masks(41 + P, nb, n, (0, n - Q))
+    enc = orc.encode_blocks(imgs, P, Q, dirs)
+    src = poisoned(orc, enc, masks, P, Q, dirs)
+    plan = mj.Plan(dirs, Q, cols)
+    ws_words = plan.workspace_words(P, nb)
+    assert ws_words > 0
+    d_src, d_mask = to_dev(src), masks_to_dev(masks)
+    d_ws = torch.full((ws_words,), -1, dtype=torch.int64, device="cuda")
+    d_out = torch.full((nb * P * Q,), -1, dtype=torch.int64, device="cuda")
+    d_status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    mj.mojette_decode_batch_chunked(plan, d_src, d_mask, nb, P, d_out, d_ws, status=d_status)
+    torch.cuda.synchronize()
+    assert int(d_status.item()) == 0
+    got = to_np(d_out).reshape(nb, Q, P)
+    bad = [b for b in range(nb) if not np.array_equal(got[b], imgs[b])]
+    assert not bad, f"blocks {bad[:5]} differ"
+    # the whole-block decode gives the same words
+    d_whole = torch.full_like(d_out, -1)
+    mj.mojette_decode_batch(d_src, d_mask, nb, P, Q, dirs, d_whole)
+    torch.cuda.synchronize()
+    assert torch.equal(d_whole, d_out)
+    plan.close()
+
+
+def test_chunked_short_rows_fall_back_and_status(mj, orc):
+    dirs, Q = synth.centered_dirs(6), 4
+    plan = mj.Plan(dirs, Q, 256)
+    # too short to cut: no workspace, whole-block decode
+    P, nb = 200, 8
+    assert plan.workspace_words(P, nb) == 0
+    imgs = synth.block_images(5, 0, nb, P, Q)
+    enc = orc.encode_blocks(imgs, P, Q, dirs)
+    d_out = torch.empty(nb * P * Q, dtype=torch.int64, device="cuda")
+    mj.mojette_decode_batch_chunked(plan, to_dev(enc), None, nb, P, d_out, None)
+    torch.cuda.synchronize()
+    assert np.array_equal(to_np(d_out).reshape(nb, Q, P), imgs)
+    # undecodable blocks are reported and left unwritten
+    P, nb = 1600, 6
+    imgs = synth.block_images(6, 0, nb, P, Q)
+    enc = orc.encode_blocks(imgs, P, Q, dirs)
+    masks = synth.erasure_masks(7, nb, 6, 2)
+    masks[[1, 4]] = 0b000111          # three lost: not reconstructible
+    d_ws = torch.empty(plan.workspace_words(P, nb), dtype=torch.int64, device="cuda")
+    d_out = torch.full((nb * P * Q,), 7, dtype=torch.int64, device="cuda")
+    d_status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    mj.mojette_decode_batch_chunked(plan, to_dev(poisoned(orc, enc, masks, P, Q, dirs)),
+                                    masks_to_dev(masks), nb, P, d_out, d_ws, status=d_status)
+    torch.cuda.synchronize()
+    assert int(d_status.item()) == mj.MOJETTE_ENOTRECON
+    got = to_np(d_out).reshape(nb, Q, P)
+    for b in range(nb):
+        if b in (1, 4):
+            assert (got[b] == 7).all()
+        else:
+            assert np.array_equal(got[b], imgs[b]), b
+    plan.close()
+
+
+def test_chunked_decode_graph_replay(mj, orc):
+    dirs, Q, P, nb = synth.centered_dirs(6), 4, 4000, 16
+    plan = mj.Plan(dirs, Q, 128)
+    imgs = synth.block_images(9, 0, nb, P, Q)
+    masks = synth.erasure_masks(10, nb, 6, (0, 2))
+    enc = orc.encode_blocks(imgs, P, Q, dirs)
+    d_src, d_mask = to_dev(poisoned(orc, enc, masks, P, Q, dirs)), masks_to_dev(masks)
+    d_ws = torch.empty(plan.workspace_words(P, nb), dtype=torch.int64, device="cuda")
+    d_out = torch.empty(nb * P * Q, dtype=torch.int64, device="cuda")
+    s = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        mj.mojette_decode_batch_chunked(plan, d_src, d_mask, nb, P, d_out, d_ws, stream=s.cuda_stream)
+    s.synchronize()
+    with torch.cuda.graph(g, stream=s):
+        mj.mojette_decode_batch_chunked(plan, d_src, d_mask, nb, P, d_out, d_ws,
+                                        stream=s.cuda_stream)
+    for rep in range(3):
+        d_out.fill_(-1)
+        d_ws.fill_(-1)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(to_np(d_out).reshape(nb, Q, P), imgs), rep
+    plan.close()
