@@ -66,9 +66,11 @@ def pct(xs, q):
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for fn in ("encode.hip", "decode.hip", "mj_internal.h", "api.hip"):
-        with open(os.path.join(ROOT, "paper_1504_07038_amd", "csrc", fn), "rb") as fh:
-            h.update(fh.read())
+    csrc = os.path.join(ROOT, "paper_1504_07038_amd", "csrc")
+    for fn in sorted(os.listdir(csrc)):
+        if fn.endswith((".hip", ".h")):
+            with open(os.path.join(csrc, fn), "rb") as fh:
+                h.update(fn.encode() + fh.read())
     return h.hexdigest()[:16]
 
 

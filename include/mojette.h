@@ -177,9 +177,11 @@ int mojette_decode_classes(const mojette_class *classes, int32_t nclasses,
  *   erased   decode: device uint16 masks, one per block, or NULL.
  * Up to MOJETTE_MAX_CLASSES jobs run in one launch.  Decode launches with any
  * `slots` support row counts 2, 4, ..., 16 alone and the {4, 8} mix
- * (MOJETTE_ENOTSUP otherwise).  Same ownership, error and stream rules as the
+ * (MOJETTE_ENOTSUP otherwise); chunked jobs take any row count.  Same ownership, error and stream rules as the
  * batch calls; safe to record into a HIP graph.
  */
+typedef struct mojette_plan mojette_plan;   /* chunked decode, see below */
+
 typedef struct mojette_job {
     int32_t P, Q, n;
     int32_t dirs[MOJETTE_MAX_DIRS];
@@ -188,6 +190,12 @@ typedef struct mojette_job {
     uint64_t *projs;
     const int64_t *slots;
     const uint16_t *erased;
+    /* decode only, optional: with a plan for this code (same dirs and Q) and
+     * rows long enough to cut, the job's blocks are decoded in chunks (see
+     * mojette_decode_batch_chunked) in launches of their own on the same
+     * stream, using `workspace` (mojette_decode_chunked_workspace() words). */
+    const mojette_plan *plan;
+    uint64_t *workspace;
 } mojette_job;
 
 /* Forward transform (Section 2.1, Eq. 1) of every block of every job. */
@@ -214,8 +222,6 @@ int mojette_decode_jobs(const mojette_job *jobs, int32_t njobs, int32_t *status,
  * MOJETTE_ENOTSUP if chunks of that length are shorter than the decode's
  * own lead-in.  mojette_plan_destroy frees the plan (NULL is a no-op).
  */
-typedef struct mojette_plan mojette_plan;
-
 int mojette_plan_create(const int32_t *dirs, int32_t n, int32_t Q, int32_t chunk_cols,
                         mojette_plan **plan);
 int mojette_plan_destroy(mojette_plan *plan);

@@ -55,12 +55,14 @@ class MojetteJob(ctypes.Structure):
     _fields_ = [("P", ctypes.c_int32), ("Q", ctypes.c_int32), ("n", ctypes.c_int32),
                 ("dirs", ctypes.c_int32 * MAX_DIRS), ("nblocks", ctypes.c_int64),
                 ("images", ctypes.c_void_p), ("projs", ctypes.c_void_p),
-                ("slots", ctypes.c_void_p), ("erased", ctypes.c_void_p)]
+                ("slots", ctypes.c_void_p), ("erased", ctypes.c_void_p),
+                ("plan", ctypes.c_void_p), ("workspace", ctypes.c_void_p)]
 
 
 def make_jobs(jobs):
     """``jobs``: iterable of dicts with P, Q, dirs, nblocks, images, projs and
-    optional slots (int64 device tensor) and erased (int16 device tensor)."""
+    optional slots (int64 device tensor), erased (int16 device tensor), plan
+    (a ``Plan``) and workspace (int64 device tensor)."""
     jobs = list(jobs)
     arr = (MojetteJob * max(1, len(jobs)))()
     for c, j in enumerate(jobs):
@@ -78,6 +80,10 @@ def make_jobs(jobs):
                 raise ValueError("slots must be int64")
         a.slots = _dev_ptr(sl, "slots")
         a.erased = _dev_ptr(j.get("erased"), "erased")
+        plan = j.get("plan")
+        a.plan = plan.handle if plan is not None else None
+        ws = j.get("workspace")
+        a.workspace = _word_tensor(ws, "workspace") if ws is not None else None
     return arr, len(jobs)
 
 

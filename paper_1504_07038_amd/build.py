@@ -14,7 +14,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmojette.so")
-SOURCES = ["api.hip", "chunk.hip", "encode.hip", "decode.hip", "synth.hip"]
+SOURCES = ["api.hip", "chunk.hip", "encode.hip", "decode_single.hip", "decode_single_hi.hip",
+           "decode_classes.hip", "decode_chunks.hip", "synth.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

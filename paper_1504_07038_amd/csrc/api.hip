@@ -79,7 +79,7 @@ bool encode_tiling(const int32_t *dirs, int32_t n, int32_t P, int32_t Q, mj::Enc
 // every Q-subset of the directions, plus one, rounded up to a power of two
 // and to at least the tile width.  D = ceil((A_l - A_r)/2) - 1 - (l-r)p_r is
 // independent of k.  A negative D would mean a pixel is read before it is
-// written; the ordering argument in decode.hip rules that out, and this
+// written; the ordering argument in decode_body.h rules that out, and this
 // function re-checks it (returns -1 then).
 struct RingKey {
     std::vector<int> p;
@@ -463,6 +463,50 @@ int64_t mojette_decode_chunked_workspace(const mojette_plan *plan, int32_t P, in
     return nblocks * (nchunks - 1) * (int64_t)plan->Q * plan->max_cols;
 }
 
+// The three launches of a chunked decode of one geometry: `a` holds the
+// geometry and buffers (pool mode, or pointer mode with slots when gathering).
+static int chunked_launch(const mojette_plan *plan, int nchunks, mj::DecodeArgs &a, int Q,
+                          bool gather, uint64_t *workspace, hipStream_t s) {
+    a.R = std::max(a.R, plan->R);
+    a.ring_stride = a.R + 1;
+    // chunks are plentiful: half-full waves keep the sweep's registers and
+    // LDS share small
+    a.nb = std::max(1, mj::decode_max_blocks_per_wave(Q) / 2);
+    while (a.nb > 0 && mj::decode_lds_bytes(Q, a.nb, a.ring_stride) > kLdsLimit) --a.nb;
+    if (a.nb < 1) return MOJETTE_ENOTSUP;
+    if (!gather && ((int64_t)a.nb * a.proj_stride * 8 >= ((int64_t)1 << 31) ||
+                    (int64_t)a.nb * a.img_stride * 8 >= ((int64_t)1 << 31)))
+        return MOJETTE_ENOTSUP;
+    a.chunk.ws = workspace;
+    a.chunk.lut = plan->lut;
+    a.chunk.state_cols = plan->state_cols;
+    a.chunk.tmat_off = plan->tmat_off;
+    a.chunk.tmat = plan->tmat;
+    a.chunk.tiles = plan->tiles;
+    a.chunk.nchunks = nchunks;
+    a.chunk.max_cols = plan->max_cols;
+    const int64_t items = a.nblocks * (nchunks - 1);
+    const int grid = (int)std::min<int64_t>((items + a.nb - 1) / a.nb, kDecodeGridCap);
+    clear_stale_error();
+    int st = status_of(mj::launch_decode(Q, gather ? mj::kLaunchChunkAGather : mj::kLaunchChunkA,
+                                         a, grid, s));
+    if (st != MOJETTE_OK) return st;
+    if (nchunks > 2) {
+        st = status_of(mj::launch_decode_carry(
+            a, Q, (int)std::min<int64_t>(a.nblocks, kDecodeGridCap), s));
+        if (st != MOJETTE_OK) return st;
+    }
+    return status_of(mj::launch_decode(Q, gather ? mj::kLaunchChunkCGather : mj::kLaunchChunkC,
+                                       a, grid, s));
+}
+
+static bool plan_matches(const mojette_plan *plan, const int32_t *dirs, int32_t n, int32_t Q) {
+    if (!plan || plan->n != n || plan->Q != Q) return false;
+    for (int i = 0; i < n; ++i)
+        if (plan->dirs[i] != dirs[i]) return false;
+    return true;
+}
+
 int mojette_decode_batch_chunked(const mojette_plan *plan, const uint64_t *projs,
                                  const uint16_t *erased, int64_t nblocks, int32_t P,
                                  uint64_t *images, int32_t *status, uint64_t *workspace,
@@ -479,22 +523,13 @@ int mojette_decode_batch_chunked(const mojette_plan *plan, const uint64_t *projs
     mj::DecodeArgs a{};
     const int rc = decode_setup(plan->dirs, n, P, Q, a);
     if (rc != MOJETTE_OK) return rc;
-    a.R = std::max(a.R, plan->R);
-    a.ring_stride = a.R + 1;
-    // chunks are plentiful: half-full waves keep the sweep's registers and
-    // LDS share small
-    a.nb = std::max(1, mj::decode_max_blocks_per_wave(Q) / 2);
-    while (a.nb > 0 && mj::decode_lds_bytes(Q, a.nb, a.ring_stride) > kLdsLimit) --a.nb;
-    if (a.nb < 1) return MOJETTE_ENOTSUP;
     int64_t off = 0;
     for (int i = 0; i < n; ++i) {
         a.off[i] = (int32_t)off;
         off += mojette_proj_size(plan->dirs[i], P, Q);
     }
-    if ((int64_t)a.nb * off * 8 >= ((int64_t)1 << 31) ||
-        (int64_t)a.nb * P * Q * 8 >= ((int64_t)1 << 31))
-        return MOJETTE_ENOTSUP;
     a.pool = projs;
+    a.slots = nullptr;
     a.proj_stride = off;
     a.images = images;
     a.img_stride = (int64_t)P * Q;
@@ -502,26 +537,7 @@ int mojette_decode_batch_chunked(const mojette_plan *plan, const uint64_t *projs
     a.mask_uniform = 0;
     a.status = status;
     a.nblocks = nblocks;
-    a.chunk.ws = workspace;
-    a.chunk.lut = plan->lut;
-    a.chunk.state_cols = plan->state_cols;
-    a.chunk.tmat_off = plan->tmat_off;
-    a.chunk.tmat = plan->tmat;
-    a.chunk.tiles = plan->tiles;
-    a.chunk.nchunks = nchunks;
-    a.chunk.max_cols = plan->max_cols;
-    const int64_t items = nblocks * (nchunks - 1);
-    const int grid = (int)std::min<int64_t>((items + a.nb - 1) / a.nb, kDecodeGridCap);
-    hipStream_t s = (hipStream_t)stream;
-    clear_stale_error();
-    int st = status_of(mj::launch_decode(Q, mj::kLaunchChunkA, a, grid, s));
-    if (st != MOJETTE_OK) return st;
-    if (nchunks > 2) {
-        st = status_of(mj::launch_decode_carry(
-            a, Q, (int)std::min<int64_t>(nblocks, kDecodeGridCap), s));
-        if (st != MOJETTE_OK) return st;
-    }
-    return status_of(mj::launch_decode(Q, mj::kLaunchChunkC, a, grid, s));
+    return chunked_launch(plan, nchunks, a, Q, false, workspace, (hipStream_t)stream);
 }
 
 int mojette_classes_layout(const mojette_class *classes, int32_t nclasses, int64_t *image_words,
@@ -655,18 +671,154 @@ static int decode_jobs_launch(const mojette_job *jobs, const std::vector<int> &w
     return status_of(mj::launch_decode_classes(qmask, gather, tab, lds, grid, stream));
 }
 
+// A job decoded in chunks: its plan fits and its rows are long enough to cut.
+static bool job_chunked(const mojette_job &j) {
+    return j.plan && j.nblocks > 0 && plan_chunks(j.plan, j.P) >= 2;
+}
+
+static int decode_job_chunked(const mojette_job &j, int64_t bw, int32_t *status,
+                              hipStream_t stream) {
+    if (!plan_matches(j.plan, j.dirs, j.n, j.Q) || !j.workspace) return MOJETTE_EINVAL;
+    mj::DecodeArgs a{};
+    const int rc = decode_setup(j.dirs, j.n, j.P, j.Q, a);
+    if (rc != MOJETTE_OK) return rc;
+    int64_t off = 0;
+    for (int i = 0; i < j.n; ++i) {
+        a.off[i] = (int32_t)off;
+        off += mojette_proj_size(j.dirs[i], j.P, j.Q);
+    }
+    a.pool = j.projs;
+    a.slots = j.slots;
+    a.proj_stride = bw;
+    a.images = j.images;
+    a.img_stride = (int64_t)j.P * j.Q;
+    a.masks = j.erased;
+    a.mask_uniform = 0;
+    a.status = status;
+    a.nblocks = j.nblocks;
+    return chunked_launch(j.plan, plan_chunks(j.plan, j.P), a, j.Q, j.slots != nullptr,
+                          j.workspace, stream);
+}
+
+// Merged chunked decode of up to kMaxChunkClasses jobs: one launch per phase.
+// Returns MOJETTE_ENOTSUP (nothing launched) when their row counts have no
+// merged kernel.
+static int decode_jobs_chunked_merged(const mojette_job *jobs, const std::vector<int> &which,
+                                      const std::vector<int64_t> &bw, int32_t *status,
+                                      hipStream_t stream) {
+    unsigned qmask = 0;
+    bool gather = false;
+    for (int c : which) {
+        qmask |= 1u << jobs[c].Q;
+        gather = gather || jobs[c].slots != nullptr;
+    }
+    if (!mj::decode_chunk_classes_supported(qmask, gather)) return MOJETTE_ENOTSUP;
+    mj::DecodeChunkTable tab{};
+    size_t lds = 0;
+    int64_t items = 0, blocks = 0;
+    int state = 0, k = 0;
+    for (int c : which) {
+        const mojette_job &j = jobs[c];
+        mj::DecodeChunkClass &d = tab.cls[k];
+        int rc = decode_setup(j.dirs, j.n, j.P, j.Q, d);
+        if (rc != MOJETTE_OK) return rc;
+        const mojette_plan *pl = j.plan;
+        d.R = std::max(d.R, pl->R);
+        d.ring_stride = d.R + 1;
+        d.nb = std::max(1, mj::decode_max_blocks_per_wave(j.Q) / 2);
+        while (d.nb > 0 && mj::decode_lds_bytes(j.Q, d.nb, d.ring_stride) > kLdsLimit) --d.nb;
+        if (d.nb < 1) return MOJETTE_ENOTSUP;
+        if (!gather && ((int64_t)d.nb * bw[c] * 8 >= ((int64_t)1 << 31) ||
+                        (int64_t)d.nb * j.P * j.Q * 8 >= ((int64_t)1 << 31)))
+            return MOJETTE_ENOTSUP;
+        d.Q = j.Q;
+        d.pool = j.projs;
+        d.slots = j.slots;
+        d.images = j.images;
+        d.masks = j.erased;
+        d.status = status;
+        d.nblocks = j.nblocks;
+        d.proj_stride = bw[c];
+        d.img_stride = (int64_t)j.P * j.Q;
+        d.mask_uniform = 0;
+        int32_t off = 0;
+        for (int i = 0; i < j.n; ++i) {
+            d.off[i] = off;
+            off += (int32_t)mojette_proj_size(j.dirs[i], j.P, j.Q);
+        }
+        const int nchunks = plan_chunks(pl, j.P);
+        d.chunk.ws = j.workspace;
+        d.chunk.lut = pl->lut;
+        d.chunk.state_cols = pl->state_cols;
+        d.chunk.tmat_off = pl->tmat_off;
+        d.chunk.tmat = pl->tmat;
+        d.chunk.tiles = pl->tiles;
+        d.chunk.nchunks = nchunks;
+        d.chunk.max_cols = pl->max_cols;
+        tab.first_item[k] = items;
+        items += (j.nblocks * (nchunks - 1) + d.nb - 1) / d.nb;
+        tab.first_block[k] = blocks;
+        blocks += j.nblocks;
+        lds = std::max(lds, mj::decode_lds_bytes(j.Q, d.nb, d.ring_stride));
+        state = std::max(state, j.Q * pl->max_cols);
+        ++k;
+    }
+    tab.nclasses = k;
+    tab.first_item[k] = items;
+    tab.first_block[k] = blocks;
+    const int grid = (int)std::min<int64_t>(items, kDecodeGridCap);
+    const int cgrid = (int)std::min<int64_t>(blocks, kDecodeGridCap);
+    const bool regs = mj::carry_rows_in_registers(state);
+    clear_stale_error();
+    int st = status_of(mj::launch_decode_chunk_classes(mj::kLaunchChunkA, qmask, gather, tab, lds,
+                                                       grid, mj::kWave, regs, stream));
+    if (st != MOJETTE_OK) return st;
+    st = status_of(mj::launch_decode_chunk_classes(mj::kLaunchCarry, qmask, gather, tab,
+                                                   mj::carry_lds_bytes(state), cgrid,
+                                                   mj::kWave * mj::carry_waves(state), regs,
+                                                   stream));
+    if (st != MOJETTE_OK) return st;
+    return status_of(mj::launch_decode_chunk_classes(mj::kLaunchChunkC, qmask, gather, tab, lds,
+                                                     grid, mj::kWave, regs, stream));
+}
+
 int mojette_decode_jobs(const mojette_job *jobs, int32_t njobs, int32_t *status, void *stream) {
     std::vector<int64_t> bw;
     int rc = jobs_check(jobs, njobs, bw);
     if (rc != MOJETTE_OK) return rc;
-    std::vector<int> order(njobs);
-    for (int c = 0; c < njobs; ++c) order[c] = c;
+    for (int c = 0; c < njobs; ++c)
+        if (job_chunked(jobs[c]) && (!plan_matches(jobs[c].plan, jobs[c].dirs, jobs[c].n, jobs[c].Q) ||
+                                     !jobs[c].workspace))
+            return MOJETTE_EINVAL;
+    std::vector<int> order;
+    for (int c = 0; c < njobs; ++c)
+        if (!job_chunked(jobs[c])) order.push_back(c);
     // longest rows (longest sweeps) first
     std::stable_sort(order.begin(), order.end(),
                      [&](int x, int y) { return jobs[x].P > jobs[y].P; });
+    // chunked jobs first, longest rows first: merged launches of up to
+    // kMaxChunkClasses jobs, else launches of their own
+    std::vector<int> chunked;
+    for (int c = 0; c < njobs; ++c)
+        if (job_chunked(jobs[c])) chunked.push_back(c);
+    std::stable_sort(chunked.begin(), chunked.end(),
+                     [&](int x, int y) { return jobs[x].P > jobs[y].P; });
+    for (size_t g = 0; g < chunked.size(); g += mj::kMaxChunkClasses) {
+        std::vector<int> grp(chunked.begin() + g,
+                             chunked.begin() + std::min(chunked.size(), g + mj::kMaxChunkClasses));
+        rc = decode_jobs_chunked_merged(jobs, grp, bw, status, (hipStream_t)stream);
+        if (rc == MOJETTE_ENOTSUP) {
+            for (int c : grp) {
+                rc = decode_job_chunked(jobs[c], bw[c], status, (hipStream_t)stream);
+                if (rc != MOJETTE_OK) return rc;
+            }
+        } else if (rc != MOJETTE_OK) {
+            return rc;
+        }
+    }
     unsigned qmask = 0;
     bool gather = false;
-    for (int c = 0; c < njobs; ++c)
+    for (int c : order)
         if (jobs[c].nblocks > 0) {
             qmask |= 1u << jobs[c].Q;
             gather = gather || jobs[c].slots != nullptr;

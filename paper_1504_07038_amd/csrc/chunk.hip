@@ -1,7 +1,7 @@
 // Host-side tables of the chunked decode: for one survivor set, the state
 // width E and the GF(2) transfer matrix of one interior chunk.
 //
-// The sweep of decode.hip reconstructs pixel (k, r) as the bin of row r's
+// The sweep of decode_body.h reconstructs pixel (k, r) as the bin of row r's
 // projection XOR the pixels (k + (l-r) p_r, l), l != r (Section 2.2), in a
 // fixed order of half-steps.  Within a chunk that lies wholly inside the
 // image, the pixels it produces are therefore a GF(2)-linear function of the

@@ -1,4 +1,5 @@
-// Inverse Mojette transform on gfx950 (Section 2.2), XOR addition.
+// Inverse Mojette transform on gfx950 (Section 2.2), XOR addition: the device
+// code shared by the decode translation units (decode_*.hip).
 //
 // Reconstruction path.  Of the surviving projections, the Q with the smallest
 // p are used; sorted by p, the r-th (p_r) is dedicated to image row r, as the
@@ -45,6 +46,8 @@
 // (stores) or answers with zero (loads).  Every memory instruction is therefore issued
 // unconditionally, the compiler knows exactly how many are in flight, and
 // waiting for a tile's bins never waits for the stores issued after them.
+#pragma once
+
 #include <algorithm>
 #include <climits>
 
@@ -472,40 +475,15 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch)
 template <int Q>
 constexpr int full_slots() { return kWave / ((Q + 1) / 2); }
 
+template <int Q>
+constexpr int half_slots() { return kWave / ((Q + 1) / 2) >= 2 ? kWave / ((Q + 1) / 2) / 2 : 1; }
+
 template <int Q, int TW, bool POOL, int CHUNK, int NBT>
 __global__ __launch_bounds__(kWave) void decode_kernel(DecodeArgs a) {
     const int64_t per = CHUNK == kWhole ? 1 : a.chunk.nchunks - 1;
     const int64_t nbatches = (a.nblocks * per + a.nb - 1) / a.nb;
     for (int64_t batch = blockIdx.x; batch < nbatches; batch += gridDim.x)
         decode_batch<Q, TW, POOL, CHUNK, NBT>(a, batch);
-}
-
-// A mixed launch: batches of every class, in the order of the class table
-// (heaviest first), one wavefront per workgroup.  QMASK has bit Q set for
-// every row count the launch may meet; only those bodies are compiled in, so
-// the kernel's registers are those of its largest body, not of all sixteen.
-template <unsigned QMASK, bool GATHER>
-__global__ __launch_bounds__(kWave) void decode_classes_kernel(DecodeClassTable tab) {
-    const int64_t total = tab.first_item[tab.nclasses];
-    for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
-        int c = 0;
-        while (item >= tab.first_item[c + 1]) ++c;
-        const DecodeClass &a = tab.cls[c];
-        const int64_t batch = item - tab.first_item[c];
-        switch (a.Q) {
-#define MJ_DEC_CASE(QQ)                                                                  \
-    case QQ:                                                                             \
-        if constexpr ((QMASK >> QQ) & 1u)                                               \
-            decode_batch<QQ, kDecodeTile, !GATHER, kWhole, full_slots<QQ>()>(a, batch);   \
-        break;
-            MJ_DEC_CASE(1) MJ_DEC_CASE(2) MJ_DEC_CASE(3) MJ_DEC_CASE(4)
-            MJ_DEC_CASE(5) MJ_DEC_CASE(6) MJ_DEC_CASE(7) MJ_DEC_CASE(8)
-            MJ_DEC_CASE(9) MJ_DEC_CASE(10) MJ_DEC_CASE(11) MJ_DEC_CASE(12)
-            MJ_DEC_CASE(13) MJ_DEC_CASE(14) MJ_DEC_CASE(15) MJ_DEC_CASE(16)
-#undef MJ_DEC_CASE
-            default: break;
-        }
-    }
 }
 
 // Carry pass of the chunked decode.  For every block, with y_c the end state
@@ -528,9 +506,9 @@ constexpr int kCarryAhead = 4;           // chunks whose end states are loaded a
 
 // RWC > 0: every thread owns at most one output word and keeps its matrix row
 // (RW <= RWC words) in registers for all chunks; RWC == 0: rows are read from
-// memory at every chunk.
-template <int RWC>
-__global__ __launch_bounds__(kWave * kCarryWaves) void decode_carry_kernel(DecodeArgs a, int Q) {
+// memory at every chunk.  `Args`: DecodeArgs or DecodeChunkClass.
+template <int RWC, class Args>
+__device__ __forceinline__ void carry_block(const Args &a, const int Q, const int64_t blk) {
     extern __shared__ uint64_t lds_carry[];
     constexpr int OPT = RWC > 0 ? 1 : kCarryOutPerThread;   // outputs per thread
     const int tid = threadIdx.x;
@@ -540,190 +518,121 @@ __global__ __launch_bounds__(kWave * kCarryWaves) void decode_carry_kernel(Decod
     const int64_t zwords = stride + 4;                // z, zero past the state
     uint64_t *z = lds_carry;
     uint64_t *tab = lds_carry + zwords;               // kCarryTableWords words
-    for (int64_t blk = blockIdx.x; blk < a.nblocks; blk += gridDim.x) {
-        const uint32_t mask = a.masks ? a.masks[blk] : a.mask_uniform;
-        uint32_t used = 0;
-        int cnt = 0;
-        for (int s = 0; s < a.n; ++s) {
-            const int id = a.id_sorted[s];
-            if (!((mask >> id) & 1u) && cnt < Q) {
-                used |= 1u << id;
-                ++cnt;
-            }
+    const uint32_t mask = a.masks ? a.masks[blk] : a.mask_uniform;
+    uint32_t used = 0;
+    int cnt = 0;
+    for (int s = 0; s < a.n; ++s) {
+        const int id = a.id_sorted[s];
+        if (!((mask >> id) & 1u) && cnt < Q) {
+            used |= 1u << id;
+            ++cnt;
         }
-        if (cnt < Q) continue;   // undecodable: reported by the sweep (uniform per block)
-        const int set = a.chunk.lut[used];
-        const int d = Q * a.chunk.state_cols[set];
-        const int RW = (d + 63) / 64;
-        const int G = (d + 3) / 4;                    // 4-word groups
-        const int GP = kCarryTableWords / 16;         // groups per table pass
-        const uint64_t *T = a.chunk.tmat + a.chunk.tmat_off[set];
-        uint64_t *ws = a.chunk.ws + blk * per * stride;
-        uint64_t trow[RWC > 0 ? RWC : 1];
-        if constexpr (RWC > 0) {
+    }
+    if (cnt < Q) return;   // undecodable: reported by the sweep (uniform per block)
+    const int set = a.chunk.lut[used];
+    const int d = Q * a.chunk.state_cols[set];
+    const int RW = (d + 63) / 64;
+    const int G = (d + 3) / 4;                        // 4-word groups
+    const int GP = kCarryTableWords / 16;             // groups per table pass
+    const uint64_t *T = a.chunk.tmat + a.chunk.tmat_off[set];
+    uint64_t *ws = a.chunk.ws + blk * per * stride;
+    uint64_t trow[RWC > 0 ? RWC : 1];
+    if constexpr (RWC > 0) {
 #pragma unroll
-            for (int w = 0; w < RWC; ++w) trow[w] = (tid < d && w < RW) ? T[(int64_t)tid * RW + w] : 0;
+        for (int w = 0; w < RWC; ++w) trow[w] = (tid < d && w < RW) ? T[(int64_t)tid * RW + w] : 0;
+    }
+    __syncthreads();   // the previous block's last reads of z are done
+    for (int i = tid; i < zwords; i += nthreads) z[i] = i < d ? ws[i] : 0;
+    // y_c of the next kCarryAhead chunks, loaded ahead of their step
+    uint64_t yq[kCarryAhead][OPT];
+#pragma unroll
+    for (int k = 0; k < kCarryAhead; ++k)
+#pragma unroll
+        for (int u = 0; u < OPT; ++u) {
+            const int i = tid + nthreads * u;
+            yq[k][u] = (i < d && 1 + k < per) ? ws[(1 + k) * stride + i] : 0;
         }
-        for (int i = tid; i < zwords; i += nthreads) z[i] = i < d ? ws[i] : 0;
-        // y_c of the next kCarryAhead chunks, loaded ahead of their step
-        uint64_t yq[kCarryAhead][OPT];
+    __syncthreads();
+    for (int c = 1; c < per; ++c) {
+        uint64_t *y = ws + c * stride;
+        uint64_t acc[OPT];
 #pragma unroll
-        for (int k = 0; k < kCarryAhead; ++k)
+        for (int u = 0; u < OPT; ++u) {
+            const int i = tid + nthreads * u;
+            acc[u] = yq[0][u];
 #pragma unroll
-            for (int u = 0; u < OPT; ++u) {
-                const int i = tid + nthreads * u;
-                yq[k][u] = (i < d && 1 + k < per) ? ws[(1 + k) * stride + i] : 0;
-            }
-        __syncthreads();
-        for (int c = 1; c < per; ++c) {
-            uint64_t *y = ws + c * stride;
-            uint64_t acc[OPT];
+            for (int k = 0; k + 1 < kCarryAhead; ++k) yq[k][u] = yq[k + 1][u];
+            yq[kCarryAhead - 1][u] =
+                (i < d && c + kCarryAhead < per) ? ws[(c + kCarryAhead) * stride + i] : 0;
+        }
+        for (int g0 = 0; g0 < G; g0 += GP) {
+            const int g1 = min(G, g0 + GP);
+            for (int e = tid; e < (g1 - g0) * 16; e += nthreads) {
+                const int g = g0 + (e >> 4), m = e & 15;
+                uint64_t v = 0;
 #pragma unroll
-            for (int u = 0; u < OPT; ++u) {
-                const int i = tid + nthreads * u;
-                acc[u] = yq[0][u];
-#pragma unroll
-                for (int k = 0; k + 1 < kCarryAhead; ++k) yq[k][u] = yq[k + 1][u];
-                yq[kCarryAhead - 1][u] =
-                    (i < d && c + kCarryAhead < per) ? ws[(c + kCarryAhead) * stride + i] : 0;
-            }
-            for (int g0 = 0; g0 < G; g0 += GP) {
-                const int g1 = min(G, g0 + GP);
-                for (int e = tid; e < (g1 - g0) * 16; e += nthreads) {
-                    const int g = g0 + (e >> 4), m = e & 15;
-                    uint64_t v = 0;
-#pragma unroll
-                    for (int k = 0; k < 4; ++k)
-                        if ((m >> k) & 1) v ^= z[4 * g + k];
-                    tab[e] = v;
-                }
-                __syncthreads();
-                if constexpr (RWC > 0) {
-                    // one pass covers every group (RWC * 16 <= GP)
-                    if (tid < d) {
-#pragma unroll
-                        for (int w = 0; w < RWC; ++w) {
-                            if (w >= RW) break;
-                            const uint64_t bits = trow[w];
-                            const int gn = min(16, G - 16 * w);
-                            for (int q = 0; q < gn; ++q)
-                                acc[0] ^= tab[((16 * w + q) << 4) | (int)((bits >> (4 * q)) & 15)];
-                        }
-                    }
-                } else {
-#pragma unroll
-                    for (int u = 0; u < OPT; ++u) {
-                        const int i = tid + nthreads * u;
-                        if (i >= d) continue;
-                        const uint64_t *row = T + (int64_t)i * RW;
-                        for (int g = g0; g < g1; g += 16) {    // one matrix word: 16 groups
-                            const uint64_t bits = row[g >> 4];
-                            const int gn = min(16, g1 - g);
-                            for (int q = 0; q < gn; ++q)
-                                acc[u] ^= tab[((g - g0 + q) << 4) | (int)((bits >> (4 * q)) & 15)];
-                        }
-                    }
-                }
-                __syncthreads();   // tables are rebuilt or z is overwritten next
-            }
-#pragma unroll
-            for (int u = 0; u < OPT; ++u) {
-                const int i = tid + nthreads * u;
-                if (i < d) {
-                    z[i] = acc[u];
-                    y[i] = acc[u];
-                }
+                for (int k = 0; k < 4; ++k)
+                    if ((m >> k) & 1) v ^= z[4 * g + k];
+                tab[e] = v;
             }
             __syncthreads();
+            if constexpr (RWC > 0) {
+                // one pass covers every group (RWC * 16 <= GP)
+                if (tid < d) {
+#pragma unroll
+                    for (int w = 0; w < RWC; ++w) {
+                        if (w >= RW) break;
+                        const uint64_t bits = trow[w];
+                        const int gn = min(16, G - 16 * w);
+                        for (int q = 0; q < gn; ++q)
+                            acc[0] ^= tab[((16 * w + q) << 4) | (int)((bits >> (4 * q)) & 15)];
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int u = 0; u < OPT; ++u) {
+                    const int i = tid + nthreads * u;
+                    if (i >= d) continue;
+                    const uint64_t *row = T + (int64_t)i * RW;
+                    for (int g = g0; g < g1; g += 16) {    // one matrix word: 16 groups
+                        const uint64_t bits = row[g >> 4];
+                        const int gn = min(16, g1 - g);
+                        for (int q = 0; q < gn; ++q)
+                            acc[u] ^= tab[((g - g0 + q) << 4) | (int)((bits >> (4 * q)) & 15)];
+                    }
+                }
+            }
+            __syncthreads();   // tables are rebuilt or z is overwritten next
         }
-    }
-}
-
-hipError_t launch_decode_carry(const DecodeArgs &a, int Q, int grid, hipStream_t s) {
-    const int state = Q * a.chunk.max_cols;
-    if (state > kCarryMaxState) return hipErrorInvalidValue;
-    const int waves = std::min(kCarryWaves, std::max(1, (state + kWave - 1) / kWave));
-    const size_t lds = ((size_t)state + 4 + kCarryTableWords) * sizeof(uint64_t);
-    // rows cached in registers while one thread per output word suffices
-    if (state <= kWave * kCarryWaves && state <= 8 * 64)
-        hipLaunchKernelGGL(decode_carry_kernel<8>, dim3(grid), dim3(kWave * waves), lds, s, a, Q);
-    else
-        hipLaunchKernelGGL(decode_carry_kernel<0>, dim3(grid), dim3(kWave * waves), lds, s, a, Q);
-    return hipGetLastError();
-}
-
-constexpr unsigned qbit(int q) { return 1u << q; }
-
-// Row-count sets with a compiled mixed kernel: every single row count, and
-// the mixes of the (4,2)+(8,4) and (4,2)+(6,3)+(8,4)+(12,4) code families.
-// Gathering launches (blocks at arbitrary projection slots) exist for the
-// even row counts up to 16 and the (4,2)+(8,4) mix.
-bool decode_classes_supported(unsigned qmask, bool gather) {
-    if (gather) {
-        switch (qmask) {
-            case qbit(2): case qbit(4): case qbit(6): case qbit(8): case qbit(10):
-            case qbit(12): case qbit(14): case qbit(16): case qbit(4) | qbit(8): return true;
-            default: return false;
+#pragma unroll
+        for (int u = 0; u < OPT; ++u) {
+            const int i = tid + nthreads * u;
+            if (i < d) {
+                z[i] = acc[u];
+                y[i] = acc[u];
+            }
         }
+        __syncthreads();
     }
-    if (qmask && !(qmask & (qmask - 1))) return true;
-    return qmask == (qbit(4) | qbit(8)) || qmask == (qbit(4) | qbit(6) | qbit(8) | qbit(12));
 }
 
-hipError_t launch_decode_classes(unsigned qmask, bool gather, const DecodeClassTable &tab,
-                                 size_t lds, int grid, hipStream_t s) {
-#define MJ_LAUNCH(M, G) \
-    hipLaunchKernelGGL((decode_classes_kernel<M, G>), dim3(grid), dim3(kWave), lds, s, tab)
-    if (gather) {
-        switch (qmask) {
-            case qbit(2): MJ_LAUNCH(qbit(2), true); break;
-            case qbit(4): MJ_LAUNCH(qbit(4), true); break;
-            case qbit(6): MJ_LAUNCH(qbit(6), true); break;
-            case qbit(8): MJ_LAUNCH(qbit(8), true); break;
-            case qbit(10): MJ_LAUNCH(qbit(10), true); break;
-            case qbit(12): MJ_LAUNCH(qbit(12), true); break;
-            case qbit(14): MJ_LAUNCH(qbit(14), true); break;
-            case qbit(16): MJ_LAUNCH(qbit(16), true); break;
-            case qbit(4) | qbit(8): MJ_LAUNCH(qbit(4) | qbit(8), true); break;
-            default: return hipErrorInvalidValue;
-        }
-        return hipGetLastError();
-    }
-    switch (qmask) {
-        case qbit(1): MJ_LAUNCH(qbit(1), false); break;
-        case qbit(2): MJ_LAUNCH(qbit(2), false); break;
-        case qbit(3): MJ_LAUNCH(qbit(3), false); break;
-        case qbit(4): MJ_LAUNCH(qbit(4), false); break;
-        case qbit(5): MJ_LAUNCH(qbit(5), false); break;
-        case qbit(6): MJ_LAUNCH(qbit(6), false); break;
-        case qbit(7): MJ_LAUNCH(qbit(7), false); break;
-        case qbit(8): MJ_LAUNCH(qbit(8), false); break;
-        case qbit(9): MJ_LAUNCH(qbit(9), false); break;
-        case qbit(10): MJ_LAUNCH(qbit(10), false); break;
-        case qbit(11): MJ_LAUNCH(qbit(11), false); break;
-        case qbit(12): MJ_LAUNCH(qbit(12), false); break;
-        case qbit(13): MJ_LAUNCH(qbit(13), false); break;
-        case qbit(14): MJ_LAUNCH(qbit(14), false); break;
-        case qbit(15): MJ_LAUNCH(qbit(15), false); break;
-        case qbit(16): MJ_LAUNCH(qbit(16), false); break;
-        case qbit(4) | qbit(8): MJ_LAUNCH(qbit(4) | qbit(8), false); break;
-        case qbit(4) | qbit(6) | qbit(8) | qbit(12):
-            MJ_LAUNCH(qbit(4) | qbit(6) | qbit(8) | qbit(12), false);
-            break;
-        default: return hipErrorInvalidValue;
-    }
-#undef MJ_LAUNCH
-    return hipGetLastError();
+template <int RWC>
+__global__ __launch_bounds__(kWave * kCarryWaves) void decode_carry_kernel(DecodeArgs a, int Q) {
+    for (int64_t blk = blockIdx.x; blk < a.nblocks; blk += gridDim.x) carry_block<RWC>(a, Q, blk);
 }
 
-int decode_tile(int) { return kDecodeTile; }
-
-size_t decode_lds_bytes(int Q, int nb, int ring_stride) {
-    return (size_t)nb * (Q * ring_stride + 1) * sizeof(uint64_t);
+template <int RWC>
+__global__ __launch_bounds__(kWave * kCarryWaves) void decode_carry_classes_kernel(
+    DecodeChunkTable tab) {
+    const int64_t total = tab.first_block[tab.nclasses];
+    for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
+        int c = 0;
+        while (item >= tab.first_block[c + 1]) ++c;
+        carry_block<RWC>(tab.cls[c], tab.cls[c].Q, item - tab.first_block[c]);
+    }
 }
 
-int decode_max_blocks_per_wave(int Q) { return kWave / ((Q + 1) / 2); }
-
+// Single-geometry launchers (static: one copy per translation unit that uses them).
 template <int Q, int NBT>
 static hipError_t launch_qn(int mode, const DecodeArgs &a, int grid, hipStream_t s) {
     const size_t lds = decode_lds_bytes(Q, a.nb, a.ring_stride);
@@ -736,12 +645,33 @@ static hipError_t launch_qn(int mode, const DecodeArgs &a, int grid, hipStream_t
             hipLaunchKernelGGL((decode_kernel<Q, kDecodeTile, false, kWhole, NBT>), dim3(grid),
                                dim3(kWave), lds, s, a);
             break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// Chunked sweeps: chunks are plentiful, so they always run the half-slot body.
+template <int Q>
+static hipError_t launch_chunk(int mode, const DecodeArgs &a, int grid, hipStream_t s) {
+    constexpr int full = full_slots<Q>();
+    constexpr int NBT = full >= 2 ? full / 2 : 1;
+    if (a.nb > NBT) return hipErrorInvalidValue;
+    const size_t lds = decode_lds_bytes(Q, a.nb, a.ring_stride);
+    switch (mode) {
         case kLaunchChunkA:
             hipLaunchKernelGGL((decode_kernel<Q, kDecodeTile, true, kChunkA, NBT>), dim3(grid),
                                dim3(kWave), lds, s, a);
             break;
         case kLaunchChunkC:
             hipLaunchKernelGGL((decode_kernel<Q, kDecodeTile, true, kChunkC, NBT>), dim3(grid),
+                               dim3(kWave), lds, s, a);
+            break;
+        case kLaunchChunkAGather:
+            hipLaunchKernelGGL((decode_kernel<Q, kDecodeTile, false, kChunkA, NBT>), dim3(grid),
+                               dim3(kWave), lds, s, a);
+            break;
+        case kLaunchChunkCGather:
+            hipLaunchKernelGGL((decode_kernel<Q, kDecodeTile, false, kChunkC, NBT>), dim3(grid),
                                dim3(kWave), lds, s, a);
             break;
         default: return hipErrorInvalidValue;
@@ -754,30 +684,9 @@ static hipError_t launch_qn(int mode, const DecodeArgs &a, int grid, hipStream_t
 template <int Q>
 static hipError_t launch_q(int mode, const DecodeArgs &a, int grid, hipStream_t s) {
     constexpr int full = full_slots<Q>();
+    if (mode >= kLaunchChunkA) return launch_chunk<Q>(mode, a, grid, s);
     if (full >= 2 && a.nb <= full / 2) return launch_qn<Q, (full >= 2 ? full / 2 : 1)>(mode, a, grid, s);
     return launch_qn<Q, full>(mode, a, grid, s);
-}
-
-hipError_t launch_decode(int Q, int mode, const DecodeArgs &a, int grid, hipStream_t s) {
-    switch (Q) {
-        case 1: return launch_q<1>(mode, a, grid, s);
-        case 2: return launch_q<2>(mode, a, grid, s);
-        case 3: return launch_q<3>(mode, a, grid, s);
-        case 4: return launch_q<4>(mode, a, grid, s);
-        case 5: return launch_q<5>(mode, a, grid, s);
-        case 6: return launch_q<6>(mode, a, grid, s);
-        case 7: return launch_q<7>(mode, a, grid, s);
-        case 8: return launch_q<8>(mode, a, grid, s);
-        case 9: return launch_q<9>(mode, a, grid, s);
-        case 10: return launch_q<10>(mode, a, grid, s);
-        case 11: return launch_q<11>(mode, a, grid, s);
-        case 12: return launch_q<12>(mode, a, grid, s);
-        case 13: return launch_q<13>(mode, a, grid, s);
-        case 14: return launch_q<14>(mode, a, grid, s);
-        case 15: return launch_q<15>(mode, a, grid, s);
-        case 16: return launch_q<16>(mode, a, grid, s);
-        default: return hipErrorInvalidValue;
-    }
 }
 
 }  // namespace mj

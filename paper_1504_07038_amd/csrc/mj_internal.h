@@ -84,7 +84,7 @@ struct EncodeClassTable {
 
 // ---- decode --------------------------------------------------------------
 // Rows of a block are swept left to right in the order fixed by the sorted
-// directions (see decode.hip).  Each lane owns two rows of one block; a wave
+// directions (see decode_body.h).  Each lane owns two rows of one block; a wave
 // holds up to 64/ceil(Q/2) blocks.  Each row keeps its last R pixels in an
 // LDS ring.
 // Chunked decode of long rows.  The tiles of a block are cut into nchunks
@@ -118,14 +118,19 @@ constexpr int kLaunchPool = 0;       // whole blocks from a projection pool
 constexpr int kLaunchPointers = 1;   // one whole block from projection pointers
 constexpr int kLaunchChunkA = 2;     // pool, first chunk sweep
 constexpr int kLaunchChunkC = 3;     // pool, final chunk sweep
+constexpr int kLaunchChunkAGather = 4;   // projection slices at slots, first chunk sweep
+constexpr int kLaunchChunkCGather = 5;   // projection slices at slots, final chunk sweep
 
 struct DecodeArgs {
     // Pool mode (batches): block b's n projections start at word
     // b*proj_stride of `pool`, projection i at word off[i] of that slice.
     const uint64_t *pool;
     int32_t off[kMaxDirs];
-    // Pointer mode (one block): projection i at in[i] (null if not given).
+    // Pointer mode: projection i of the one block at in[i] (null if not
+    // given) when `pool` is null; else block b's slice is slice slots[b] of
+    // `pool` (gathering launches).
     const uint64_t *in[kMaxDirs];
+    const int64_t *slots;
     int64_t proj_stride;
     uint64_t *images;
     int64_t img_stride;
@@ -139,7 +144,9 @@ struct DecodeArgs {
     int32_t p_sorted[kMaxDirs];      // directions in ascending p
     int32_t id_sorted[kMaxDirs];     // their indices in the caller's dirs
     ChunkInfo chunk;                 // chunked launches only
-    __device__ const uint64_t *proj_base(int64_t, int id) const { return in[id]; }
+    __device__ const uint64_t *proj_base(int64_t blk, int id) const {
+        return pool ? pool + slots[blk] * proj_stride + off[id] : in[id];
+    }
 };
 
 // One geometry class of a mixed decode launch (pool mode only).  Field names
@@ -172,6 +179,32 @@ struct DecodeClassTable {
 // Status of a HIP call as a library status code; a failure is remembered for
 // mojette_last_hip_error() on the calling thread.
 int hip_status(hipError_t e);
+
+// One class of a merged chunked decode launch: a DecodeClass with its chunk
+// layout (plan tables, workspace, chunk length and count).
+struct DecodeChunkClass : DecodeClass {
+    ChunkInfo chunk;
+};
+
+constexpr int kMaxChunkClasses = 8;   // keeps the table within the kernel-argument limit
+
+struct DecodeChunkTable {
+    DecodeChunkClass cls[kMaxChunkClasses];
+    int64_t first_item[kMaxChunkClasses + 1];    // sweeps: batches of class c
+    int64_t first_block[kMaxChunkClasses + 1];   // carry: blocks of class c
+    int32_t nclasses;
+};
+
+bool decode_chunk_classes_supported(unsigned qmask, bool gather);
+// mode: kLaunchChunkA or kLaunchChunkC (sweeps, one wave per workgroup), or
+// kLaunchCarry (carry pass, `threads` per workgroup).
+constexpr int kLaunchCarry = 6;
+hipError_t launch_decode_chunk_classes(int mode, unsigned qmask, bool gather,
+                                       const DecodeChunkTable &tab, size_t lds, int grid,
+                                       int threads, bool rows_in_registers, hipStream_t s);
+int carry_waves(int state);
+size_t carry_lds_bytes(int state);
+bool carry_rows_in_registers(int state);
 
 hipError_t launch_encode(const EncodeArgs &a, int grid, hipStream_t s);
 hipError_t launch_encode_classes(int qmax, const EncodeClassTable &tab, size_t lds, int grid,

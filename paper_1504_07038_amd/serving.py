@@ -198,7 +198,8 @@ class Server:
     image bytes per kind per iteration (sets `cap`)."""
 
     def __init__(self, budget_bytes: int = 64 << 30, depth: int = 3, seed: int = 1,
-                 geos=None, prefill: float = 0.5, per_iter_bytes: int = 16 << 20):
+                 geos=None, prefill: float = 0.5, per_iter_bytes: int = 16 << 20,
+                 chunk_min_P: int = 1024, chunk_cols: int = 256, side_streams: int = 3):
         import torch
 
         self.torch = torch
@@ -211,8 +212,21 @@ class Server:
         self.L = mj.lib()
         caps = [int(max(4, min(4096, per_iter_bytes // (g.img_words * 8)))) for g in self.geos]
         stage_words = sum(2 * c + c // 4 + 1 for c in caps) + 64
+        # Long rows are read back by the chunked decode: one plan per code,
+        # a workspace per class and in-flight iteration, launched on side
+        # streams so the chunked reads of several classes overlap.
+        self.plans = {}
+        ws_words = []
+        for g, cap in zip(self.geos, caps):
+            w = 0
+            if chunk_min_P and g.P >= chunk_min_P:
+                key = (tuple(g.dirs), g.Q)
+                if key not in self.plans:
+                    self.plans[key] = mj.Plan(g.dirs, g.Q, chunk_cols)
+                w = self.plans[key].workspace_words(g.P, cap)
+            ws_words.append(w)
         fixed = sum((depth + 2) * c * g.img_words * 8 for c, g in zip(caps, self.geos))
-        fixed += 2 * depth * stage_words * 8
+        fixed += 2 * depth * stage_words * 8 + depth * 8 * sum(ws_words)
         if fixed >= budget_bytes:
             raise ValueError("budget too small for the payload pools and output rings")
         share = (budget_bytes - fixed) // len(self.geos)
@@ -221,7 +235,13 @@ class Server:
             slots = share // (g.words * 8)
             if slots < 2 * cap:
                 raise ValueError(f"budget leaves class {c} fewer than {2 * cap} slots")
-            self.cs.append(_Class(g, int(slots), cap, depth, self.dev, torch))
+            st = _Class(g, int(slots), cap, depth, self.dev, torch)
+            st.plan = self.plans.get((tuple(g.dirs), g.Q)) if ws_words[c] else None
+            st.ws_words = ws_words[c]
+            st.ws = (torch.empty(depth * ws_words[c], dtype=torch.int64, device=self.dev)
+                     if ws_words[c] else None)
+            self.cs.append(st)
+        self.side = [torch.cuda.Stream() for _ in range(side_streams)]
         for c, st in enumerate(self.cs):
             mj.mojette_fill_splitmix64(st.payload, st.payload.numel(), seed * 1000 + c,
                                        stream=self.stream_ptr)
@@ -232,6 +252,7 @@ class Server:
         self.d_stage_ptr = self.d_stage.data_ptr()
         self.status = torch.zeros(1, dtype=torch.int32, device=self.dev)
         self.jobs = [(mj.MojetteJob * mj.MAX_CLASSES)() for _ in range(2)]
+        self.chunk_jobs = (mj.MojetteJob * mj.MAX_CLASSES)()
         self.iter_no = 0
         self._prefill(prefill)
         self.stream.synchronize()
@@ -241,9 +262,26 @@ class Server:
         b = (self.h_stage.numel() + self.d_stage.numel()) * 8
         for st in self.cs:
             b += (st.arena.numel() + st.payload.numel() + st.out.numel()) * 8
+            b += st.ws.numel() * 8 if st.ws is not None else 0
         return b
 
     # ---- launches -----------------------------------------------------------
+
+    def _run_chunked(self, entries, ring: int, stream_ptr: int) -> None:
+        """Long-row classes' reads: chunked decode jobs in one call on
+        `stream_ptr` (the library merges up to 8 classes per launch)."""
+        arr = self.chunk_jobs
+        size = ctypes.sizeof(mj.MojetteJob)
+        for i, (c, nb, img, slots, erased) in enumerate(entries):
+            st = self.cs[c]
+            ctypes.memmove(ctypes.addressof(arr[i]), ctypes.addressof(st.template), size)
+            a = arr[i]
+            a.nblocks, a.images, a.projs, a.slots, a.erased = nb, img, st.arena_ptr, slots, erased
+            a.plan = st.plan.handle
+            a.workspace = st.ws.data_ptr() + ring * st.ws_words * 8
+        rc = self.L.mojette_decode_jobs(arr, len(entries), self.status.data_ptr(), stream_ptr)
+        if rc != mj.MOJETTE_OK:
+            raise mj.MojetteError(rc, "mojette_decode_jobs")
 
     def _run_jobs(self, kind: str, entries) -> None:
         """entries: (class, nblocks, images ptr, slots ptr, erased ptr)."""
@@ -309,13 +347,33 @@ class Server:
             pos += k + nw
         begin = torch.cuda.Event(enable_timing=True)
         done = torch.cuda.Event(enable_timing=True)
+        chunked = [e for e in rl if self.cs[e[0]].plan is not None]
+        whole = [e for e in rl if self.cs[e[0]].plan is None]
         with torch.cuda.stream(self.stream):
             begin.record(self.stream)
             self.d_stage[base:pos].copy_(self.h_stage[base:pos], non_blocking=True)
+            joins = []
+            if chunked:
+                staged = torch.cuda.Event()
+                staged.record(self.stream)
+                # groups of 8 classes (one merged launch each), spread over the side streams
+                groups = [chunked[i:i + 8] for i in range(0, len(chunked), 8)]
+                per_side = [groups[k::len(self.side)] for k in range(len(self.side))]
+                for side, grps in zip(self.side, per_side):
+                    if not grps:
+                        continue
+                    side.wait_event(staged)
+                    for g in grps:
+                        self._run_chunked(g, ring, side.cuda_stream)
+                    ev = torch.cuda.Event()
+                    ev.record(side)
+                    joins.append(ev)
             if wl:
                 self._run_jobs("w", wl)
-            if rl:
-                self._run_jobs("r", rl)
+            if whole:
+                self._run_jobs("r", whole)
+            for ev in joins:
+                self.stream.wait_event(ev)
             done.record(self.stream)
         return begin, done, ring
 

@@ -133,3 +133,58 @@ def test_chunked_decode_graph_replay(mj, orc):
         torch.cuda.synchronize()
         assert np.array_equal(to_np(d_out).reshape(nb, Q, P), imgs), rep
     plan.close()
+
+
+def test_jobs_mix_chunked_and_whole_with_slots(mj, orc):
+    """One decode_jobs call: long-row jobs with plans (gathered from scattered
+    projection slots, and from a plain pool) next to whole-block jobs."""
+    specs = [  # (P, Q, dirs, nblocks, plan chunk cols or None, gather)
+        (8192, 4, synth.centered_dirs(6), 5, 256, True),
+        (4096, 8, synth.centered_dirs(12), 3, 256, True),
+        (2048, 4, synth.centered_dirs(6), 4, 256, False),
+        (128, 4, synth.centered_dirs(6), 40, None, True),
+        (64, 8, synth.centered_dirs(12), 30, None, True),
+    ]
+    rng = np.random.default_rng(3)
+    jobs, expect, plans, outs = [], [], [], []
+    for c, (P, Q, dirs, nb, cols, gather) in enumerate(specs):
+        n = len(dirs)
+        imgs = synth.block_images(70 + c, 0, nb, P, Q)
+        masks = synth.erasure_masks(80 + c, nb, n, (0, n - Q))
+        enc = poisoned(orc, orc.encode_blocks(imgs, P, Q, dirs), masks, P, Q, dirs)
+        words = enc.shape[1]
+        if gather:
+            nslots = 2 * nb + 3
+            slots = rng.permutation(nslots)[:nb]
+            arena = np.full((nslots, words), POISON, dtype=np.uint64)
+            arena[slots] = enc
+            d_proj = to_dev(arena)
+            d_slots = torch.from_numpy(slots.astype(np.int64)).cuda()
+        else:
+            d_proj, d_slots = to_dev(enc), None
+        d_out = torch.full((nb * P * Q,), -1, dtype=torch.int64, device="cuda")
+        job = dict(P=P, Q=Q, dirs=dirs, nblocks=nb, images=d_out, projs=d_proj, slots=d_slots,
+                   erased=masks_to_dev(masks))
+        if cols:
+            plan = mj.Plan(dirs, Q, cols)
+            plans.append(plan)
+            job["plan"] = plan
+            job["workspace"] = torch.empty(plan.workspace_words(P, nb), dtype=torch.int64,
+                                           device="cuda")
+        jobs.append(job)
+        expect.append(imgs)
+        outs.append(d_out)
+    say(f"jobs mix: {[(j['P'], j['Q'], 'plan' in j, j['slots'] is not None) for j in jobs]}")
+    d_status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    mj.mojette_decode_jobs(jobs, status=d_status)
+    torch.cuda.synchronize()
+    assert int(d_status.item()) == 0
+    for (P, Q, *_), imgs, d_out in zip(specs, expect, outs):
+        assert np.array_equal(to_np(d_out).reshape(-1, Q, P), imgs), (P, Q)
+    # a plan for another code is refused before anything runs
+    bad = dict(jobs[0])
+    bad["plan"] = plans[1]
+    with pytest.raises(mj.MojetteError):
+        mj.mojette_decode_jobs([bad])
+    for p in plans:
+        p.close()
