@@ -128,6 +128,21 @@ int mojette_decode_batch(const uint64_t *projs, const uint16_t *erased, int64_t 
                          int32_t *status, void *stream);
 
 /*
+ * mojette_decode_batch with the decode schedule's blocks per wavefront set by
+ * the caller (an autotuner): blocks_per_wave >= 1 caps it, 0 keeps the
+ * library's choice (the most that fit in LDS, which also caps any request).
+ * Fewer blocks per wavefront spread a small batch over more compute units.
+ */
+int mojette_decode_batch_tuned(const uint64_t *projs, const uint16_t *erased, int64_t nblocks,
+                               int32_t P, int32_t Q, const int32_t *dirs, int32_t n,
+                               uint64_t *images, int32_t *status, int32_t blocks_per_wave,
+                               void *stream);
+
+/* The library's blocks per decode wavefront for this geometry (-1 on bad
+ * arguments). */
+int32_t mojette_decode_max_blocks_per_wave(const int32_t *dirs, int32_t n, int32_t P, int32_t Q);
+
+/*
  * Mixed batches: blocks of up to MOJETTE_MAX_CLASSES geometry classes (each
  * class: nblocks blocks of one P, Q and direction set) encoded or decoded in
  * ONE launch.  Classes are laid out one after another in each pool, in the
@@ -253,6 +268,30 @@ int mojette_decode_batch_chunked(const mojette_plan *plan, const uint64_t *projs
                                  const uint16_t *erased, int64_t nblocks, int32_t P,
                                  uint64_t *images, int32_t *status, uint64_t *workspace,
                                  void *stream);
+
+/*
+ * Cost model of the schedule autotuner (not part of the paper's method: it
+ * predicts how long a decode schedule takes and never touches pixel or bin
+ * bits).  A two-hidden-layer fp32 perceptron with ReLU units and one linear
+ * output, d_in inputs (1..16) and `hidden` units per layer (16 or 32):
+ *   y = w3 . relu(W2 relu(W1 x + b1) + b2) + b3,
+ * parameters packed as W1 (hidden x d_in, row-major), b1, W2 (hidden x
+ * hidden), b2, w3, b3.  All buffers are device fp32; x is n x d_in row-major.
+ */
+int32_t mojette_mlp_params(int32_t d_in, int32_t hidden);   /* parameter count, -1 if unsupported */
+int mojette_mlp_forward(const float *params, int32_t d_in, int32_t hidden, const float *x,
+                        int64_t n, float *y, void *stream);
+/* Gradient of the mean squared error L = (1/n) sum (y - t)^2 by
+ * backpropagation: grad receives the parameter count + 1 floats, the last
+ * one L.  workspace: mojette_mlp_grad_workspace() floats.  Deterministic (no
+ * atomics). */
+int64_t mojette_mlp_grad_workspace(int32_t d_in, int32_t hidden, int64_t n);
+int mojette_mlp_grad(const float *params, int32_t d_in, int32_t hidden, const float *x,
+                     const float *t, int64_t n, float *grad, float *workspace, void *stream);
+/* One Adam step (Kingma and Ba, with bias correction; step counts from 1)
+ * on params in place; m and v are the moment buffers. */
+int mojette_mlp_adam(float *params, const float *grad, float *m, float *v, int32_t nparams,
+                     float lr, float beta1, float beta2, float eps, int32_t step, void *stream);
 
 /* Ring length (words per row) the decoder needs for this geometry: the
  * longest distance, over every choice of Q survivors, between a pixel a row

@@ -128,6 +128,9 @@ def lib() -> ctypes.CDLL:
         "mojette_decode": ([vp, vp, i32, vp, i32, i32, i32, vp, vp], ctypes.c_int),
         "mojette_encode_batch": ([vp, i64, i32, i32, vp, i32, vp, vp], ctypes.c_int),
         "mojette_decode_batch": ([vp, vp, i64, i32, i32, vp, i32, vp, vp, vp], ctypes.c_int),
+        "mojette_decode_batch_tuned": ([vp, vp, i64, i32, i32, vp, i32, vp, vp, i32, vp],
+                                       ctypes.c_int),
+        "mojette_decode_max_blocks_per_wave": ([vp, i32, i32, i32], i32),
         "mojette_classes_layout": ([vp, i32, vp, vp], ctypes.c_int),
         "mojette_encode_classes": ([vp, i32, vp, vp, vp], ctypes.c_int),
         "mojette_decode_classes": ([vp, i32, vp, vp, vp, vp, vp], ctypes.c_int),
@@ -138,6 +141,12 @@ def lib() -> ctypes.CDLL:
         "mojette_chunk_matrix": ([vp, i32, i32, vp, vp, i64], i64),
         "mojette_decode_chunked_workspace": ([vp, i32, i64], i64),
         "mojette_decode_batch_chunked": ([vp, vp, vp, i64, i32, vp, vp, vp, vp], ctypes.c_int),
+        "mojette_mlp_params": ([i32, i32], i32),
+        "mojette_mlp_forward": ([vp, i32, i32, vp, i64, vp, vp], ctypes.c_int),
+        "mojette_mlp_grad_workspace": ([i32, i32, i64], i64),
+        "mojette_mlp_grad": ([vp, i32, i32, vp, vp, i64, vp, vp, vp], ctypes.c_int),
+        "mojette_mlp_adam": ([vp, vp, vp, vp, i32, ctypes.c_float, ctypes.c_float,
+                              ctypes.c_float, ctypes.c_float, i32, vp], ctypes.c_int),
         "mojette_fill_splitmix64": ([vp, i64, u64, u64, vp], ctypes.c_int),
         "mojette_copy_words": ([vp, vp, i64, vp], ctypes.c_int),
     }
@@ -168,10 +177,13 @@ def exported_symbols() -> list[str]:
         "mojette_strerror", "mojette_last_hip_error", "mojette_proj_size",
         "mojette_bin_offset", "mojette_block_words", "mojette_decode_ring", "mojette_encode",
         "mojette_decode", "mojette_encode_batch", "mojette_decode_batch",
+        "mojette_decode_batch_tuned", "mojette_decode_max_blocks_per_wave",
         "mojette_classes_layout", "mojette_encode_classes", "mojette_decode_classes",
         "mojette_encode_jobs", "mojette_decode_jobs", "mojette_plan_create",
         "mojette_plan_destroy", "mojette_chunk_matrix", "mojette_decode_chunked_workspace",
-        "mojette_decode_batch_chunked", "mojette_fill_splitmix64", "mojette_copy_words",
+        "mojette_decode_batch_chunked", "mojette_mlp_params", "mojette_mlp_forward",
+        "mojette_mlp_grad_workspace", "mojette_mlp_grad", "mojette_mlp_adam",
+        "mojette_fill_splitmix64", "mojette_copy_words",
     ]
 
 
@@ -280,6 +292,27 @@ def mojette_decode_batch(projs, erased, nblocks: int, P: int, Q: int, dirs, imag
                                     nblocks, P, Q, arr, n, _word_tensor(images, "images"),
                                     _dev_ptr(status, "status"), _stream(stream))
     return _check(rc, "mojette_decode_batch", check)
+
+
+def mojette_decode_batch_tuned(projs, erased, nblocks: int, P: int, Q: int, dirs, images,
+                               blocks_per_wave: int, status=None, stream=None,
+                               check: bool = True) -> int:
+    import torch
+
+    arr, n = _i32_array(dirs)
+    if erased is not None and erased.dtype not in (torch.int16, torch.uint16):
+        raise ValueError("erased must be 16-bit masks")
+    rc = lib().mojette_decode_batch_tuned(_word_tensor(projs, "projs"),
+                                          _dev_ptr(erased, "erased"), nblocks, P, Q, arr, n,
+                                          _word_tensor(images, "images"),
+                                          _dev_ptr(status, "status"), blocks_per_wave,
+                                          _stream(stream))
+    return _check(rc, "mojette_decode_batch_tuned", check)
+
+
+def mojette_decode_max_blocks_per_wave(dirs, P: int, Q: int) -> int:
+    arr, n = _i32_array(dirs)
+    return int(lib().mojette_decode_max_blocks_per_wave(arr, n, P, Q))
 
 
 def mojette_classes_layout(classes) -> tuple[int, int]:
@@ -400,6 +433,46 @@ def mojette_decode_batch_chunked(plan: Plan, projs, erased, nblocks: int, P: int
                                             _word_tensor(images, "images"),
                                             _dev_ptr(status, "status"), ws, _stream(stream))
     return _check(rc, "mojette_decode_batch_chunked", check)
+
+
+def _f32_tensor(t, name: str) -> int:
+    import torch
+
+    if t.dtype != torch.float32:
+        raise ValueError(f"{name} must be float32")
+    return _dev_ptr(t, name)
+
+
+def mojette_mlp_params(d_in: int, hidden: int) -> int:
+    return int(lib().mojette_mlp_params(d_in, hidden))
+
+
+def mojette_mlp_forward(params, d_in: int, hidden: int, x, y, stream=None, check: bool = True):
+    n = x.shape[0] if x.dim() > 1 else x.numel() // d_in
+    rc = lib().mojette_mlp_forward(_f32_tensor(params, "params"), d_in, hidden,
+                                   _f32_tensor(x, "x"), n, _f32_tensor(y, "y"), _stream(stream))
+    return _check(rc, "mojette_mlp_forward", check)
+
+
+def mojette_mlp_grad_workspace(d_in: int, hidden: int, n: int) -> int:
+    return int(lib().mojette_mlp_grad_workspace(d_in, hidden, n))
+
+
+def mojette_mlp_grad(params, d_in: int, hidden: int, x, t, grad, workspace, stream=None,
+                     check: bool = True):
+    n = t.numel()
+    rc = lib().mojette_mlp_grad(_f32_tensor(params, "params"), d_in, hidden, _f32_tensor(x, "x"),
+                                _f32_tensor(t, "t"), n, _f32_tensor(grad, "grad"),
+                                _f32_tensor(workspace, "workspace"), _stream(stream))
+    return _check(rc, "mojette_mlp_grad", check)
+
+
+def mojette_mlp_adam(params, grad, m, v, lr: float, beta1: float, beta2: float, eps: float,
+                     step: int, stream=None, check: bool = True):
+    rc = lib().mojette_mlp_adam(_f32_tensor(params, "params"), _f32_tensor(grad, "grad"),
+                                _f32_tensor(m, "m"), _f32_tensor(v, "v"), params.numel(), lr,
+                                beta1, beta2, eps, step, _stream(stream))
+    return _check(rc, "mojette_mlp_adam", check)
 
 
 def mojette_fill_splitmix64(dst, nwords: int, seed: int, start: int = 0, stream=None,

@@ -6,6 +6,7 @@
 #include <map>
 #include <mutex>
 #include <new>
+#include <thread>
 #include <vector>
 
 #include "mj_internal.h"
@@ -371,32 +372,54 @@ int mojette_plan_create(const int32_t *dirs, int32_t n, int32_t Q, int32_t chunk
     std::sort(order.begin(), order.end(), [&](int x, int y) { return dirs[x] < dirs[y]; });
     std::vector<int> sp(n);
     for (int i = 0; i < n; ++i) sp[i] = dirs[order[i]];
+    // every Q-subset of the directions, in lexicographic order of sorted index
+    std::vector<std::vector<int>> subsets;
+    {
+        std::vector<int> pick(Q);
+        for (int i = 0; i < Q; ++i) pick[i] = i;
+        while (true) {
+            subsets.push_back(pick);
+            int i = Q - 1;
+            while (i >= 0 && pick[i] == n - Q + i) --i;
+            if (i < 0) break;
+            ++pick[i];
+            for (int j = i + 1; j < Q; ++j) pick[j] = pick[j - 1] + 1;
+        }
+    }
+    const size_t nsub = subsets.size();
+    std::vector<int> Es(nsub, 0);
+    std::vector<std::vector<uint64_t>> Ts(nsub);
+    std::vector<char> ok(nsub, 0);
+    // the matrices are independent: host threads share the subsets
+    const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    const unsigned nth = (unsigned)std::min<size_t>(hw, (nsub + 7) / 8);
+    auto work = [&](unsigned w) {
+        for (size_t k = w; k < nsub; k += nth) {
+            int32_t ps[MOJETTE_MAX_ROWS];
+            for (int r = 0; r < Q; ++r) ps[r] = sp[subsets[k][r]];
+            ok[k] = mj::chunk_transfer(ps, Q, tiles, Es[k], Ts[k]) ? 1 : 0;
+        }
+    };
+    if (nth <= 1) {
+        work(0);
+    } else {
+        std::vector<std::thread> pool;
+        for (unsigned w = 0; w < nth; ++w) pool.emplace_back(work, w);
+        for (auto &th : pool) th.join();
+    }
     std::vector<int32_t> lut((size_t)1 << n, -1), cols;
     std::vector<int64_t> toff;
     std::vector<uint64_t> tmat;
-    std::vector<int> pick(Q);
-    for (int i = 0; i < Q; ++i) pick[i] = i;
     int max_cols = 0;
-    while (true) {
-        int32_t ps[MOJETTE_MAX_ROWS];
+    for (size_t k = 0; k < nsub; ++k) {
+        if (!ok[k]) return MOJETTE_ENOTSUP;
         uint32_t used = 0;
-        for (int r = 0; r < Q; ++r) {
-            ps[r] = sp[pick[r]];
-            used |= 1u << order[pick[r]];
-        }
-        int E = 0;
-        std::vector<uint64_t> T;
-        if (!mj::chunk_transfer(ps, Q, tiles, E, T)) return MOJETTE_ENOTSUP;
+        for (int r = 0; r < Q; ++r) used |= 1u << order[subsets[k][r]];
         lut[used] = (int32_t)cols.size();
-        cols.push_back(E);
+        cols.push_back(Es[k]);
         toff.push_back((int64_t)tmat.size());
-        tmat.insert(tmat.end(), T.begin(), T.end());
-        max_cols = std::max(max_cols, E);
-        int i = Q - 1;
-        while (i >= 0 && pick[i] == n - Q + i) --i;
-        if (i < 0) break;
-        ++pick[i];
-        for (int j = i + 1; j < Q; ++j) pick[j] = pick[j - 1] + 1;
+        tmat.insert(tmat.end(), Ts[k].begin(), Ts[k].end());
+        max_cols = std::max(max_cols, Es[k]);
     }
     if (Q * max_cols > mj::kCarryMaxState) return MOJETTE_ENOTSUP;
     int R = ring_length(sp, Q);
@@ -538,6 +561,47 @@ int mojette_decode_batch_chunked(const mojette_plan *plan, const uint64_t *projs
     a.status = status;
     a.nblocks = nblocks;
     return chunked_launch(plan, nchunks, a, Q, false, workspace, (hipStream_t)stream);
+}
+
+int mojette_decode_batch_tuned(const uint64_t *projs, const uint16_t *erased, int64_t nblocks,
+                               int32_t P, int32_t Q, const int32_t *dirs, int32_t n,
+                               uint64_t *images, int32_t *status, int32_t blocks_per_wave,
+                               void *stream) {
+    if (nblocks < 0 || blocks_per_wave < 0 || !geometry_ok(dirs, n, P, Q)) return MOJETTE_EINVAL;
+    if (nblocks == 0) return MOJETTE_OK;
+    if (!projs || !images) return MOJETTE_EINVAL;
+    mj::DecodeArgs a{};
+    const int rc = decode_setup(dirs, n, P, Q, a);
+    if (rc != MOJETTE_OK) return rc;
+    if (blocks_per_wave > 0) a.nb = std::min(a.nb, (int)blocks_per_wave);
+    int64_t off = 0;
+    for (int i = 0; i < n; ++i) {
+        a.off[i] = (int32_t)off;
+        off += mojette_proj_size(dirs[i], P, Q);
+    }
+    if ((int64_t)a.nb * off * 8 >= ((int64_t)1 << 31) ||
+        (int64_t)a.nb * P * Q * 8 >= ((int64_t)1 << 31))
+        return MOJETTE_ENOTSUP;
+    a.pool = projs;
+    a.proj_stride = off;
+    a.images = images;
+    a.img_stride = (int64_t)P * Q;
+    a.masks = erased;
+    a.mask_uniform = 0;
+    a.status = status;
+    a.nblocks = nblocks;
+    const int64_t batches = (nblocks + a.nb - 1) / a.nb;
+    const int grid = (int)std::min<int64_t>(batches, kDecodeGridCap);
+    clear_stale_error();
+    return status_of(mj::launch_decode(Q, mj::kLaunchPool, a, grid, (hipStream_t)stream));
+}
+
+int32_t mojette_decode_max_blocks_per_wave(const int32_t *dirs, int32_t n, int32_t P,
+                                           int32_t Q) {
+    if (!geometry_ok(dirs, n, P, Q)) return -1;
+    mj::DecodeArgs a{};
+    if (decode_setup(dirs, n, P, Q, a) != MOJETTE_OK) return -1;
+    return a.nb;
 }
 
 int mojette_classes_layout(const mojette_class *classes, int32_t nclasses, int64_t *image_words,
