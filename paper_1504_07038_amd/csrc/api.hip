@@ -17,6 +17,7 @@ using mj::kMaxDirs;
 using mj::kMaxRows;
 
 constexpr size_t kLdsLimit = 64 * 1024;        // dynamic LDS per workgroup used by the kernels
+constexpr size_t kMixedEncodeLds = 20 * 1024;  // per workgroup in mixed encode launches
 constexpr int kMaxP = 1 << 24;                 // keeps every bin index inside int32
 constexpr int kMaxAbsP = 1 << 16;
 constexpr int kEncodeGridCap = 256 * 64;       // workgroups; larger batches loop inside the kernel
@@ -46,17 +47,22 @@ thread_local hipError_t g_last_hip = hipSuccess;
 // Encode tiling: the whole row when it fits, else the widest multiple of 64
 // columns whose tile plus halo fits the LDS budget.  Four waves per
 // workgroup when their four tiles fit (at least min(P, 256) columns each),
-// else two, else one; `max_waves` caps that choice.
+// else two, else one; `max_waves` caps that choice.  `lds_budget` (bytes per
+// workgroup) defaults to all the LDS a workgroup may take; mixed launches,
+// which give every workgroup the LDS of their largest class, pass less so
+// that more wavefronts share a compute unit.
 bool encode_tiling(const int32_t *dirs, int32_t n, int32_t P, int32_t Q, mj::EncodeArgs &a,
-                   int max_waves = mj::kEncodeWaves) {
+                   int max_waves = mj::kEncodeWaves, size_t lds_budget = kLdsLimit) {
     int maxabs = 0;
     for (int i = 0; i < n; ++i) maxabs = std::max(maxabs, std::abs(dirs[i]));
     const int H = (Q - 1) * maxabs;
     const int want = std::min(P, 256);
+    // a tile of at least 128 columns beside its halo always fits
+    lds_budget = std::min(kLdsLimit, std::max(lds_budget, (size_t)Q * (2 * H + 128) * 8));
     int waves = max_waves;
     size_t cols_fit = 0;
     for (; waves >= 1; waves /= 2) {
-        cols_fit = kLdsLimit / ((size_t)waves * Q * sizeof(uint64_t));
+        cols_fit = lds_budget / ((size_t)waves * Q * sizeof(uint64_t));
         if (cols_fit >= (size_t)(2 * H + want) || (waves == 1 && cols_fit >= (size_t)(2 * H + 64)))
             break;
     }
@@ -640,7 +646,8 @@ int mojette_encode_jobs(const mojette_job *jobs, int32_t njobs, void *stream) {
     for (int c = 0; c < njobs; ++c) {
         order[c] = c;
         const mojette_job &j = jobs[c];
-        if (!encode_tiling(j.dirs, j.n, j.P, j.Q, geo[c], 1)) return MOJETTE_ENOTSUP;
+        if (!encode_tiling(j.dirs, j.n, j.P, j.Q, geo[c], 1, kMixedEncodeLds))
+            return MOJETTE_ENOTSUP;
     }
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
         const int64_t wx = (int64_t)geo[x].W * jobs[x].Q * jobs[x].n;
