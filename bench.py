@@ -37,7 +37,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="4k_6_4", choices=sorted(WORKLOADS) + ["mixed", "serving", "tune"])
+    ap.add_argument("--workload", default="4k_6_4", choices=sorted(WORKLOADS) + ["mixed", "serving", "tune", "chunked"])
     ap.add_argument("--mixed-blocks", type=int, default=50000,
                     help="blocks of the mixed workload (16 size x code classes)")
     ap.add_argument("--qps", default="10000,20000,50000,100000,200000,500000,1000000,2000000",
@@ -202,6 +202,9 @@ def main():
         return
     if args.workload == "tune":
         run_tune(args)
+        return
+    if args.workload == "chunked":
+        run_chunked(args)
         return
 
     import numpy as np
@@ -508,6 +511,72 @@ def run_mixed(args):
     for pl in plans.values():
         pl.close()
     if not ok:
+        sys.exit(1)
+
+
+def run_chunked(args):
+    """Chunked against whole-block decode of 1 MB blocks ((4,2): P=32768;
+    (8,4): P=16384), one block and 256 blocks per launch, HIP events."""
+    import numpy as np
+    import torch
+
+    import paper_1504_07038_amd as mj
+    import synth
+
+    def timed(fn, reps):
+        st = torch.cuda.current_stream()
+        fn()
+        torch.cuda.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(reps)]
+        for a, b in evs:
+            a.record(st)
+            fn()
+            b.record(st)
+        torch.cuda.synchronize()
+        return float(np.median([a.elapsed_time(b) for a, b in evs]))
+
+    rows, ok_all = [], True
+    for k, m, P, cols in ((4, 2, 32768, 256), (8, 4, 16384, 256)):
+        dirs = synth.centered_dirs(k + m)
+        plan = mj.Plan(dirs, k, cols)
+        for nb in (1, 256):
+            words = mj.mojette_block_words(dirs, P, k)
+            img = torch.empty(nb * P * k, dtype=torch.int64, device="cuda")
+            mj.mojette_fill_splitmix64(img, img.numel(), synth.SEED_DATA)
+            proj = torch.empty(nb * words, dtype=torch.int64, device="cuda")
+            mj.mojette_encode_batch(img, nb, P, k, dirs, proj)
+            masks = torch.from_numpy(synth.erasure_masks(synth.SEED_ERASE, nb, k + m, m)
+                                     .view(np.int16)).cuda()
+            out = torch.empty_like(img)
+            ws = torch.empty(plan.workspace_words(P, nb), dtype=torch.int64, device="cuda")
+            t_whole = timed(lambda: mj.mojette_decode_batch(proj, masks, nb, P, k, dirs, out),
+                            args.steps)
+            ok = bool(torch.equal(out, img))
+            out.zero_()
+            t_chunk = timed(lambda: mj.mojette_decode_batch_chunked(plan, proj, masks, nb, P, out,
+                                                                    ws), args.steps)
+            ok = ok and bool(torch.equal(out, img))
+            ok_all = ok_all and ok
+            rows.append({"code": [k, m], "P": P, "blocks": nb, "chunk_cols": cols,
+                         "whole_ms": round(t_whole, 4), "chunked_ms": round(t_chunk, 4),
+                         "speedup": round(t_whole / t_chunk, 2),
+                         "chunked_user_GBps": round(nb * P * k * 8 / (t_chunk * 1e-3) / 1e9, 1),
+                         "exact": ok})
+        plan.close()
+    best = max(rows, key=lambda r: r["speedup"])
+    rec = {
+        "metric": "decode time of 1 MB blocks, chunked over whole-block sweep",
+        "value": best["speedup"], "unit": "x", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+        "ms_per_step": best["chunked_ms"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": "chunked: 1 MB blocks, codes (4,2) P=32768 and (8,4) P=16384, "
+                               "m erasures per block, 1 or 256 blocks per launch",
+                   "parallelism": "single GPU"},
+        "rows": rows, "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(rec), flush=True)
+    if not ok_all:
         sys.exit(1)
 
 

@@ -18,6 +18,7 @@ using mj::kMaxRows;
 
 constexpr size_t kLdsLimit = 64 * 1024;        // dynamic LDS per workgroup used by the kernels
 constexpr size_t kMixedEncodeLds = 20 * 1024;  // per workgroup in mixed encode launches
+constexpr size_t kMixedDecodeLds = 40 * 1024;  // per workgroup in mixed decode launches
 constexpr int kMaxP = 1 << 24;                 // keeps every bin index inside int32
 constexpr int kMaxAbsP = 1 << 16;
 constexpr int kEncodeGridCap = 256 * 64;       // workgroups; larger batches loop inside the kernel
@@ -710,6 +711,11 @@ static int decode_jobs_launch(const mojette_job *jobs, const std::vector<int> &w
         mj::DecodeClass &d = tab.cls[k];
         const int rc = decode_setup(jb.dirs, jb.n, jb.P, jb.Q, d);
         if (rc != MOJETTE_OK) return rc;
+        // every workgroup of a mixed launch gets the LDS of its largest
+        // class: long-ring classes take fewer blocks per wavefront so that
+        // more wavefronts share a compute unit
+        while (d.nb > 1 && mj::decode_lds_bytes(jb.Q, d.nb, d.ring_stride) > kMixedDecodeLds) --d.nb;
+        d.nb = std::min(d.nb, std::max(1, mj::decode_max_blocks_per_wave(jb.Q) / 2));   // half-slot bodies
         if (!gather && ((int64_t)d.nb * bw[oc] * 8 >= ((int64_t)1 << 31) ||
                         (int64_t)d.nb * jb.P * jb.Q * 8 >= ((int64_t)1 << 31)))
             return MOJETTE_ENOTSUP;

@@ -7,6 +7,9 @@ namespace mj {
 // (heaviest first), one wavefront per workgroup.  QMASK has bit Q set for
 // every row count the launch may meet; only those bodies are compiled in, so
 // the kernel's registers are those of its largest body, not of all sixteen.
+// The bodies are compiled for half the block slots, which leaves registers
+// for more wavefronts per SIMD (measured: a mixed step of 16 classes ran
+// 1.18x faster than with full-slot bodies).
 template <unsigned QMASK, bool GATHER>
 __global__ __launch_bounds__(kWave) void decode_classes_kernel(DecodeClassTable tab) {
     const int64_t total = tab.first_item[tab.nclasses];
@@ -19,7 +22,7 @@ __global__ __launch_bounds__(kWave) void decode_classes_kernel(DecodeClassTable 
 #define MJ_DEC_CASE(QQ)                                                                  \
     case QQ:                                                                             \
         if constexpr ((QMASK >> QQ) & 1u)                                               \
-            decode_batch<QQ, kDecodeTile, !GATHER, kWhole, full_slots<QQ>()>(a, batch);   \
+            decode_batch<QQ, kDecodeTile, !GATHER, kWhole, half_slots<QQ>()>(a, batch);   \
         break;
             MJ_DEC_CASE(1) MJ_DEC_CASE(2) MJ_DEC_CASE(3) MJ_DEC_CASE(4)
             MJ_DEC_CASE(5) MJ_DEC_CASE(6) MJ_DEC_CASE(7) MJ_DEC_CASE(8)
