@@ -129,18 +129,22 @@ int mojette_decode_batch(const uint64_t *projs, const uint16_t *erased, int64_t 
 
 /*
  * mojette_decode_batch with the decode schedule's blocks per wavefront set by
- * the caller (an autotuner): blocks_per_wave >= 1 caps it, 0 keeps the
- * library's choice (the most that fit in LDS, which also caps any request).
- * Fewer blocks per wavefront spread a small batch over more compute units.
+ * the caller (an autotuner): blocks_per_wave >= 1 asks for that many (capped
+ * by what fits in LDS), 0 keeps the library's choice.  Fewer blocks per
+ * wavefront spread a small batch over more compute units and leave LDS for
+ * more wavefronts per unit; more give each wavefront more independent work.
  */
 int mojette_decode_batch_tuned(const uint64_t *projs, const uint16_t *erased, int64_t nblocks,
                                int32_t P, int32_t Q, const int32_t *dirs, int32_t n,
                                uint64_t *images, int32_t *status, int32_t blocks_per_wave,
                                void *stream);
 
-/* The library's blocks per decode wavefront for this geometry (-1 on bad
- * arguments). */
+/* Blocks per decode wavefront for this geometry: the most that fit in LDS,
+ * and the library's own choice (all when their rings take at most 34 KB of
+ * LDS, else at most half of them within 26 KB).  -1 on bad arguments. */
 int32_t mojette_decode_max_blocks_per_wave(const int32_t *dirs, int32_t n, int32_t P, int32_t Q);
+int32_t mojette_decode_default_blocks_per_wave(const int32_t *dirs, int32_t n, int32_t P,
+                                               int32_t Q);
 
 /*
  * Mixed batches: blocks of up to MOJETTE_MAX_CLASSES geometry classes (each

@@ -131,6 +131,7 @@ def lib() -> ctypes.CDLL:
         "mojette_decode_batch_tuned": ([vp, vp, i64, i32, i32, vp, i32, vp, vp, i32, vp],
                                        ctypes.c_int),
         "mojette_decode_max_blocks_per_wave": ([vp, i32, i32, i32], i32),
+        "mojette_decode_default_blocks_per_wave": ([vp, i32, i32, i32], i32),
         "mojette_classes_layout": ([vp, i32, vp, vp], ctypes.c_int),
         "mojette_encode_classes": ([vp, i32, vp, vp, vp], ctypes.c_int),
         "mojette_decode_classes": ([vp, i32, vp, vp, vp, vp, vp], ctypes.c_int),
@@ -178,6 +179,7 @@ def exported_symbols() -> list[str]:
         "mojette_bin_offset", "mojette_block_words", "mojette_decode_ring", "mojette_encode",
         "mojette_decode", "mojette_encode_batch", "mojette_decode_batch",
         "mojette_decode_batch_tuned", "mojette_decode_max_blocks_per_wave",
+        "mojette_decode_default_blocks_per_wave",
         "mojette_classes_layout", "mojette_encode_classes", "mojette_decode_classes",
         "mojette_encode_jobs", "mojette_decode_jobs", "mojette_plan_create",
         "mojette_plan_destroy", "mojette_chunk_matrix", "mojette_decode_chunked_workspace",
@@ -313,6 +315,11 @@ def mojette_decode_batch_tuned(projs, erased, nblocks: int, P: int, Q: int, dirs
 def mojette_decode_max_blocks_per_wave(dirs, P: int, Q: int) -> int:
     arr, n = _i32_array(dirs)
     return int(lib().mojette_decode_max_blocks_per_wave(arr, n, P, Q))
+
+
+def mojette_decode_default_blocks_per_wave(dirs, P: int, Q: int) -> int:
+    arr, n = _i32_array(dirs)
+    return int(lib().mojette_decode_default_blocks_per_wave(arr, n, P, Q))
 
 
 def mojette_classes_layout(classes) -> tuple[int, int]:

@@ -19,6 +19,8 @@ using mj::kMaxRows;
 constexpr size_t kLdsLimit = 64 * 1024;        // dynamic LDS per workgroup used by the kernels
 constexpr size_t kMixedEncodeLds = 20 * 1024;  // per workgroup in mixed encode launches
 constexpr size_t kMixedDecodeLds = 40 * 1024;  // per workgroup in mixed decode launches
+constexpr size_t kDecodeLdsShare = 34 * 1024;  // decode LDS per wavefront, short rings
+constexpr size_t kDecodeLdsLong = 26 * 1024;   // decode LDS per wavefront, long rings
 constexpr int kMaxP = 1 << 24;                 // keeps every bin index inside int32
 constexpr int kMaxAbsP = 1 << 16;
 constexpr int kEncodeGridCap = 256 * 64;       // workgroups; larger batches loop inside the kernel
@@ -162,9 +164,19 @@ int decode_setup(const int32_t *dirs, int32_t n, int32_t P, int32_t Q, A &a) {
     if (R < 0) return MOJETTE_EINVAL;
     a.R = R;
     a.ring_stride = R + 1;  // odd stride spreads the rows over the LDS banks
+    // Blocks per wavefront: all the lanes allow when their rings fit a 34 KB
+    // share of LDS (short rings: the (6,4) code's 32 blocks); otherwise at
+    // most half of them (the body compiled for half the slots needs far
+    // fewer registers) and no more than 26 KB, so that several wavefronts
+    // share a compute unit.  Measured on 2^19 blocks: (12,8) 3 blocks per
+    // wavefront 1.25x faster than 7; (6,3) 10 blocks 1.3x faster than 20;
+    // (12,4) 2 blocks 1.17x faster than 5.
     a.nb = mj::decode_max_blocks_per_wave(Q);
-    while (a.nb > 0 && mj::decode_lds_bytes(Q, a.nb, a.ring_stride) > kLdsLimit) --a.nb;
-    if (a.nb < 1) return MOJETTE_ENOTSUP;
+    if (mj::decode_lds_bytes(Q, a.nb, a.ring_stride) > kDecodeLdsShare) {
+        a.nb = std::max(1, a.nb / 2);
+        while (a.nb > 1 && mj::decode_lds_bytes(Q, a.nb, a.ring_stride) > kDecodeLdsLong) --a.nb;
+    }
+    if (mj::decode_lds_bytes(Q, a.nb, a.ring_stride) > kLdsLimit) return MOJETTE_ENOTSUP;
     a.P = P;
     a.n = n;
     return MOJETTE_OK;
@@ -580,7 +592,10 @@ int mojette_decode_batch_tuned(const uint64_t *projs, const uint16_t *erased, in
     mj::DecodeArgs a{};
     const int rc = decode_setup(dirs, n, P, Q, a);
     if (rc != MOJETTE_OK) return rc;
-    if (blocks_per_wave > 0) a.nb = std::min(a.nb, (int)blocks_per_wave);
+    if (blocks_per_wave > 0) {
+        a.nb = std::min(mj::decode_max_blocks_per_wave(Q), (int)blocks_per_wave);
+        while (a.nb > 1 && mj::decode_lds_bytes(Q, a.nb, a.ring_stride) > kLdsLimit) --a.nb;
+    }
     int64_t off = 0;
     for (int i = 0; i < n; ++i) {
         a.off[i] = (int32_t)off;
@@ -605,6 +620,16 @@ int mojette_decode_batch_tuned(const uint64_t *projs, const uint16_t *erased, in
 
 int32_t mojette_decode_max_blocks_per_wave(const int32_t *dirs, int32_t n, int32_t P,
                                            int32_t Q) {
+    if (!geometry_ok(dirs, n, P, Q)) return -1;
+    mj::DecodeArgs a{};
+    if (decode_setup(dirs, n, P, Q, a) != MOJETTE_OK) return -1;
+    int nb = mj::decode_max_blocks_per_wave(Q);
+    while (nb > 1 && mj::decode_lds_bytes(Q, nb, a.ring_stride) > kLdsLimit) --nb;
+    return nb;
+}
+
+int32_t mojette_decode_default_blocks_per_wave(const int32_t *dirs, int32_t n, int32_t P,
+                                               int32_t Q) {
     if (!geometry_ok(dirs, n, P, Q)) return -1;
     mj::DecodeArgs a{};
     if (decode_setup(dirs, n, P, Q, a) != MOJETTE_OK) return -1;

@@ -51,10 +51,11 @@ class Workload:
 def candidates(w: Workload):
     """Every schedule the tuner considers for w."""
     full = mj.mojette_decode_max_blocks_per_wave(w.dirs, w.P, w.k)
-    out = []
+    out = [("whole", mj.mojette_decode_default_blocks_per_wave(w.dirs, w.P, w.k))]
     nb = full
-    while nb >= 1 and len(out) < 4:
-        out.append(("whole", nb))
+    while nb >= 1 and len(out) < 5:
+        if ("whole", nb) not in out:
+            out.append(("whole", nb))
         nb //= 2
     for cols in CHUNK_COLS:
         if (w.P // TILE) // (cols // TILE) >= 2:
@@ -63,8 +64,8 @@ def candidates(w: Workload):
 
 
 def default_schedule(w: Workload):
-    """The untuned method: whole blocks, as many per wavefront as fit."""
-    return ("whole", mj.mojette_decode_max_blocks_per_wave(w.dirs, w.P, w.k))
+    """The untuned method: whole blocks, the library's blocks per wavefront."""
+    return ("whole", mj.mojette_decode_default_blocks_per_wave(w.dirs, w.P, w.k))
 
 
 def features(w: Workload, s) -> np.ndarray:
