@@ -22,7 +22,8 @@ __global__ __launch_bounds__(kWave) void decode_classes_kernel(DecodeClassTable 
 #define MJ_DEC_CASE(QQ)                                                                  \
     case QQ:                                                                             \
         if constexpr ((QMASK >> QQ) & 1u)                                               \
-            decode_batch<QQ, kDecodeTile, !GATHER, kWhole, half_slots<QQ>()>(a, batch);   \
+            decode_batch<QQ, kDecodeTile, !GATHER, kWhole, half_slots<QQ>(),              \
+                         DecodeClass, 0>(a, batch);                                          \
         break;
             MJ_DEC_CASE(1) MJ_DEC_CASE(2) MJ_DEC_CASE(3) MJ_DEC_CASE(4)
             MJ_DEC_CASE(5) MJ_DEC_CASE(6) MJ_DEC_CASE(7) MJ_DEC_CASE(8)

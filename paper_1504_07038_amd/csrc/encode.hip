@@ -6,7 +6,8 @@
 // LDS with coalesced loads, zero-filled outside the image so that no bin
 // needs a bounds check, then each lane produces consecutive bins of one
 // projection at a time, so every store instruction writes 64 contiguous
-// words of a projection.
+// words of a projection.  (Non-temporal loads or stores made it slower on the
+// MI355X: 1.73 and 1.77 against 1.93 TB/s of user data for 4 KB blocks.)
 #include "mj_internal.h"
 
 namespace mj {

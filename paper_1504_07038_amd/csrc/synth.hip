@@ -28,10 +28,33 @@ struct alignas(16) W2 {
     uint64_t x, y;
 };
 
+// 16-byte words, 8 per thread per pass (all loads issued before the stores),
+// non-temporal: the fastest of the streaming copies measured on the MI355X
+// (5.8 TB/s for 8 GiB each way, against 5.0-5.4 for one word per thread).
+constexpr int kCopyUnroll = 8;
+
 __global__ void copy16_kernel(W2 *dst, const W2 *src, int64_t n2) {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += stride)
-        dst[i] = src[i];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x * kCopyUnroll;
+    for (int64_t b = (int64_t)blockIdx.x * blockDim.x * kCopyUnroll + threadIdx.x; b < n2;
+         b += stride) {
+        uint64_t x[kCopyUnroll], y[kCopyUnroll];
+#pragma unroll
+        for (int u = 0; u < kCopyUnroll; ++u) {
+            const int64_t i = b + (int64_t)u * blockDim.x;
+            if (i < n2) {
+                x[u] = __builtin_nontemporal_load(&src[i].x);
+                y[u] = __builtin_nontemporal_load(&src[i].y);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kCopyUnroll; ++u) {
+            const int64_t i = b + (int64_t)u * blockDim.x;
+            if (i < n2) {
+                __builtin_nontemporal_store(x[u], &dst[i].x);
+                __builtin_nontemporal_store(y[u], &dst[i].y);
+            }
+        }
+    }
 }
 
 __global__ void copy8_kernel(uint64_t *dst, const uint64_t *src, int64_t n) {
@@ -65,8 +88,10 @@ int mojette_copy_words(uint64_t *dst, const uint64_t *src, int64_t nwords, void 
     const bool aligned = ((((uintptr_t)dst) | ((uintptr_t)src)) & 15u) == 0 && (nwords % 2) == 0;
     if (aligned) {
         const int64_t n2 = nwords / 2;
-        hipLaunchKernelGGL(copy16_kernel, dim3(grid_for(n2, 256)), dim3(256), 0,
-                           (hipStream_t)stream, (W2 *)dst, (const W2 *)src, n2);
+        const int64_t per_block = 1024 * kCopyUnroll;
+        const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((n2 + per_block - 1) / per_block, 8192));
+        hipLaunchKernelGGL(copy16_kernel, dim3(grid), dim3(1024), 0, (hipStream_t)stream,
+                           (W2 *)dst, (const W2 *)src, n2);
     } else {
         hipLaunchKernelGGL(copy8_kernel, dim3(grid_for(nwords, 256)), dim3(256), 0,
                            (hipStream_t)stream, dst, src, nwords);
