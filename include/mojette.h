@@ -258,7 +258,8 @@ int64_t mojette_chunk_matrix(const int32_t *p_sorted, int32_t Q, int32_t chunk_c
 
 /* Device workspace (words) a chunked decode of nblocks blocks of row length
  * P needs; 0 when P is too short to cut (the call then decodes whole
- * blocks).  -1 on bad arguments. */
+ * blocks).  It is non-decreasing in nblocks: a workspace sized for nblocks
+ * serves every call on at most nblocks blocks.  -1 on bad arguments. */
 int64_t mojette_decode_chunked_workspace(const mojette_plan *plan, int32_t P, int64_t nblocks);
 
 /*

@@ -23,10 +23,12 @@
 
 namespace mj {
 
-bool chunk_transfer(const int32_t *ps, int Q, int tiles, int &E, std::vector<uint64_t> &T) {
-    constexpr int TW = kDecodeTile;
-    std::vector<int> A(Q), d(Q);
-    std::vector<bool> isx(Q);
+// Schedule of one survivor set: A_r, row parity, first column d_r of tile 0.
+static void survivor_schedule(const int32_t *ps, int Q, std::vector<int> &d,
+                              std::vector<bool> &isx, int &dmin) {
+    std::vector<int> A(Q);
+    d.assign(Q, 0);
+    isx.assign(Q, false);
     int psum = 0;
     for (int r = 0; r < Q; ++r) {
         A[r] = 2 * psum + r;
@@ -38,16 +40,41 @@ bool chunk_transfer(const int32_t *ps, int Q, int tiles, int &E, std::vector<uin
         isx[r] = (r & 1) == (Amax & 1);
         d[r] = isx[r] ? -((Amax - A[r]) >> 1) : -((Amax - A[r] - 1) >> 1);
     }
-    const int dmin = -((Amax - Amin) >> 1);
-    // An interior chunk must start at column >= 0 in every row.
-    if (tiles * TW < -dmin) return false;
-    E = 0;
+    dmin = -((Amax - Amin) >> 1);
+}
+
+// State width E: the deepest read back of the sweep and the unstored window.
+static int state_width(const int32_t *ps, int Q, const std::vector<int> &d) {
+    constexpr int TW = kDecodeTile;
+    int E = 0;
     for (int r = 0; r < Q; ++r) {
         const int lag = (-d[r] + TW - 1) / TW;
         E = std::max(E, d[r] + lag * TW);             // the unstored window
         for (int l = 0; l < Q; ++l)
             if (l != r) E = std::max(E, d[l] - d[r] - (l - r) * ps[r]);   // deepest read back
     }
+    return E;
+}
+
+bool chunk_state_cols(const int32_t *ps, int Q, int tiles, int &E) {
+    std::vector<int> d;
+    std::vector<bool> isx;
+    int dmin = 0;
+    survivor_schedule(ps, Q, d, isx, dmin);
+    if (tiles * kDecodeTile < -dmin) return false;
+    E = state_width(ps, Q, d);
+    return true;
+}
+
+bool chunk_transfer(const int32_t *ps, int Q, int tiles, int &E, std::vector<uint64_t> &T) {
+    constexpr int TW = kDecodeTile;
+    std::vector<int> d;
+    std::vector<bool> isx;
+    int dmin = 0;
+    survivor_schedule(ps, Q, d, isx, dmin);
+    // An interior chunk must start at column >= 0 in every row.
+    if (tiles * TW < -dmin) return false;
+    E = state_width(ps, Q, d);
     const int dim = Q * E;
     const int RW = (dim + 63) / 64;
     const int W = E + tiles * TW;                     // columns per row in the run
@@ -82,6 +109,32 @@ bool chunk_transfer(const int32_t *ps, int Q, int tiles, int &E, std::vector<uin
             std::copy(src, src + RW, &T[(size_t)(r * E + e) * RW]);
         }
     return true;
+}
+
+void chunk_powers(const std::vector<uint64_t> &T, int dim, int npow, std::vector<uint64_t> &out) {
+    const int RW = (dim + 63) / 64;
+    const size_t msz = (size_t)dim * RW;
+    out.assign(msz * npow, 0);
+    if (dim == 0 || npow == 0) return;
+    std::copy(T.begin(), T.begin() + msz, out.begin());
+    for (int s = 1; s < npow; ++s) {
+        const uint64_t *A = &out[msz * (s - 1)];
+        uint64_t *C = &out[msz * s];
+        // row i of A*A: XOR of the rows j of A that row i of A selects
+        for (int i = 0; i < dim; ++i) {
+            uint64_t *ci = C + (size_t)i * RW;
+            const uint64_t *ai = A + (size_t)i * RW;
+            for (int w = 0; w < RW; ++w) {
+                uint64_t bits = ai[w];
+                while (bits) {
+                    const int j = 64 * w + __builtin_ctzll(bits);
+                    bits &= bits - 1;
+                    const uint64_t *aj = A + (size_t)j * RW;
+                    for (int v = 0; v < RW; ++v) ci[v] ^= aj[v];
+                }
+            }
+        }
+    }
 }
 
 }  // namespace mj

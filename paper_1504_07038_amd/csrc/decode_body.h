@@ -624,6 +624,71 @@ __device__ __forceinline__ void carry_block(const Args &a, const int Q, const in
     }
 }
 
+// One item of a parallel-carry step: entry c of block blk.  dst[c] =
+// src[c] XOR M src[c - h] with M = T^h, h = 2^step (table-lookup product as in
+// carry_block), or dst[c] = src[c] when c < h.  State at most kScanMaxState
+// words, so every thread owns at most one output word.
+template <class Args>
+__device__ __forceinline__ void scan_item(const Args &a, const int Q, const int64_t blk,
+                                          const int c, const int step, const uint64_t *src,
+                                          uint64_t *dst) {
+    extern __shared__ uint64_t lds_carry[];
+    const int tid = threadIdx.x;
+    const int nthreads = blockDim.x;
+    const int per = a.chunk.nchunks - 1;
+    const int64_t stride = (int64_t)Q * a.chunk.max_cols;
+    const int64_t zwords = stride + 4;
+    uint64_t *z = lds_carry;
+    uint64_t *tab = lds_carry + zwords;
+    const uint32_t mask = a.masks ? a.masks[blk] : a.mask_uniform;
+    uint32_t used = 0;
+    int cnt = 0;
+    for (int s = 0; s < a.n; ++s) {
+        const int id = a.id_sorted[s];
+        if (!((mask >> id) & 1u) && cnt < Q) {
+            used |= 1u << id;
+            ++cnt;
+        }
+    }
+    if (cnt < Q) return;   // undecodable: reported by the sweep (uniform per block)
+    const int set = a.chunk.lut[used];
+    const int d = Q * a.chunk.state_cols[set];
+    const int RW = (d + 63) / 64;
+    const int G = (d + 3) / 4;
+    const int h = 1 << step;
+    const uint64_t *in = src + (blk * per + c) * stride;
+    uint64_t *out = dst + (blk * per + c) * stride;
+    if (c < h) {
+        for (int i = tid; i < d; i += nthreads) out[i] = in[i];
+        return;
+    }
+    const uint64_t *M = a.chunk.tmat + a.chunk.tmat_off[set] + (int64_t)step * d * RW;
+    const uint64_t *zin = in - (int64_t)h * stride;
+    __syncthreads();   // the previous item's reads of z and tab are done
+    for (int i = tid; i < zwords; i += nthreads) z[i] = i < d ? zin[i] : 0;
+    __syncthreads();
+    for (int e = tid; e < G * 16; e += nthreads) {
+        const int g = e >> 4, m = e & 15;
+        uint64_t v = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if ((m >> k) & 1) v ^= z[4 * g + k];
+        tab[e] = v;
+    }
+    __syncthreads();
+    if (tid < d) {
+        uint64_t acc = in[tid];
+        const uint64_t *row = M + (int64_t)tid * RW;
+        for (int w = 0; w < RW; ++w) {
+            const uint64_t bits = row[w];
+            const int gn = min(16, G - 16 * w);
+            for (int q = 0; q < gn; ++q)
+                acc ^= tab[((16 * w + q) << 4) | (int)((bits >> (4 * q)) & 15)];
+        }
+        out[tid] = acc;
+    }
+}
+
 template <int RWC>
 __global__ __launch_bounds__(kWave * kCarryWaves) void decode_carry_kernel(DecodeArgs a, int Q) {
     for (int64_t blk = blockIdx.x; blk < a.nblocks; blk += gridDim.x) carry_block<RWC>(a, Q, blk);

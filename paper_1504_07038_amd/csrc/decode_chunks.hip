@@ -41,6 +41,24 @@ bool decode_chunk_classes_supported(unsigned qmask, bool gather) {
     }
 }
 
+// One step of the parallel carry over the classes of a table.
+__global__ __launch_bounds__(kWave * kCarryWaves) void decode_scan_classes_kernel(
+    DecodeChunkTable tab, int step) {
+    const int64_t total = tab.first_pair[tab.nclasses];
+    for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
+        int c = 0;
+        while (item >= tab.first_pair[c + 1]) ++c;
+        const DecodeChunkClass &a = tab.cls[c];
+        if (!a.chunk.ws_alt) continue;   // one chunk boundary: nothing to carry
+        const int per = a.chunk.nchunks - 1;
+        const int64_t local = item - tab.first_pair[c];
+        const int64_t blk = local / per;
+        const uint64_t *src = (step & 1) ? a.chunk.ws_alt : a.chunk.ws;
+        uint64_t *dst = (step & 1) ? a.chunk.ws : a.chunk.ws_alt;
+        scan_item(a, a.Q, blk, (int)(local - blk * per), step, src, dst);
+    }
+}
+
 template <unsigned M, bool G>
 static hipError_t launch_chunk_sweep(int mode, const DecodeChunkTable &tab, size_t lds, int grid,
                                      hipStream_t s) {
@@ -56,6 +74,11 @@ static hipError_t launch_chunk_sweep(int mode, const DecodeChunkTable &tab, size
 hipError_t launch_decode_chunk_classes(int mode, unsigned qmask, bool gather,
                                        const DecodeChunkTable &tab, size_t lds, int grid,
                                        int threads, bool rows_in_registers, hipStream_t s) {
+    if (mode >= kLaunchScan) {
+        hipLaunchKernelGGL(decode_scan_classes_kernel, dim3(grid), dim3(threads), lds, s, tab,
+                           mode - kLaunchScan);
+        return hipGetLastError();
+    }
     if (mode == kLaunchCarry) {
         if (rows_in_registers)
             hipLaunchKernelGGL(decode_carry_classes_kernel<8>, dim3(grid), dim3(threads), lds, s,

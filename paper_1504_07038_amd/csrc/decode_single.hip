@@ -37,6 +37,31 @@ hipError_t launch_decode_carry(const DecodeArgs &a, int Q, int grid, hipStream_t
     return hipGetLastError();
 }
 
+// One step of the parallel carry over the chunks of every block.
+__global__ __launch_bounds__(kWave * kCarryWaves) void decode_scan_kernel(DecodeArgs a, int Q,
+                                                                          int step,
+                                                                          const uint64_t *src,
+                                                                          uint64_t *dst) {
+    const int per = a.chunk.nchunks - 1;
+    const int64_t total = a.nblocks * per;
+    for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
+        const int64_t blk = item / per;
+        scan_item(a, Q, blk, (int)(item - blk * per), step, src, dst);
+    }
+}
+
+hipError_t launch_decode_scan(const DecodeArgs &a, int Q, int step, const uint64_t *src,
+                              uint64_t *dst, hipStream_t s) {
+    const int state = Q * a.chunk.max_cols;
+    if (state > kScanMaxState) return hipErrorInvalidValue;
+    const int threads = kWave * carry_waves(state);
+    const size_t lds = ((size_t)state + 4 + (size_t)(state + 3) / 4 * 16) * sizeof(uint64_t);
+    const int64_t items = a.nblocks * (a.chunk.nchunks - 1);
+    const int grid = (int)std::min<int64_t>(items, 256 * 128);
+    hipLaunchKernelGGL(decode_scan_kernel, dim3(grid), dim3(threads), lds, s, a, Q, step, src, dst);
+    return hipGetLastError();
+}
+
 hipError_t launch_decode_hi(int Q, int mode, const DecodeArgs &a, int grid, hipStream_t s);
 
 hipError_t launch_decode(int Q, int mode, const DecodeArgs &a, int grid, hipStream_t s) {

@@ -104,14 +104,24 @@ constexpr int kCarryMaxState = 2048;   // most state words (Q * E) the carry pas
 
 struct ChunkInfo {
     uint64_t *ws;                    // per (block, chunk boundary): Q * max_cols words
+    uint64_t *ws_alt;                // second buffer of the same layout (parallel carry)
     const int32_t *lut;              // survivor id mask -> set index (-1: none)
     const int32_t *state_cols;       // per set: E
-    const int64_t *tmat_off;         // per set: word offset of its matrix in tmat
-    const uint64_t *tmat;            // per set: Q*E rows of ceil(Q*E/64) words
+    const int64_t *tmat_off;         // per set: word offset of its matrices in tmat
+    const uint64_t *tmat;            // per set: T, T^2, T^4, ... (npow matrices), each
+                                     // Q*E rows of ceil(Q*E/64) words
     int32_t tiles;                   // tiles per chunk
     int32_t nchunks;                 // chunks per block (>= 2 in chunked launches)
     int32_t max_cols;                // largest E over the sets
+    int32_t npow;                    // matrices per set
 };
+
+// The carry as a parallel prefix (Kogge-Stone) over the chunks of a block,
+// for survivor sets of at most kScanMaxState state words: after step s,
+// entry c holds sum_{c - 2^(s+1) < j <= c} T^(c-j) y_j; ceil(log2(C-1))
+// steps leave z_{c+1} in entry c.  Plans keep kScanPowers powers T^(2^s).
+constexpr int kScanMaxState = 512;
+constexpr int kScanPowers = 10;
 
 // Launch modes of launch_decode.
 constexpr int kLaunchPool = 0;       // whole blocks from a projection pool
@@ -192,6 +202,7 @@ struct DecodeChunkTable {
     DecodeChunkClass cls[kMaxChunkClasses];
     int64_t first_item[kMaxChunkClasses + 1];    // sweeps: batches of class c
     int64_t first_block[kMaxChunkClasses + 1];   // carry: blocks of class c
+    int64_t first_pair[kMaxChunkClasses + 1];    // parallel carry: (block, chunk) of class c
     int32_t nclasses;
 };
 
@@ -199,6 +210,9 @@ bool decode_chunk_classes_supported(unsigned qmask, bool gather);
 // mode: kLaunchChunkA or kLaunchChunkC (sweeps, one wave per workgroup), or
 // kLaunchCarry (carry pass, `threads` per workgroup).
 constexpr int kLaunchCarry = 6;
+// kLaunchScan + s: step s of the parallel carry (ws -> ws_alt for even s,
+// ws_alt -> ws for odd s).
+constexpr int kLaunchScan = 16;
 hipError_t launch_decode_chunk_classes(int mode, unsigned qmask, bool gather,
                                        const DecodeChunkTable &tab, size_t lds, int grid,
                                        int threads, bool rows_in_registers, hipStream_t s);
@@ -217,6 +231,14 @@ hipError_t launch_decode(int Q, int mode, const DecodeArgs &a, int grid, hipStre
 // interior chunk of `tiles` tiles for the survivor directions ps[0..Q) in
 // ascending order.  False if chunks that short cannot be interior.
 bool chunk_transfer(const int32_t *ps, int Q, int tiles, int &E, std::vector<uint64_t> &T);
+// The state width E alone (no matrix); false as for chunk_transfer.
+bool chunk_state_cols(const int32_t *ps, int Q, int tiles, int &E);
+// T^(2^s), s = 0..npow-1, of a dim x dim transfer matrix, back to back.
+void chunk_powers(const std::vector<uint64_t> &T, int dim, int npow, std::vector<uint64_t> &out);
+// One step of the parallel carry: entry c of dst = entry c of src XOR
+// T^(2^step) (entry c - 2^step of src), or a copy of entry c when c < 2^step.
+hipError_t launch_decode_scan(const DecodeArgs &a, int Q, int step, const uint64_t *src,
+                              uint64_t *dst, hipStream_t s);
 hipError_t launch_decode_carry(const DecodeArgs &a, int Q, int grid, hipStream_t s);
 size_t decode_lds_bytes(int Q, int nb, int ring_stride);
 int decode_max_blocks_per_wave(int Q);

@@ -1,6 +1,8 @@
 """Chunked decode of long rows on the GPU: bit-identical to the oracle's
 decode and to the whole-block decode, for several codes, chunk lengths,
-erasure patterns and 1 MB blocks; undecodable blocks; graph replay."""
+erasure patterns and 1 MB blocks, through both carries (the parallel scan
+for few blocks of small-state codes, the sequential pass for many blocks or
+wide states); undecodable blocks; graph replay."""
 import numpy as np
 import pytest
 
@@ -40,6 +42,7 @@ CASES = [
     (1531, 6, synth.centered_dirs(9), 10, 96),
     (777, 2, [5, -1, 3], 40, 32),
     (3000, 12, list(range(-8, 8)), 4, 512),
+    (1024, 4, synth.centered_dirs(6), 1100, 128),   # many blocks: sequential carry
     (32768, 4, synth.centered_dirs(6), 3, 512),     # 1 MB blocks of the (4,2) code
     (16384, 8, synth.centered_dirs(12), 2, 1024),   # 1 MB blocks of the (8,4) code
 ]
@@ -188,3 +191,21 @@ def test_jobs_mix_chunked_and_whole_with_slots(mj, orc):
         mj.mojette_decode_jobs([bad])
     for p in plans:
         p.close()
+
+
+def test_workspace_serves_every_smaller_batch(mj):
+    """A workspace sized for N blocks must cover a call on fewer blocks, which
+    may choose the parallel carry (two buffers) where N blocks would not."""
+    for dirs, Q, P, cols in ((synth.centered_dirs(6), 4, 1218, 128),
+                             (synth.centered_dirs(12), 8, 4096, 256)):
+        plan = mj.Plan(dirs, Q, cols)
+        per = (P // 16) // ((cols + 15) // 16) - 1
+        stride = Q * max(1, plan.workspace_words(P, 1) // (2 * per * Q))
+        prev = 0
+        for n in (1, 2, 100, 146, 147, 1000, 1024, 1025, 1721, 4096):
+            w = plan.workspace_words(P, n)
+            assert w >= prev, n
+            # twice the end states of n blocks: room for the second buffer
+            assert w == 2 * n * per * stride, (n, w)
+            prev = w
+        plan.close()
