@@ -13,6 +13,8 @@ Paper: Pertin et al., arXiv 1504.07038.
   - ``inverse``      Section 2.2, the peeling reconstruction.
   - ``encode_blocks`` / ``decode_blocks``  Section 2.3 and Section 3: the XOR
     erasure code with q_i = 1, one call per block.
+  - ``encode_blocks_wide`` / ``decode_blocks_wide``  Section 3.1: the same code
+    on 128-bit pixels and bins.
 
 Group: ``kind=0`` XOR on uint64 words; ``kind=1`` integers modulo ``mod``.
 """
@@ -170,3 +172,27 @@ def decode_blocks(projs: np.ndarray, erased: np.ndarray, P: int, Q: int, p_list)
     if rc != OK:
         raise ValueError(f"orc_decode_blocks failed: {rc}")
     return out
+
+
+def encode_blocks_wide(images: np.ndarray, P: int, Q: int, p_list) -> np.ndarray:
+    """The XOR code on 128-bit pixels and bins (Section 3.1).
+
+    ``images`` is (nblocks, Q, P, 2) uint64: the two 64-bit words of each
+    16-byte pixel in memory order.  XOR adds 128-bit values bit by bit, so
+    word h of every bin is the XOR of word h of the pixels on its line: the
+    transform is the 64-bit transform of the plane of first words beside that
+    of the plane of second words.  Returns (nblocks, sum B_i, 2).
+    """
+    img = np.ascontiguousarray(images, dtype=np.uint64).reshape(-1, Q, P, 2)
+    planes = [encode_blocks(np.ascontiguousarray(img[..., h]), P, Q, p_list) for h in (0, 1)]
+    return np.stack(planes, axis=-1)
+
+
+def decode_blocks_wide(projs: np.ndarray, erased: np.ndarray, P: int, Q: int,
+                       p_list) -> np.ndarray:
+    """Inverse of ``encode_blocks_wide``, word plane by word plane (Section 2.2
+    peeling on each); ``projs`` is (nblocks, sum B_i, 2)."""
+    pr = np.ascontiguousarray(projs, dtype=np.uint64).reshape(-1, block_stride(P, Q, p_list), 2)
+    planes = [decode_blocks(np.ascontiguousarray(pr[..., h]), erased, P, Q, p_list)
+              for h in (0, 1)]
+    return np.stack(planes, axis=-1)
