@@ -25,10 +25,12 @@ if ROOT not in sys.path:
 HBM_PEAK_GBPS = 8000.0  # MI355X published HBM3E bandwidth
 
 WORKLOADS = {
-    # name: (P, Q, n, nblocks, erasures per block)
-    "4k_6_4": (128, 4, 6, 1 << 21, 2),
-    "8k_6_4": (256, 4, 6, 1 << 20, (0, 2)),
-    "8k_12_8": (128, 8, 12, 1 << 19, 4),
+    # name: (P, Q, n, nblocks, erasures per block, 64-bit words per pixel)
+    "4k_6_4": (128, 4, 6, 1 << 21, 2, 1),
+    "8k_6_4": (256, 4, 6, 1 << 20, (0, 2), 1),
+    "8k_12_8": (128, 8, 12, 1 << 19, 4, 1),
+    # the paper's own geometry: 16-byte pixels, so a 4 KB (6,4) block is 64 x 4
+    "4k_6_4_w128": (64, 4, 6, 1 << 21, 2, 2),
 }
 
 
@@ -98,8 +100,8 @@ def pmc_summary(workload: str, fetch_csv: str, write_csv: str, command: str) -> 
     and written once)."""
     import csv
 
-    P, Q, n, nblocks, _ = WORKLOADS[workload]
-    copy_bytes = nblocks * P * Q * 8
+    P, Q, n, nblocks, _, pw = WORKLOADS[workload]
+    copy_bytes = nblocks * P * Q * 8 * pw
 
     def per_kernel(path, counter):
         vals = {k: [] for k in KERNEL_TAGS}
@@ -213,15 +215,18 @@ def main():
     import paper_1504_07038_amd as mj
     import synth
 
-    P, Q, n, nblocks, ner = WORKLOADS[args.workload]
+    P, Q, n, nblocks, ner, pw = WORKLOADS[args.workload]
     dirs = synth.centered_dirs(n)
-    words = mj.mojette_block_words(dirs, P, Q)
-    block_bytes = P * Q * 8
+    words = pw * mj.mojette_block_words(dirs, P, Q)
+    block_bytes = P * Q * 8 * pw
+    # 16-byte pixels (pw = 2) go through the wide entry points
+    encode_batch = mj.mojette_encode_batch if pw == 1 else mj.mojette_encode_batch_wide
+    decode_batch = mj.mojette_decode_batch if pw == 1 else mj.mojette_decode_batch_wide
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
 
-    d_img = torch.empty(nblocks * Q * P, dtype=torch.int64, device=dev)
+    d_img = torch.empty(nblocks * Q * P * pw, dtype=torch.int64, device=dev)
     mj.mojette_fill_splitmix64(d_img, d_img.numel(), synth.SEED_DATA)
     masks = synth.erasure_masks(synth.SEED_ERASE, nblocks, n, ner)
     d_mask = torch.from_numpy(masks.view(np.int16)).to(dev)
@@ -233,10 +238,10 @@ def main():
     def step(evs=None):
         if evs:
             evs[0].record(stream)
-        mj.mojette_encode_batch(d_img, nblocks, P, Q, dirs, d_proj)
+        encode_batch(d_img, nblocks, P, Q, dirs, d_proj)
         if evs:
             evs[1].record(stream)
-        mj.mojette_decode_batch(d_proj, d_mask, nblocks, P, Q, dirs, d_out, d_status)
+        decode_batch(d_proj, d_mask, nblocks, P, Q, dirs, d_out, d_status)
         if evs:
             evs[2].record(stream)
 
@@ -261,8 +266,8 @@ def main():
     user_bytes = nblocks * block_bytes
     enc_avg = sum(enc_ms) / len(enc_ms)
     dec_avg = sum(dec_ms) / len(dec_ms)
-    enc_alg = 8 * (P * Q + words)          # read the image, write every bin
-    dec_alg = 16 * P * Q                   # read P bins of Q survivors, write the image
+    enc_alg = 8 * (pw * P * Q + words)     # read the image, write every bin
+    dec_alg = 16 * pw * P * Q              # read P bins of Q survivors, write the image
     kernels = {
         "encode": {"ms": enc_avg, "alg_bytes_per_block": enc_alg},
         "decode": {"ms": dec_avg, "alg_bytes_per_block": dec_alg},
@@ -299,12 +304,12 @@ def main():
 
     # plain path: one launch per block, against the batched path on the same blocks
     plain = None
-    if not args.no_plain:
+    if not args.no_plain and pw == 1:   # the one-block calls take 64-bit pixels
         plain = plain_vs_batched(mj, torch, np, d_img, d_proj, masks, P, Q, dirs, words,
                                  args.plain_blocks, block_bytes)
 
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and pw == 1:
         cpu = cpu_baseline(P, Q, dirs, min(args.cpu_sample, nblocks), ner)
 
     rec = {
@@ -318,11 +323,12 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u64",
+        "dtype": "u64" if pw == 1 else "u128",
         "data": "synthetic",
         "config": {
             "workload": f"{args.workload}: {nblocks} blocks of {block_bytes} B, P={P} Q={Q} "
-                        f"n={n} p={dirs[0]}..{dirs[-1]} q=1, XOR, erasures/block={ner}",
+                        f"n={n} p={dirs[0]}..{dirs[-1]} q=1, XOR on {64 * pw}-bit pixels, "
+                        f"erasures/block={ner}",
             "blocks": nblocks, "P": P, "Q": Q, "n": n, "erasures": str(ner),
             "parallelism": "single GPU",
         },

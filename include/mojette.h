@@ -128,6 +128,25 @@ int mojette_decode_batch(const uint64_t *projs, const uint16_t *erased, int64_t 
                          int32_t *status, void *stream);
 
 /*
+ * 128-bit pixels and bins (Section 3.1 sets pixel and bin to 128 bits for
+ * the XOR code): the same two calls for blocks of P x Q pixels of 16 bytes.
+ *   images  device, nblocks x Q x P pixels, each pixel two 64-bit words
+ *           (block b at word 2*b*Q*P, pixel (k,l) at words 2*(l*P+k) and
+ *           2*(l*P+k)+1).
+ *   projs   device, nblocks x 2*mojette_block_words(dirs, n, P, Q) words:
+ *           projection i of a block holds mojette_proj_size(dirs[i], P, Q)
+ *           bins of two words each, bin j's words in the order of a
+ *           pixel's (bin j is the XOR of its line's pixels, word by word).
+ *   erased, status  as for mojette_decode_batch.
+ * P may be up to 2^23 and |p| up to 2^15.  Returns as the 64-bit calls.
+ */
+int mojette_encode_batch_wide(const uint64_t *images, int64_t nblocks, int32_t P, int32_t Q,
+                              const int32_t *dirs, int32_t n, uint64_t *projs, void *stream);
+int mojette_decode_batch_wide(const uint64_t *projs, const uint16_t *erased, int64_t nblocks,
+                              int32_t P, int32_t Q, const int32_t *dirs, int32_t n,
+                              uint64_t *images, int32_t *status, void *stream);
+
+/*
  * mojette_decode_batch with the decode schedule's blocks per wavefront set by
  * the caller (an autotuner): blocks_per_wave >= 1 asks for that many (capped
  * by what fits in LDS), 0 keeps the library's choice.  Fewer blocks per

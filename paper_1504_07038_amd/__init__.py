@@ -128,6 +128,9 @@ def lib() -> ctypes.CDLL:
         "mojette_decode": ([vp, vp, i32, vp, i32, i32, i32, vp, vp], ctypes.c_int),
         "mojette_encode_batch": ([vp, i64, i32, i32, vp, i32, vp, vp], ctypes.c_int),
         "mojette_decode_batch": ([vp, vp, i64, i32, i32, vp, i32, vp, vp, vp], ctypes.c_int),
+        "mojette_encode_batch_wide": ([vp, i64, i32, i32, vp, i32, vp, vp], ctypes.c_int),
+        "mojette_decode_batch_wide": ([vp, vp, i64, i32, i32, vp, i32, vp, vp, vp],
+                                      ctypes.c_int),
         "mojette_decode_batch_tuned": ([vp, vp, i64, i32, i32, vp, i32, vp, vp, i32, vp],
                                        ctypes.c_int),
         "mojette_decode_max_blocks_per_wave": ([vp, i32, i32, i32], i32),
@@ -178,6 +181,7 @@ def exported_symbols() -> list[str]:
         "mojette_strerror", "mojette_last_hip_error", "mojette_proj_size",
         "mojette_bin_offset", "mojette_block_words", "mojette_decode_ring", "mojette_encode",
         "mojette_decode", "mojette_encode_batch", "mojette_decode_batch",
+        "mojette_encode_batch_wide", "mojette_decode_batch_wide",
         "mojette_decode_batch_tuned", "mojette_decode_max_blocks_per_wave",
         "mojette_decode_default_blocks_per_wave",
         "mojette_classes_layout", "mojette_encode_classes", "mojette_decode_classes",
@@ -281,19 +285,42 @@ def mojette_encode_batch(images, nblocks: int, P: int, Q: int, dirs, projs, stre
     return _check(rc, "mojette_encode_batch", check)
 
 
-def mojette_decode_batch(projs, erased, nblocks: int, P: int, Q: int, dirs, images,
-                         status=None, stream=None, check: bool = True) -> int:
+def _decode_masks(erased, status):
     import torch
 
-    arr, n = _i32_array(dirs)
     if erased is not None and erased.dtype not in (torch.int16, torch.uint16):
         raise ValueError("erased must be 16-bit masks")
     if status is not None and status.dtype != torch.int32:
         raise ValueError("status must be int32")
-    rc = lib().mojette_decode_batch(_word_tensor(projs, "projs"), _dev_ptr(erased, "erased"),
-                                    nblocks, P, Q, arr, n, _word_tensor(images, "images"),
-                                    _dev_ptr(status, "status"), _stream(stream))
+    return _dev_ptr(erased, "erased"), _dev_ptr(status, "status")
+
+
+def mojette_decode_batch(projs, erased, nblocks: int, P: int, Q: int, dirs, images,
+                         status=None, stream=None, check: bool = True) -> int:
+    arr, n = _i32_array(dirs)
+    er, st = _decode_masks(erased, status)
+    rc = lib().mojette_decode_batch(_word_tensor(projs, "projs"), er, nblocks, P, Q, arr, n,
+                                    _word_tensor(images, "images"), st, _stream(stream))
     return _check(rc, "mojette_decode_batch", check)
+
+
+def mojette_encode_batch_wide(images, nblocks: int, P: int, Q: int, dirs, projs, stream=None,
+                              check: bool = True) -> int:
+    """128-bit pixels: ``images`` holds nblocks x Q x P pixels of two words each."""
+    arr, n = _i32_array(dirs)
+    rc = lib().mojette_encode_batch_wide(_word_tensor(images, "images"), nblocks, P, Q, arr, n,
+                                         _word_tensor(projs, "projs"), _stream(stream))
+    return _check(rc, "mojette_encode_batch_wide", check)
+
+
+def mojette_decode_batch_wide(projs, erased, nblocks: int, P: int, Q: int, dirs, images,
+                              status=None, stream=None, check: bool = True) -> int:
+    """128-bit pixels: projections of two-word bins, images of two-word pixels."""
+    arr, n = _i32_array(dirs)
+    er, st = _decode_masks(erased, status)
+    rc = lib().mojette_decode_batch_wide(_word_tensor(projs, "projs"), er, nblocks, P, Q, arr,
+                                         n, _word_tensor(images, "images"), st, _stream(stream))
+    return _check(rc, "mojette_decode_batch_wide", check)
 
 
 def mojette_decode_batch_tuned(projs, erased, nblocks: int, P: int, Q: int, dirs, images,

@@ -38,6 +38,20 @@ bool geometry_ok(const int32_t *dirs, int32_t n, int32_t P, int32_t Q) {
     return true;
 }
 
+// 128-bit pixels (Section 3.1) run on the 64-bit kernels: half h of pixel k
+// is word column 2k + h of a 2P-wide image of words, whose projection along
+// (2p, 1) holds bin j of the 16-byte projection along (p, 1) in word bins
+// 2j+1 and 2j (the kernels exchange the two with bin_swap).  Checks the
+// 16-byte geometry and fills dirs2 with the doubled directions.
+bool wide_geometry(const int32_t *dirs, int32_t n, int32_t P, int32_t Q, int32_t *dirs2) {
+    if (!geometry_ok(dirs, n, P, Q) || P > kMaxP / 2) return false;
+    for (int i = 0; i < n; ++i) {
+        if (dirs[i] < -kMaxAbsP / 2 || dirs[i] > kMaxAbsP / 2) return false;
+        dirs2[i] = 2 * dirs[i];
+    }
+    return geometry_ok(dirs2, n, 2 * P, Q);
+}
+
 int status_of(hipError_t e) { return mj::hip_status(e); }
 
 // Kernel launches report through hipGetLastError(), which also returns an
@@ -276,14 +290,16 @@ int mojette_encode(const uint64_t *image, int32_t P, int32_t Q, const int32_t *d
     return status_of(mj::launch_encode(a, grid, (hipStream_t)stream));
 }
 
-int mojette_encode_batch(const uint64_t *images, int64_t nblocks, int32_t P, int32_t Q,
-                         const int32_t *dirs, int32_t n, uint64_t *projs, void *stream) {
+static int encode_batch_impl(const uint64_t *images, int64_t nblocks, int32_t P, int32_t Q,
+                             const int32_t *dirs, int32_t n, uint64_t *projs, void *stream,
+                             int bin_swap) {
     if (nblocks < 0 || !geometry_ok(dirs, n, P, Q)) return MOJETTE_EINVAL;
     if (nblocks == 0) return MOJETTE_OK;
     if (!images || !projs) return MOJETTE_EINVAL;
     mj::EncodeArgs a{};
     if (!encode_tiling(dirs, n, P, Q, a)) return MOJETTE_ENOTSUP;
     a.images = images;
+    a.bin_swap = bin_swap;
     int64_t off = 0;
     for (int i = 0; i < n; ++i) {
         a.out[i] = projs + off;
@@ -296,6 +312,18 @@ int mojette_encode_batch(const uint64_t *images, int64_t nblocks, int32_t P, int
     const int grid = (int)std::min<int64_t>(want, kEncodeGridCap);
     clear_stale_error();
     return status_of(mj::launch_encode(a, grid, (hipStream_t)stream));
+}
+
+int mojette_encode_batch(const uint64_t *images, int64_t nblocks, int32_t P, int32_t Q,
+                         const int32_t *dirs, int32_t n, uint64_t *projs, void *stream) {
+    return encode_batch_impl(images, nblocks, P, Q, dirs, n, projs, stream, 0);
+}
+
+int mojette_encode_batch_wide(const uint64_t *images, int64_t nblocks, int32_t P, int32_t Q,
+                              const int32_t *dirs, int32_t n, uint64_t *projs, void *stream) {
+    int32_t dirs2[kMaxDirs];
+    if (nblocks < 0 || !wide_geometry(dirs, n, P, Q, dirs2)) return MOJETTE_EINVAL;
+    return encode_batch_impl(images, nblocks, 2 * P, Q, dirs2, n, projs, stream, 1);
 }
 
 int mojette_decode(const uint64_t *const *proj, const int32_t *proj_ids, int32_t m,
@@ -327,9 +355,9 @@ int mojette_decode(const uint64_t *const *proj, const int32_t *proj_ids, int32_t
     return status_of(mj::launch_decode(Q, mj::kLaunchPointers, a, 1, (hipStream_t)stream));
 }
 
-int mojette_decode_batch(const uint64_t *projs, const uint16_t *erased, int64_t nblocks,
-                         int32_t P, int32_t Q, const int32_t *dirs, int32_t n, uint64_t *images,
-                         int32_t *status, void *stream) {
+static int decode_batch_impl(const uint64_t *projs, const uint16_t *erased, int64_t nblocks,
+                             int32_t P, int32_t Q, const int32_t *dirs, int32_t n,
+                             uint64_t *images, int32_t *status, void *stream, int bin_swap) {
     if (nblocks < 0 || !geometry_ok(dirs, n, P, Q)) return MOJETTE_EINVAL;
     if (nblocks == 0) return MOJETTE_OK;
     if (!projs || !images) return MOJETTE_EINVAL;
@@ -354,10 +382,26 @@ int mojette_decode_batch(const uint64_t *projs, const uint16_t *erased, int64_t 
     a.mask_uniform = 0;
     a.status = status;
     a.nblocks = nblocks;
+    a.bin_swap = bin_swap;
     const int64_t batches = (nblocks + a.nb - 1) / a.nb;
     const int grid = (int)std::min<int64_t>(batches, kDecodeGridCap);
     clear_stale_error();
     return status_of(mj::launch_decode(Q, mj::kLaunchPool, a, grid, (hipStream_t)stream));
+}
+
+int mojette_decode_batch(const uint64_t *projs, const uint16_t *erased, int64_t nblocks,
+                         int32_t P, int32_t Q, const int32_t *dirs, int32_t n, uint64_t *images,
+                         int32_t *status, void *stream) {
+    return decode_batch_impl(projs, erased, nblocks, P, Q, dirs, n, images, status, stream, 0);
+}
+
+int mojette_decode_batch_wide(const uint64_t *projs, const uint16_t *erased, int64_t nblocks,
+                              int32_t P, int32_t Q, const int32_t *dirs, int32_t n,
+                              uint64_t *images, int32_t *status, void *stream) {
+    int32_t dirs2[kMaxDirs];
+    if (nblocks < 0 || !wide_geometry(dirs, n, P, Q, dirs2)) return MOJETTE_EINVAL;
+    return decode_batch_impl(projs, erased, nblocks, 2 * P, Q, dirs2, n, images, status, stream,
+                             1);
 }
 
 // ---- chunked decode of long rows -------------------------------------------

@@ -357,16 +357,18 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch)
                 if constexpr (POOL) {
                     // one 8-byte load per word, so each word is bounds checked
                     // on its own (a window may start just before the slice)
-                    const uint32_t off0 = s.on ? (uint32_t)(s.gbin - c) * 8u : kOffNone;
-                    const uint32_t off1 = s.on ? (uint32_t)(s.gbin - c + 1) * 8u : kOffNone;
+                    const uint32_t off0 =
+                        s.on ? (uint32_t)((s.gbin - c) ^ a.bin_swap) * 8u : kOffNone;
+                    const uint32_t off1 =
+                        s.on ? (uint32_t)((s.gbin - c + 1) ^ a.bin_swap) * 8u : kOffNone;
                     const u32x2 w0 = __builtin_amdgcn_raw_buffer_load_b64(rin, off0, 0, 0);
                     const u32x2 w1 = __builtin_amdgcn_raw_buffer_load_b64(rin, off1, 0, 0);
                     buf[it] = u32x4{w0.x, w0.y, w1.x, w1.y};
                 } else {
                     const uint64_t *bins = s.bins;
                     const int c0 = min(max(c, 0), P - 1), c1 = min(max(c - 1, 0), P - 1);
-                    const uint64_t w0 = s.on ? bins[s.gbin - c0] : 0;
-                    const uint64_t w1 = s.on ? bins[s.gbin - c1] : 0;
+                    const uint64_t w0 = s.on ? bins[(s.gbin - c0) ^ a.bin_swap] : 0;
+                    const uint64_t w1 = s.on ? bins[(s.gbin - c1) ^ a.bin_swap] : 0;
                     buf[it] = u32x4{(uint32_t)w0, (uint32_t)(w0 >> 32), (uint32_t)w1,
                                     (uint32_t)(w1 >> 32)};
                 }

@@ -8,6 +8,14 @@
 // projection at a time, so every store instruction writes 64 contiguous
 // words of a projection.  (Non-temporal loads or stores made it slower on the
 // MI355X: 1.73 and 1.77 against 1.93 TB/s of user data for 4 KB blocks.)
+//
+// 128-bit pixels (Section 3.1) use the same kernel.  XOR acts on every bit
+// alone, so a P x Q image of 16-byte pixels is a 2P x Q image of 8-byte
+// words, half h of pixel k at word column 2k + h, and its projection along
+// (p, 1) is that word image's projection along (2p, 1): half h of pixel k
+// lands on word bin 2b - h.  Word bins 2j+1 and 2j thus hold the two halves
+// of bin j in reverse order; with bin_swap = 1 word bin j is stored at word
+// j ^ 1, which keeps every 16-byte bin in a pixel's half order.
 #include "mj_internal.h"
 
 namespace mj {
@@ -52,7 +60,7 @@ __device__ __forceinline__ void encode_item(const A &a, int64_t blk, int t, uint
             uint64_t v = 0;
 #pragma unroll
             for (int l = 0; l < Q; ++l) v ^= tile[l * rstride + base - b];
-            dst[b - bmin] = v;
+            dst[(b - bmin) ^ a.bin_swap] = v;
         }
     }
     wave_sync();  // the next item restages this wave's tile

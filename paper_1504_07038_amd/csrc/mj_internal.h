@@ -51,6 +51,7 @@ struct EncodeArgs {
     int32_t P, Q, n;
     int32_t W, H, S, ntiles;         // tile width, halo, LDS row stride, tiles per block
     int32_t waves;                   // waves per workgroup (1, 2 or 4), one LDS tile each
+    int32_t bin_swap;                // 1: bin j is stored at word j ^ 1 (128-bit pixels), else 0
     int32_t p[kMaxDirs];
     __device__ int dir(int i) const { return p[i]; }
     __device__ uint64_t *proj(int i, int64_t blk) const { return out[i] + blk * proj_stride; }
@@ -66,6 +67,7 @@ struct EncodeClass {
     int64_t nblocks;
     int32_t proj_stride;             // words per block slice
     int32_t P, Q, n, W, H, S, ntiles;
+    int32_t bin_swap;                // always 0: mixed launches take 64-bit pixels
     int32_t off[kMaxDirs];           // projection i at off[i] within a slice
     int16_t p[kMaxDirs];
     __device__ int dir(int i) const { return p[i]; }
@@ -151,6 +153,7 @@ struct DecodeArgs {
     int32_t P, n;
     int32_t R, ring_stride;          // ring length (power of two), words per LDS ring row
     int32_t nb;                      // blocks per wavefront (at most 64/ceil(Q/2), fewer if LDS is short)
+    int32_t bin_swap;                // 1: bin j is stored at word j ^ 1 (128-bit pixels), else 0
     int32_t p_sorted[kMaxDirs];      // directions in ascending p
     int32_t id_sorted[kMaxDirs];     // their indices in the caller's dirs
     ChunkInfo chunk;                 // chunked launches only
@@ -172,6 +175,7 @@ struct DecodeClass {
     int64_t img_stride;
     int32_t P, Q, n, nb, R, ring_stride;
     uint32_t mask_uniform;
+    int32_t bin_swap;                // always 0: mixed launches take 64-bit pixels
     int32_t off[kMaxDirs];
     int16_t p_sorted[kMaxDirs];
     int8_t id_sorted[kMaxDirs];
