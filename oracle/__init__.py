@@ -15,6 +15,8 @@ Paper: Pertin et al., arXiv 1504.07038.
     erasure code with q_i = 1, one call per block.
   - ``encode_blocks_wide`` / ``decode_blocks_wide``  Section 3.1: the same code
     on 128-bit pixels and bins.
+  - ``kept_bins`` / ``encode_blocks_kept`` / ``decode_blocks_kept``  Section 2.3:
+    the code with the bins that reconstruction never uses left out.
 
 Group: ``kind=0`` XOR on uint64 words; ``kind=1`` integers modulo ``mod``.
 """
@@ -73,6 +75,9 @@ def _load():
     lib.orc_forward.restype = i32
     lib.orc_inverse.argtypes = [i32, u64, vp, vp, vp, vp, i32, i32, i32, vp, i32, vp]
     lib.orc_inverse.restype = i32
+    lib.orc_inverse_kept.argtypes = [i32, u64, vp, vp, vp, vp, i32, i32, i32, vp, vp, vp, i32,
+                                     vp]
+    lib.orc_inverse_kept.restype = i32
     lib.orc_encode_blocks.argtypes = [vp, i64, i32, i32, vp, i32, vp]
     lib.orc_encode_blocks.restype = i32
     lib.orc_decode_blocks.argtypes = [vp, vp, i64, i32, i32, vp, i32, vp]
@@ -196,3 +201,77 @@ def decode_blocks_wide(projs: np.ndarray, erased: np.ndarray, P: int, Q: int,
     planes = [decode_blocks(np.ascontiguousarray(pr[..., h]), erased, P, Q, p_list)
               for h in (0, 1)]
     return np.stack(planes, axis=-1)
+
+
+def kept_bins(p_list, P: int, Q: int) -> list[tuple[int, int]]:
+    """The bins each projection of the XOR code (q_i = 1) must keep (Section
+    2.3: bins that no reconstruction uses can be left out), for the
+    reconstruction path of Section 2.2 as this project fixes it: of the
+    surviving projections the Q with the smallest p are used and the r-th of
+    them rebuilds image row r from its bins r*p - k, k = 0..P-1.
+
+    Enumerates every erasure pattern that leaves at least Q projections and
+    marks the bins the path reads.  Returns, per projection in the order of
+    ``p_list``, (first kept index, count) with indices as in ``forward``
+    (b - b_min); raises if a projection's kept bins are not contiguous.
+    """
+    n = len(p_list)
+    order = sorted(range(n), key=lambda i: p_list[i])
+    used = [np.zeros(proj_size(int(p), 1, P, Q), dtype=bool) for p in p_list]
+    for mask in range(1 << n):
+        alive = [i for i in order if not (mask >> i) & 1]
+        if len(alive) < Q:
+            continue
+        for r, i in enumerate(alive[:Q]):
+            p = int(p_list[i])
+            b0 = bin_min(p, 1, P, Q)
+            # bins r*p - k for k = 0..P-1, i.e. r*p - P + 1 .. r*p
+            used[i][r * p - P + 1 - b0: r * p + 1 - b0] = True
+    out = []
+    for u in used:
+        idx = np.flatnonzero(u)
+        if len(idx) == 0:
+            out.append((0, 0))
+            continue
+        if idx[-1] - idx[0] + 1 != len(idx):
+            raise ValueError("kept bins are not contiguous")
+        out.append((int(idx[0]), int(len(idx))))
+    return out
+
+
+def encode_blocks_kept(images: np.ndarray, P: int, Q: int, p_list) -> np.ndarray:
+    """The XOR code storing only the kept bins of each projection, projections
+    back to back in the order of ``p_list``: (nblocks, sum of kept counts)."""
+    full = encode_blocks(images, P, Q, p_list)
+    keep = kept_bins(p_list, P, Q)
+    offs = np.concatenate([[0], np.cumsum([proj_size(int(p), 1, P, Q) for p in p_list])])
+    parts = [full[:, offs[i] + lo: offs[i] + lo + cnt] for i, (lo, cnt) in enumerate(keep)]
+    return np.ascontiguousarray(np.concatenate(parts, axis=1))
+
+
+def decode_blocks_kept(projs: np.ndarray, erased: np.ndarray, P: int, Q: int,
+                       p_list) -> np.ndarray:
+    """Peeling (Section 2.2) of each block from the kept bins of its
+    projections not flagged in ``erased``; the missing bins are never used."""
+    keep = kept_bins(p_list, P, Q)
+    words = sum(c for _, c in keep)
+    pr = np.ascontiguousarray(projs, dtype=np.uint64).reshape(-1, words)
+    er = np.ascontiguousarray(erased, dtype=np.uint16).reshape(-1)
+    offs = np.concatenate([[0], np.cumsum([c for _, c in keep])]).astype(np.int64)
+    out = np.zeros((er.shape[0], Q, P), dtype=np.uint64)
+    lib = _load()
+    for b in range(er.shape[0]):
+        alive = [i for i in range(len(p_list)) if not (int(er[b]) >> i) & 1]
+        p = np.ascontiguousarray([int(p_list[i]) for i in alive], dtype=np.int32)
+        q = np.ones(len(alive), dtype=np.int32)
+        off = np.ascontiguousarray([offs[i] for i in alive], dtype=np.int64)
+        lo = np.ascontiguousarray([keep[i][0] for i in alive], dtype=np.int64)
+        cnt = np.ascontiguousarray([keep[i][1] for i in alive], dtype=np.int64)
+        row = np.ascontiguousarray(pr[b])
+        img = np.zeros((Q, P), dtype=np.uint64)
+        rc = lib.orc_inverse_kept(XOR, 0, _ptr(row), _ptr(off), _ptr(p), _ptr(q), len(alive),
+                                  P, Q, _ptr(lo), _ptr(cnt), _ptr(img), 0, None)
+        if rc != OK:
+            raise ValueError(f"orc_inverse_kept failed on block {b}: {rc}")
+        out[b] = img
+    return out

@@ -152,9 +152,10 @@ int32_t orc_forward(int32_t kind, uint64_t mod, const uint64_t *image, int32_t P
  * ops_out (may be NULL) receives the number of group subtractions made in
  * step 4, for the operation-count checks.
  */
-int32_t orc_inverse(int32_t kind, uint64_t mod, const uint64_t *proj, const int64_t *proj_off,
-                    const int32_t *p, const int32_t *q, int32_t m, int32_t P, int32_t Q,
-                    uint64_t *image, int32_t verify, int64_t *ops_out) {
+static int32_t inverse_impl(int32_t kind, uint64_t mod, const uint64_t *proj,
+                            const int64_t *proj_off, const int32_t *p, const int32_t *q, int32_t m,
+                            int32_t P, int32_t Q, const int64_t *keep_lo, const int64_t *keep_n,
+                            uint64_t *image, int32_t verify, int64_t *ops_out) {
     if (!grp_ok(kind, mod) || P <= 0 || Q <= 0 || m < 0) return ORC_EINVAL;
     int64_t npix = (int64_t)P * Q;
     int64_t total = 0;
@@ -175,10 +176,18 @@ int32_t orc_inverse(int32_t kind, uint64_t mod, const uint64_t *proj, const int6
         return ORC_ENOMEM;
     }
 
-    /* step 1 and 2 */
+    /* step 1 and 2 (without keep_lo, every bin is given; with it, only bins
+     * keep_lo[i] .. keep_lo[i]+keep_n[i]-1 of projection i are, stored from
+     * proj[proj_off[i]], and a missing bin never becomes reconstructible) */
     for (int32_t i = 0; i < m; i++) {
         int64_t B = start[i + 1] - start[i];
-        for (int64_t j = 0; j < B; j++) resid[start[i] + j] = proj[proj_off[i] + j];
+        int64_t lo = keep_lo ? keep_lo[i] : 0, nk = keep_lo ? keep_n[i] : B;
+        if (lo < 0 || nk < 0 || lo + nk > B) {
+            free(start); free(resid); free(count); free(queue); free(known);
+            return ORC_EINVAL;
+        }
+        for (int64_t j = 0; j < B; j++)
+            resid[start[i] + j] = (j >= lo && j < lo + nk) ? proj[proj_off[i] + j - lo] : 0;
     }
     for (int32_t l = 0; l < Q; l++)
         for (int32_t k = 0; k < P; k++)
@@ -186,6 +195,11 @@ int32_t orc_inverse(int32_t kind, uint64_t mod, const uint64_t *proj, const int6
                 int64_t b = -(int64_t)k * q[i] + (int64_t)l * p[i];
                 count[start[i] + b - orc_bin_min(p[i], q[i], P, Q)] += 1;
             }
+    if (keep_lo) {
+        for (int32_t i = 0; i < m; i++)
+            for (int64_t j = 0; j < start[i + 1] - start[i]; j++)
+                if (j < keep_lo[i] || j >= keep_lo[i] + keep_n[i]) count[start[i] + j] = -(P + Q) - 1;
+    }
     /* A bin can be queued at most twice: once at start, once when its count
      * falls to one; the queue is sized for that. */
     int64_t qhead = 0, qtail = 0;
@@ -241,6 +255,28 @@ int32_t orc_inverse(int32_t kind, uint64_t mod, const uint64_t *proj, const int6
     if (ops_out) *ops_out = ops;
     free(start); free(resid); free(count); free(queue); free(known);
     return rc;
+}
+
+int32_t orc_inverse(int32_t kind, uint64_t mod, const uint64_t *proj, const int64_t *proj_off,
+                    const int32_t *p, const int32_t *q, int32_t m, int32_t P, int32_t Q,
+                    uint64_t *image, int32_t verify, int64_t *ops_out) {
+    return inverse_impl(kind, mod, proj, proj_off, p, q, m, P, Q, NULL, NULL, image, verify,
+                        ops_out);
+}
+
+/*
+ * The same peeling when only some bins of each projection are stored: the
+ * never-used bins of Section 2.3 left out.  Projection i holds bins
+ * keep_lo[i] .. keep_lo[i]+keep_n[i]-1 (indices as in orc_inverse) at
+ * proj[proj_off[i]]; the other bins are unknown and never used.
+ */
+int32_t orc_inverse_kept(int32_t kind, uint64_t mod, const uint64_t *proj, const int64_t *proj_off,
+                         const int32_t *p, const int32_t *q, int32_t m, int32_t P, int32_t Q,
+                         const int64_t *keep_lo, const int64_t *keep_n, uint64_t *image,
+                         int32_t verify, int64_t *ops_out) {
+    if (!keep_lo || !keep_n) return ORC_EINVAL;
+    return inverse_impl(kind, mod, proj, proj_off, p, q, m, P, Q, keep_lo, keep_n, image, verify,
+                        ops_out);
 }
 
 /* ---- erasure-code convenience: many independent blocks --------------- */
