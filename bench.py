@@ -25,12 +25,16 @@ if ROOT not in sys.path:
 HBM_PEAK_GBPS = 8000.0  # MI355X published HBM3E bandwidth
 
 WORKLOADS = {
-    # name: (P, Q, n, nblocks, erasures per block, 64-bit words per pixel)
-    "4k_6_4": (128, 4, 6, 1 << 21, 2, 1),
-    "8k_6_4": (256, 4, 6, 1 << 20, (0, 2), 1),
-    "8k_12_8": (128, 8, 12, 1 << 19, 4, 1),
-    # the paper's own geometry: 16-byte pixels, so a 4 KB (6,4) block is 64 x 4
-    "4k_6_4_w128": (64, 4, 6, 1 << 21, 2, 2),
+    # name: (P, Q, n, nblocks, erasures per block, layout)
+    #   layout "full": 64-bit pixels, every bin of Eq. 2 stored;
+    #   "wide": 16-byte pixels (the paper's own geometry: a 4 KB (6,4) block
+    #   is 64 x 4); "trim": 64-bit pixels, never-used bins left out
+    "4k_6_4": (128, 4, 6, 1 << 21, 2, "full"),
+    "8k_6_4": (256, 4, 6, 1 << 20, (0, 2), "full"),
+    "8k_12_8": (128, 8, 12, 1 << 19, 4, "full"),
+    "4k_6_4_w128": (64, 4, 6, 1 << 21, 2, "wide"),
+    "4k_6_4_trim": (128, 4, 6, 1 << 21, 2, "trim"),
+    "8k_12_8_trim": (128, 8, 12, 1 << 19, 4, "trim"),
 }
 
 
@@ -100,8 +104,8 @@ def pmc_summary(workload: str, fetch_csv: str, write_csv: str, command: str) -> 
     and written once)."""
     import csv
 
-    P, Q, n, nblocks, _, pw = WORKLOADS[workload]
-    copy_bytes = nblocks * P * Q * 8 * pw
+    P, Q, n, nblocks, _, layout = WORKLOADS[workload]
+    copy_bytes = nblocks * P * Q * 8 * (2 if layout == "wide" else 1)
 
     def per_kernel(path, counter):
         vals = {k: [] for k in KERNEL_TAGS}
@@ -215,13 +219,19 @@ def main():
     import paper_1504_07038_amd as mj
     import synth
 
-    P, Q, n, nblocks, ner, pw = WORKLOADS[args.workload]
+    P, Q, n, nblocks, ner, layout = WORKLOADS[args.workload]
     dirs = synth.centered_dirs(n)
-    words = pw * mj.mojette_block_words(dirs, P, Q)
+    pw = 2 if layout == "wide" else 1       # 64-bit words per pixel
+    if layout == "trim":
+        words, _ = mj.mojette_trimmed_layout(dirs, P, Q)
+    else:
+        words = pw * mj.mojette_block_words(dirs, P, Q)
     block_bytes = P * Q * 8 * pw
-    # 16-byte pixels (pw = 2) go through the wide entry points
-    encode_batch = mj.mojette_encode_batch if pw == 1 else mj.mojette_encode_batch_wide
-    decode_batch = mj.mojette_decode_batch if pw == 1 else mj.mojette_decode_batch_wide
+    encode_batch, decode_batch = {
+        "full": (mj.mojette_encode_batch, mj.mojette_decode_batch),
+        "wide": (mj.mojette_encode_batch_wide, mj.mojette_decode_batch_wide),
+        "trim": (mj.mojette_encode_batch_trimmed, mj.mojette_decode_batch_trimmed),
+    }[layout]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
@@ -304,12 +314,12 @@ def main():
 
     # plain path: one launch per block, against the batched path on the same blocks
     plain = None
-    if not args.no_plain and pw == 1:   # the one-block calls take 64-bit pixels
+    if not args.no_plain and layout == "full":   # the one-block calls take the full layout
         plain = plain_vs_batched(mj, torch, np, d_img, d_proj, masks, P, Q, dirs, words,
                                  args.plain_blocks, block_bytes)
 
     cpu = None
-    if not args.no_cpu_baseline and pw == 1:
+    if not args.no_cpu_baseline and layout == "full":
         cpu = cpu_baseline(P, Q, dirs, min(args.cpu_sample, nblocks), ner)
 
     rec = {
@@ -328,6 +338,7 @@ def main():
         "config": {
             "workload": f"{args.workload}: {nblocks} blocks of {block_bytes} B, P={P} Q={Q} "
                         f"n={n} p={dirs[0]}..{dirs[-1]} q=1, XOR on {64 * pw}-bit pixels, "
+                        f"{'never-used bins left out, ' if layout == 'trim' else ''}"
                         f"erasures/block={ner}",
             "blocks": nblocks, "P": P, "Q": Q, "n": n, "erasures": str(ner),
             "parallelism": "single GPU",

@@ -147,6 +147,32 @@ int mojette_decode_batch_wide(const uint64_t *projs, const uint16_t *erased, int
                               uint64_t *images, int32_t *status, void *stream);
 
 /*
+ * Never-used bins left out (Section 2.3 notes that some bins are used by no
+ * reconstruction, whatever the projections at hand).  For this library's
+ * reconstruction path (of the survivors the Q with the smallest p are used,
+ * the r-th rebuilding image row r from its bins r*p - k, k = 0..P-1) the
+ * projection whose p has rank i among the sorted directions keeps the bins
+ * it can be read from, r = max(0, i - (n - Q)) .. min(i, Q - 1): P +
+ * (r_hi - r_lo)*|p| consecutive bins instead of Eq. 2's |p|(Q-1) + P.
+ *
+ * mojette_trimmed_layout: words per block of the trimmed layout (the kept
+ *   bins of projection 0, then of projection 1, ...), or -1 on bad
+ *   arguments (including n < Q).  first[i] (may be NULL) receives the index
+ *   (b - b_min, as in the full projection) of projection i's first kept
+ *   bin, count[i] (may be NULL) their number; both host arrays of n.
+ * mojette_encode_batch_trimmed / mojette_decode_batch_trimmed: as the
+ *   batched calls, projections in the trimmed layout (block b's slice at
+ *   word b * mojette_trimmed_layout()).
+ */
+int64_t mojette_trimmed_layout(const int32_t *dirs, int32_t n, int32_t P, int32_t Q,
+                               int64_t *first, int64_t *count);
+int mojette_encode_batch_trimmed(const uint64_t *images, int64_t nblocks, int32_t P, int32_t Q,
+                                 const int32_t *dirs, int32_t n, uint64_t *projs, void *stream);
+int mojette_decode_batch_trimmed(const uint64_t *projs, const uint16_t *erased, int64_t nblocks,
+                                 int32_t P, int32_t Q, const int32_t *dirs, int32_t n,
+                                 uint64_t *images, int32_t *status, void *stream);
+
+/*
  * mojette_decode_batch with the decode schedule's blocks per wavefront set by
  * the caller (an autotuner): blocks_per_wave >= 1 asks for that many (capped
  * by what fits in LDS), 0 keeps the library's choice.  Fewer blocks per

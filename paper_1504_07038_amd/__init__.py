@@ -129,6 +129,10 @@ def lib() -> ctypes.CDLL:
         "mojette_encode_batch": ([vp, i64, i32, i32, vp, i32, vp, vp], ctypes.c_int),
         "mojette_decode_batch": ([vp, vp, i64, i32, i32, vp, i32, vp, vp, vp], ctypes.c_int),
         "mojette_encode_batch_wide": ([vp, i64, i32, i32, vp, i32, vp, vp], ctypes.c_int),
+        "mojette_trimmed_layout": ([vp, i32, i32, i32, vp, vp], i64),
+        "mojette_encode_batch_trimmed": ([vp, i64, i32, i32, vp, i32, vp, vp], ctypes.c_int),
+        "mojette_decode_batch_trimmed": ([vp, vp, i64, i32, i32, vp, i32, vp, vp, vp],
+                                         ctypes.c_int),
         "mojette_decode_batch_wide": ([vp, vp, i64, i32, i32, vp, i32, vp, vp, vp],
                                       ctypes.c_int),
         "mojette_decode_batch_tuned": ([vp, vp, i64, i32, i32, vp, i32, vp, vp, i32, vp],
@@ -182,6 +186,7 @@ def exported_symbols() -> list[str]:
         "mojette_bin_offset", "mojette_block_words", "mojette_decode_ring", "mojette_encode",
         "mojette_decode", "mojette_encode_batch", "mojette_decode_batch",
         "mojette_encode_batch_wide", "mojette_decode_batch_wide",
+        "mojette_trimmed_layout", "mojette_encode_batch_trimmed", "mojette_decode_batch_trimmed",
         "mojette_decode_batch_tuned", "mojette_decode_max_blocks_per_wave",
         "mojette_decode_default_blocks_per_wave",
         "mojette_classes_layout", "mojette_encode_classes", "mojette_decode_classes",
@@ -321,6 +326,38 @@ def mojette_decode_batch_wide(projs, erased, nblocks: int, P: int, Q: int, dirs,
     rc = lib().mojette_decode_batch_wide(_word_tensor(projs, "projs"), er, nblocks, P, Q, arr,
                                          n, _word_tensor(images, "images"), st, _stream(stream))
     return _check(rc, "mojette_decode_batch_wide", check)
+
+
+def mojette_trimmed_layout(dirs, P: int, Q: int):
+    """(block words, [(first kept bin index, count) per projection]) of the
+    layout without never-used bins; raises on bad arguments."""
+    arr, n = _i32_array(dirs)
+    first = (ctypes.c_int64 * max(1, n))()
+    count = (ctypes.c_int64 * max(1, n))()
+    words = lib().mojette_trimmed_layout(arr, n, P, Q, first, count)
+    if words < 0:
+        raise MojetteError(MOJETTE_EINVAL, "mojette_trimmed_layout")
+    return int(words), [(int(first[i]), int(count[i])) for i in range(n)]
+
+
+def mojette_encode_batch_trimmed(images, nblocks: int, P: int, Q: int, dirs, projs, stream=None,
+                                 check: bool = True) -> int:
+    """Batched encode storing only the bins some reconstruction reads."""
+    arr, n = _i32_array(dirs)
+    rc = lib().mojette_encode_batch_trimmed(_word_tensor(images, "images"), nblocks, P, Q, arr,
+                                            n, _word_tensor(projs, "projs"), _stream(stream))
+    return _check(rc, "mojette_encode_batch_trimmed", check)
+
+
+def mojette_decode_batch_trimmed(projs, erased, nblocks: int, P: int, Q: int, dirs, images,
+                                 status=None, stream=None, check: bool = True) -> int:
+    """Batched decode from projections in the trimmed layout."""
+    arr, n = _i32_array(dirs)
+    er, st = _decode_masks(erased, status)
+    rc = lib().mojette_decode_batch_trimmed(_word_tensor(projs, "projs"), er, nblocks, P, Q,
+                                            arr, n, _word_tensor(images, "images"), st,
+                                            _stream(stream))
+    return _check(rc, "mojette_decode_batch_trimmed", check)
 
 
 def mojette_decode_batch_tuned(projs, erased, nblocks: int, P: int, Q: int, dirs, images,

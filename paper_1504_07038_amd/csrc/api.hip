@@ -52,6 +52,30 @@ bool wide_geometry(const int32_t *dirs, int32_t n, int32_t P, int32_t Q, int32_t
     return geometry_ok(dirs2, n, 2 * P, Q);
 }
 
+// Never-used bins (Section 2.3) for the reconstruction path of the decode
+// kernels: of the survivors the Q with the smallest p are used, the r-th for
+// image row r, which reads bins r*p - k for k in [0, P).  The projection of
+// rank i among the sorted directions is the r-th for some erasure pattern
+// exactly when max(0, i - (n - Q)) <= r <= min(i, Q - 1), so it keeps the
+// bins from min(r_lo*p, r_hi*p) - P + 1 to max(r_lo*p, r_hi*p):
+// P + (r_hi - r_lo)*|p| of them.  Fills, per projection in the caller's
+// order, the first kept bin index (b - b_min) and the count; false if the
+// geometry is invalid or n < Q.
+bool kept_layout(const int32_t *dirs, int32_t n, int32_t P, int32_t Q, int32_t *first,
+                 int32_t *count) {
+    if (!geometry_ok(dirs, n, P, Q) || n < Q) return false;
+    for (int i = 0; i < n; ++i) {
+        int rank = 0;
+        for (int j = 0; j < n; ++j) rank += dirs[j] < dirs[i];
+        const int r_lo = std::max(0, rank - (n - Q)), r_hi = std::min(rank, Q - 1);
+        const int64_t p = dirs[i];
+        const int64_t b_first = std::min(r_lo * p, r_hi * p) - P + 1;
+        first[i] = (int32_t)(b_first - mojette_bin_offset(dirs[i], P, Q));
+        count[i] = (int32_t)(P + (int64_t)(r_hi - r_lo) * std::llabs(p));
+    }
+    return true;
+}
+
 int status_of(hipError_t e) { return mj::hip_status(e); }
 
 // Kernel launches report through hipGetLastError(), which also returns an
@@ -290,9 +314,11 @@ int mojette_encode(const uint64_t *image, int32_t P, int32_t Q, const int32_t *d
     return status_of(mj::launch_encode(a, grid, (hipStream_t)stream));
 }
 
+// keep_first/keep_count: the stored bins of each projection (null: all).
 static int encode_batch_impl(const uint64_t *images, int64_t nblocks, int32_t P, int32_t Q,
                              const int32_t *dirs, int32_t n, uint64_t *projs, void *stream,
-                             int bin_swap) {
+                             int bin_swap, const int32_t *keep_first = nullptr,
+                             const int32_t *keep_count = nullptr) {
     if (nblocks < 0 || !geometry_ok(dirs, n, P, Q)) return MOJETTE_EINVAL;
     if (nblocks == 0) return MOJETTE_OK;
     if (!images || !projs) return MOJETTE_EINVAL;
@@ -303,7 +329,13 @@ static int encode_batch_impl(const uint64_t *images, int64_t nblocks, int32_t P,
     int64_t off = 0;
     for (int i = 0; i < n; ++i) {
         a.out[i] = projs + off;
-        off += mojette_proj_size(dirs[i], P, Q);
+        if (keep_first) {
+            a.keep_lo[i] = keep_first[i];
+            a.keep_n[i] = keep_count[i];
+            off += keep_count[i];
+        } else {
+            off += mojette_proj_size(dirs[i], P, Q);
+        }
     }
     a.proj_stride = off;
     a.nblocks = nblocks;
@@ -324,6 +356,27 @@ int mojette_encode_batch_wide(const uint64_t *images, int64_t nblocks, int32_t P
     int32_t dirs2[kMaxDirs];
     if (nblocks < 0 || !wide_geometry(dirs, n, P, Q, dirs2)) return MOJETTE_EINVAL;
     return encode_batch_impl(images, nblocks, 2 * P, Q, dirs2, n, projs, stream, 1);
+}
+
+int64_t mojette_trimmed_layout(const int32_t *dirs, int32_t n, int32_t P, int32_t Q,
+                               int64_t *first, int64_t *count) {
+    int32_t f[kMaxDirs], c[kMaxDirs];
+    if (!kept_layout(dirs, n, P, Q, f, c)) return -1;
+    int64_t total = 0;
+    for (int i = 0; i < n; ++i) {
+        if (first) first[i] = f[i];
+        if (count) count[i] = c[i];
+        total += c[i];
+    }
+    return total;
+}
+
+int mojette_encode_batch_trimmed(const uint64_t *images, int64_t nblocks, int32_t P, int32_t Q,
+                                 const int32_t *dirs, int32_t n, uint64_t *projs,
+                                 void *stream) {
+    int32_t f[kMaxDirs], c[kMaxDirs];
+    if (nblocks < 0 || !kept_layout(dirs, n, P, Q, f, c)) return MOJETTE_EINVAL;
+    return encode_batch_impl(images, nblocks, P, Q, dirs, n, projs, stream, 0, f, c);
 }
 
 int mojette_decode(const uint64_t *const *proj, const int32_t *proj_ids, int32_t m,
@@ -357,7 +410,9 @@ int mojette_decode(const uint64_t *const *proj, const int32_t *proj_ids, int32_t
 
 static int decode_batch_impl(const uint64_t *projs, const uint16_t *erased, int64_t nblocks,
                              int32_t P, int32_t Q, const int32_t *dirs, int32_t n,
-                             uint64_t *images, int32_t *status, void *stream, int bin_swap) {
+                             uint64_t *images, int32_t *status, void *stream, int bin_swap,
+                             const int32_t *keep_first = nullptr,
+                             const int32_t *keep_count = nullptr) {
     if (nblocks < 0 || !geometry_ok(dirs, n, P, Q)) return MOJETTE_EINVAL;
     if (nblocks == 0) return MOJETTE_OK;
     if (!projs || !images) return MOJETTE_EINVAL;
@@ -367,7 +422,12 @@ static int decode_batch_impl(const uint64_t *projs, const uint16_t *erased, int6
     int64_t off = 0;
     for (int i = 0; i < n; ++i) {
         a.off[i] = (int32_t)off;
-        off += mojette_proj_size(dirs[i], P, Q);
+        if (keep_first) {
+            a.keep_lo[i] = keep_first[i];
+            off += keep_count[i];
+        } else {
+            off += mojette_proj_size(dirs[i], P, Q);
+        }
     }
     // A wave's slice of the pool and of the images must be addressable with
     // 32-bit byte offsets.
@@ -402,6 +462,15 @@ int mojette_decode_batch_wide(const uint64_t *projs, const uint16_t *erased, int
     if (nblocks < 0 || !wide_geometry(dirs, n, P, Q, dirs2)) return MOJETTE_EINVAL;
     return decode_batch_impl(projs, erased, nblocks, 2 * P, Q, dirs2, n, images, status, stream,
                              1);
+}
+
+int mojette_decode_batch_trimmed(const uint64_t *projs, const uint16_t *erased, int64_t nblocks,
+                                 int32_t P, int32_t Q, const int32_t *dirs, int32_t n,
+                                 uint64_t *images, int32_t *status, void *stream) {
+    int32_t f[kMaxDirs], c[kMaxDirs];
+    if (nblocks < 0 || !kept_layout(dirs, n, P, Q, f, c)) return MOJETTE_EINVAL;
+    return decode_batch_impl(projs, erased, nblocks, P, Q, dirs, n, images, status, stream, 0,
+                             f, c);
 }
 
 // ---- chunked decode of long rows -------------------------------------------

@@ -264,8 +264,8 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch)
             }
             X.d = X.on ? -((A_max - Ax) >> 1) : 0;       // (Ax - A_max)/2, exact
             Y.d = Y.on ? -((A_max - Ay - 1) >> 1) : 0;   // (Ay - A_max + 1)/2, exact
-            jb0 = r0 * p0 - bin_offset(p0, P, Q);
-            jb1 = r1 * p1 - bin_offset(p1, P, Q);
+            jb0 = r0 * p0 - (bin_offset(p0, P, Q) + a.kept_first(id0));
+            jb1 = r1 * p1 - (bin_offset(p1, P, Q) + a.kept_first(id1));
         }
 
         // Per-iteration row windows, from the lanes that own their rows.

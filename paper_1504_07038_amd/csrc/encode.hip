@@ -50,8 +50,9 @@ __device__ __forceinline__ void encode_item(const A &a, int64_t blk, int t, uint
     const int base = H - x0;
     for (int i = 0; i < a.n; ++i) {
         const int p = a.dir(i);
-        const int bmin = bin_offset(p, P, Q);
-        const int bmax = bmin + proj_bins(p, P, Q) - 1;
+        // the stored bins: all of Eq. 2's, or the kept ones (Section 2.3)
+        const int bmin = bin_offset(p, P, Q) + a.kept_first(i);
+        const int bmax = bmin + a.kept_count(i, proj_bins(p, P, Q)) - 1;
         const int bh = first ? bmax : min(bmax, -x0);
         const int bl = last ? bmin : max(bmin, -x0 - W + 1);
         uint64_t *dst = a.proj(i, blk);

@@ -53,8 +53,13 @@ struct EncodeArgs {
     int32_t waves;                   // waves per workgroup (1, 2 or 4), one LDS tile each
     int32_t bin_swap;                // 1: bin j is stored at word j ^ 1 (128-bit pixels), else 0
     int32_t p[kMaxDirs];
+    // Projection i stores keep_n[i] bins from bin index keep_lo[i] on (the
+    // never-used bins left out); keep_n[i] == 0: all of Eq. 2's bins.
+    int32_t keep_lo[kMaxDirs], keep_n[kMaxDirs];
     __device__ int dir(int i) const { return p[i]; }
     __device__ uint64_t *proj(int i, int64_t blk) const { return out[i] + blk * proj_stride; }
+    __device__ int kept_first(int i) const { return keep_lo[i]; }
+    __device__ int kept_count(int i, int full) const { return keep_n[i] ? keep_n[i] : full; }
 };
 
 // One geometry class of a mixed launch: nblocks blocks with the same P, Q and
@@ -74,6 +79,8 @@ struct EncodeClass {
     __device__ uint64_t *proj(int i, int64_t blk) const {
         return projs + (slots ? slots[blk] : blk) * proj_stride + off[i];
     }
+    __device__ int kept_first(int) const { return 0; }      // mixed launches keep every bin
+    __device__ int kept_count(int, int full) const { return full; }
 };
 
 constexpr int kMaxClasses = MOJETTE_MAX_CLASSES;
@@ -157,9 +164,11 @@ struct DecodeArgs {
     int32_t p_sorted[kMaxDirs];      // directions in ascending p
     int32_t id_sorted[kMaxDirs];     // their indices in the caller's dirs
     ChunkInfo chunk;                 // chunked launches only
+    int32_t keep_lo[kMaxDirs];       // projection i's first stored bin index (0: Eq. 2's first)
     __device__ const uint64_t *proj_base(int64_t blk, int id) const {
         return pool ? pool + slots[blk] * proj_stride + off[id] : in[id];
     }
+    __device__ int kept_first(int id) const { return keep_lo[id]; }
 };
 
 // One geometry class of a mixed decode launch (pool mode only).  Field names
@@ -182,6 +191,7 @@ struct DecodeClass {
     __device__ const uint64_t *proj_base(int64_t blk, int id) const {
         return pool + (slots ? slots[blk] : blk) * proj_stride + off[id];
     }
+    __device__ int kept_first(int) const { return 0; }      // mixed launches keep every bin
 };
 
 struct DecodeClassTable {

@@ -1,0 +1,97 @@
+"""GPU parity for the code without never-used bins (Section 2.3): the HIP
+library's trimmed entry points against the oracle, bit for bit."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpuutil import masks_to_dev, say, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def mj():
+    import paper_1504_07038_amd as mj
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    mj.lib()
+    return mj
+
+
+POISON = np.uint64(0xDEADBEEFCAFEF00D)
+
+
+@pytest.mark.parametrize("P,Q,n,ner,nblocks", [
+    (128, 4, 6, 2, 70),        # 4 KB (6,4)
+    (128, 8, 12, 4, 19),       # 8 KB (8,4)
+    (256, 4, 6, (0, 2), 33),   # 8 KB (4,2)
+    (64, 4, 12, (0, 8), 25),   # (12,4)
+    (37, 3, 6, 3, 41),         # odd row length, ragged batch
+    (300, 2, 4, 2, 9),         # rows wider than one encode tile
+    (5, 1, 3, 2, 7),
+])
+def test_trimmed_parity(mj, P, Q, n, ner, nblocks):
+    dirs = synth.centered_dirs(n)
+    say(f"trimmed parity P={P} Q={Q} n={n} blocks={nblocks}")
+    words, keep = mj.mojette_trimmed_layout(dirs, P, Q)
+    imgs = synth.block_images(300 + P + n, 0, nblocks, P, Q)
+    masks = synth.erasure_masks(17 + n, nblocks, n, ner)
+    d_img = to_dev(imgs)
+    d_proj = torch.full((nblocks * words,), -1, dtype=torch.int64, device="cuda")
+    mj.mojette_encode_batch_trimmed(d_img, nblocks, P, Q, dirs, d_proj)
+    torch.cuda.synchronize()
+    enc = to_np(d_proj).reshape(nblocks, words)
+    assert np.array_equal(enc, oracle.encode_blocks_kept(imgs, P, Q, dirs))
+    src = enc.copy()
+    offs = np.concatenate([[0], np.cumsum([c for _, c in keep])])
+    for i in range(n):
+        src[np.flatnonzero((masks >> i) & 1), offs[i]:offs[i + 1]] = POISON
+    d_out = torch.full((nblocks * Q * P,), -1, dtype=torch.int64, device="cuda")
+    d_status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    mj.mojette_decode_batch_trimmed(to_dev(src), masks_to_dev(masks), nblocks, P, Q, dirs,
+                                    d_out, d_status)
+    torch.cuda.synchronize()
+    assert int(d_status.item()) == 0
+    out = to_np(d_out).reshape(nblocks, Q, P)
+    assert np.array_equal(out, imgs)
+    assert np.array_equal(out[:4], oracle.decode_blocks_kept(src[:4], masks[:4], P, Q, dirs))
+
+
+@pytest.mark.parametrize("P,Q,n,nblocks,ner", [(128, 4, 6, 1 << 21, 2), (128, 8, 12, 1 << 19, 4)])
+def test_trimmed_full_size(mj, P, Q, n, nblocks, ner):
+    dirs = synth.centered_dirs(n)
+    words, _ = mj.mojette_trimmed_layout(dirs, P, Q)
+    say(f"trimmed full size: {nblocks} blocks P={P} Q={Q} n={n}")
+    d_img = torch.empty(nblocks * Q * P, dtype=torch.int64, device="cuda")
+    mj.mojette_fill_splitmix64(d_img, d_img.numel(), synth.SEED_DATA + 9)
+    masks = synth.erasure_masks(synth.SEED_ERASE, nblocks, n, ner)
+    d_proj = torch.empty(nblocks * words, dtype=torch.int64, device="cuda")
+    d_out = torch.empty_like(d_img)
+    d_status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    mj.mojette_encode_batch_trimmed(d_img, nblocks, P, Q, dirs, d_proj)
+    mj.mojette_decode_batch_trimmed(d_proj, masks_to_dev(masks), nblocks, P, Q, dirs, d_out,
+                                    d_status)
+    torch.cuda.synchronize()
+    assert int(d_status.item()) == 0
+    assert torch.equal(d_out, d_img)
+    rng = np.random.default_rng(6)
+    sample = np.unique(np.concatenate([[0, nblocks - 1], rng.integers(0, nblocks, 40)]))
+    idx = torch.from_numpy(sample).cuda()
+    imgs = to_np(d_img.view(nblocks, -1)[idx]).reshape(len(sample), Q, P)
+    got = to_np(d_proj.view(nblocks, words)[idx])
+    assert np.array_equal(got, oracle.encode_blocks_kept(imgs, P, Q, dirs))
+    del d_img, d_proj, d_out
+    torch.cuda.empty_cache()
+
+
+def test_trimmed_argument_checks(mj):
+    d = torch.zeros(16, dtype=torch.int64, device="cuda")
+    assert mj.mojette_encode_batch_trimmed(d, 1, 8, 3, [0, 1], d,
+                                           check=False) == mj.MOJETTE_EINVAL
+    assert mj.mojette_decode_batch_trimmed(d, None, -1, 8, 2, [0, 1], d,
+                                           check=False) == mj.MOJETTE_EINVAL
+    assert mj.mojette_encode_batch_trimmed(d, 0, 8, 2, [0, 1], d) == 0
