@@ -17,6 +17,8 @@ Paper: Pertin et al., arXiv 1504.07038.
     on 128-bit pixels and bins.
   - ``kept_bins`` / ``encode_blocks_kept`` / ``decode_blocks_kept``  Section 2.3:
     the code with the bins that reconstruction never uses left out.
+  - ``encode_blocks_sys`` / ``decode_blocks_sys``  Section 2.3's systematic
+    version: data lines stored as they are, parity projections beside them.
 
 Group: ``kind=0`` XOR on uint64 words; ``kind=1`` integers modulo ``mod``.
 """
@@ -78,6 +80,8 @@ def _load():
     lib.orc_inverse_kept.argtypes = [i32, u64, vp, vp, vp, vp, i32, i32, i32, vp, vp, vp, i32,
                                      vp]
     lib.orc_inverse_kept.restype = i32
+    lib.orc_inverse_known.argtypes = [i32, u64, vp, vp, vp, vp, i32, i32, i32, vp, vp, i32, vp]
+    lib.orc_inverse_known.restype = i32
     lib.orc_encode_blocks.argtypes = [vp, i64, i32, i32, vp, i32, vp]
     lib.orc_encode_blocks.restype = i32
     lib.orc_decode_blocks.argtypes = [vp, vp, i64, i32, i32, vp, i32, vp]
@@ -275,3 +279,52 @@ def decode_blocks_kept(projs: np.ndarray, erased: np.ndarray, P: int, Q: int,
             raise ValueError(f"orc_inverse_kept failed on block {b}: {rc}")
         out[b] = img
     return out
+
+
+def encode_blocks_sys(images: np.ndarray, P: int, Q: int, parity_dirs) -> np.ndarray:
+    """Systematic code (Section 2.3 mentions a systematic version without
+    giving it; this is the construction used here): a block's Q data lines
+    are stored as they are, and m parity projections along (p, 1) for p in
+    ``parity_dirs`` are stored beside them.  Returns the parity pool
+    (nblocks, sum B_i); the data lines are ``images`` themselves."""
+    return encode_blocks(images, P, Q, parity_dirs)
+
+
+def decode_blocks_sys(images: np.ndarray, parity: np.ndarray, erased: np.ndarray, P: int,
+                      Q: int, parity_dirs, return_rc: bool = False):
+    """Rebuild each block of the systematic code.  Packet i < Q is data line
+    i, packet Q + j parity projection j; bit i of ``erased[b]`` set = packet i
+    of block b lost (its contents are ignored).  The surviving lines are
+    pixels known in advance; the peeling of Section 2.2 finds the others from
+    the surviving parity projections.  Returns the images (and, with
+    ``return_rc``, the per-block status: OK or ENOTRECON)."""
+    img = np.ascontiguousarray(images, dtype=np.uint64).reshape(-1, Q, P)
+    m = len(parity_dirs)
+    words = block_stride(P, Q, parity_dirs)
+    par = np.ascontiguousarray(parity, dtype=np.uint64).reshape(-1, words)
+    er = np.ascontiguousarray(erased, dtype=np.uint16).reshape(-1)
+    sizes = [proj_size(int(p), 1, P, Q) for p in parity_dirs]
+    offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    out = np.zeros_like(img)
+    rcs = np.zeros(er.shape[0], dtype=np.int32)
+    lib = _load()
+    for b in range(er.shape[0]):
+        mask = int(er[b])
+        known = np.zeros((Q, P), dtype=np.uint8)
+        cur = np.zeros((Q, P), dtype=np.uint64)
+        for r in range(Q):
+            if not (mask >> r) & 1:
+                known[r] = 1
+                cur[r] = img[b, r]
+        alive = [j for j in range(m) if not (mask >> (Q + j)) & 1]
+        p = np.ascontiguousarray([int(parity_dirs[j]) for j in alive], dtype=np.int32)
+        q = np.ones(len(alive), dtype=np.int32)
+        off = np.ascontiguousarray([offs[j] for j in alive], dtype=np.int64)
+        row = np.ascontiguousarray(par[b])
+        rc = lib.orc_inverse_known(XOR, 0, _ptr(row), _ptr(off), _ptr(p), _ptr(q), len(alive),
+                                   P, Q, _ptr(known), _ptr(cur), 0, None)
+        if rc not in (OK, ENOTRECON):
+            raise ValueError(f"orc_inverse_known failed on block {b}: {rc}")
+        rcs[b] = rc
+        out[b] = cur
+    return (out, rcs) if return_rc else out

@@ -155,7 +155,8 @@ int32_t orc_forward(int32_t kind, uint64_t mod, const uint64_t *image, int32_t P
 static int32_t inverse_impl(int32_t kind, uint64_t mod, const uint64_t *proj,
                             const int64_t *proj_off, const int32_t *p, const int32_t *q, int32_t m,
                             int32_t P, int32_t Q, const int64_t *keep_lo, const int64_t *keep_n,
-                            uint64_t *image, int32_t verify, int64_t *ops_out) {
+                            const unsigned char *known_in, uint64_t *image, int32_t verify,
+                            int64_t *ops_out) {
     if (!grp_ok(kind, mod) || P <= 0 || Q <= 0 || m < 0) return ORC_EINVAL;
     int64_t npix = (int64_t)P * Q;
     int64_t total = 0;
@@ -199,6 +200,23 @@ static int32_t inverse_impl(int32_t kind, uint64_t mod, const uint64_t *proj,
         for (int32_t i = 0; i < m; i++)
             for (int64_t j = 0; j < start[i + 1] - start[i]; j++)
                 if (j < keep_lo[i] || j >= keep_lo[i] + keep_n[i]) count[start[i] + j] = -(P + Q) - 1;
+    }
+    /* Pixels known in advance (known_in[x] set, value in image[x]) are
+     * removed from every projection first, as step 4 removes a pixel it has
+     * just found. */
+    if (known_in) {
+        for (int32_t l = 0; l < Q; l++)
+            for (int32_t k = 0; k < P; k++) {
+                int64_t x = (int64_t)l * P + k;
+                if (!known_in[x]) continue;
+                known[x] = 1;
+                for (int32_t i = 0; i < m; i++) {
+                    int64_t b = -(int64_t)k * q[i] + (int64_t)l * p[i];
+                    int64_t t = start[i] + b - orc_bin_min(p[i], q[i], P, Q);
+                    resid[t] = grp_sub(kind, mod, resid[t], image[x]);
+                    count[t] -= 1;
+                }
+            }
     }
     /* A bin can be queued at most twice: once at start, once when its count
      * falls to one; the queue is sized for that. */
@@ -260,7 +278,7 @@ static int32_t inverse_impl(int32_t kind, uint64_t mod, const uint64_t *proj,
 int32_t orc_inverse(int32_t kind, uint64_t mod, const uint64_t *proj, const int64_t *proj_off,
                     const int32_t *p, const int32_t *q, int32_t m, int32_t P, int32_t Q,
                     uint64_t *image, int32_t verify, int64_t *ops_out) {
-    return inverse_impl(kind, mod, proj, proj_off, p, q, m, P, Q, NULL, NULL, image, verify,
+    return inverse_impl(kind, mod, proj, proj_off, p, q, m, P, Q, NULL, NULL, NULL, image, verify,
                         ops_out);
 }
 
@@ -275,8 +293,23 @@ int32_t orc_inverse_kept(int32_t kind, uint64_t mod, const uint64_t *proj, const
                          const int64_t *keep_lo, const int64_t *keep_n, uint64_t *image,
                          int32_t verify, int64_t *ops_out) {
     if (!keep_lo || !keep_n) return ORC_EINVAL;
-    return inverse_impl(kind, mod, proj, proj_off, p, q, m, P, Q, keep_lo, keep_n, image, verify,
-                        ops_out);
+    return inverse_impl(kind, mod, proj, proj_off, p, q, m, P, Q, keep_lo, keep_n, NULL, image,
+                        verify, ops_out);
+}
+
+/*
+ * The same peeling when some pixels are known in advance: known_in[x] set
+ * means image[x] already holds pixel x.  The systematic code (Section 2.3
+ * mentions a systematic version; data lines are stored as they are) decodes
+ * lost lines this way from the surviving lines and parity projections.
+ */
+int32_t orc_inverse_known(int32_t kind, uint64_t mod, const uint64_t *proj,
+                          const int64_t *proj_off, const int32_t *p, const int32_t *q, int32_t m,
+                          int32_t P, int32_t Q, const unsigned char *known_in, uint64_t *image,
+                          int32_t verify, int64_t *ops_out) {
+    if (!known_in) return ORC_EINVAL;
+    return inverse_impl(kind, mod, proj, proj_off, p, q, m, P, Q, NULL, NULL, known_in, image,
+                        verify, ops_out);
 }
 
 /* ---- erasure-code convenience: many independent blocks --------------- */
