@@ -173,6 +173,43 @@ int mojette_decode_batch_trimmed(const uint64_t *projs, const uint16_t *erased, 
                                  uint64_t *images, int32_t *status, void *stream);
 
 /*
+ * Systematic code (Section 2.3 mentions a systematic version of the code as
+ * under development and gives no construction; this is the one used here).
+ * A block's Q data lines are stored as they are (the image, Q x P words),
+ * and m parity projections along (p, 1), p = pdirs[0..m-1], beside them
+ * (the layout of mojette_encode_batch with n = m).  Packet i < Q is data
+ * line i, packet Q + j parity projection j; Q + m <= 16, 1 <= m <= 8.
+ *
+ * mojette_encode_batch_sys: computes the parity pool from the images (the
+ *   data lines need no encoding).  Returns as mojette_encode_batch.
+ * mojette_decode_batch_sys: rebuilds, in place in `images`, every lost line
+ *   of every block; surviving lines are read and never written, and a block
+ *   that lost no line is not touched (its read is the lines themselves).
+ *   Lost lines are rebuilt from the surviving parity projections: the
+ *   surviving lines' pixels are removed from the bins (a residual pass into
+ *   `workspace`), then the lost lines are peeled in the order of Section 2.2
+ *   (the r-th lost line from the r-th surviving projection in ascending p).
+ *     images     device, nblocks x Q x P words, in/out.
+ *     parity     device, the parity pool, read only.
+ *     erased     device, nblocks uint16 masks (bit i = packet i lost); NULL
+ *                means nothing lost (no-op).
+ *     workspace  device, mojette_sys_workspace() words, owned by the caller;
+ *                no contents are kept between calls.
+ *     status     as for mojette_decode_batch: a block that lost more lines
+ *                than it has surviving parity projections is left as it is
+ *                and MOJETTE_ENOTRECON is stored.
+ * mojette_sys_workspace: words of workspace for nblocks blocks, -1 on bad
+ *   arguments.
+ */
+int mojette_encode_batch_sys(const uint64_t *images, int64_t nblocks, int32_t P, int32_t Q,
+                             const int32_t *pdirs, int32_t m, uint64_t *parity, void *stream);
+int64_t mojette_sys_workspace(const int32_t *pdirs, int32_t m, int32_t P, int32_t Q,
+                              int64_t nblocks);
+int mojette_decode_batch_sys(uint64_t *images, const uint64_t *parity, const uint16_t *erased,
+                             int64_t nblocks, int32_t P, int32_t Q, const int32_t *pdirs,
+                             int32_t m, uint64_t *workspace, int32_t *status, void *stream);
+
+/*
  * mojette_decode_batch with the decode schedule's blocks per wavefront set by
  * the caller (an autotuner): blocks_per_wave >= 1 asks for that many (capped
  * by what fits in LDS), 0 keeps the library's choice.  Fewer blocks per

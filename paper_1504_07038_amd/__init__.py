@@ -130,6 +130,10 @@ def lib() -> ctypes.CDLL:
         "mojette_decode_batch": ([vp, vp, i64, i32, i32, vp, i32, vp, vp, vp], ctypes.c_int),
         "mojette_encode_batch_wide": ([vp, i64, i32, i32, vp, i32, vp, vp], ctypes.c_int),
         "mojette_trimmed_layout": ([vp, i32, i32, i32, vp, vp], i64),
+        "mojette_encode_batch_sys": ([vp, i64, i32, i32, vp, i32, vp, vp], ctypes.c_int),
+        "mojette_sys_workspace": ([vp, i32, i32, i32, i64], i64),
+        "mojette_decode_batch_sys": ([vp, vp, vp, i64, i32, i32, vp, i32, vp, vp, vp],
+                                     ctypes.c_int),
         "mojette_encode_batch_trimmed": ([vp, i64, i32, i32, vp, i32, vp, vp], ctypes.c_int),
         "mojette_decode_batch_trimmed": ([vp, vp, i64, i32, i32, vp, i32, vp, vp, vp],
                                          ctypes.c_int),
@@ -187,6 +191,7 @@ def exported_symbols() -> list[str]:
         "mojette_decode", "mojette_encode_batch", "mojette_decode_batch",
         "mojette_encode_batch_wide", "mojette_decode_batch_wide",
         "mojette_trimmed_layout", "mojette_encode_batch_trimmed", "mojette_decode_batch_trimmed",
+        "mojette_encode_batch_sys", "mojette_sys_workspace", "mojette_decode_batch_sys",
         "mojette_decode_batch_tuned", "mojette_decode_max_blocks_per_wave",
         "mojette_decode_default_blocks_per_wave",
         "mojette_classes_layout", "mojette_encode_classes", "mojette_decode_classes",
@@ -358,6 +363,32 @@ def mojette_decode_batch_trimmed(projs, erased, nblocks: int, P: int, Q: int, di
                                             arr, n, _word_tensor(images, "images"), st,
                                             _stream(stream))
     return _check(rc, "mojette_decode_batch_trimmed", check)
+
+
+def mojette_encode_batch_sys(images, nblocks: int, P: int, Q: int, pdirs, parity, stream=None,
+                             check: bool = True) -> int:
+    """Systematic code: the parity projections of each block's data lines."""
+    arr, m = _i32_array(pdirs)
+    rc = lib().mojette_encode_batch_sys(_word_tensor(images, "images"), nblocks, P, Q, arr, m,
+                                        _word_tensor(parity, "parity"), _stream(stream))
+    return _check(rc, "mojette_encode_batch_sys", check)
+
+
+def mojette_sys_workspace(pdirs, P: int, Q: int, nblocks: int) -> int:
+    arr, m = _i32_array(pdirs)
+    return int(lib().mojette_sys_workspace(arr, m, P, Q, nblocks))
+
+
+def mojette_decode_batch_sys(images, parity, erased, nblocks: int, P: int, Q: int, pdirs,
+                             workspace, status=None, stream=None, check: bool = True) -> int:
+    """Systematic code: rebuild every lost data line in place in ``images``."""
+    arr, m = _i32_array(pdirs)
+    er, st = _decode_masks(erased, status)
+    rc = lib().mojette_decode_batch_sys(_word_tensor(images, "images"),
+                                        _word_tensor(parity, "parity"), er, nblocks, P, Q, arr,
+                                        m, _word_tensor(workspace, "workspace"), st,
+                                        _stream(stream))
+    return _check(rc, "mojette_decode_batch_sys", check)
 
 
 def mojette_decode_batch_tuned(projs, erased, nblocks: int, P: int, Q: int, dirs, images,

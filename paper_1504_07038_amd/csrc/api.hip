@@ -26,6 +26,7 @@ constexpr int kMaxP = 1 << 24;                 // keeps every bin index inside i
 constexpr int kMaxAbsP = 1 << 16;
 constexpr int kEncodeGridCap = 256 * 64;       // workgroups; larger batches loop inside the kernel
 constexpr int kDecodeGridCap = 256 * 128;
+constexpr int kMaxSysParity = 8;               // parity projections of the systematic code
 
 bool geometry_ok(const int32_t *dirs, int32_t n, int32_t P, int32_t Q) {
     if (!dirs || n < 1 || n > kMaxDirs || P < 1 || P > kMaxP || Q < 1 || Q > kMaxRows) return false;
@@ -182,6 +183,45 @@ int ring_length(const std::vector<int> &sorted_p, int Q) {
     }
     std::lock_guard<std::mutex> g(mu);
     cache[key] = R;
+    return R;
+}
+
+// Ring length of the systematic decode: as ring_length, over every set of
+// lost lines (1 to m of the Q) and every choice of as many parity
+// directions, with the sweep rows at the lost lines' image rows (A of the
+// next lost line: A + 2 (its row - this row) p + 1).  -1 if a pixel would
+// be read before it is written (the ordering argument rules it out).
+int ring_length_sys(const std::vector<int> &sorted_p, int Q) {
+    const int m = (int)sorted_p.size();
+    int Dmax = 0;
+    bool ok = true;
+    for (uint32_t lines = 1; lines < (1u << Q); ++lines) {
+        const int e = __builtin_popcount(lines);
+        if (e > m) continue;
+        std::vector<int> rows;
+        for (int l = 0; l < Q; ++l)
+            if ((lines >> l) & 1u) rows.push_back(l);
+        for (uint32_t dirs = 1; dirs < (1u << m); ++dirs) {
+            if (__builtin_popcount(dirs) != e) continue;
+            std::vector<int> p, A(e);
+            for (int i = 0; i < m; ++i)
+                if ((dirs >> i) & 1u) p.push_back(sorted_p[i]);
+            A[0] = 0;
+            for (int r = 0; r + 1 < e; ++r) A[r + 1] = A[r] + 2 * (rows[r + 1] - rows[r]) * p[r] + 1;
+            for (int r = 0; r < e; ++r)
+                for (int l = 0; l < e; ++l) {
+                    if (l == r) continue;
+                    const int diff = A[l] - A[r];
+                    const int ceil_half = (diff >= 0) ? (diff + 1) / 2 : -((-diff) / 2);
+                    const int D = ceil_half - 1 - (rows[l] - rows[r]) * p[r];
+                    if (D < 0) ok = false;
+                    Dmax = std::max(Dmax, D);
+                }
+        }
+    }
+    if (!ok) return -1;
+    int R = 2 * mj::kDecodeTile;
+    while (R < mj::kDecodeTile + Dmax + 1) R <<= 1;
     return R;
 }
 
@@ -471,6 +511,102 @@ int mojette_decode_batch_trimmed(const uint64_t *projs, const uint16_t *erased, 
     if (nblocks < 0 || !kept_layout(dirs, n, P, Q, f, c)) return MOJETTE_EINVAL;
     return decode_batch_impl(projs, erased, nblocks, P, Q, dirs, n, images, status, stream, 0,
                              f, c);
+}
+
+// ---- systematic code -----------------------------------------------------
+
+static bool sys_geometry_ok(const int32_t *pdirs, int32_t m, int32_t P, int32_t Q) {
+    return geometry_ok(pdirs, m, P, Q) && m <= kMaxSysParity && Q + m <= 16;
+}
+
+int64_t mojette_sys_workspace(const int32_t *pdirs, int32_t m, int32_t P, int32_t Q,
+                              int64_t nblocks) {
+    if (nblocks < 0 || !sys_geometry_ok(pdirs, m, P, Q)) return -1;
+    return nblocks * mojette_block_words(pdirs, m, P, Q);
+}
+
+int mojette_encode_batch_sys(const uint64_t *images, int64_t nblocks, int32_t P, int32_t Q,
+                             const int32_t *pdirs, int32_t m, uint64_t *parity, void *stream) {
+    if (!sys_geometry_ok(pdirs, m, P, Q)) return MOJETTE_EINVAL;
+    return encode_batch_impl(images, nblocks, P, Q, pdirs, m, parity, stream, 0);
+}
+
+int mojette_decode_batch_sys(uint64_t *images, const uint64_t *parity, const uint16_t *erased,
+                             int64_t nblocks, int32_t P, int32_t Q, const int32_t *pdirs,
+                             int32_t m, uint64_t *workspace, int32_t *status, void *stream) {
+    if (nblocks < 0 || !sys_geometry_ok(pdirs, m, P, Q)) return MOJETTE_EINVAL;
+    if (nblocks == 0 || !erased) return MOJETTE_OK;   // nothing lost: the lines are the data
+    if (!images || !parity || !workspace) return MOJETTE_EINVAL;
+
+    // the sweep: rows = lost lines (at most m), projections = parity
+    mj::DecodeArgs a{};
+    std::vector<int> order(m), sp(m);
+    for (int i = 0; i < m; ++i) order[i] = i;
+    std::sort(order.begin(), order.end(), [&](int x, int y) { return pdirs[x] < pdirs[y]; });
+    for (int s = 0; s < m; ++s) {
+        a.p_sorted[s] = pdirs[order[s]];
+        a.id_sorted[s] = order[s];
+        sp[s] = pdirs[order[s]];
+    }
+    static std::mutex mu;
+    static std::map<RingKey, int> cache;
+    int R;
+    {
+        std::lock_guard<std::mutex> g(mu);
+        RingKey key{sp, Q};
+        auto it = cache.find(key);
+        R = it != cache.end() ? it->second : (cache[key] = ring_length_sys(sp, Q));
+    }
+    if (R < 0) return MOJETTE_EINVAL;
+    a.R = R;
+    a.ring_stride = R + 1;
+    a.nb = mj::decode_max_blocks_per_wave(m);
+    if (mj::decode_lds_bytes(m, a.nb, a.ring_stride) > kDecodeLdsShare) {
+        a.nb = std::max(1, a.nb / 2);
+        while (a.nb > 1 && mj::decode_lds_bytes(m, a.nb, a.ring_stride) > kDecodeLdsLong) --a.nb;
+    }
+    if (mj::decode_lds_bytes(m, a.nb, a.ring_stride) > kLdsLimit) return MOJETTE_ENOTSUP;
+    int64_t off = 0;
+    for (int i = 0; i < m; ++i) {
+        a.off[i] = (int32_t)off;
+        off += mojette_proj_size(pdirs[i], P, Q);
+    }
+    if ((int64_t)a.nb * off * 8 >= ((int64_t)1 << 31) ||
+        (int64_t)a.nb * P * Q * 8 >= ((int64_t)1 << 31))
+        return MOJETTE_ENOTSUP;
+    a.P = P;
+    a.n = m;
+    a.sys_rows = Q;
+    a.pool = workspace;
+    a.proj_stride = off;
+    a.images = images;
+    a.img_stride = (int64_t)P * Q;
+    a.masks = erased;
+    a.mask_uniform = 0;
+    a.status = status;
+    a.nblocks = nblocks;
+
+    // the residual pass: parity bins with the surviving lines removed
+    mj::ResidArgs r{};
+    if (!encode_tiling(pdirs, m, P, Q, r)) return MOJETTE_ENOTSUP;
+    r.images = images;
+    for (int i = 0; i < m; ++i) {
+        r.out[i] = workspace + a.off[i];
+        r.par[i] = parity + a.off[i];
+    }
+    r.proj_stride = off;
+    r.nblocks = nblocks;
+    r.masks = erased;
+    for (int s = 0; s < m; ++s) r.id_sorted[s] = a.id_sorted[s];
+
+    const int64_t items = nblocks * r.ntiles;
+    const int egrid = (int)std::min<int64_t>((items + r.waves - 1) / r.waves, kEncodeGridCap);
+    const int64_t batches = (nblocks + a.nb - 1) / a.nb;
+    const int dgrid = (int)std::min<int64_t>(batches, kDecodeGridCap);
+    clear_stale_error();
+    const int rc = status_of(mj::launch_resid(r, egrid, (hipStream_t)stream));
+    if (rc != MOJETTE_OK) return rc;
+    return status_of(mj::launch_decode_sys(m, a, dgrid, (hipStream_t)stream));
 }
 
 // ---- chunked decode of long rows -------------------------------------------

@@ -143,7 +143,21 @@ struct SegParam {
 //
 // STPOL is the cache policy of the image stores in pool mode (kStreamPolicy:
 // non-temporal; 0: default).
-template <int Q, int TW, bool POOL, int CHUNK, int NBT, class Args, int STPOL = kStreamPolicy>
+//
+// SYS: the systematic code (DecodeArgs only, whole blocks, pool mode).  A
+// block is a.sys_rows data lines stored as they are plus a.n parity
+// projections (mask bits 0..sys_rows-1 lines, then projections).  The lost
+// lines, in ascending order, are the sweep rows (Q = the most that can be
+// lost); the pool holds the parity bins with the surviving lines' pixels
+// already removed (residual bins), so the sweep involves the lost lines
+// only.  The r-th lost line m_r takes the r-th surviving projection in
+// ascending p, and A_{r+1} = A_r + 2 (m_{r+1} - m_r) p_r + 1, which keeps
+// every dependency strictly earlier: for l > r the gap is
+// sum 2 (m_{i+1} - m_i)(p_i - p_r) + (l - r) > 0, and for l < r it is at
+// least sum 2 (m_{i+1} - m_i)(p_r - p_i) - (r - l) >= (r - l)^2 > 0.  Rows
+// of consecutive sweep index still alternate in parity.
+template <int Q, int TW, bool POOL, int CHUNK, int NBT, class Args, int STPOL = kStreamPolicy,
+          bool SYS = false>
 __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch) {
     extern __shared__ uint64_t lds[];
     constexpr int LPB = (Q + 1) / 2;        // lanes per block
@@ -178,7 +192,9 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch)
     uint64_t *slot_base = lds + (size_t)(lane_used ? slot : 0) * SS;
     const int r0 = 2 * j, r1 = 2 * j + 1;   // this lane's rows
     const int q = lane % LPS;
-    const int QP = Q * P;
+    int QI = Q;                            // image rows (projection geometry)
+    if constexpr (SYS) QI = a.sys_rows;
+    const int QP = QI * P;
 
     {
         const bool blk_ok = lane_used && blk < a.nblocks;
@@ -189,11 +205,40 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch)
         int p0 = 0, p1 = 0, id0 = 0, id1 = 0, A0 = 0, A1 = 0;
         int A_max = INT_MIN, A_min = INT_MAX, cnt = 0, psum = 0;
         uint32_t used = 0;
+        // Systematic code: sweep row r is image row arow[r], the r-th lost
+        // line; `nrows` sweep rows are in use.  Otherwise arow[r] = r.
+        int arow[Q];
+        int nrows = Q;
+        uint32_t pbase = 0;                 // mask bit of projection 0
+        if constexpr (SYS) {
+            uint32_t lost = mask & ((1u << a.sys_rows) - 1u);
+            nrows = __builtin_popcount(lost);
+#pragma unroll
+            for (int r = 0; r < Q; ++r) {
+                arow[r] = lost ? __builtin_ctz(lost) : 0;
+                lost &= lost - 1u;
+            }
+            pbase = a.sys_rows;
+        } else {
+#pragma unroll
+            for (int r = 0; r < Q; ++r) arow[r] = r;
+        }
+        int A_next = 0;                     // SYS: A of sweep row cnt
         for (int s = 0; s < a.n; ++s) {
             const int id = a.id_sorted[s];
             const int p = a.p_sorted[s];
-            if (!((mask >> id) & 1u) && cnt < Q) {
-                const int A = 2 * psum + cnt;
+            if (!((mask >> (pbase + id)) & 1u) && cnt < nrows) {
+                int A = 2 * psum + cnt;
+                if constexpr (SYS) {
+                    A = A_next;
+                    int m_here = 0, m_next = 0;   // image rows of sweep rows cnt, cnt + 1
+#pragma unroll
+                    for (int r = 0; r < Q; ++r) {
+                        m_here = r == cnt ? arow[r] : m_here;
+                        m_next = r == cnt + 1 ? arow[r] : m_next;
+                    }
+                    A_next = A + 2 * (m_next - m_here) * p + 1;
+                }
                 if (cnt == r0) { p0 = p; id0 = id; A0 = A; }
                 if (cnt == r1) { p1 = p; id1 = id; A1 = A; }
                 A_max = max(A_max, A);
@@ -204,7 +249,10 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch)
             }
         }
         bool valid = blk_ok;
-        if (cnt < Q) {
+        if constexpr (SYS) {
+            if (nrows == 0) valid = false;   // every line survived: nothing to rebuild
+        }
+        if (valid && cnt < nrows) {
             // reported once per block: by its whole sweep or its first chunk
             if (blk_ok && j == 0 && a.status && (CHUNK == kWhole || (CHUNK == kChunkA && chunk == 0)))
                 a.status[0] = MOJETTE_ENOTRECON;
@@ -246,12 +294,13 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch)
         RowState<Q> X, Y;
         const bool r0_is_x = ((r0 & 1) == par);
         int jb0 = 0, jb1 = 0;   // bin index of column 0 for rows r0 and r1
+        int arow0 = r0, arow1 = r1;   // their image rows
         {
             const int rx = r0_is_x ? r0 : r1, ry = r0_is_x ? r1 : r0;
             const int px = r0_is_x ? p0 : p1, py = r0_is_x ? p1 : p0;
             const int Ax = r0_is_x ? A0 : A1, Ay = r0_is_x ? A1 : A0;
-            X.on = valid && rx < Q;
-            Y.on = valid && ry < Q;
+            X.on = valid && rx < nrows;
+            Y.on = valid && ry < nrows;
             X.ring = slot_base + (rx < Q ? rx : 0) * RS;
             Y.ring = slot_base + (ry < Q ? ry : 0) * RS;
 #pragma unroll
@@ -259,13 +308,38 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch)
                 const int lx = m + (m >= rx ? 1 : 0), ly = m + (m >= ry ? 1 : 0);
                 X.dep[m] = slot_base + (lx < Q ? lx : 0) * RS;
                 Y.dep[m] = slot_base + (ly < Q ? ly : 0) * RS;
-                X.delta[m] = (lx - rx) * px;
-                Y.delta[m] = (ly - ry) * py;
+                if constexpr (SYS) {
+                    // image rows of the sweep rows involved (rows past
+                    // nrows are never written: their rings read zero)
+                    int mx = 0, my = 0, mlx = 0, mly = 0;
+#pragma unroll
+                    for (int r = 0; r < Q; ++r) {
+                        mx = r == rx ? arow[r] : mx;
+                        my = r == ry ? arow[r] : my;
+                        mlx = r == lx ? arow[r] : mlx;
+                        mly = r == ly ? arow[r] : mly;
+                    }
+                    X.delta[m] = (mlx - mx) * px;
+                    Y.delta[m] = (mly - my) * py;
+                } else {
+                    X.delta[m] = (lx - rx) * px;
+                    Y.delta[m] = (ly - ry) * py;
+                }
             }
             X.d = X.on ? -((A_max - Ax) >> 1) : 0;       // (Ax - A_max)/2, exact
             Y.d = Y.on ? -((A_max - Ay - 1) >> 1) : 0;   // (Ay - A_max + 1)/2, exact
-            jb0 = r0 * p0 - (bin_offset(p0, P, Q) + a.kept_first(id0));
-            jb1 = r1 * p1 - (bin_offset(p1, P, Q) + a.kept_first(id1));
+            if constexpr (SYS) {
+                int m0 = 0, m1 = 0;
+#pragma unroll
+                for (int r = 0; r < Q; ++r) {
+                    m0 = r == r0 ? arow[r] : m0;
+                    m1 = r == r1 ? arow[r] : m1;
+                }
+                arow0 = m0;
+                arow1 = m1;
+            }
+            jb0 = arow0 * p0 - (bin_offset(p0, P, QI) + a.kept_first(id0));
+            jb1 = arow1 * p1 - (bin_offset(p1, P, QI) + a.kept_first(id1));
         }
 
         // Per-iteration row windows, from the lanes that own their rows.
@@ -277,8 +351,8 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch)
             // pool mode: word offset of column 0's bin within the wave's slice
             const int g0 = POOL ? rel * (int)a.proj_stride + a.off[id0] + jb0 : jb0;
             const int g1 = POOL ? rel * (int)a.proj_stride + a.off[id1] + jb1 : jb1;
-            const int own0 = valid ? dr0 : INT_MIN;
-            const int own1 = valid ? dr1 : INT_MIN;
+            const int own0 = valid && r0 < nrows ? dr0 : INT_MIN;
+            const int own1 = valid && r1 < nrows ? dr1 : INT_MIN;
             // pointer mode: the projections of this lane's two rows
             uint64_t pb0 = 0, pb1 = 0;
             if constexpr (!POOL) {
@@ -296,6 +370,11 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch)
                 const int src = owner < kWave ? owner : 0;
                 const int od0 = __shfl(own0, src), od1 = __shfl(own1, src);
                 const int og0 = __shfl(g0, src), og1 = __shfl(g1, src);
+                int orow = srow;                 // image row of the segment
+                if constexpr (SYS) {
+                    const int oa0 = __shfl(arow0, src), oa1 = __shfl(arow1, src);
+                    orow = (srow & 1) ? oa1 : oa0;
+                }
                 int orel = sslot, oshift = 0;   // whole blocks: slot = block
                 if constexpr (CHUNK != kWhole) {
                     orel = __shfl(rel, src);
@@ -325,7 +404,7 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch)
                 s.col0 = dd + TW - 1 - 2 * q + oshift;
                 const int L = (-dd + TW - 1) / TW;
                 s.scol0 = -TW * L + 2 * q + oshift;
-                s.img = orel * QP + srow * P;
+                s.img = orel * QP + orow * P;
             }
         }
 
