@@ -137,18 +137,33 @@ struct RingKey {
     bool operator<(const RingKey &o) const { return Q != o.Q ? Q < o.Q : p < o.p; }
 };
 
-int ring_length(const std::vector<int> &sorted_p, int Q) {
+// Ring for a depth D: a staged bin must not land on a pixel still needed
+// (TW + D + 1) or on one not yet stored (2 TW).
+static int ring_for_depth(int D) {
+    int R = 2 * mj::kDecodeTile;
+    while (R < mj::kDecodeTile + D + 1) R <<= 1;
+    return R;
+}
+
+// Also returns in *common the shortest ring that serves at least 90% of
+// the survivor sets (the whole-block pool decode sweeps the others in a
+// second launch with the full ring).
+int ring_length(const std::vector<int> &sorted_p, int Q, int *common = nullptr) {
     static std::mutex mu;
-    static std::map<RingKey, int> cache;
+    static std::map<RingKey, std::pair<int, int>> cache;
     RingKey key{sorted_p, Q};
     {
         std::lock_guard<std::mutex> g(mu);
         auto it = cache.find(key);
-        if (it != cache.end()) return it->second;
+        if (it != cache.end()) {
+            if (common) *common = it->second.second;
+            return it->second.first;
+        }
     }
     const int n = (int)sorted_p.size();
     int Dmax = 0;
     bool ok = true;
+    std::vector<int> depths;
     std::vector<int> pick(Q), A(Q);
     for (int i = 0; i < Q; ++i) pick[i] = i;
     while (true) {
@@ -157,6 +172,7 @@ int ring_length(const std::vector<int> &sorted_p, int Q) {
             A[r] = 2 * psum + r;
             psum += sorted_p[pick[r]];
         }
+        int Dset = 0;
         for (int r = 0; r < Q; ++r) {
             const int pr = sorted_p[pick[r]];
             for (int l = 0; l < Q; ++l) {
@@ -165,24 +181,26 @@ int ring_length(const std::vector<int> &sorted_p, int Q) {
                 const int ceil_half = (diff >= 0) ? (diff + 1) / 2 : -((-diff) / 2);
                 const int D = ceil_half - 1 - (l - r) * pr;
                 if (D < 0) ok = false;
-                Dmax = std::max(Dmax, D);
+                Dset = std::max(Dset, D);
             }
         }
+        depths.push_back(Dset);
+        Dmax = std::max(Dmax, Dset);
         int i = Q - 1;
         while (i >= 0 && pick[i] == n - Q + i) --i;
         if (i < 0) break;
         ++pick[i];
         for (int j = i + 1; j < Q; ++j) pick[j] = pick[j - 1] + 1;
     }
-    // A staged bin must not land on a pixel still needed (TW + D + 1) or on
-    // one not yet stored (2 TW).
-    int R = -1;
+    int R = -1, Rc = -1;
     if (ok) {
-        R = 2 * mj::kDecodeTile;
-        while (R < mj::kDecodeTile + Dmax + 1) R <<= 1;
+        R = ring_for_depth(Dmax);
+        std::sort(depths.begin(), depths.end());
+        Rc = ring_for_depth(depths[(depths.size() * 9 + 9) / 10 - 1]);   // 90th percentile
     }
+    if (common) *common = Rc;
     std::lock_guard<std::mutex> g(mu);
-    cache[key] = R;
+    cache[key] = {R, Rc};
     return R;
 }
 
@@ -225,6 +243,22 @@ int ring_length_sys(const std::vector<int> &sorted_p, int Q) {
     return R;
 }
 
+// Blocks per wavefront: all the lanes allow when their rings fit a 34 KB
+// share of LDS (short rings: the (6,4) code's 32 blocks); otherwise at most
+// half of them (the body compiled for half the slots needs far fewer
+// registers) and no more than 26 KB, so that several wavefronts share a
+// compute unit.  Measured on 2^19 blocks: (12,8) 3 blocks per wavefront
+// 1.25x faster than 7; (6,3) 10 blocks 1.3x faster than 20; (12,4) 2 blocks
+// 1.17x faster than 5.
+int default_blocks(int Q, int ring_stride) {
+    int nb = mj::decode_max_blocks_per_wave(Q);
+    if (mj::decode_lds_bytes(Q, nb, ring_stride) > kDecodeLdsShare) {
+        nb = std::max(1, nb / 2);
+        while (nb > 1 && mj::decode_lds_bytes(Q, nb, ring_stride) > kDecodeLdsLong) --nb;
+    }
+    return nb;
+}
+
 // Fills the geometry part of decode arguments (DecodeArgs or DecodeClass).
 // Returns a status.
 template <class A>
@@ -243,22 +277,55 @@ int decode_setup(const int32_t *dirs, int32_t n, int32_t P, int32_t Q, A &a) {
     if (R < 0) return MOJETTE_EINVAL;
     a.R = R;
     a.ring_stride = R + 1;  // odd stride spreads the rows over the LDS banks
-    // Blocks per wavefront: all the lanes allow when their rings fit a 34 KB
-    // share of LDS (short rings: the (6,4) code's 32 blocks); otherwise at
-    // most half of them (the body compiled for half the slots needs far
-    // fewer registers) and no more than 26 KB, so that several wavefronts
-    // share a compute unit.  Measured on 2^19 blocks: (12,8) 3 blocks per
-    // wavefront 1.25x faster than 7; (6,3) 10 blocks 1.3x faster than 20;
-    // (12,4) 2 blocks 1.17x faster than 5.
-    a.nb = mj::decode_max_blocks_per_wave(Q);
-    if (mj::decode_lds_bytes(Q, a.nb, a.ring_stride) > kDecodeLdsShare) {
-        a.nb = std::max(1, a.nb / 2);
-        while (a.nb > 1 && mj::decode_lds_bytes(Q, a.nb, a.ring_stride) > kDecodeLdsLong) --a.nb;
-    }
+    a.nb = default_blocks(Q, a.ring_stride);
     if (mj::decode_lds_bytes(Q, a.nb, a.ring_stride) > kLdsLimit) return MOJETTE_ENOTSUP;
     a.P = P;
     a.n = n;
     return MOJETTE_OK;
+}
+
+// Launches the whole-block pool decode described by `a` (from decode_setup,
+// pool fields filled).  nb_req > 0: blocks per wavefront asked by the caller
+// (capped by LDS).  When a shorter ring serves at least 90% of the survivor
+// sets, two launches run: that ring over the blocks whose set fits it (more
+// blocks per wavefront), then the full ring over the rest.
+int launch_pool_whole(mj::DecodeArgs a, int Q, int nb_req, hipStream_t stream) {
+    auto pick_nb = [&](mj::DecodeArgs &b) {
+        if (nb_req > 0) {
+            b.nb = std::min(mj::decode_max_blocks_per_wave(Q), nb_req);
+            while (b.nb > 1 && mj::decode_lds_bytes(Q, b.nb, b.ring_stride) > kLdsLimit) --b.nb;
+        }
+    };
+    auto go = [&](const mj::DecodeArgs &b) {
+        // a wave's slice of the pool and of the images: 32-bit byte offsets
+        if ((int64_t)b.nb * b.proj_stride * 8 >= ((int64_t)1 << 31) ||
+            (int64_t)b.nb * b.img_stride * 8 >= ((int64_t)1 << 31))
+            return MOJETTE_ENOTSUP;
+        const int64_t batches = (b.nblocks + b.nb - 1) / b.nb;
+        const int grid = (int)std::min<int64_t>(batches, kDecodeGridCap);
+        clear_stale_error();
+        return status_of(mj::launch_decode(Q, mj::kLaunchPool, b, grid, stream));
+    };
+    std::vector<int> sp(a.p_sorted, a.p_sorted + a.n);
+    int common = -1;
+    ring_length(sp, Q, &common);
+    if (common <= 0 || common >= a.R) {
+        a.ring_mode = 0;
+        pick_nb(a);
+        return go(a);
+    }
+    // the short ring serves sets whose depth is at most common - TW - 1
+    a.ring_depth = common - mj::kDecodeTile - 1;
+    mj::DecodeArgs m1 = a;
+    m1.R = common;
+    m1.ring_stride = common + 1;
+    m1.nb = default_blocks(Q, m1.ring_stride);
+    m1.ring_mode = 1;
+    pick_nb(m1);
+    const int rc = go(m1);
+    if (rc != MOJETTE_OK) return rc;
+    a.ring_mode = 2;
+    return go(a);
 }
 
 // Checks a class table and returns, per class, block words and pool offsets.
@@ -469,11 +536,6 @@ static int decode_batch_impl(const uint64_t *projs, const uint16_t *erased, int6
             off += mojette_proj_size(dirs[i], P, Q);
         }
     }
-    // A wave's slice of the pool and of the images must be addressable with
-    // 32-bit byte offsets.
-    if ((int64_t)a.nb * off * 8 >= ((int64_t)1 << 31) ||
-        (int64_t)a.nb * P * Q * 8 >= ((int64_t)1 << 31))
-        return MOJETTE_ENOTSUP;
     a.pool = projs;
     a.proj_stride = off;
     a.images = images;
@@ -483,10 +545,7 @@ static int decode_batch_impl(const uint64_t *projs, const uint16_t *erased, int6
     a.status = status;
     a.nblocks = nblocks;
     a.bin_swap = bin_swap;
-    const int64_t batches = (nblocks + a.nb - 1) / a.nb;
-    const int grid = (int)std::min<int64_t>(batches, kDecodeGridCap);
-    clear_stale_error();
-    return status_of(mj::launch_decode(Q, mj::kLaunchPool, a, grid, (hipStream_t)stream));
+    return launch_pool_whole(a, Q, 0, (hipStream_t)stream);
 }
 
 int mojette_decode_batch(const uint64_t *projs, const uint16_t *erased, int64_t nblocks,
@@ -897,18 +956,11 @@ int mojette_decode_batch_tuned(const uint64_t *projs, const uint16_t *erased, in
     mj::DecodeArgs a{};
     const int rc = decode_setup(dirs, n, P, Q, a);
     if (rc != MOJETTE_OK) return rc;
-    if (blocks_per_wave > 0) {
-        a.nb = std::min(mj::decode_max_blocks_per_wave(Q), (int)blocks_per_wave);
-        while (a.nb > 1 && mj::decode_lds_bytes(Q, a.nb, a.ring_stride) > kLdsLimit) --a.nb;
-    }
     int64_t off = 0;
     for (int i = 0; i < n; ++i) {
         a.off[i] = (int32_t)off;
         off += mojette_proj_size(dirs[i], P, Q);
     }
-    if ((int64_t)a.nb * off * 8 >= ((int64_t)1 << 31) ||
-        (int64_t)a.nb * P * Q * 8 >= ((int64_t)1 << 31))
-        return MOJETTE_ENOTSUP;
     a.pool = projs;
     a.proj_stride = off;
     a.images = images;
@@ -917,10 +969,15 @@ int mojette_decode_batch_tuned(const uint64_t *projs, const uint16_t *erased, in
     a.mask_uniform = 0;
     a.status = status;
     a.nblocks = nblocks;
-    const int64_t batches = (nblocks + a.nb - 1) / a.nb;
-    const int grid = (int)std::min<int64_t>(batches, kDecodeGridCap);
-    clear_stale_error();
-    return status_of(mj::launch_decode(Q, mj::kLaunchPool, a, grid, (hipStream_t)stream));
+    return launch_pool_whole(a, Q, blocks_per_wave, (hipStream_t)stream);
+}
+
+// Ring stride of the main launch of launch_pool_whole.
+static int main_ring_stride(const mj::DecodeArgs &a, int Q) {
+    std::vector<int> sp(a.p_sorted, a.p_sorted + a.n);
+    int common = -1;
+    ring_length(sp, Q, &common);
+    return (common > 0 && common < a.R) ? common + 1 : a.ring_stride;
 }
 
 int32_t mojette_decode_max_blocks_per_wave(const int32_t *dirs, int32_t n, int32_t P,
@@ -928,8 +985,9 @@ int32_t mojette_decode_max_blocks_per_wave(const int32_t *dirs, int32_t n, int32
     if (!geometry_ok(dirs, n, P, Q)) return -1;
     mj::DecodeArgs a{};
     if (decode_setup(dirs, n, P, Q, a) != MOJETTE_OK) return -1;
+    const int rs = main_ring_stride(a, Q);
     int nb = mj::decode_max_blocks_per_wave(Q);
-    while (nb > 1 && mj::decode_lds_bytes(Q, nb, a.ring_stride) > kLdsLimit) --nb;
+    while (nb > 1 && mj::decode_lds_bytes(Q, nb, rs) > kLdsLimit) --nb;
     return nb;
 }
 
@@ -938,7 +996,7 @@ int32_t mojette_decode_default_blocks_per_wave(const int32_t *dirs, int32_t n, i
     if (!geometry_ok(dirs, n, P, Q)) return -1;
     mj::DecodeArgs a{};
     if (decode_setup(dirs, n, P, Q, a) != MOJETTE_OK) return -1;
-    return a.nb;
+    return default_blocks(Q, main_ring_stride(a, Q));
 }
 
 int mojette_classes_layout(const mojette_class *classes, int32_t nclasses, int64_t *image_words,

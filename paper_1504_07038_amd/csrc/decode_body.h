@@ -50,10 +50,16 @@
 
 #include <algorithm>
 #include <climits>
+#include <type_traits>
 
 #include "mj_internal.h"
 
 namespace mj {
+
+__device__ __forceinline__ int ceil_half(int x) { return x >= 0 ? (x + 1) / 2 : -((-x) / 2); }
+
+template <class T>
+constexpr bool kIsDecodeArgs = std::is_same<T, DecodeArgs>::value;
 
 __device__ __forceinline__ int wave_max(int v) {
 #pragma unroll
@@ -257,6 +263,40 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch)
             if (blk_ok && j == 0 && a.status && (CHUNK == kWhole || (CHUNK == kChunkA && chunk == 0)))
                 a.status[0] = MOJETTE_ENOTRECON;
             valid = false;
+        }
+        // Ring classes (whole-block pool sweeps of DecodeArgs): ring_mode 1
+        // takes only the blocks whose survivor set reads at most
+        // a.ring_depth columns behind the newest pixel of a row (the short
+        // ring of this launch serves them), ring_mode 2 only the others.
+        // The depth of a set is the largest ceil((A_l - A_r)/2) - 1 -
+        // (l - r) p_r.
+        if constexpr (CHUNK == kWhole && !SYS && POOL && kIsDecodeArgs<Args>) {
+            if (a.ring_mode != 0) {
+                int depth = INT_MIN;
+                if (valid) {
+                    int c2 = 0, ps2 = 0;
+                    for (int s = 0; s < a.n; ++s) {
+                        const int id = a.id_sorted[s];
+                        const int p = a.p_sorted[s];
+                        if (!((mask >> id) & 1u) && c2 < Q) {
+                            const int A = 2 * ps2 + c2;
+                            if (c2 != r0 && r0 < Q)
+                                depth = max(depth, ceil_half(A - A0) - 1 - (c2 - r0) * p0);
+                            if (c2 != r1 && r1 < Q)
+                                depth = max(depth, ceil_half(A - A1) - 1 - (c2 - r1) * p1);
+                            ps2 += p;
+                            ++c2;
+                        }
+                    }
+                }
+                // a block's rows are spread over its LPB lanes
+                int bdepth = depth;
+#pragma unroll
+                for (int jj = 0; jj < LPB; ++jj) bdepth = max(bdepth, __shfl(depth, slot * LPB + jj));
+                const bool fits = bdepth <= a.ring_depth;
+                if (a.ring_mode == 1 ? !fits : fits) valid = false;
+                if (!__any(valid)) return;   // nothing for this wavefront in this launch
+            }
         }
         // Chunked sweeps: the state width E of this survivor set.
         int E = 0;

@@ -175,6 +175,9 @@ struct DecodeArgs {
     ChunkInfo chunk;                 // chunked launches only
     int32_t keep_lo[kMaxDirs];       // projection i's first stored bin index (0: Eq. 2's first)
     int32_t sys_rows;                // systematic decode: data lines per block (else unused)
+    int32_t ring_mode;               // whole-block pool sweeps: 0 every block; 1 only blocks
+                                     // whose survivor set's depth is <= ring_depth; 2 the others
+    int32_t ring_depth;
     __device__ const uint64_t *proj_base(int64_t blk, int id) const {
         return pool ? pool + slots[blk] * proj_stride + off[id] : in[id];
     }

@@ -1,0 +1,87 @@
+"""Whole-block decode with two ring classes: blocks whose survivor set reads
+deep (far behind the newest pixel) and shallow blocks go to different
+launches.  Batches made only of deep sets, only of shallow sets, and both
+mixed at random, against the oracle."""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpuutil import masks_to_dev, say, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def mj():
+    import paper_1504_07038_amd as mj
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    mj.lib()
+    return mj
+
+
+def depth(ps_sorted_used):
+    """Deepest read behind a row's newest pixel for the used survivors (the
+    r-th smallest p rebuilds row r): max ceil((A_l - A_r)/2) - 1 - (l-r) p_r."""
+    Q = len(ps_sorted_used)
+    A, s = [], 0
+    for r in range(Q):
+        A.append(2 * s + r)
+        s += ps_sorted_used[r]
+    best = 0
+    for r in range(Q):
+        for l in range(Q):
+            if l != r:
+                d = A[l] - A[r]
+                ch = (d + 1) // 2 if d >= 0 else -((-d) // 2)
+                best = max(best, ch - 1 - (l - r) * ps_sorted_used[r])
+    return best
+
+
+def masks_by_depth(dirs, Q):
+    n = len(dirs)
+    out = []
+    for keep in itertools.combinations(range(n), Q):
+        used = sorted(dirs[i] for i in keep)
+        mask = sum(1 << i for i in range(n) if i not in keep)
+        out.append((depth(used), mask))
+    return sorted(out)
+
+
+def run(mj, P, Q, dirs, masks):
+    nb = len(masks)
+    imgs = synth.block_images(901 + nb, 0, nb, P, Q)
+    words = mj.mojette_block_words(dirs, P, Q)
+    d_img = to_dev(imgs)
+    d_proj = torch.empty(nb * words, dtype=torch.int64, device="cuda")
+    mj.mojette_encode_batch(d_img, nb, P, Q, dirs, d_proj)
+    d_out = torch.full((nb * Q * P,), -1, dtype=torch.int64, device="cuda")
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    mj.mojette_decode_batch(d_proj, masks_to_dev(masks), nb, P, Q, dirs, d_out, st)
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0
+    out = to_np(d_out).reshape(nb, Q, P)
+    assert np.array_equal(out, imgs)
+    enc = to_np(d_proj).reshape(nb, words)
+    assert np.array_equal(out[:6], oracle.decode_blocks(enc[:6], masks[:6], P, Q, dirs))
+
+
+@pytest.mark.parametrize("n,Q,P", [(12, 8, 128), (8, 4, 96), (16, 12, 40)])
+def test_deep_shallow_and_mixed_batches(mj, n, Q, P):
+    dirs = synth.centered_dirs(n)
+    by_depth = masks_by_depth(dirs, Q)
+    deep = np.array([m for _, m in by_depth[-5:]] * 20, dtype=np.uint16)
+    shallow = np.array([m for _, m in by_depth[:5]] * 20, dtype=np.uint16)
+    say(f"ring split n={n} Q={Q} P={P}: depths {by_depth[0][0]}..{by_depth[-1][0]}")
+    run(mj, P, Q, dirs, deep)
+    run(mj, P, Q, dirs, shallow)
+    rng = np.random.default_rng(n)
+    mixed = np.array([by_depth[i][1] for i in rng.integers(0, len(by_depth), 150)],
+                     dtype=np.uint16)
+    run(mj, P, Q, dirs, mixed)
