@@ -1033,10 +1033,41 @@ static int jobs_check(const mojette_job *jobs, int32_t njobs, std::vector<int64_
     return MOJETTE_OK;
 }
 
+// A job whose single-geometry launch has at least this many work items
+// (enough to fill the chip alone) gets a launch of its own, with the
+// single-geometry kernel's tiles and waves; the rest share one mixed launch.
+// Measured on the mixed batch of 16 classes: the 1 MB classes encode ~3x
+// faster alone than as items of the mixed launch, whose one-wavefront
+// workgroups and shared LDS budget leave few wavefronts per compute unit.
+constexpr int64_t kOwnEncodeItems = 8192;
+
 int mojette_encode_jobs(const mojette_job *jobs, int32_t njobs, void *stream) {
     std::vector<int64_t> bw;
     int rc = jobs_check(jobs, njobs, bw);
     if (rc != MOJETTE_OK) return rc;
+    // big jobs: a launch each
+    std::vector<char> own(njobs, 0);
+    for (int c = 0; c < njobs; ++c) {
+        const mojette_job &j = jobs[c];
+        mj::EncodeArgs a{};
+        if (j.nblocks == 0 || !encode_tiling(j.dirs, j.n, j.P, j.Q, a)) continue;
+        if (j.nblocks * a.ntiles < kOwnEncodeItems) continue;
+        own[c] = 1;
+        a.images = j.images;
+        a.slots = j.slots;
+        int64_t off = 0;
+        for (int i = 0; i < j.n; ++i) {
+            a.out[i] = j.projs + off;
+            off += mojette_proj_size(j.dirs[i], j.P, j.Q);
+        }
+        a.proj_stride = off;
+        a.nblocks = j.nblocks;
+        const int64_t want = (j.nblocks * a.ntiles + a.waves - 1) / a.waves;
+        const int grid = (int)std::min<int64_t>(want, kEncodeGridCap);
+        clear_stale_error();
+        rc = status_of(mj::launch_encode(a, grid, (hipStream_t)stream));
+        if (rc != MOJETTE_OK) return rc;
+    }
     // heaviest items (widest tiles x rows x directions) first
     std::vector<int> order(njobs);
     std::vector<mj::EncodeArgs> geo(njobs);
@@ -1058,7 +1089,7 @@ int mojette_encode_jobs(const mojette_job *jobs, int32_t njobs, void *stream) {
     int k = 0;
     for (int oc : order) {
         const mojette_job &jb = jobs[oc];
-        if (jb.nblocks == 0) continue;
+        if (jb.nblocks == 0 || own[oc]) continue;
         mj::EncodeClass &e = tab.cls[k];
         e.images = jb.images;
         e.projs = jb.projs;

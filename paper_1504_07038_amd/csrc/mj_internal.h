@@ -46,6 +46,7 @@ __host__ __device__ inline int32_t proj_bins(int32_t p, int32_t P, int32_t Q) {
 struct EncodeArgs {
     const uint64_t *images;          // block b's image at images + b*P*Q
     uint64_t *out[kMaxDirs];         // projection i of block b: out[i] + b*proj_stride
+    const int64_t *slots;            // if set, block b's projections at slice slots[b] instead
     int64_t proj_stride;
     int64_t nblocks;
     int32_t P, Q, n;
@@ -57,7 +58,9 @@ struct EncodeArgs {
     // never-used bins left out); keep_n[i] == 0: all of Eq. 2's bins.
     int32_t keep_lo[kMaxDirs], keep_n[kMaxDirs];
     __device__ int dir(int i) const { return p[i]; }
-    __device__ uint64_t *proj(int i, int64_t blk) const { return out[i] + blk * proj_stride; }
+    __device__ uint64_t *proj(int i, int64_t blk) const {
+        return out[i] + (slots ? slots[blk] : blk) * proj_stride;
+    }
     __device__ int kept_first(int i) const { return keep_lo[i]; }
     __device__ int kept_count(int i, int full) const { return keep_n[i] ? keep_n[i] : full; }
 };

@@ -179,3 +179,37 @@ def test_jobs_scatter_and_gather_slots(mj):
         untouched = np.setdiff1d(np.arange(cap), slots)
         assert (ar[untouched] == 7).all()
         assert np.array_equal(to_np(d_out).reshape(nb, Q, P), imgs)
+
+
+def test_jobs_big_job_gets_its_own_launch_with_slots(mj):
+    """A job large enough for a launch of its own (here 9,000 4 KB blocks at
+    scattered slots) beside a small job sharing the mixed launch: both must
+    land exactly where the mixed launch alone would put them."""
+    rng = np.random.default_rng(9)
+    specs = [(128, 4, synth.centered_dirs(6), 9000, 9500), (64, 8, synth.centered_dirs(12), 50, 80),
+             (1024, 4, synth.centered_dirs(6), 40, 40)]
+    jobs_e, ref_e, host = [], [], []
+    for c, (P, Q, dirs, nb, cap) in enumerate(specs):
+        words = mj.mojette_block_words(dirs, P, Q)
+        d_img = torch.empty(nb * Q * P, dtype=torch.int64, device="cuda")
+        mj.mojette_fill_splitmix64(d_img, d_img.numel(), 40 + c)
+        slots = rng.permutation(cap)[:nb].astype(np.int64)
+        d_slots = torch.from_numpy(slots).cuda()
+        arena = torch.full((cap * words,), 7, dtype=torch.int64, device="cuda")
+        jobs_e.append(dict(P=P, Q=Q, dirs=dirs, nblocks=nb, images=d_img, projs=arena,
+                           slots=d_slots))
+        host.append((d_img, slots, arena, words, cap))
+    say("jobs: big job + small jobs")
+    mj.mojette_encode_jobs(jobs_e)
+    torch.cuda.synchronize()
+    for (P, Q, dirs, nb, cap), (d_img, slots, arena, words, _) in zip(specs, host):
+        ref = torch.empty(nb * words, dtype=torch.int64, device="cuda")
+        mj.mojette_encode_batch(d_img, nb, P, Q, dirs, ref)
+        torch.cuda.synchronize()
+        ar = to_np(arena).reshape(cap, words)
+        assert np.array_equal(ar[slots], to_np(ref).reshape(nb, words))
+        untouched = np.setdiff1d(np.arange(cap), slots)
+        assert (ar[untouched] == 7).all()
+        pick = rng.integers(0, nb, 6)
+        imgs = to_np(d_img).reshape(nb, Q, P)[pick]
+        assert np.array_equal(ar[slots[pick]], oracle.encode_blocks(imgs, P, Q, dirs))
