@@ -119,11 +119,12 @@ __device__ __forceinline__ void encode_bins(const A &a, int64_t blk, int t, cons
 // of the next work item's tile in registers, loaded while the current item's
 // bins are made and stored, so a wavefront always has loads in flight.  It
 // pays where the tiles' LDS leaves few wavefronts per compute unit (5 to 8
-// rows: 8 KB (8,4) blocks encode 2.2x faster); with up to 4 rows 32
-// wavefronts share a unit and the extra registers cost more than they hide
-// (8 KB (4,2) blocks 7% slower), and above 8 rows the registers run out.
+// rows: 8 KB (8,4) blocks encode 2.2x faster; 9 to 12 rows, tiles up to 320
+// columns: 1 MB (12,4) blocks 2.4x faster); with up to 4 rows 32 wavefronts
+// share a unit and the extra registers cost more than they hide (8 KB (4,2)
+// blocks 7% slower), and above 12 rows the registers run out.
 template <int Q>
-constexpr int encode_prefetch_chunks() { return Q >= 5 && Q <= 8 ? 4 : 0; }
+constexpr int encode_prefetch_chunks() { return Q >= 5 && Q <= 8 ? 4 : Q >= 9 && Q <= 12 ? 5 : 0; }
 
 template <int Q, int PF>
 __device__ __forceinline__ void encode_pipelined(const EncodeArgs &a, uint64_t *tile, int lane,
