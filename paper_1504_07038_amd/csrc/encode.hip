@@ -87,6 +87,7 @@ __device__ __forceinline__ void encode_bins(const A &a, int64_t blk, int t, cons
     // also takes the edge bins with -b < 0, the last those with -b >= P.
     const bool first = (t == 0), last = (t == a.ntiles - 1);
     const int base = H - x0;
+    const int64_t slice = a.slice(blk);   // read once: the stores below cannot alias it
     for (int i = 0; i < a.n; ++i) {
         const int p = a.dir(i);
         // the stored bins: all of Eq. 2's, or the kept ones (Section 2.3)
@@ -102,7 +103,7 @@ __device__ __forceinline__ void encode_bins(const A &a, int64_t blk, int t, cons
             bl = max(bl, m * p - P + 1);
             src = a.par[i] + blk * a.proj_stride;
         }
-        uint64_t *dst = a.proj(i, blk);
+        uint64_t *dst = a.proj_in(i, slice);
         const int rstride = S + p;
         for (int b = bl + lane; b <= bh; b += kWave) {
             uint64_t v = 0;

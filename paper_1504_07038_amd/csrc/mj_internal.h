@@ -58,8 +58,10 @@ struct EncodeArgs {
     // never-used bins left out); keep_n[i] == 0: all of Eq. 2's bins.
     int32_t keep_lo[kMaxDirs], keep_n[kMaxDirs];
     __device__ int dir(int i) const { return p[i]; }
-    __device__ uint64_t *proj(int i, int64_t blk) const {
-        return out[i] + (slots ? slots[blk] : blk) * proj_stride;
+    // block blk's slice index, then projection i within slice `slice`
+    __device__ int64_t slice(int64_t blk) const { return slots ? slots[blk] : blk; }
+    __device__ uint64_t *proj_in(int i, int64_t slice) const {
+        return out[i] + slice * proj_stride;
     }
     __device__ int kept_first(int i) const { return keep_lo[i]; }
     __device__ int kept_count(int i, int full) const { return keep_n[i] ? keep_n[i] : full; }
@@ -88,8 +90,9 @@ struct EncodeClass {
     int32_t off[kMaxDirs];           // projection i at off[i] within a slice
     int16_t p[kMaxDirs];
     __device__ int dir(int i) const { return p[i]; }
-    __device__ uint64_t *proj(int i, int64_t blk) const {
-        return projs + (slots ? slots[blk] : blk) * proj_stride + off[i];
+    __device__ int64_t slice(int64_t blk) const { return slots ? slots[blk] : blk; }
+    __device__ uint64_t *proj_in(int i, int64_t slice) const {
+        return projs + slice * proj_stride + off[i];
     }
     __device__ int kept_first(int) const { return 0; }      // mixed launches keep every bin
     __device__ int kept_count(int, int full) const { return full; }
