@@ -292,11 +292,30 @@ int decode_setup(const int32_t *dirs, int32_t n, int32_t P, int32_t Q, A &a) {
     return MOJETTE_OK;
 }
 
+// Compute units of the current device (cached per device).
+static int device_cus() {
+    static std::mutex mu;
+    static std::map<int, int> cus;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    std::lock_guard<std::mutex> g(mu);
+    auto it = cus.find(dev);
+    if (it != cus.end()) return it->second;
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        n <= 0)
+        n = 256;
+    return cus[dev] = n;
+}
+
 // Launches the whole-block pool decode described by `a` (from decode_setup,
 // pool fields filled).  nb_req > 0: blocks per wavefront asked by the caller
 // (capped by LDS).  When a shorter ring serves at least 90% of the survivor
-// sets, two launches run: that ring over the blocks whose set fits it (more
-// blocks per wavefront), then the full ring over the rest.
+// sets and the batch is large enough to keep the chip busy for at least two
+// rounds of wavefronts, two launches run: that ring over the blocks whose
+// set fits it (more blocks per wavefront), then the full ring over the rest.
+// A smaller batch is bound by one block's sweep, which a second launch would
+// repeat (256 1 MB (8,4) blocks: 6.2 ms in one launch, 12.6 ms in two).
 int launch_pool_whole(mj::DecodeArgs a, int Q, int nb_req, hipStream_t stream) {
     auto pick_nb = [&](mj::DecodeArgs &b) {
         if (nb_req > 0) {
@@ -317,7 +336,16 @@ int launch_pool_whole(mj::DecodeArgs a, int Q, int nb_req, hipStream_t stream) {
     std::vector<int> sp(a.p_sorted, a.p_sorted + a.n);
     int common = -1;
     ring_length(sp, Q, &common);
-    if (common <= 0 || common >= a.R) {
+    bool split = common > 0 && common < a.R;
+    if (split) {
+        mj::DecodeArgs b = a;
+        pick_nb(b);
+        const size_t lds = mj::decode_lds_bytes(Q, b.nb, b.ring_stride);
+        const int64_t per_cu = std::max<int64_t>(1, std::min<int64_t>(32, (160 * 1024) / lds));
+        const int64_t batches = (b.nblocks + b.nb - 1) / b.nb;
+        split = batches >= 2 * per_cu * device_cus();
+    }
+    if (!split) {
         a.ring_mode = 0;
         pick_nb(a);
         return go(a);

@@ -1,7 +1,8 @@
-"""Whole-block decode with two ring classes: blocks whose survivor set reads
-deep (far behind the newest pixel) and shallow blocks go to different
-launches.  Batches made only of deep sets, only of shallow sets, and both
-mixed at random, against the oracle."""
+"""Whole-block decode with two ring classes: in a batch large enough to keep
+the chip busy, blocks whose survivor set reads deep (far behind the newest
+pixel) and shallow blocks go to different launches.  Batches made only of
+deep sets, only of shallow sets, and both mixed at random, against the
+oracle."""
 import itertools
 
 import numpy as np
@@ -55,10 +56,12 @@ def masks_by_depth(dirs, Q):
 
 
 def run(mj, P, Q, dirs, masks):
+    """Round trip of every block on the device, the oracle on a sample.  The
+    batches are large enough for the library to split them."""
     nb = len(masks)
-    imgs = synth.block_images(901 + nb, 0, nb, P, Q)
     words = mj.mojette_block_words(dirs, P, Q)
-    d_img = to_dev(imgs)
+    d_img = torch.empty(nb * Q * P, dtype=torch.int64, device="cuda")
+    mj.mojette_fill_splitmix64(d_img, d_img.numel(), 900 + nb)
     d_proj = torch.empty(nb * words, dtype=torch.int64, device="cuda")
     mj.mojette_encode_batch(d_img, nb, P, Q, dirs, d_proj)
     d_out = torch.full((nb * Q * P,), -1, dtype=torch.int64, device="cuda")
@@ -66,22 +69,25 @@ def run(mj, P, Q, dirs, masks):
     mj.mojette_decode_batch(d_proj, masks_to_dev(masks), nb, P, Q, dirs, d_out, st)
     torch.cuda.synchronize()
     assert int(st.item()) == 0
-    out = to_np(d_out).reshape(nb, Q, P)
-    assert np.array_equal(out, imgs)
-    enc = to_np(d_proj).reshape(nb, words)
-    assert np.array_equal(out[:6], oracle.decode_blocks(enc[:6], masks[:6], P, Q, dirs))
+    assert torch.equal(d_out, d_img)
+    pick = np.array([0, 1, nb // 2, nb - 1])
+    idx = torch.from_numpy(pick).cuda()
+    enc = to_np(d_proj.view(nb, words)[idx])
+    want = oracle.decode_blocks(enc, masks[pick], P, Q, dirs)
+    assert np.array_equal(to_np(d_out.view(nb, -1)[idx]).reshape(len(pick), Q, P), want)
 
 
-@pytest.mark.parametrize("n,Q,P", [(12, 8, 128), (8, 4, 96), (16, 12, 40)])
-def test_deep_shallow_and_mixed_batches(mj, n, Q, P):
+@pytest.mark.parametrize("n,Q,P,nb", [(12, 8, 128, 12000), (8, 4, 96, 40000),
+                                      (16, 12, 40, 12000)])   # the last: one ring for every set
+def test_deep_shallow_and_mixed_batches(mj, n, Q, P, nb):
     dirs = synth.centered_dirs(n)
     by_depth = masks_by_depth(dirs, Q)
-    deep = np.array([m for _, m in by_depth[-5:]] * 20, dtype=np.uint16)
-    shallow = np.array([m for _, m in by_depth[:5]] * 20, dtype=np.uint16)
+    deep = np.resize(np.array([m for _, m in by_depth[-5:]], dtype=np.uint16), nb)
+    shallow = np.resize(np.array([m for _, m in by_depth[:5]], dtype=np.uint16), nb)
     say(f"ring split n={n} Q={Q} P={P}: depths {by_depth[0][0]}..{by_depth[-1][0]}")
     run(mj, P, Q, dirs, deep)
     run(mj, P, Q, dirs, shallow)
     rng = np.random.default_rng(n)
-    mixed = np.array([by_depth[i][1] for i in rng.integers(0, len(by_depth), 150)],
+    mixed = np.array([by_depth[i][1] for i in rng.integers(0, len(by_depth), nb)],
                      dtype=np.uint16)
     run(mj, P, Q, dirs, mixed)
