@@ -292,6 +292,17 @@ int decode_setup(const int32_t *dirs, int32_t n, int32_t P, int32_t Q, A &a) {
     return MOJETTE_OK;
 }
 
+// The library's blocks per wavefront for a single-geometry pool decode.  For
+// 3 or 4 rows at most half of what the lanes allow, so that the body
+// compiled for half the slots runs, the one whose loads fetch every line
+// once (ALIGN in decode_body.h; 4 KB (6,4): 3.93 ms at 16 blocks per
+// wavefront against 4.04 ms at 32 with the unaligned full-slot body).
+int pool_default_blocks(int Q, int ring_stride) {
+    const int nb = default_blocks(Q, ring_stride);
+    if (Q != 3 && Q != 4) return nb;
+    return std::min(nb, std::max(1, mj::decode_max_blocks_per_wave(Q) / 2));
+}
+
 // Compute units of the current device (cached per device).
 static int device_cus() {
     static std::mutex mu;
@@ -321,6 +332,8 @@ int launch_pool_whole(mj::DecodeArgs a, int Q, int nb_req, hipStream_t stream) {
         if (nb_req > 0) {
             b.nb = std::min(mj::decode_max_blocks_per_wave(Q), nb_req);
             while (b.nb > 1 && mj::decode_lds_bytes(Q, b.nb, b.ring_stride) > kLdsLimit) --b.nb;
+        } else {
+            b.nb = pool_default_blocks(Q, b.ring_stride);
         }
     };
     auto go = [&](const mj::DecodeArgs &b) {
@@ -355,12 +368,12 @@ int launch_pool_whole(mj::DecodeArgs a, int Q, int nb_req, hipStream_t stream) {
     mj::DecodeArgs m1 = a;
     m1.R = common;
     m1.ring_stride = common + 1;
-    m1.nb = default_blocks(Q, m1.ring_stride);
     m1.ring_mode = 1;
     pick_nb(m1);
     const int rc = go(m1);
     if (rc != MOJETTE_OK) return rc;
     a.ring_mode = 2;
+    a.nb = pool_default_blocks(Q, a.ring_stride);
     return go(a);
 }
 
@@ -1032,7 +1045,7 @@ int32_t mojette_decode_default_blocks_per_wave(const int32_t *dirs, int32_t n, i
     if (!geometry_ok(dirs, n, P, Q)) return -1;
     mj::DecodeArgs a{};
     if (decode_setup(dirs, n, P, Q, a) != MOJETTE_OK) return -1;
-    return default_blocks(Q, main_ring_stride(a, Q));
+    return pool_default_blocks(Q, main_ring_stride(a, Q));
 }
 
 int mojette_classes_layout(const mojette_class *classes, int32_t nclasses, int64_t *image_words,

@@ -124,6 +124,7 @@ struct SegParam {
                    // pointer mode: bin index of column 0 (jbase)
     int col0;      // column of word 2q of the load window of tile 0
     int scol0;     // first column stored by this lane at tile 0 (window lag applied)
+    int mis;       // aligned loads: the row window's offset past a 128-byte line, in words
     int img;       // word offset (in the wave's image slice) of the segment's row
     const uint64_t *bins;   // pointer mode: the row's projection
     bool on;       // segment belongs to a block slot in use
@@ -162,8 +163,15 @@ struct SegParam {
 // sum 2 (m_{i+1} - m_i)(p_i - p_r) + (l - r) > 0, and for l < r it is at
 // least sum 2 (m_{i+1} - m_i)(p_r - p_i) - (r - l) >= (r - l)^2 > 0.  Rows
 // of consecutive sweep index still alternate in parity.
+//
+// ALIGN (pool mode): each row's bins are loaded as the 128-byte line where
+// the tile's window starts, and the words of that line that belong to the
+// next tile are kept in registers until then, so no line is fetched for two
+// tiles (an unaligned 16-word window shares a line with the next tile's,
+// and the line is gone from L2 by then).  The held words cost registers:
+// only the bodies compiled for half the slots take it.
 template <int Q, int TW, bool POOL, int CHUNK, int NBT, class Args, int STPOL = kStreamPolicy,
-          bool SYS = false>
+          bool SYS = false, bool ALIGN = false>
 __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch) {
     extern __shared__ uint64_t lds[];
     constexpr int LPB = (Q + 1) / 2;        // lanes per block
@@ -387,6 +395,10 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch)
         const int dr1 = r0_is_x ? Y.d : X.d;
         SegParam sp[NIT];
         uint32_t store_in = 0, store_past = 0;   // chunked sweeps: see first_last
+        constexpr bool AL = POOL && ALIGN;
+        // aligned loads: word offset of the wave's pool slice past a 128-byte line
+        const int slice_mis =
+            AL ? (int)(((uintptr_t)(a.pool + blk_lo * a.proj_stride) >> 3) & 15) : 0;
         {
             // pool mode: word offset of column 0's bin within the wave's slice
             const int g0 = POOL ? rel * (int)a.proj_stride + a.off[id0] + jb0 : jb0;
@@ -442,6 +454,8 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch)
                                                     : (((uint64_t)hi0 << 32) | lo0));
                 }
                 s.col0 = dd + TW - 1 - 2 * q + oshift;
+                // the window of tile t starts at word gbin - col0 - 2q - TW*t
+                s.mis = AL ? (slice_mis + s.gbin - s.col0 - 2 * q) & 15 : 0;
                 const int L = (-dd + TW - 1) / TW;
                 s.scol0 = -TW * L + 2 * q + oshift;
                 s.img = orel * QP + orow * P;
@@ -467,7 +481,10 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch)
         }
 
         // Loads the bins of tile t: words 2q, 2q+1 of each row window are the
-        // bins of columns c and c - 1, c = t*TW + col0.
+        // bins of columns c and c - 1, c = t*TW + col0.  Aligned loads take
+        // the line where the window starts instead: its words 2q, 2q+1 are
+        // window words 2q - mis and 2q + 1 - mis, and those below 0 belong
+        // to the window of tile t+1 (see stage_tile).
         auto load_tile = [&](int t, u32x4 (&buf)[NIT]) {
 #pragma unroll
             for (int it = 0; it < NIT; ++it) {
@@ -476,10 +493,10 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch)
                 if constexpr (POOL) {
                     // one 8-byte load per word, so each word is bounds checked
                     // on its own (a window may start just before the slice)
-                    const uint32_t off0 =
-                        s.on ? (uint32_t)((s.gbin - c) ^ a.bin_swap) * 8u : kOffNone;
+                    const int w = s.gbin - c - (AL ? s.mis : 0);
+                    const uint32_t off0 = s.on ? (uint32_t)(w ^ a.bin_swap) * 8u : kOffNone;
                     const uint32_t off1 =
-                        s.on ? (uint32_t)((s.gbin - c + 1) ^ a.bin_swap) * 8u : kOffNone;
+                        s.on ? (uint32_t)((w + 1) ^ a.bin_swap) * 8u : kOffNone;
                     const u32x2 w0 = __builtin_amdgcn_raw_buffer_load_b64(rin, off0, 0, 0);
                     const u32x2 w1 = __builtin_amdgcn_raw_buffer_load_b64(rin, off1, 0, 0);
                     buf[it] = u32x4{w0.x, w0.y, w1.x, w1.y};
@@ -493,16 +510,28 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch)
                 }
             }
         };
-        // Writes loaded bins of tile t into the rings.
-        auto stage_tile = [&](int t, const u32x4 (&buf)[NIT]) {
+        // Writes the bins of tile t into the rings: `buf` holds the loads of
+        // tile t, `prev` (aligned loads) those of tile t-1.  Window word v of
+        // tile t is column t*TW + col0 + 2q - v; with aligned loads it is word
+        // v + mis of this tile's line when v + mis < TW, else word
+        // v + mis - TW of the previous tile's line.
+        auto stage_tile = [&](int t, const u32x4 (&buf)[NIT],
+                              const u32x4 (&prev)[AL ? NIT : 1]) {
 #pragma unroll
             for (int it = 0; it < NIT; ++it) {
                 const SegParam &s = sp[it];
                 if (!s.on) continue;
-                const int c = t * TW + s.col0;
                 uint64_t *row = lds + s.ring;
-                row[c & Rmask] = lo64(buf[it]);
-                row[(c - 1) & Rmask] = hi64(buf[it]);
+                if constexpr (AL) {
+                    const int c = t * TW + s.col0 + s.mis;   // column of this line's word 2q
+                    const bool h0 = 2 * q < s.mis, h1 = 2 * q + 1 < s.mis;
+                    row[(c - (h0 ? TW : 0)) & Rmask] = h0 ? lo64(prev[it]) : lo64(buf[it]);
+                    row[(c - 1 - (h1 ? TW : 0)) & Rmask] = h1 ? hi64(prev[it]) : hi64(buf[it]);
+                } else {
+                    const int c = t * TW + s.col0;
+                    row[c & Rmask] = lo64(buf[it]);
+                    row[(c - 1) & Rmask] = hi64(buf[it]);
+                }
             }
         };
         // Stores the completed TW-aligned window of every row at the end of
@@ -560,9 +589,15 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch)
             }
         }
         u32x4 buf[NIT];
+        u32x4 prev[AL ? NIT : 1];      // aligned loads: the previous tile's lines
+        if constexpr (AL) load_tile(-1, prev);
         load_tile(0, buf);
         wave_sync();
-        stage_tile(0, buf);
+        stage_tile(0, buf, prev);
+        if constexpr (AL) {
+#pragma unroll
+            for (int it = 0; it < NIT; ++it) prev[it] = buf[it];
+        }
         load_tile(1, buf);
         wave_sync();
 
@@ -583,7 +618,11 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch)
             }
             store_tile(t);
             wave_sync();
-            stage_tile(t + 1, buf);
+            stage_tile(t + 1, buf, prev);
+            if constexpr (AL) {
+#pragma unroll
+                for (int it = 0; it < NIT; ++it) prev[it] = buf[it];
+            }
             load_tile(t + 2, buf);
             wave_sync();
         }
@@ -607,12 +646,12 @@ constexpr int full_slots() { return kWave / ((Q + 1) / 2); }
 template <int Q>
 constexpr int half_slots() { return kWave / ((Q + 1) / 2) >= 2 ? kWave / ((Q + 1) / 2) / 2 : 1; }
 
-template <int Q, int TW, bool POOL, int CHUNK, int NBT>
+template <int Q, int TW, bool POOL, int CHUNK, int NBT, bool ALIGN = false>
 __global__ __launch_bounds__(kWave) void decode_kernel(DecodeArgs a) {
     const int64_t per = CHUNK == kWhole ? 1 : a.chunk.nchunks - 1;
     const int64_t nbatches = (a.nblocks * per + a.nb - 1) / a.nb;
     for (int64_t batch = blockIdx.x; batch < nbatches; batch += gridDim.x)
-        decode_batch<Q, TW, POOL, CHUNK, NBT>(a, batch);
+        decode_batch<Q, TW, POOL, CHUNK, NBT, DecodeArgs, kStreamPolicy, false, ALIGN>(a, batch);
 }
 
 // Carry pass of the chunked decode.  For every block, with y_c the end state
@@ -830,10 +869,14 @@ __global__ __launch_bounds__(kWave * kCarryWaves) void decode_carry_classes_kern
 template <int Q, int NBT>
 static hipError_t launch_qn(int mode, const DecodeArgs &a, int grid, hipStream_t s) {
     const size_t lds = decode_lds_bytes(Q, a.nb, a.ring_stride);
+    // pool sweeps of the half-slot body load whole lines (ALIGN) for 3 or 4
+    // rows; measured with more rows, the extra registers cost more than the
+    // fetches saved (8 KB (8,4): 5.49 against 5.06 ms)
+    constexpr bool kAlign = NBT < full_slots<Q>() && (Q == 3 || Q == 4);
     switch (mode) {
         case kLaunchPool:
-            hipLaunchKernelGGL((decode_kernel<Q, kDecodeTile, true, kWhole, NBT>), dim3(grid),
-                               dim3(kWave), lds, s, a);
+            hipLaunchKernelGGL((decode_kernel<Q, kDecodeTile, true, kWhole, NBT, kAlign>),
+                               dim3(grid), dim3(kWave), lds, s, a);
             break;
         case kLaunchPointers:
             hipLaunchKernelGGL((decode_kernel<Q, kDecodeTile, false, kWhole, NBT>), dim3(grid),
