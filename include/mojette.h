@@ -46,6 +46,7 @@ extern "C" {
 #define MOJETTE_ENOTRECON (-2)     /* fewer than Q projections survive (Eq. 3) */
 #define MOJETTE_EHIP (-3)          /* a HIP runtime call failed */
 #define MOJETTE_ENOMEM (-4)        /* host-side bookkeeping could not allocate */
+#define MOJETTE_EINCONSISTENT (-5) /* projections that no image has (mojette_verify_batch) */
 #define MOJETTE_ENOTSUP (-6)       /* geometry beyond the kernels' LDS limits */
 
 #define MOJETTE_MAX_DIRS 16
@@ -126,6 +127,24 @@ int mojette_encode_batch(const uint64_t *images, int64_t nblocks, int32_t P, int
 int mojette_decode_batch(const uint64_t *projs, const uint16_t *erased, int64_t nblocks,
                          int32_t P, int32_t Q, const int32_t *dirs, int32_t n, uint64_t *images,
                          int32_t *status, void *stream);
+
+/*
+ * Consistency check of decoded blocks (the peeling of Section 2.2 detects
+ * projections that are not the projections of any image: a bin left with a
+ * nonzero residue once every pixel on its line is known).  For every block,
+ * every projection whose bit is clear in erased[b] is recomputed from the
+ * block's image (Eq. 1) and compared bin by bin, all of Eq. 2's bins, with
+ * the stored one; any difference stores MOJETTE_EINCONSISTENT to *status
+ * (device int32, required; the call never clears it).  With the image from
+ * mojette_decode_batch on the same masks, a clean *status means every
+ * surviving projection is exactly the projection of the decoded image.  A
+ * single corrupted bin is always caught once two projections survive: the
+ * bins of each projection XOR to the XOR of all pixels.  Arguments as for
+ * mojette_decode_batch; nothing is written but *status.
+ */
+int mojette_verify_batch(const uint64_t *projs, const uint16_t *erased, int64_t nblocks,
+                         int32_t P, int32_t Q, const int32_t *dirs, int32_t n,
+                         const uint64_t *images, int32_t *status, void *stream);
 
 /*
  * 128-bit pixels and bins (Section 3.1 sets pixel and bin to 128 bits for

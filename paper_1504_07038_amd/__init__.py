@@ -23,6 +23,7 @@ MOJETTE_EINVAL = -1
 MOJETTE_ENOTRECON = -2
 MOJETTE_EHIP = -3
 MOJETTE_ENOMEM = -4
+MOJETTE_EINCONSISTENT = -5
 MOJETTE_ENOTSUP = -6
 MAX_DIRS = 16
 MAX_ROWS = 16
@@ -129,6 +130,7 @@ def lib() -> ctypes.CDLL:
         "mojette_encode_batch": ([vp, i64, i32, i32, vp, i32, vp, vp], ctypes.c_int),
         "mojette_decode_batch": ([vp, vp, i64, i32, i32, vp, i32, vp, vp, vp], ctypes.c_int),
         "mojette_encode_batch_wide": ([vp, i64, i32, i32, vp, i32, vp, vp], ctypes.c_int),
+        "mojette_verify_batch": ([vp, vp, i64, i32, i32, vp, i32, vp, vp, vp], ctypes.c_int),
         "mojette_trimmed_layout": ([vp, i32, i32, i32, vp, vp], i64),
         "mojette_encode_batch_sys": ([vp, i64, i32, i32, vp, i32, vp, vp], ctypes.c_int),
         "mojette_sys_workspace": ([vp, i32, i32, i32, i64], i64),
@@ -189,7 +191,7 @@ def exported_symbols() -> list[str]:
         "mojette_strerror", "mojette_last_hip_error", "mojette_proj_size",
         "mojette_bin_offset", "mojette_block_words", "mojette_decode_ring", "mojette_encode",
         "mojette_decode", "mojette_encode_batch", "mojette_decode_batch",
-        "mojette_encode_batch_wide", "mojette_decode_batch_wide",
+        "mojette_encode_batch_wide", "mojette_decode_batch_wide", "mojette_verify_batch",
         "mojette_trimmed_layout", "mojette_encode_batch_trimmed", "mojette_decode_batch_trimmed",
         "mojette_encode_batch_sys", "mojette_sys_workspace", "mojette_decode_batch_sys",
         "mojette_decode_batch_tuned", "mojette_decode_max_blocks_per_wave",
@@ -312,6 +314,17 @@ def mojette_decode_batch(projs, erased, nblocks: int, P: int, Q: int, dirs, imag
     rc = lib().mojette_decode_batch(_word_tensor(projs, "projs"), er, nblocks, P, Q, arr, n,
                                     _word_tensor(images, "images"), st, _stream(stream))
     return _check(rc, "mojette_decode_batch", check)
+
+
+def mojette_verify_batch(projs, erased, nblocks: int, P: int, Q: int, dirs, images, status,
+                         stream=None, check: bool = True) -> int:
+    """Compare every surviving projection with the projection of ``images``;
+    a difference stores MOJETTE_EINCONSISTENT to ``status``."""
+    arr, n = _i32_array(dirs)
+    er, st = _decode_masks(erased, status)
+    rc = lib().mojette_verify_batch(_word_tensor(projs, "projs"), er, nblocks, P, Q, arr, n,
+                                    _word_tensor(images, "images"), st, _stream(stream))
+    return _check(rc, "mojette_verify_batch", check)
 
 
 def mojette_encode_batch_wide(images, nblocks: int, P: int, Q: int, dirs, projs, stream=None,

@@ -426,6 +426,7 @@ const char *mojette_strerror(int status) {
         case MOJETTE_EHIP: return "HIP runtime error";
         case MOJETTE_ENOMEM: return "out of host memory";
         case MOJETTE_ENOTSUP: return "geometry exceeds the kernels' LDS limits";
+        case MOJETTE_EINCONSISTENT: return "projections disagree with the image";
         default: return "unknown status";
     }
 }
@@ -619,6 +620,30 @@ int mojette_decode_batch_trimmed(const uint64_t *projs, const uint16_t *erased, 
     if (nblocks < 0 || !kept_layout(dirs, n, P, Q, f, c)) return MOJETTE_EINVAL;
     return decode_batch_impl(projs, erased, nblocks, P, Q, dirs, n, images, status, stream, 0,
                              f, c);
+}
+
+int mojette_verify_batch(const uint64_t *projs, const uint16_t *erased, int64_t nblocks,
+                         int32_t P, int32_t Q, const int32_t *dirs, int32_t n,
+                         const uint64_t *images, int32_t *status, void *stream) {
+    if (nblocks < 0 || !geometry_ok(dirs, n, P, Q) || !status) return MOJETTE_EINVAL;
+    if (nblocks == 0) return MOJETTE_OK;
+    if (!projs || !images) return MOJETTE_EINVAL;
+    mj::VerifyArgs a{};
+    if (!encode_tiling(dirs, n, P, Q, a)) return MOJETTE_ENOTSUP;
+    a.images = images;
+    int64_t off = 0;
+    for (int i = 0; i < n; ++i) {
+        a.par[i] = projs + off;
+        off += mojette_proj_size(dirs[i], P, Q);
+    }
+    a.proj_stride = off;
+    a.nblocks = nblocks;
+    a.masks = erased;
+    a.status = status;
+    const int64_t items = nblocks * a.ntiles;
+    const int grid = (int)std::min<int64_t>((items + a.waves - 1) / a.waves, kEncodeGridCap);
+    clear_stale_error();
+    return status_of(mj::launch_verify(a, grid, (hipStream_t)stream));
 }
 
 // ---- systematic code -----------------------------------------------------

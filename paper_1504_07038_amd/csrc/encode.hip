@@ -31,11 +31,13 @@ namespace mj {
 // pixels on the bin's line.  Only the projections the decode reads (the
 // r-th surviving one in ascending p for the r-th lost line m_r) are
 // computed, and of those only the bins m_r*p - k, k in [0, P), it reads.
-template <int Q, class A, bool RESID>
+template <int Q, class A, bool RESID, bool VERIFY = false>
 __device__ __forceinline__ void encode_bins(const A &a, int64_t blk, int t, const uint64_t *tile,
                                             int lane, uint32_t use, uint64_t row_of);
 
-template <int Q, class A, bool RESID = false>
+// VERIFY (A = VerifyArgs): the bins of every surviving projection are
+// compared with the stored ones instead of being written.
+template <int Q, class A, bool RESID = false, bool VERIFY = false>
 __device__ __forceinline__ void encode_item(const A &a, int64_t blk, int t, uint64_t *tile,
                                             int lane) {
     const int P = a.P, W = a.W, H = a.H, S = a.S;
@@ -58,6 +60,10 @@ __device__ __forceinline__ void encode_item(const A &a, int64_t blk, int t, uint
         }
         if (left) return;                   // too few projections: the decode reports it
     }
+    if constexpr (VERIFY) {
+        const uint32_t mask = a.masks ? a.masks[blk] : 0u;
+        use = ~mask & ((1u << a.n) - 1u);
+    }
 
     // Stage image columns [x0 - H, x0 + W + H) of every row, zeros outside
     // (and, RESID, zeros for the lost lines).
@@ -73,12 +79,12 @@ __device__ __forceinline__ void encode_item(const A &a, int64_t blk, int t, uint
         }
     }
     wave_sync();
-    encode_bins<Q, A, RESID>(a, blk, t, tile, lane, use, row_of);
+    encode_bins<Q, A, RESID, VERIFY>(a, blk, t, tile, lane, use, row_of);
 }
 
 // The bins of work item (blk, t) from the wave's staged LDS tile; ends with
 // the wave done reading the tile.
-template <int Q, class A, bool RESID>
+template <int Q, class A, bool RESID, bool VERIFY>
 __device__ __forceinline__ void encode_bins(const A &a, int64_t blk, int t, const uint64_t *tile,
                                             int lane, uint32_t use, uint64_t row_of) {
     const int P = a.P, W = a.W, H = a.H, S = a.S;
@@ -96,6 +102,10 @@ __device__ __forceinline__ void encode_bins(const A &a, int64_t blk, int t, cons
         int bh = first ? bmax : min(bmax, -x0);
         int bl = last ? bmin : max(bmin, -x0 - W + 1);
         const uint64_t *src = nullptr;
+        if constexpr (VERIFY) {
+            if (!((use >> i) & 1u)) continue;
+            src = a.par[i] + blk * a.proj_stride;
+        }
         if constexpr (RESID) {
             if (!((use >> i) & 1u)) continue;
             const int m = (int)((row_of >> (4 * i)) & 15u);
@@ -109,6 +119,10 @@ __device__ __forceinline__ void encode_bins(const A &a, int64_t blk, int t, cons
             uint64_t v = 0;
 #pragma unroll
             for (int l = 0; l < Q; ++l) v ^= tile[l * rstride + base - b];
+            if constexpr (VERIFY) {
+                if (v != src[b - bmin]) *a.status = MOJETTE_EINCONSISTENT;
+                continue;
+            }
             if constexpr (RESID) v ^= src[b - bmin];
             dst[(b - bmin) ^ a.bin_swap] = v;
         }
@@ -211,6 +225,21 @@ __global__ __launch_bounds__(kWave *kEncodeWaves) void resid_kernel(ResidArgs a)
     }
 }
 
+template <int Q>
+__global__ __launch_bounds__(kWave *kEncodeWaves) void verify_kernel(VerifyArgs a) {
+    extern __shared__ uint64_t lds[];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wv = threadIdx.x >> 6;
+    uint64_t *tile = lds + (size_t)wv * Q * a.S;
+    const int64_t nitems = a.nblocks * a.ntiles;
+    const int64_t nwaves = (int64_t)gridDim.x * a.waves;
+    for (int64_t item = (int64_t)blockIdx.x * a.waves + wv; item < nitems; item += nwaves) {
+        const int64_t blk = item / a.ntiles;
+        const int t = (int)(item - blk * a.ntiles);
+        encode_item<Q, VerifyArgs, false, true>(a, blk, t, tile, lane);
+    }
+}
+
 template <int QMAX>
 __global__ __launch_bounds__(kWave) void encode_classes_kernel(EncodeClassTable tab) {
     extern __shared__ uint64_t lds[];
@@ -286,6 +315,35 @@ hipError_t launch_resid(const ResidArgs &a, int grid, hipStream_t s) {
         case 13: return launch_resid_q<13>(a, grid, s);
         case 14: return launch_resid_q<14>(a, grid, s);
         case 15: return launch_resid_q<15>(a, grid, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int Q>
+static hipError_t launch_verify_q(const VerifyArgs &a, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(verify_kernel<Q>, dim3(grid), dim3(kWave * a.waves),
+                       encode_lds_bytes(Q, a.S, a.waves), s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_verify(const VerifyArgs &a, int grid, hipStream_t s) {
+    switch (a.Q) {
+        case 1: return launch_verify_q<1>(a, grid, s);
+        case 2: return launch_verify_q<2>(a, grid, s);
+        case 3: return launch_verify_q<3>(a, grid, s);
+        case 4: return launch_verify_q<4>(a, grid, s);
+        case 5: return launch_verify_q<5>(a, grid, s);
+        case 6: return launch_verify_q<6>(a, grid, s);
+        case 7: return launch_verify_q<7>(a, grid, s);
+        case 8: return launch_verify_q<8>(a, grid, s);
+        case 9: return launch_verify_q<9>(a, grid, s);
+        case 10: return launch_verify_q<10>(a, grid, s);
+        case 11: return launch_verify_q<11>(a, grid, s);
+        case 12: return launch_verify_q<12>(a, grid, s);
+        case 13: return launch_verify_q<13>(a, grid, s);
+        case 14: return launch_verify_q<14>(a, grid, s);
+        case 15: return launch_verify_q<15>(a, grid, s);
+        case 16: return launch_verify_q<16>(a, grid, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -76,6 +76,14 @@ struct ResidArgs : EncodeArgs {
     int32_t id_sorted[kMaxDirs];     // parity projections in ascending p
 };
 
+// Consistency check: every surviving projection recomputed from the image and
+// compared with the stored one (par[i] + b*proj_stride).
+struct VerifyArgs : EncodeArgs {
+    const uint64_t *par[kMaxDirs];
+    const uint16_t *masks;           // bit i: projection i lost (not checked); may be null
+    int32_t *status;
+};
+
 // One geometry class of a mixed launch: nblocks blocks with the same P, Q and
 // directions, images back to back at `images`, projection slices back to back
 // at `projs`.
@@ -255,6 +263,7 @@ bool carry_rows_in_registers(int state);
 
 hipError_t launch_encode(const EncodeArgs &a, int grid, hipStream_t s);
 hipError_t launch_resid(const ResidArgs &a, int grid, hipStream_t s);
+hipError_t launch_verify(const VerifyArgs &a, int grid, hipStream_t s);
 hipError_t launch_decode_sys(int Q, const DecodeArgs &a, int grid, hipStream_t s);
 hipError_t launch_encode_classes(int qmax, const EncodeClassTable &tab, size_t lds, int grid,
                                  hipStream_t s);
