@@ -243,8 +243,8 @@ int mojette_decode_batch_tuned(const uint64_t *projs, const uint16_t *erased, in
 /* Blocks per decode wavefront for this geometry: the most that fit in LDS,
  * and the library's own choice for mojette_decode_batch (all the lanes
  * allow when their rings take at most 34 KB of LDS, else at most half of
- * them within 26 KB; for 3- and 4-row codes at most half, the body that
- * loads whole lines).  Both use the ring of the launch that sweeps most
+ * them within 26 KB; for 4-row codes with 32-word rings at most half, the
+ * body that loads whole lines).  Both use the ring of the launch that sweeps most
  * blocks: the shorter ring when a large batch is decoded in two ring
  * classes.  -1 on bad arguments. */
 int32_t mojette_decode_max_blocks_per_wave(const int32_t *dirs, int32_t n, int32_t P, int32_t Q);

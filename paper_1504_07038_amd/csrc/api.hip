@@ -2,6 +2,7 @@
 // kernel launches.  Only the plan calls of the chunked decode allocate device
 // memory or synchronise; every other call does neither.
 #include <algorithm>
+#include <cmath>
 #include <cstdlib>
 #include <map>
 #include <mutex>
@@ -155,17 +156,25 @@ static int ring_for_depth(int D) {
 
 // Also returns in *common the shortest ring that serves at least 90% of
 // the survivor sets (the whole-block pool decode sweeps the others in a
-// second launch with the full ring).
-int ring_length(const std::vector<int> &sorted_p, int Q, int *common = nullptr) {
+// second launch with the full ring) and in *deep the fraction of sets it
+// does not serve.
+struct RingInfo {
+    int R, common;
+    double deep;
+};
+
+int ring_length(const std::vector<int> &sorted_p, int Q, int *common = nullptr,
+                double *deep = nullptr) {
     static std::mutex mu;
-    static std::map<RingKey, std::pair<int, int>> cache;
+    static std::map<RingKey, RingInfo> cache;
     RingKey key{sorted_p, Q};
     {
         std::lock_guard<std::mutex> g(mu);
         auto it = cache.find(key);
         if (it != cache.end()) {
-            if (common) *common = it->second.second;
-            return it->second.first;
+            if (common) *common = it->second.common;
+            if (deep) *deep = it->second.deep;
+            return it->second.R;
         }
     }
     const int n = (int)sorted_p.size();
@@ -201,14 +210,19 @@ int ring_length(const std::vector<int> &sorted_p, int Q, int *common = nullptr) 
         for (int j = i + 1; j < Q; ++j) pick[j] = pick[j - 1] + 1;
     }
     int R = -1, Rc = -1;
+    double frac = 0;
     if (ok) {
         R = ring_for_depth(Dmax);
         std::sort(depths.begin(), depths.end());
         Rc = ring_for_depth(depths[(depths.size() * 9 + 9) / 10 - 1]);   // 90th percentile
+        int64_t over = 0;
+        for (int d : depths) over += d > Rc - mj::kDecodeTile - 1;
+        frac = (double)over / (double)depths.size();
     }
     if (common) *common = Rc;
+    if (deep) *deep = frac;
     std::lock_guard<std::mutex> g(mu);
-    cache[key] = {R, Rc};
+    cache[key] = {R, Rc, frac};
     return R;
 }
 
@@ -293,13 +307,13 @@ int decode_setup(const int32_t *dirs, int32_t n, int32_t P, int32_t Q, A &a) {
 }
 
 // The library's blocks per wavefront for a single-geometry pool decode.  For
-// 3 or 4 rows at most half of what the lanes allow, so that the body
-// compiled for half the slots runs, the one whose loads fetch every line
-// once (ALIGN in decode_body.h; 4 KB (6,4): 3.93 ms at 16 blocks per
-// wavefront against 4.04 ms at 32 with the unaligned full-slot body).
+// 4 rows and the shortest ring, at most half of what the lanes allow, so
+// that the body compiled for half the slots runs, the one whose loads fetch
+// every line once (ALIGN in decode_body.h; 4 KB (6,4): 3.85 ms at 16 blocks
+// per wavefront against 4.00 ms at 32 with the unaligned full-slot body).
 int pool_default_blocks(int Q, int ring_stride) {
     const int nb = default_blocks(Q, ring_stride);
-    if (Q != 3 && Q != 4) return nb;
+    if (Q != 4 || ring_stride != 2 * mj::kDecodeTile + 1) return nb;
     return std::min(nb, std::max(1, mj::decode_max_blocks_per_wave(Q) / 2));
 }
 
@@ -326,7 +340,11 @@ static int device_cus() {
 // rounds of wavefronts, two launches run: that ring over the blocks whose
 // set fits it (more blocks per wavefront), then the full ring over the rest.
 // A smaller batch is bound by one block's sweep, which a second launch would
-// repeat (256 1 MB (8,4) blocks: 6.2 ms in one launch, 12.6 ms in two).
+// repeat (256 1 MB (8,4) blocks: 6.2 ms in one launch, 12.6 ms in two).  The
+// second launch sweeps every batch that holds a deep block, so the split is
+// taken only while, with the deep sets drawn uniformly, at most a quarter
+// of its batches would (the 128-bit (6,4) geometry, 1 deep set in 15 at 12
+// blocks per wavefront, ran 1,380 against 1,823 GB/s split).
 int launch_pool_whole(mj::DecodeArgs a, int Q, int nb_req, hipStream_t stream) {
     auto pick_nb = [&](mj::DecodeArgs &b) {
         if (nb_req > 0) {
@@ -336,7 +354,9 @@ int launch_pool_whole(mj::DecodeArgs a, int Q, int nb_req, hipStream_t stream) {
             b.nb = pool_default_blocks(Q, b.ring_stride);
         }
     };
-    auto go = [&](const mj::DecodeArgs &b) {
+    auto go = [&](mj::DecodeArgs b) {
+        // whole-line loads pay with the shortest rings only
+        b.align = b.R == 2 * mj::kDecodeTile;
         // a wave's slice of the pool and of the images: 32-bit byte offsets
         if ((int64_t)b.nb * b.proj_stride * 8 >= ((int64_t)1 << 31) ||
             (int64_t)b.nb * b.img_stride * 8 >= ((int64_t)1 << 31))
@@ -348,7 +368,8 @@ int launch_pool_whole(mj::DecodeArgs a, int Q, int nb_req, hipStream_t stream) {
     };
     std::vector<int> sp(a.p_sorted, a.p_sorted + a.n);
     int common = -1;
-    ring_length(sp, Q, &common);
+    double deep = 1;
+    ring_length(sp, Q, &common, &deep);
     bool split = common > 0 && common < a.R;
     if (split) {
         mj::DecodeArgs b = a;
@@ -356,7 +377,8 @@ int launch_pool_whole(mj::DecodeArgs a, int Q, int nb_req, hipStream_t stream) {
         const size_t lds = mj::decode_lds_bytes(Q, b.nb, b.ring_stride);
         const int64_t per_cu = std::max<int64_t>(1, std::min<int64_t>(32, (160 * 1024) / lds));
         const int64_t batches = (b.nblocks + b.nb - 1) / b.nb;
-        split = batches >= 2 * per_cu * device_cus();
+        const int nb2 = pool_default_blocks(Q, a.ring_stride);
+        split = batches >= 2 * per_cu * device_cus() && 1.0 - std::pow(1.0 - deep, nb2) <= 0.25;
     }
     if (!split) {
         a.ring_mode = 0;
@@ -1046,12 +1068,16 @@ int mojette_decode_batch_tuned(const uint64_t *projs, const uint16_t *erased, in
     return launch_pool_whole(a, Q, blocks_per_wave, (hipStream_t)stream);
 }
 
-// Ring stride of the main launch of launch_pool_whole.
+// Ring stride of the main launch of launch_pool_whole for a large batch.
 static int main_ring_stride(const mj::DecodeArgs &a, int Q) {
     std::vector<int> sp(a.p_sorted, a.p_sorted + a.n);
     int common = -1;
-    ring_length(sp, Q, &common);
-    return (common > 0 && common < a.R) ? common + 1 : a.ring_stride;
+    double deep = 1;
+    ring_length(sp, Q, &common, &deep);
+    const int nb2 = pool_default_blocks(Q, a.ring_stride);
+    const bool split =
+        common > 0 && common < a.R && 1.0 - std::pow(1.0 - deep, nb2) <= 0.25;
+    return split ? common + 1 : a.ring_stride;
 }
 
 int32_t mojette_decode_max_blocks_per_wave(const int32_t *dirs, int32_t n, int32_t P,

@@ -170,8 +170,12 @@ struct SegParam {
 // tiles (an unaligned 16-word window shares a line with the next tile's,
 // and the line is gone from L2 by then).  The held words cost registers:
 // only the bodies compiled for half the slots take it.
+//
+// RCLS: the launch sweeps one ring class only (a.ring_mode, see below).  A
+// separate instantiation, so that launches over every block carry none of
+// its code (with it, they measured up to 30% slower).
 template <int Q, int TW, bool POOL, int CHUNK, int NBT, class Args, int STPOL = kStreamPolicy,
-          bool SYS = false, bool ALIGN = false>
+          bool SYS = false, bool ALIGN = false, bool RCLS = false>
 __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch) {
     extern __shared__ uint64_t lds[];
     constexpr int LPB = (Q + 1) / 2;        // lanes per block
@@ -278,8 +282,8 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch)
         // ring of this launch serves them), ring_mode 2 only the others.
         // The depth of a set is the largest ceil((A_l - A_r)/2) - 1 -
         // (l - r) p_r.
-        if constexpr (CHUNK == kWhole && !SYS && POOL && kIsDecodeArgs<Args>) {
-            if (a.ring_mode != 0) {
+        if constexpr (RCLS && CHUNK == kWhole && !SYS && POOL && kIsDecodeArgs<Args>) {
+            {
                 int depth = INT_MIN;
                 if (valid) {
                     int c2 = 0, ps2 = 0;
@@ -646,12 +650,13 @@ constexpr int full_slots() { return kWave / ((Q + 1) / 2); }
 template <int Q>
 constexpr int half_slots() { return kWave / ((Q + 1) / 2) >= 2 ? kWave / ((Q + 1) / 2) / 2 : 1; }
 
-template <int Q, int TW, bool POOL, int CHUNK, int NBT, bool ALIGN = false>
+template <int Q, int TW, bool POOL, int CHUNK, int NBT, bool ALIGN = false, bool RCLS = false>
 __global__ __launch_bounds__(kWave) void decode_kernel(DecodeArgs a) {
     const int64_t per = CHUNK == kWhole ? 1 : a.chunk.nchunks - 1;
     const int64_t nbatches = (a.nblocks * per + a.nb - 1) / a.nb;
     for (int64_t batch = blockIdx.x; batch < nbatches; batch += gridDim.x)
-        decode_batch<Q, TW, POOL, CHUNK, NBT, DecodeArgs, kStreamPolicy, false, ALIGN>(a, batch);
+        decode_batch<Q, TW, POOL, CHUNK, NBT, DecodeArgs, kStreamPolicy, false, ALIGN, RCLS>(
+            a, batch);
 }
 
 // Carry pass of the chunked decode.  For every block, with y_c the end state
@@ -869,14 +874,28 @@ __global__ __launch_bounds__(kWave * kCarryWaves) void decode_carry_classes_kern
 template <int Q, int NBT>
 static hipError_t launch_qn(int mode, const DecodeArgs &a, int grid, hipStream_t s) {
     const size_t lds = decode_lds_bytes(Q, a.nb, a.ring_stride);
-    // pool sweeps of the half-slot body load whole lines (ALIGN) for 3 or 4
-    // rows; measured with more rows, the extra registers cost more than the
-    // fetches saved (8 KB (8,4): 5.49 against 5.06 ms)
-    constexpr bool kAlign = NBT < full_slots<Q>() && (Q == 3 || Q == 4);
+    // Pool sweeps of the half-slot body load whole lines (ALIGN) for 4 rows
+    // when the host asks (a.align: the shortest rings); measured with other
+    // row counts the extra registers cost more than the fetches saved (8 KB
+    // (8,4): 5.49 against 5.06 ms; 4 KB (3,3): 3.19 against 3.02 ms), and so
+    // they did with 64-word rings (the 128-bit pixel geometry: 1,565 against
+    // 1,823 GB/s).
+    constexpr bool kAlign = NBT < full_slots<Q>() && Q == 4;
     switch (mode) {
         case kLaunchPool:
-            hipLaunchKernelGGL((decode_kernel<Q, kDecodeTile, true, kWhole, NBT, kAlign>),
-                               dim3(grid), dim3(kWave), lds, s, a);
+#define MJ_POOL_LAUNCH(AL, RC)                                                                \
+    hipLaunchKernelGGL((decode_kernel<Q, kDecodeTile, true, kWhole, NBT, AL, RC>), dim3(grid), \
+                       dim3(kWave), lds, s, a)
+            // the held words' registers leave room for 2 wavefronts per SIMD:
+            // worth it only while the wavefront's slots are mostly in use
+            if (a.ring_mode != 0) {
+                if (kAlign && a.align && 2 * a.nb > NBT) MJ_POOL_LAUNCH(kAlign, true);
+                else MJ_POOL_LAUNCH(false, true);
+            } else {
+                if (kAlign && a.align && 2 * a.nb > NBT) MJ_POOL_LAUNCH(kAlign, false);
+                else MJ_POOL_LAUNCH(false, false);
+            }
+#undef MJ_POOL_LAUNCH
             break;
         case kLaunchPointers:
             hipLaunchKernelGGL((decode_kernel<Q, kDecodeTile, false, kWhole, NBT>), dim3(grid),

@@ -192,6 +192,7 @@ struct DecodeArgs {
     int32_t ring_mode;               // whole-block pool sweeps: 0 every block; 1 only blocks
                                      // whose survivor set's depth is <= ring_depth; 2 the others
     int32_t ring_depth;
+    int32_t align;                   // whole-block pool sweeps: whole-line loads where compiled
     __device__ const uint64_t *proj_base(int64_t blk, int id) const {
         return pool ? pool + slots[blk] * proj_stride + off[id] : in[id];
     }
