@@ -37,7 +37,9 @@
 // wave (1) stores, for every row, the TW-aligned window of TW pixels that has
 // just been completed (lagging the sweep by less than one tile), (2) writes
 // the bins of tile t+1, loaded one tile earlier, into the rings, and (3)
-// issues the loads for tile t+2.  Loads and stores are cooperative: TW/2
+// issues the loads for tile t+2 (t+3 in the body with whole-line loads,
+// which has the registers for two tiles in flight).  Only bins of columns
+// inside the image are loaded.  Loads and stores are cooperative: TW/2
 // consecutive lanes move one row window as 16-byte pieces, so every
 // instruction touches whole cache lines (bins are loaded one 8-byte word per
 // instruction so that every word is bounds checked on its own).  In pool mode
@@ -400,6 +402,7 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch)
         SegParam sp[NIT];
         uint32_t store_in = 0, store_past = 0;   // chunked sweeps: see first_last
         constexpr bool AL = POOL && ALIGN;
+        constexpr bool DEEP = AL;        // loads two tiles ahead (registers allow it)
         // aligned loads: word offset of the wave's pool slice past a 128-byte line
         const int slice_mis =
             AL ? (int)(((uintptr_t)(a.pool + blk_lo * a.proj_stride) >> 3) & 15) : 0;
@@ -496,11 +499,17 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch)
                 const int c = t * TW + s.col0;
                 if constexpr (POOL) {
                     // one 8-byte load per word, so each word is bounds checked
-                    // on its own (a window may start just before the slice)
+                    // on its own (a window may start just before the slice).
+                    // Only columns inside the image load: the sweep zeroes the
+                    // pixels of the others whatever their bins hold, so the
+                    // lines a row's window covers before column 0 and past
+                    // column P-1 are never fetched.
                     const int w = s.gbin - c - (AL ? s.mis : 0);
-                    const uint32_t off0 = s.on ? (uint32_t)(w ^ a.bin_swap) * 8u : kOffNone;
-                    const uint32_t off1 =
-                        s.on ? (uint32_t)((w + 1) ^ a.bin_swap) * 8u : kOffNone;
+                    const int cw = c + (AL ? s.mis : 0);     // column of word 2q
+                    const bool in0 = s.on && (unsigned)cw < (unsigned)P;
+                    const bool in1 = s.on && (unsigned)(cw - 1) < (unsigned)P;
+                    const uint32_t off0 = in0 ? (uint32_t)(w ^ a.bin_swap) * 8u : kOffNone;
+                    const uint32_t off1 = in1 ? (uint32_t)((w + 1) ^ a.bin_swap) * 8u : kOffNone;
                     const u32x2 w0 = __builtin_amdgcn_raw_buffer_load_b64(rin, off0, 0, 0);
                     const u32x2 w1 = __builtin_amdgcn_raw_buffer_load_b64(rin, off1, 0, 0);
                     buf[it] = u32x4{w0.x, w0.y, w1.x, w1.y};
@@ -603,9 +612,9 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch)
             for (int it = 0; it < NIT; ++it) prev[it] = buf[it];
         }
         load_tile(1, buf);
-        wave_sync();
 
-        for (int t = 0; t < ntiles_wave; ++t) {
+        // Sweeps tile t and stores the rows' completed windows.
+        auto sweep_tile = [&](int t) {
             const int kx = t * TW + X.d, ky = t * TW + Y.d;
             int ox[QM], oy[QM];
 #pragma unroll
@@ -622,13 +631,37 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch)
             }
             store_tile(t);
             wave_sync();
-            stage_tile(t + 1, buf, prev);
+        };
+        // Stages tile t+1 from `cur`, which then takes the loads of tile
+        // t+1+ahead.
+        auto advance = [&](int t, u32x4 (&cur)[NIT], int ahead) {
+            stage_tile(t + 1, cur, prev);
             if constexpr (AL) {
 #pragma unroll
-                for (int it = 0; it < NIT; ++it) prev[it] = buf[it];
+                for (int it = 0; it < NIT; ++it) prev[it] = cur[it];
             }
-            load_tile(t + 2, buf);
+            load_tile(t + 1 + ahead, cur);
             wave_sync();
+        };
+        if constexpr (DEEP) {
+            // Two tiles of loads in flight: the two buffers take turns (a
+            // copy between them would wait for the younger loads).
+            u32x4 buf2[NIT];
+            load_tile(2, buf2);
+            wave_sync();
+            for (int t = 0; t < ntiles_wave; t += 2) {
+                sweep_tile(t);
+                advance(t, buf, 2);
+                if (t + 1 >= ntiles_wave) break;
+                sweep_tile(t + 1);
+                advance(t + 1, buf2, 2);
+            }
+        } else {
+            wave_sync();
+            for (int t = 0; t < ntiles_wave; ++t) {
+                sweep_tile(t);
+                advance(t, buf, 1);
+            }
         }
         // The end state of a chunk: the last E pixels of every row.
         if constexpr (CHUNK == kChunkA) {
