@@ -40,11 +40,12 @@ bool geometry_ok(const int32_t *dirs, int32_t n, int32_t P, int32_t Q) {
     return true;
 }
 
-// 128-bit pixels (Section 3.1) run on the 64-bit kernels: half h of pixel k
-// is word column 2k + h of a 2P-wide image of words, whose projection along
-// (2p, 1) holds bin j of the 16-byte projection along (p, 1) in word bins
-// 2j+1 and 2j (the kernels exchange the two with bin_swap).  Checks the
-// 16-byte geometry and fills dirs2 with the doubled directions.
+// The encode of 128-bit pixels (Section 3.1) runs on the 64-bit kernels:
+// half h of pixel k is word column 2k + h of a 2P-wide image of words, whose
+// projection along (2p, 1) holds bin j of the 16-byte projection along
+// (p, 1) in word bins 2j+1 and 2j (the kernel exchanges the two with
+// bin_swap).  Checks the 16-byte geometry and fills dirs2 with the doubled
+// directions.
 bool wide_geometry(const int32_t *dirs, int32_t n, int32_t P, int32_t Q, int32_t *dirs2) {
     if (!geometry_ok(dirs, n, P, Q) || P > kMaxP / 2) return false;
     for (int i = 0; i < n; ++i) {
@@ -589,7 +590,7 @@ int mojette_decode(const uint64_t *const *proj, const int32_t *proj_ids, int32_t
 
 static int decode_batch_impl(const uint64_t *projs, const uint16_t *erased, int64_t nblocks,
                              int32_t P, int32_t Q, const int32_t *dirs, int32_t n,
-                             uint64_t *images, int32_t *status, void *stream, int bin_swap,
+                             uint64_t *images, int32_t *status, void *stream,
                              const int32_t *keep_first = nullptr,
                              const int32_t *keep_count = nullptr) {
     if (nblocks < 0 || !geometry_ok(dirs, n, P, Q)) return MOJETTE_EINVAL;
@@ -616,23 +617,72 @@ static int decode_batch_impl(const uint64_t *projs, const uint16_t *erased, int6
     a.mask_uniform = 0;
     a.status = status;
     a.nblocks = nblocks;
-    a.bin_swap = bin_swap;
     return launch_pool_whole(a, Q, 0, (hipStream_t)stream);
 }
 
 int mojette_decode_batch(const uint64_t *projs, const uint16_t *erased, int64_t nblocks,
                          int32_t P, int32_t Q, const int32_t *dirs, int32_t n, uint64_t *images,
                          int32_t *status, void *stream) {
-    return decode_batch_impl(projs, erased, nblocks, P, Q, dirs, n, images, status, stream, 0);
+    return decode_batch_impl(projs, erased, nblocks, P, Q, dirs, n, images, status, stream);
 }
 
+// Blocks per wavefront of the 16-byte pixel decode: the count that keeps the
+// most blocks resident per compute unit (rings of 16-byte slots; at most 8
+// wavefronts per CU, at most half the full slot count), the larger on ties.
+static int wide_blocks(int Q, int ring_stride) {
+    const int most = std::max(1, mj::decode_max_blocks_per_wave(Q) / 2);
+    int best = 1;
+    int64_t best_res = 0;
+    for (int nb = most; nb >= 1; --nb) {
+        const size_t lds = 2 * mj::decode_lds_bytes(Q, nb, ring_stride);
+        if (lds > kLdsLimit) continue;
+        const int64_t waves = std::min<int64_t>(8, (160 * 1024) / lds);
+        if (waves * nb > best_res) {
+            best_res = waves * nb;
+            best = nb;
+        }
+    }
+    return best;
+}
+
+// 128-bit pixels (Section 3.1), decoded in the 16-byte geometry itself: P
+// pixels per row, directions p, rings of 16-byte slots.
 int mojette_decode_batch_wide(const uint64_t *projs, const uint16_t *erased, int64_t nblocks,
                               int32_t P, int32_t Q, const int32_t *dirs, int32_t n,
                               uint64_t *images, int32_t *status, void *stream) {
     int32_t dirs2[kMaxDirs];
     if (nblocks < 0 || !wide_geometry(dirs, n, P, Q, dirs2)) return MOJETTE_EINVAL;
-    return decode_batch_impl(projs, erased, nblocks, 2 * P, Q, dirs2, n, images, status, stream,
-                             1);
+    if (nblocks == 0) return MOJETTE_OK;
+    if (!projs || !images) return MOJETTE_EINVAL;
+    mj::DecodeArgs a{};
+    const int rc = decode_setup(dirs, n, P, Q, a);
+    if (rc != MOJETTE_OK) return rc;
+    a.nb = wide_blocks(Q, a.ring_stride);
+    if (2 * mj::decode_lds_bytes(Q, a.nb, a.ring_stride) > kLdsLimit) return MOJETTE_ENOTSUP;
+    // whole-line loads for 4-row codes (measured, 4 KB (6,4) at P = 64: 4.51
+    // -> 4.38 ms; 8 rows: 12.5 -> 12.9 ms, so the others load unaligned)
+    a.align = Q == 4;
+    int64_t off = 0;   // in 16-byte bins
+    for (int i = 0; i < n; ++i) {
+        a.off[i] = (int32_t)off;
+        off += mojette_proj_size(dirs[i], P, Q);
+    }
+    // a wave's slice of the pool and of the images: 32-bit byte offsets
+    if ((int64_t)a.nb * off * 16 >= ((int64_t)1 << 31) ||
+        (int64_t)a.nb * P * Q * 16 >= ((int64_t)1 << 31))
+        return MOJETTE_ENOTSUP;
+    a.pool = projs;
+    a.proj_stride = off;
+    a.images = images;
+    a.img_stride = (int64_t)P * Q;
+    a.masks = erased;
+    a.mask_uniform = 0;
+    a.status = status;
+    a.nblocks = nblocks;
+    const int64_t batches = (nblocks + a.nb - 1) / a.nb;
+    const int grid = (int)std::min<int64_t>(batches, kDecodeGridCap);
+    clear_stale_error();
+    return status_of(mj::launch_decode_wide(Q, a, grid, (hipStream_t)stream));
 }
 
 int mojette_decode_batch_trimmed(const uint64_t *projs, const uint16_t *erased, int64_t nblocks,
@@ -640,7 +690,7 @@ int mojette_decode_batch_trimmed(const uint64_t *projs, const uint16_t *erased, 
                                  uint64_t *images, int32_t *status, void *stream) {
     int32_t f[kMaxDirs], c[kMaxDirs];
     if (nblocks < 0 || !kept_layout(dirs, n, P, Q, f, c)) return MOJETTE_EINVAL;
-    return decode_batch_impl(projs, erased, nblocks, P, Q, dirs, n, images, status, stream, 0,
+    return decode_batch_impl(projs, erased, nblocks, P, Q, dirs, n, images, status, stream,
                              f, c);
 }
 

@@ -93,12 +93,27 @@ __device__ __forceinline__ void store_pair(uint64_t *dst, uint64_t lo, uint64_t 
     *reinterpret_cast<WordPair *>(dst) = WordPair{lo, hi};
 }
 
-// Sweep state of one row of one lane.
-template <int Q>
+// A 16-byte pixel or bin (Section 3.1's 128-bit pixels): word 0 is the low
+// half.  XOR acts on each word.
+struct __attribute__((aligned(16))) Pix128 {
+    uint64_t lo, hi;
+};
+__device__ __forceinline__ Pix128 operator^(Pix128 a, Pix128 b) { return {a.lo ^ b.lo, a.hi ^ b.hi}; }
+__device__ __forceinline__ Pix128 &operator^=(Pix128 &a, Pix128 b) { return a = a ^ b; }
+
+// Pixel of W words: uint64_t (W = 1) or Pix128 (W = 2).
+template <int W>
+using PixT = typename std::conditional<W == 1, uint64_t, Pix128>::type;
+
+template <class T>
+__device__ __forceinline__ T pix_zero() { return T{}; }
+
+// Sweep state of one row of one lane (pixels of type T).
+template <int Q, class T = uint64_t>
 struct RowState {
     static constexpr int QM = Q > 1 ? Q - 1 : 1;
-    uint64_t *ring;          // this row's ring
-    uint64_t *dep[QM];       // rings of the other rows
+    T *ring;                 // this row's ring
+    T *dep[QM];              // rings of the other rows
     int delta[QM];           // column offset (l - r) * p_r of each other row
     int d;                   // first column of tile 0
     bool on;                 // a real row of a decodable block
@@ -106,15 +121,16 @@ struct RowState {
 
 // Reconstructs column k0 + i of one row: the bin staged in the row's slot
 // XOR the other rows' pixels on the same line, zero outside the image.
-template <int Q>
-__device__ __forceinline__ void sweep_pixel(const RowState<Q> &s, const int (&o)[RowState<Q>::QM],
-                                            int k0, int i, int Rmask, int P) {
+template <int Q, class T>
+__device__ __forceinline__ void sweep_pixel(const RowState<Q, T> &s,
+                                            const int (&o)[RowState<Q, T>::QM], int k0, int i,
+                                            int Rmask, int P) {
     if (!s.on) return;
     const int k = k0 + i;
-    uint64_t v = s.ring[k & Rmask];
+    T v = s.ring[k & Rmask];
 #pragma unroll
     for (int m = 0; m < Q - 1; ++m) v ^= s.dep[m][(o[m] + i) & Rmask];
-    if ((unsigned)k >= (unsigned)P) v = 0;
+    if ((unsigned)k >= (unsigned)P) v = pix_zero<T>();
     s.ring[k & Rmask] = v;
 }
 
@@ -177,15 +193,21 @@ struct SegParam {
 // separate instantiation, so that launches over every block carry none of
 // its code (with it, they measured up to 30% slower).
 template <int Q, int TW, bool POOL, int CHUNK, int NBT, class Args, int STPOL = kStreamPolicy,
-          bool SYS = false, bool ALIGN = false, bool RCLS = false>
+          bool SYS = false, bool ALIGN = false, bool RCLS = false, int W = 1>
 __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch) {
-    extern __shared__ uint64_t lds[];
+    static_assert(W == 1 || (W == 2 && POOL && CHUNK == kWhole && !SYS && !RCLS),
+                  "16-byte pixels: whole-block pool sweeps only");
+    using T = PixT<W>;
+    extern __shared__ uint64_t lds_words[];
+    T *const lds = reinterpret_cast<T *>(lds_words);
     constexpr int LPB = (Q + 1) / 2;        // lanes per block
     constexpr int NBMAX = NBT;              // blocks per wavefront at most
-    constexpr int LPS = TW / 2;             // lanes per row window (two words each)
+    // Lanes per row window: each moves two words (W = 1) or two 16-byte
+    // pixels TW/2 columns apart (W = 2).
+    constexpr int LPS = TW / 2;
     constexpr int SPI = kWave / LPS;        // row windows per iteration
     constexpr int NIT = (NBMAX * Q + SPI - 1) / SPI;
-    constexpr int QM = RowState<Q>::QM;
+    constexpr int QM = RowState<Q, T>::QM;
 
     const int lane = threadIdx.x;
     const int slot = lane / LPB;
@@ -209,7 +231,7 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch)
     const int SS = Q * RS + 1;              // words per block slot (odd)
     const int Rmask = a.R - 1;
     const int P = a.P;
-    uint64_t *slot_base = lds + (size_t)(lane_used ? slot : 0) * SS;
+    T *slot_base = lds + (size_t)(lane_used ? slot : 0) * SS;
     const int r0 = 2 * j, r1 = 2 * j + 1;   // this lane's rows
     const int q = lane % LPS;
     int QI = Q;                            // image rows (projection geometry)
@@ -345,7 +367,7 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch)
         }
         const int ntiles_wave = wave_max(ntiles);
 
-        RowState<Q> X, Y;
+        RowState<Q, T> X, Y;
         const bool r0_is_x = ((r0 & 1) == par);
         int jb0 = 0, jb1 = 0;   // bin index of column 0 for rows r0 and r1
         int arow0 = r0, arow1 = r1;   // their image rows
@@ -402,10 +424,15 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch)
         SegParam sp[NIT];
         uint32_t store_in = 0, store_past = 0;   // chunked sweeps: see first_last
         constexpr bool AL = POOL && ALIGN;
-        constexpr bool DEEP = AL;        // loads two tiles ahead (registers allow it)
-        // aligned loads: word offset of the wave's pool slice past a 128-byte line
+        // loads two tiles ahead (the 64-bit body's registers allow it)
+        constexpr bool DEEP = AL && W == 1;
+        // aligned loads: offset of the wave's pool slice past a 128-byte
+        // line, in pixels (16 words or 8 pixels of 16 bytes per line)
+        constexpr int kLinePix = 128 / (8 * W);
         const int slice_mis =
-            AL ? (int)(((uintptr_t)(a.pool + blk_lo * a.proj_stride) >> 3) & 15) : 0;
+            AL ? (int)(((uintptr_t)(a.pool + blk_lo * a.proj_stride * W) >> (W == 1 ? 3 : 4)) &
+                       (kLinePix - 1))
+               : 0;
         {
             // pool mode: word offset of column 0's bin within the wave's slice
             const int g0 = POOL ? rel * (int)a.proj_stride + a.off[id0] + jb0 : jb0;
@@ -460,11 +487,12 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch)
                     s.bins = (const uint64_t *)(odd ? (((uint64_t)hi1 << 32) | lo1)
                                                     : (((uint64_t)hi0 << 32) | lo0));
                 }
-                s.col0 = dd + TW - 1 - 2 * q + oshift;
+                s.col0 = dd + TW - 1 - (W == 1 ? 2 * q : q) + oshift;
                 // the window of tile t starts at word gbin - col0 - 2q - TW*t
-                s.mis = AL ? (slice_mis + s.gbin - s.col0 - 2 * q) & 15 : 0;
+                s.mis = AL ? (slice_mis + s.gbin - s.col0 - (W == 1 ? 2 * q : q)) & (kLinePix - 1)
+                           : 0;
                 const int L = (-dd + TW - 1) / TW;
-                s.scol0 = -TW * L + 2 * q + oshift;
+                s.scol0 = -TW * L + (W == 1 ? 2 * q : q) + oshift;
                 s.img = orel * QP + orow * P;
             }
         }
@@ -480,11 +508,11 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch)
         __amdgpu_buffer_rsrc_t rin, rout;
         if constexpr (POOL) {
             rin = __builtin_amdgcn_make_buffer_rsrc(
-                (void *)(a.pool + first * a.proj_stride), 0,
-                (int)(nblk * a.proj_stride * sizeof(uint64_t)), kBufferWord3);
+                (void *)(a.pool + first * a.proj_stride * W), 0,
+                (int)(nblk * a.proj_stride * sizeof(T)), kBufferWord3);
             rout = __builtin_amdgcn_make_buffer_rsrc(
-                (void *)(a.images + first * a.img_stride), 0,
-                (int)(nblk * a.img_stride * sizeof(uint64_t)), kBufferWord3);
+                (void *)(a.images + first * a.img_stride * W), 0,
+                (int)(nblk * a.img_stride * sizeof(T)), kBufferWord3);
         }
 
         // Loads the bins of tile t: words 2q, 2q+1 of each row window are the
@@ -492,12 +520,24 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch)
         // the line where the window starts instead: its words 2q, 2q+1 are
         // window words 2q - mis and 2q + 1 - mis, and those below 0 belong
         // to the window of tile t+1 (see stage_tile).
-        auto load_tile = [&](int t, u32x4 (&buf)[NIT]) {
+        auto load_tile = [&](int t, u32x4 (&buf)[NIT * W]) {
 #pragma unroll
             for (int it = 0; it < NIT; ++it) {
                 const SegParam &s = sp[it];
                 const int c = t * TW + s.col0;
-                if constexpr (POOL) {
+                if constexpr (W == 2) {
+                    // 16-byte bins of columns c and c - TW/2: each load
+                    // instruction covers TW/2 consecutive bins of a row
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        // aligned loads: the two lines from where the window
+                        // starts; pixels below mis belong to tile t+1
+                        const int ch = c + (AL ? s.mis : 0) - h * LPS;
+                        const bool in = s.on && (unsigned)ch < (unsigned)P;
+                        const uint32_t off = in ? (uint32_t)(s.gbin - ch) * 16u : kOffNone;
+                        buf[it * W + h] = __builtin_amdgcn_raw_buffer_load_b128(rin, off, 0, 0);
+                    }
+                } else if constexpr (POOL) {
                     // one 8-byte load per word, so each word is bounds checked
                     // on its own (a window may start just before the slice).
                     // Only columns inside the image load: the sweep zeroes the
@@ -508,16 +548,16 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch)
                     const int cw = c + (AL ? s.mis : 0);     // column of word 2q
                     const bool in0 = s.on && (unsigned)cw < (unsigned)P;
                     const bool in1 = s.on && (unsigned)(cw - 1) < (unsigned)P;
-                    const uint32_t off0 = in0 ? (uint32_t)(w ^ a.bin_swap) * 8u : kOffNone;
-                    const uint32_t off1 = in1 ? (uint32_t)((w + 1) ^ a.bin_swap) * 8u : kOffNone;
+                    const uint32_t off0 = in0 ? (uint32_t)w * 8u : kOffNone;
+                    const uint32_t off1 = in1 ? (uint32_t)(w + 1) * 8u : kOffNone;
                     const u32x2 w0 = __builtin_amdgcn_raw_buffer_load_b64(rin, off0, 0, 0);
                     const u32x2 w1 = __builtin_amdgcn_raw_buffer_load_b64(rin, off1, 0, 0);
                     buf[it] = u32x4{w0.x, w0.y, w1.x, w1.y};
                 } else {
                     const uint64_t *bins = s.bins;
                     const int c0 = min(max(c, 0), P - 1), c1 = min(max(c - 1, 0), P - 1);
-                    const uint64_t w0 = s.on ? bins[(s.gbin - c0) ^ a.bin_swap] : 0;
-                    const uint64_t w1 = s.on ? bins[(s.gbin - c1) ^ a.bin_swap] : 0;
+                    const uint64_t w0 = s.on ? bins[s.gbin - c0] : 0;
+                    const uint64_t w1 = s.on ? bins[s.gbin - c1] : 0;
                     buf[it] = u32x4{(uint32_t)w0, (uint32_t)(w0 >> 32), (uint32_t)w1,
                                     (uint32_t)(w1 >> 32)};
                 }
@@ -528,14 +568,22 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch)
         // tile t is column t*TW + col0 + 2q - v; with aligned loads it is word
         // v + mis of this tile's line when v + mis < TW, else word
         // v + mis - TW of the previous tile's line.
-        auto stage_tile = [&](int t, const u32x4 (&buf)[NIT],
+        auto stage_tile = [&](int t, const u32x4 (&buf)[NIT * W],
                               const u32x4 (&prev)[AL ? NIT : 1]) {
 #pragma unroll
             for (int it = 0; it < NIT; ++it) {
                 const SegParam &s = sp[it];
                 if (!s.on) continue;
-                uint64_t *row = lds + s.ring;
-                if constexpr (AL) {
+                T *row = lds + s.ring;
+                if constexpr (W == 2) {
+                    const int c = t * TW + s.col0 + (AL ? s.mis : 0);
+                    // the first pixel: held for tile t+1 when below mis (the
+                    // previous tile's, from `prev`, goes in instead)
+                    const bool held = AL && q < s.mis;
+                    const u32x4 v0 = held ? prev[AL ? it : 0] : buf[it * W];
+                    row[(c - (held ? TW : 0)) & Rmask] = Pix128{lo64(v0), hi64(v0)};
+                    row[(c - LPS) & Rmask] = Pix128{lo64(buf[it * W + 1]), hi64(buf[it * W + 1])};
+                } else if constexpr (AL) {
                     const int c = t * TW + s.col0 + s.mis;   // column of this line's word 2q
                     const bool h0 = 2 * q < s.mis, h1 = 2 * q + 1 < s.mis;
                     row[(c - (h0 ? TW : 0)) & Rmask] = h0 ? lo64(prev[it]) : lo64(buf[it]);
@@ -548,35 +596,50 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch)
             }
         };
         // Stores the completed TW-aligned window of every row at the end of
-        // tile t: columns t*TW + scol0 and the next one.
+        // tile t: columns t*TW + scol0 and the next one (16-byte pixels:
+        // t*TW + scol0 and TW/2 columns further).
         auto store_tile = [&](int t) {
 #pragma unroll
             for (int it = 0; it < NIT; ++it) {
                 const SegParam &s = sp[it];
                 const int c = t * TW + s.scol0;
-                const uint64_t *row = lds + s.ring;
-                const uint64_t w0 = row[c & Rmask], w1 = row[(c + 1) & Rmask];
-                bool in_chunk = true;
-                if constexpr (CHUNK != kWhole)
-                    in_chunk = ((t < a.chunk.tiles ? store_in : store_past) >> it) & 1u;
-                const bool both = s.on && in_chunk && c >= 0 && c + 1 < P;
-                const bool last = s.on && in_chunk && c == P - 1;
-                if constexpr (POOL) {
-                    const uint32_t off2 = both ? (uint32_t)(s.img + c) * 8u : kOffNone;
-                    const uint32_t off1 = last ? (uint32_t)(s.img + c) * 8u : kOffNone;
-                    __builtin_amdgcn_raw_buffer_store_b128(
-                        u32x4{(uint32_t)w0, (uint32_t)(w0 >> 32), (uint32_t)w1,
-                              (uint32_t)(w1 >> 32)},
-                        rout, off2, 0, STPOL);
-                    if (P & 1)   // only an odd row length leaves a single last word
-                        __builtin_amdgcn_raw_buffer_store_b64(
-                            u32x2{(uint32_t)w0, (uint32_t)(w0 >> 32)}, rout, off1, 0, STPOL);
+                const T *row = lds + s.ring;
+                if constexpr (W == 2) {
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const int ch = c + h * LPS;
+                        const Pix128 v = row[ch & Rmask];
+                        const bool in = s.on && (unsigned)ch < (unsigned)P;
+                        const uint32_t off = in ? (uint32_t)(s.img + ch) * 16u : kOffNone;
+                        __builtin_amdgcn_raw_buffer_store_b128(
+                            u32x4{(uint32_t)v.lo, (uint32_t)(v.lo >> 32), (uint32_t)v.hi,
+                                  (uint32_t)(v.hi >> 32)},
+                            rout, off, 0, STPOL);
+                    }
                 } else {
-                    uint64_t *dst = a.images + first * a.img_stride + s.img;
-                    if (both) {
-                        store_pair(dst + c, w0, w1);
-                    } else if (last) {
-                        dst[c] = w0;
+                    const uint64_t w0 = row[c & Rmask], w1 = row[(c + 1) & Rmask];
+                    bool in_chunk = true;
+                    if constexpr (CHUNK != kWhole)
+                        in_chunk = ((t < a.chunk.tiles ? store_in : store_past) >> it) & 1u;
+                    const bool both = s.on && in_chunk && c >= 0 && c + 1 < P;
+                    const bool last = s.on && in_chunk && c == P - 1;
+                    if constexpr (POOL) {
+                        const uint32_t off2 = both ? (uint32_t)(s.img + c) * 8u : kOffNone;
+                        const uint32_t off1 = last ? (uint32_t)(s.img + c) * 8u : kOffNone;
+                        __builtin_amdgcn_raw_buffer_store_b128(
+                            u32x4{(uint32_t)w0, (uint32_t)(w0 >> 32), (uint32_t)w1,
+                                  (uint32_t)(w1 >> 32)},
+                            rout, off2, 0, STPOL);
+                        if (P & 1)   // only an odd row length leaves a single last word
+                            __builtin_amdgcn_raw_buffer_store_b64(
+                                u32x2{(uint32_t)w0, (uint32_t)(w0 >> 32)}, rout, off1, 0, STPOL);
+                    } else {
+                        uint64_t *dst = a.images + first * a.img_stride + s.img;
+                        if (both) {
+                            store_pair(dst + c, w0, w1);
+                        } else if (last) {
+                            dst[c] = w0;
+                        }
                     }
                 }
             }
@@ -585,8 +648,8 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch)
         // Rings start zeroed; then the bins of tile 0 go in.
         if (lane_used) {
             for (int c = 0; c < a.R; ++c) {
-                if (r0 < Q) slot_base[r0 * RS + c] = 0;
-                if (r1 < Q) slot_base[r1 * RS + c] = 0;
+                if (r0 < Q) slot_base[r0 * RS + c] = pix_zero<T>();
+                if (r1 < Q) slot_base[r1 * RS + c] = pix_zero<T>();
             }
         }
         // A chunk after the first starts from the exact state left by the
@@ -601,15 +664,25 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch)
                 }
             }
         }
-        u32x4 buf[NIT];
-        u32x4 prev[AL ? NIT : 1];      // aligned loads: the previous tile's lines
-        if constexpr (AL) load_tile(-1, prev);
-        load_tile(0, buf);
+        u32x4 buf[NIT * W];
+        // aligned loads: the previous tile's lines (16-byte pixels: its
+        // first pixel per lane, the only one that can be held)
+        u32x4 prev[AL ? NIT : 1];
+        if constexpr (AL && W == 1) load_tile(-1, prev);
+        if constexpr (AL && W == 2) {
+            u32x4 first[NIT * W];
+            load_tile(-1, first);
+            load_tile(0, buf);
+#pragma unroll
+            for (int it = 0; it < NIT; ++it) prev[it] = first[it * W];
+        } else {
+            load_tile(0, buf);
+        }
         wave_sync();
         stage_tile(0, buf, prev);
         if constexpr (AL) {
 #pragma unroll
-            for (int it = 0; it < NIT; ++it) prev[it] = buf[it];
+            for (int it = 0; it < NIT; ++it) prev[it] = buf[it * W];
         }
         load_tile(1, buf);
 
@@ -634,11 +707,11 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch)
         };
         // Stages tile t+1 from `cur`, which then takes the loads of tile
         // t+1+ahead.
-        auto advance = [&](int t, u32x4 (&cur)[NIT], int ahead) {
+        auto advance = [&](int t, u32x4 (&cur)[NIT * W], int ahead) {
             stage_tile(t + 1, cur, prev);
             if constexpr (AL) {
 #pragma unroll
-                for (int it = 0; it < NIT; ++it) prev[it] = cur[it];
+                for (int it = 0; it < NIT; ++it) prev[it] = cur[it * W];
             }
             load_tile(t + 1 + ahead, cur);
             wave_sync();
@@ -646,7 +719,7 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch)
         if constexpr (DEEP) {
             // Two tiles of loads in flight: the two buffers take turns (a
             // copy between them would wait for the younger loads).
-            u32x4 buf2[NIT];
+            u32x4 buf2[NIT * W];
             load_tile(2, buf2);
             wave_sync();
             for (int t = 0; t < ntiles_wave; t += 2) {
@@ -683,12 +756,13 @@ constexpr int full_slots() { return kWave / ((Q + 1) / 2); }
 template <int Q>
 constexpr int half_slots() { return kWave / ((Q + 1) / 2) >= 2 ? kWave / ((Q + 1) / 2) / 2 : 1; }
 
-template <int Q, int TW, bool POOL, int CHUNK, int NBT, bool ALIGN = false, bool RCLS = false>
+template <int Q, int TW, bool POOL, int CHUNK, int NBT, bool ALIGN = false, bool RCLS = false,
+          int W = 1>
 __global__ __launch_bounds__(kWave) void decode_kernel(DecodeArgs a) {
     const int64_t per = CHUNK == kWhole ? 1 : a.chunk.nchunks - 1;
     const int64_t nbatches = (a.nblocks * per + a.nb - 1) / a.nb;
     for (int64_t batch = blockIdx.x; batch < nbatches; batch += gridDim.x)
-        decode_batch<Q, TW, POOL, CHUNK, NBT, DecodeArgs, kStreamPolicy, false, ALIGN, RCLS>(
+        decode_batch<Q, TW, POOL, CHUNK, NBT, DecodeArgs, kStreamPolicy, false, ALIGN, RCLS, W>(
             a, batch);
 }
 
@@ -965,6 +1039,23 @@ static hipError_t launch_chunk(int mode, const DecodeArgs &a, int grid, hipStrea
             break;
         default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+// 16-byte pixels (whole blocks from a pool): the body compiled for half the
+// slots (the full one would need twice the row-window registers), with
+// whole-line loads when a.align is set.
+template <int Q>
+static hipError_t launch_wide_q(const DecodeArgs &a, int grid, hipStream_t s) {
+    constexpr int NBT = half_slots<Q>();
+    if (a.nb > NBT) return hipErrorInvalidValue;
+    const size_t lds = 2 * decode_lds_bytes(Q, a.nb, a.ring_stride);
+    if (a.align)
+        hipLaunchKernelGGL((decode_kernel<Q, kDecodeTile, true, kWhole, NBT, true, false, 2>),
+                           dim3(grid), dim3(kWave), lds, s, a);
+    else
+        hipLaunchKernelGGL((decode_kernel<Q, kDecodeTile, true, kWhole, NBT, false, false, 2>),
+                           dim3(grid), dim3(kWave), lds, s, a);
     return hipGetLastError();
 }
 

@@ -183,7 +183,6 @@ struct DecodeArgs {
     int32_t P, n;
     int32_t R, ring_stride;          // ring length (power of two), words per LDS ring row
     int32_t nb;                      // blocks per wavefront (at most 64/ceil(Q/2), fewer if LDS is short)
-    int32_t bin_swap;                // 1: bin j is stored at word j ^ 1 (128-bit pixels), else 0
     int32_t p_sorted[kMaxDirs];      // directions in ascending p
     int32_t id_sorted[kMaxDirs];     // their indices in the caller's dirs
     ChunkInfo chunk;                 // chunked launches only
@@ -212,7 +211,6 @@ struct DecodeClass {
     int64_t img_stride;
     int32_t P, Q, n, nb, R, ring_stride;
     uint32_t mask_uniform;
-    int32_t bin_swap;                // always 0: mixed launches take 64-bit pixels
     int32_t off[kMaxDirs];
     int16_t p_sorted[kMaxDirs];
     int8_t id_sorted[kMaxDirs];
@@ -272,6 +270,9 @@ hipError_t launch_decode_classes(unsigned qmask, bool gather, const DecodeClassT
                                  size_t lds, int grid, hipStream_t s);
 bool decode_classes_supported(unsigned qmask, bool gather);
 hipError_t launch_decode(int Q, int mode, const DecodeArgs &a, int grid, hipStream_t s);
+// Whole blocks of 16-byte pixels from a pool (P, p, offsets and strides in
+// pixels; a.nb at most half the full slot count).
+hipError_t launch_decode_wide(int Q, const DecodeArgs &a, int grid, hipStream_t s);
 // State width E and transfer matrix (Q*E rows of ceil(Q*E/64) words) of an
 // interior chunk of `tiles` tiles for the survivor directions ps[0..Q) in
 // ascending order.  False if chunks that short cannot be interior.
