@@ -192,6 +192,13 @@ struct SegParam {
 // RCLS: the launch sweeps one ring class only (a.ring_mode, see below).  A
 // separate instantiation, so that launches over every block carry none of
 // its code (with it, they measured up to 30% slower).
+//
+// W: words per pixel.  W = 2 sweeps 128-bit pixels (Section 3.1) in the
+// 16-byte image's own geometry: ring slots, bins and pixels of 16 bytes,
+// P, strides and offsets counted in pixels.  A lane of a row window then
+// moves the pixels of columns c and c - TW/2, so each memory instruction
+// covers TW/2 consecutive pixels (a 128-byte line when aligned).  Whole-
+// block pool sweeps only.
 template <int Q, int TW, bool POOL, int CHUNK, int NBT, class Args, int STPOL = kStreamPolicy,
           bool SYS = false, bool ALIGN = false, bool RCLS = false, int W = 1>
 __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch) {
