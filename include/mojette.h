@@ -204,21 +204,20 @@ int mojette_decode_batch_trimmed(const uint64_t *projs, const uint16_t *erased, 
  * mojette_decode_batch_sys: rebuilds, in place in `images`, every lost line
  *   of every block; surviving lines are read and never written, and a block
  *   that lost no line is not touched (its read is the lines themselves).
- *   Lost lines are rebuilt from the surviving parity projections: the
- *   surviving lines' pixels are removed from the bins (a residual pass into
- *   `workspace`), then the lost lines are peeled in the order of Section 2.2
- *   (the r-th lost line from the r-th surviving projection in ascending p).
+ *   Lost lines are rebuilt from the surviving parity projections and the
+ *   surviving lines, peeled in the order of Section 2.2 (the r-th lost line
+ *   from the r-th surviving projection in ascending p; the surviving lines'
+ *   pixels on a bin's line are read from `images` as the sweep goes).
  *     images     device, nblocks x Q x P words, in/out.
  *     parity     device, the parity pool, read only.
  *     erased     device, nblocks uint16 masks (bit i = packet i lost); NULL
  *                means nothing lost (no-op).
- *     workspace  device, mojette_sys_workspace() words, owned by the caller;
- *                no contents are kept between calls.
+ *     workspace  unused (the decode needs none; may be NULL).
  *     status     as for mojette_decode_batch: a block that lost more lines
  *                than it has surviving parity projections is left as it is
  *                and MOJETTE_ENOTRECON is stored.
- * mojette_sys_workspace: words of workspace for nblocks blocks, -1 on bad
- *   arguments.
+ * mojette_sys_workspace: words of workspace for nblocks blocks (0), -1 on
+ *   bad arguments.
  */
 int mojette_encode_batch_sys(const uint64_t *images, int64_t nblocks, int32_t P, int32_t Q,
                              const int32_t *pdirs, int32_t m, uint64_t *parity, void *stream);

@@ -393,14 +393,15 @@ def mojette_sys_workspace(pdirs, P: int, Q: int, nblocks: int) -> int:
 
 
 def mojette_decode_batch_sys(images, parity, erased, nblocks: int, P: int, Q: int, pdirs,
-                             workspace, status=None, stream=None, check: bool = True) -> int:
-    """Systematic code: rebuild every lost data line in place in ``images``."""
+                             workspace=None, status=None, stream=None, check: bool = True) -> int:
+    """Systematic code: rebuild every lost data line in place in ``images``
+    (``workspace`` is unused and may be None)."""
     arr, m = _i32_array(pdirs)
     er, st = _decode_masks(erased, status)
+    ws = _word_tensor(workspace, "workspace") if workspace is not None else None
     rc = lib().mojette_decode_batch_sys(_word_tensor(images, "images"),
                                         _word_tensor(parity, "parity"), er, nblocks, P, Q, arr,
-                                        m, _word_tensor(workspace, "workspace"), st,
-                                        _stream(stream))
+                                        m, ws, st, _stream(stream))
     return _check(rc, "mojette_decode_batch_sys", check)
 
 

@@ -15,8 +15,8 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmojette.so")
 SOURCES = ["api.hip", "chunk.hip", "encode.hip", "decode_single.hip", "decode_single_hi.hip",
-           "decode_classes.hip", "decode_chunks.hip", "decode_sys.hip", "decode_wide.hip", "mlp.hip",
-           "synth.hip"]
+           "decode_classes.hip", "decode_chunks.hip", "decode_sys.hip", "decode_sys_hi.hip",
+           "decode_wide.hip", "mlp.hip", "synth.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

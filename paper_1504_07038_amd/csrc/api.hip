@@ -230,11 +230,15 @@ int ring_length(const std::vector<int> &sorted_p, int Q, int *common = nullptr,
 // Ring length of the systematic decode: as ring_length, over every set of
 // lost lines (1 to m of the Q) and every choice of as many parity
 // directions, with the sweep rows at the lost lines' image rows (A of the
-// next lost line: A + 2 (its row - this row) p + 1).  -1 if a pixel would
-// be read before it is written (the ordering argument rules it out).
-int ring_length_sys(const std::vector<int> &sorted_p, int Q) {
+// next lost line: A + 2 (its row - this row) p + 1).  A known line l is read
+// by sweep row r at offset d_r + (l - m_r) p_r from the tile's first column
+// (d_r = -floor((A_max - A_r)/2)); its windows are staged at the largest of
+// those offsets, so the ring also spans their spread, and *lead tiles of it
+// are staged before the sweep starts.  -1 if a pixel would be read before
+// it is written (the ordering argument rules it out).
+int ring_length_sys(const std::vector<int> &sorted_p, int Q, int *lead) {
     const int m = (int)sorted_p.size();
-    int Dmax = 0;
+    int Dmax = 0, spread = 0;
     bool ok = true;
     for (uint32_t lines = 1; lines < (1u << Q); ++lines) {
         const int e = __builtin_popcount(lines);
@@ -258,11 +262,24 @@ int ring_length_sys(const std::vector<int> &sorted_p, int Q) {
                     if (D < 0) ok = false;
                     Dmax = std::max(Dmax, D);
                 }
+            const int A_max = *std::max_element(A.begin(), A.end());
+            for (int l = 0; l < Q; ++l) {
+                if ((lines >> l) & 1u) continue;
+                int lo = INT32_MAX, hi = INT32_MIN;
+                for (int r = 0; r < e; ++r) {
+                    const int o = -((A_max - A[r]) >> 1) + (l - rows[r]) * p[r];
+                    lo = std::min(lo, o);
+                    hi = std::max(hi, o);
+                }
+                spread = std::max(spread, hi - lo);
+            }
         }
     }
     if (!ok) return -1;
-    int R = 2 * mj::kDecodeTile;
-    while (R < mj::kDecodeTile + Dmax + 1) R <<= 1;
+    const int TW = mj::kDecodeTile;
+    *lead = (spread + TW - 1) / TW;
+    int R = 2 * TW;
+    while (R < TW + Dmax + 1 || R < TW + spread || R < (*lead + 1) * TW) R <<= 1;
     return R;
 }
 
@@ -727,7 +744,7 @@ static bool sys_geometry_ok(const int32_t *pdirs, int32_t m, int32_t P, int32_t 
 int64_t mojette_sys_workspace(const int32_t *pdirs, int32_t m, int32_t P, int32_t Q,
                               int64_t nblocks) {
     if (nblocks < 0 || !sys_geometry_ok(pdirs, m, P, Q)) return -1;
-    return nblocks * mojette_block_words(pdirs, m, P, Q);
+    return 0;   // the decode needs none
 }
 
 int mojette_encode_batch_sys(const uint64_t *images, int64_t nblocks, int32_t P, int32_t Q,
@@ -739,11 +756,12 @@ int mojette_encode_batch_sys(const uint64_t *images, int64_t nblocks, int32_t P,
 int mojette_decode_batch_sys(uint64_t *images, const uint64_t *parity, const uint16_t *erased,
                              int64_t nblocks, int32_t P, int32_t Q, const int32_t *pdirs,
                              int32_t m, uint64_t *workspace, int32_t *status, void *stream) {
+    (void)workspace;   // not needed: the sweep reads the surviving lines itself
     if (nblocks < 0 || !sys_geometry_ok(pdirs, m, P, Q)) return MOJETTE_EINVAL;
     if (nblocks == 0 || !erased) return MOJETTE_OK;   // nothing lost: the lines are the data
-    if (!images || !parity || !workspace) return MOJETTE_EINVAL;
+    if (!images || !parity) return MOJETTE_EINVAL;
 
-    // the sweep: rows = lost lines (at most m), projections = parity
+    // the sweep: rows = the Q lines (the lost ones swept), projections = parity
     mj::DecodeArgs a{};
     std::vector<int> order(m), sp(m);
     for (int i = 0; i < m; ++i) order[i] = i;
@@ -754,23 +772,28 @@ int mojette_decode_batch_sys(uint64_t *images, const uint64_t *parity, const uin
         sp[s] = pdirs[order[s]];
     }
     static std::mutex mu;
-    static std::map<RingKey, int> cache;
-    int R;
+    static std::map<RingKey, std::pair<int, int>> cache;   // ring length, lead tiles
+    std::pair<int, int> rl;
     {
         std::lock_guard<std::mutex> g(mu);
         RingKey key{sp, Q};
         auto it = cache.find(key);
-        R = it != cache.end() ? it->second : (cache[key] = ring_length_sys(sp, Q));
+        if (it != cache.end()) {
+            rl = it->second;
+        } else {
+            int lead = 0;
+            const int R = ring_length_sys(sp, Q, &lead);
+            rl = cache[key] = {R, lead};
+        }
     }
-    if (R < 0) return MOJETTE_EINVAL;
-    a.R = R;
-    a.ring_stride = R + 1;
-    a.nb = mj::decode_max_blocks_per_wave(m);
-    if (mj::decode_lds_bytes(m, a.nb, a.ring_stride) > kDecodeLdsShare) {
-        a.nb = std::max(1, a.nb / 2);
-        while (a.nb > 1 && mj::decode_lds_bytes(m, a.nb, a.ring_stride) > kDecodeLdsLong) --a.nb;
-    }
-    if (mj::decode_lds_bytes(m, a.nb, a.ring_stride) > kLdsLimit) return MOJETTE_ENOTSUP;
+    if (rl.first < 0) return MOJETTE_EINVAL;
+    a.R = rl.first;
+    a.ring_stride = rl.first + 1;
+    a.sys_lead = rl.second;
+    // the kernels are compiled for half the slots
+    a.nb = std::min(default_blocks(Q, a.ring_stride),
+                    std::max(1, mj::decode_max_blocks_per_wave(Q) / 2));
+    if (mj::decode_lds_bytes(Q, a.nb, a.ring_stride) > kLdsLimit) return MOJETTE_ENOTSUP;
     int64_t off = 0;
     for (int i = 0; i < m; ++i) {
         a.off[i] = (int32_t)off;
@@ -781,8 +804,7 @@ int mojette_decode_batch_sys(uint64_t *images, const uint64_t *parity, const uin
         return MOJETTE_ENOTSUP;
     a.P = P;
     a.n = m;
-    a.sys_rows = Q;
-    a.pool = workspace;
+    a.pool = parity;
     a.proj_stride = off;
     a.images = images;
     a.img_stride = (int64_t)P * Q;
@@ -790,28 +812,10 @@ int mojette_decode_batch_sys(uint64_t *images, const uint64_t *parity, const uin
     a.mask_uniform = 0;
     a.status = status;
     a.nblocks = nblocks;
-
-    // the residual pass: parity bins with the surviving lines removed
-    mj::ResidArgs r{};
-    if (!encode_tiling(pdirs, m, P, Q, r)) return MOJETTE_ENOTSUP;
-    r.images = images;
-    for (int i = 0; i < m; ++i) {
-        r.out[i] = workspace + a.off[i];
-        r.par[i] = parity + a.off[i];
-    }
-    r.proj_stride = off;
-    r.nblocks = nblocks;
-    r.masks = erased;
-    for (int s = 0; s < m; ++s) r.id_sorted[s] = a.id_sorted[s];
-
-    const int64_t items = nblocks * r.ntiles;
-    const int egrid = (int)std::min<int64_t>((items + r.waves - 1) / r.waves, kEncodeGridCap);
     const int64_t batches = (nblocks + a.nb - 1) / a.nb;
-    const int dgrid = (int)std::min<int64_t>(batches, kDecodeGridCap);
+    const int grid = (int)std::min<int64_t>(batches, kDecodeGridCap);
     clear_stale_error();
-    const int rc = status_of(mj::launch_resid(r, egrid, (hipStream_t)stream));
-    if (rc != MOJETTE_OK) return rc;
-    return status_of(mj::launch_decode_sys(m, a, dgrid, (hipStream_t)stream));
+    return status_of(mj::launch_decode_sys(Q, a, grid, (hipStream_t)stream));
 }
 
 // ---- chunked decode of long rows -------------------------------------------

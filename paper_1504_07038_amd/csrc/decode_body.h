@@ -146,6 +146,7 @@ struct SegParam {
     int img;       // word offset (in the wave's image slice) of the segment's row
     const uint64_t *bins;   // pointer mode: the row's projection
     bool on;       // segment belongs to a block slot in use
+    bool known;    // systematic code: a surviving line (staged from the image, not stored)
 };
 
 // One batch of up to nb blocks of one geometry, swept by one wavefront.  `A`
@@ -170,18 +171,19 @@ struct SegParam {
 // non-temporal; 0: default).
 //
 // SYS: the systematic code (DecodeArgs only, whole blocks, pool mode).  A
-// block is a.sys_rows data lines stored as they are plus a.n parity
-// projections (mask bits 0..sys_rows-1 lines, then projections).  The lost
-// lines, in ascending order, are the sweep rows (Q = the most that can be
-// lost); the pool holds the parity bins with the surviving lines' pixels
-// already removed (residual bins), so the sweep involves the lost lines
-// only.  The r-th lost line m_r takes the r-th surviving projection in
-// ascending p, and A_{r+1} = A_r + 2 (m_{r+1} - m_r) p_r + 1, which keeps
-// every dependency strictly earlier: for l > r the gap is
+// block is Q data lines stored as they are (the image) plus a.n parity
+// projections in the pool (mask bits 0..Q-1 lines, then projections).  The
+// rows are the Q lines.  The lost ones, in ascending order, are swept: the
+// r-th lost line m_r takes the r-th surviving projection in ascending p, and
+// A_{r+1} = A_r + 2 (m_{r+1} - m_r) p_r + 1, which keeps every dependency on
+// another lost line strictly earlier: for l > r the gap is
 // sum 2 (m_{i+1} - m_i)(p_i - p_r) + (l - r) > 0, and for l < r it is at
 // least sum 2 (m_{i+1} - m_i)(p_r - p_i) - (r - l) >= (r - l)^2 > 0.  Rows
-// of consecutive sweep index still alternate in parity.
-//
+// of consecutive sweep index still alternate in parity.  The surviving
+// lines are known: their windows are staged into their rings from the image
+// instead of bins, so the sweep reads their pixels as it reads the lost
+// lines' (no pass removes them from the parity bins first).
+
 // ALIGN (pool mode): each row's bins are loaded as the 128-byte line where
 // the tile's window starts, and the words of that line that belong to the
 // next tile are kept in registers until then, so no line is fetched for two
@@ -241,9 +243,7 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch)
     T *slot_base = lds + (size_t)(lane_used ? slot : 0) * SS;
     const int r0 = 2 * j, r1 = 2 * j + 1;   // this lane's rows
     const int q = lane % LPS;
-    int QI = Q;                            // image rows (projection geometry)
-    if constexpr (SYS) QI = a.sys_rows;
-    const int QP = QI * P;
+    const int QP = Q * P;
 
     {
         const bool blk_ok = lane_used && blk < a.nblocks;
@@ -254,23 +254,28 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch)
         int p0 = 0, p1 = 0, id0 = 0, id1 = 0, A0 = 0, A1 = 0;
         int A_max = INT_MIN, A_min = INT_MAX, cnt = 0, psum = 0;
         uint32_t used = 0;
-        // Systematic code: sweep row r is image row arow[r], the r-th lost
-        // line; `nrows` sweep rows are in use.  Otherwise arow[r] = r.
-        int arow[Q];
+        // Systematic code: the rows are the block's lines.  The `nrows` lost
+        // ones are the sweep rows: sweep row s is line msw[s] (ascending)
+        // and takes the s-th surviving parity projection in ascending p
+        // (its p in psw[s], its A in Asw[s]).  The others are known: their
+        // rings are filled from the image, and they are never swept.
         int nrows = Q;
         uint32_t pbase = 0;                 // mask bit of projection 0
+        uint32_t lost = 0;
+        constexpr int QS = SYS ? Q : 1;
+        int msw[QS], Asw[QS], psw[QS];
         if constexpr (SYS) {
-            uint32_t lost = mask & ((1u << a.sys_rows) - 1u);
+            lost = mask & ((1u << Q) - 1u);
             nrows = __builtin_popcount(lost);
+            uint32_t rest = lost;
 #pragma unroll
             for (int r = 0; r < Q; ++r) {
-                arow[r] = lost ? __builtin_ctz(lost) : 0;
-                lost &= lost - 1u;
+                msw[r] = rest ? __builtin_ctz(rest) : 0;
+                rest &= rest - 1u;
+                Asw[r] = 0;
+                psw[r] = 0;
             }
-            pbase = a.sys_rows;
-        } else {
-#pragma unroll
-            for (int r = 0; r < Q; ++r) arow[r] = r;
+            pbase = Q;
         }
         int A_next = 0;                     // SYS: A of sweep row cnt
         for (int s = 0; s < a.n; ++s) {
@@ -280,16 +285,23 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch)
                 int A = 2 * psum + cnt;
                 if constexpr (SYS) {
                     A = A_next;
-                    int m_here = 0, m_next = 0;   // image rows of sweep rows cnt, cnt + 1
+                    int m_here = 0, m_next = 0;   // lines of sweep rows cnt, cnt + 1
 #pragma unroll
                     for (int r = 0; r < Q; ++r) {
-                        m_here = r == cnt ? arow[r] : m_here;
-                        m_next = r == cnt + 1 ? arow[r] : m_next;
+                        m_here = r == cnt ? msw[r] : m_here;
+                        m_next = r == cnt + 1 ? msw[r] : m_next;
+                        if (r == cnt) {
+                            Asw[r] = A;
+                            psw[r] = p;
+                        }
                     }
                     A_next = A + 2 * (m_next - m_here) * p + 1;
+                    if (m_here == r0) { p0 = p; id0 = id; A0 = A; }
+                    if (m_here == r1) { p1 = p; id1 = id; A1 = A; }
+                } else {
+                    if (cnt == r0) { p0 = p; id0 = id; A0 = A; }
+                    if (cnt == r1) { p1 = p; id1 = id; A1 = A; }
                 }
-                if (cnt == r0) { p0 = p; id0 = id; A0 = A; }
-                if (cnt == r1) { p1 = p; id1 = id; A1 = A; }
                 A_max = max(A_max, A);
                 A_min = min(A_min, A);
                 psum += p;
@@ -375,15 +387,22 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch)
         const int ntiles_wave = wave_max(ntiles);
 
         RowState<Q, T> X, Y;
-        const bool r0_is_x = ((r0 & 1) == par);
+        // Swept rows: every row, or (systematic code) the lost lines.  Row X
+        // of a lane is the one whose A has the parity of A_max (A_r = r mod
+        // 2 without the systematic code; with it, a lane's two lines are
+        // consecutive sweep rows when both are lost, so their A differ in
+        // parity).
+        const bool sw0 = SYS ? ((lost >> r0) & 1u) != 0 : r0 < nrows;
+        const bool sw1 = SYS ? r1 < Q && ((lost >> r1) & 1u) != 0 : r1 < nrows;
+        bool r0_is_x = ((r0 & 1) == par);
+        if constexpr (SYS) r0_is_x = sw0 ? (A0 & 1) == par : !(sw1 && (A1 & 1) == par);
         int jb0 = 0, jb1 = 0;   // bin index of column 0 for rows r0 and r1
-        int arow0 = r0, arow1 = r1;   // their image rows
         {
             const int rx = r0_is_x ? r0 : r1, ry = r0_is_x ? r1 : r0;
             const int px = r0_is_x ? p0 : p1, py = r0_is_x ? p1 : p0;
             const int Ax = r0_is_x ? A0 : A1, Ay = r0_is_x ? A1 : A0;
-            X.on = valid && rx < nrows;
-            Y.on = valid && ry < nrows;
+            X.on = valid && (r0_is_x ? sw0 : sw1);
+            Y.on = valid && (r0_is_x ? sw1 : sw0);
             X.ring = slot_base + (rx < Q ? rx : 0) * RS;
             Y.ring = slot_base + (ry < Q ? ry : 0) * RS;
 #pragma unroll
@@ -391,43 +410,36 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch)
                 const int lx = m + (m >= rx ? 1 : 0), ly = m + (m >= ry ? 1 : 0);
                 X.dep[m] = slot_base + (lx < Q ? lx : 0) * RS;
                 Y.dep[m] = slot_base + (ly < Q ? ly : 0) * RS;
-                if constexpr (SYS) {
-                    // image rows of the sweep rows involved (rows past
-                    // nrows are never written: their rings read zero)
-                    int mx = 0, my = 0, mlx = 0, mly = 0;
-#pragma unroll
-                    for (int r = 0; r < Q; ++r) {
-                        mx = r == rx ? arow[r] : mx;
-                        my = r == ry ? arow[r] : my;
-                        mlx = r == lx ? arow[r] : mlx;
-                        mly = r == ly ? arow[r] : mly;
-                    }
-                    X.delta[m] = (mlx - mx) * px;
-                    Y.delta[m] = (mly - my) * py;
-                } else {
-                    X.delta[m] = (lx - rx) * px;
-                    Y.delta[m] = (ly - ry) * py;
-                }
+                X.delta[m] = (lx - rx) * px;
+                Y.delta[m] = (ly - ry) * py;
             }
             X.d = X.on ? -((A_max - Ax) >> 1) : 0;       // (Ax - A_max)/2, exact
             Y.d = Y.on ? -((A_max - Ay - 1) >> 1) : 0;   // (Ay - A_max + 1)/2, exact
-            if constexpr (SYS) {
-                int m0 = 0, m1 = 0;
-#pragma unroll
-                for (int r = 0; r < Q; ++r) {
-                    m0 = r == r0 ? arow[r] : m0;
-                    m1 = r == r1 ? arow[r] : m1;
-                }
-                arow0 = m0;
-                arow1 = m1;
-            }
-            jb0 = arow0 * p0 - (bin_offset(p0, P, QI) + a.kept_first(id0));
-            jb1 = arow1 * p1 - (bin_offset(p1, P, QI) + a.kept_first(id1));
+            jb0 = r0 * p0 - (bin_offset(p0, P, Q) + a.kept_first(id0));
+            jb1 = r1 * p1 - (bin_offset(p1, P, Q) + a.kept_first(id1));
         }
 
         // Per-iteration row windows, from the lanes that own their rows.
-        const int dr0 = r0_is_x ? X.d : Y.d;     // first column of tile 0, unshifted
-        const int dr1 = r0_is_x ? Y.d : X.d;
+        int dr0 = r0_is_x ? X.d : Y.d;           // first column of tile 0, unshifted
+        int dr1 = r0_is_x ? Y.d : X.d;
+        // Systematic code: a known line l is read by sweep row s at columns
+        // t*TW + d_s + (l - msw[s]) psw[s] + i during tile t (i < TW), so its
+        // windows are staged at the furthest of those offsets; the ring
+        // (long enough for the spread of the offsets, with a.sys_lead tiles
+        // staged ahead of the sweep) keeps the nearest.
+        if constexpr (SYS) {
+            int k0 = INT_MIN, k1 = INT_MIN;
+#pragma unroll
+            for (int r = 0; r < Q; ++r) {
+                if (r < nrows) {
+                    const int ds = -((A_max - Asw[r]) >> 1);
+                    k0 = max(k0, ds + (r0 - msw[r]) * psw[r]);
+                    k1 = max(k1, ds + (r1 - msw[r]) * psw[r]);
+                }
+            }
+            if (!sw0) dr0 = k0;
+            if (!sw1) dr1 = k1;
+        }
         SegParam sp[NIT];
         uint32_t store_in = 0, store_past = 0;   // chunked sweeps: see first_last
         constexpr bool AL = POOL && ALIGN;
@@ -441,11 +453,19 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch)
                        (kLinePix - 1))
                : 0;
         {
-            // pool mode: word offset of column 0's bin within the wave's slice
-            const int g0 = POOL ? rel * (int)a.proj_stride + a.off[id0] + jb0 : jb0;
-            const int g1 = POOL ? rel * (int)a.proj_stride + a.off[id1] + jb1 : jb1;
-            const int own0 = valid && r0 < nrows ? dr0 : INT_MIN;
-            const int own1 = valid && r1 < nrows ? dr1 : INT_MIN;
+            // pool mode: word offset of column 0's bin within the wave's
+            // slice (a known line: of its column 0 in the image slice)
+            int g0 = POOL ? rel * (int)a.proj_stride + a.off[id0] + jb0 : jb0;
+            int g1 = POOL ? rel * (int)a.proj_stride + a.off[id1] + jb1 : jb1;
+            if constexpr (SYS) {
+                if (!sw0) g0 = rel * QP + r0 * P;
+                if (!sw1) g1 = rel * QP + r1 * P;
+            }
+            // rows whose windows are staged (and, unless known, stored)
+            const bool st0 = SYS ? r0 < Q : sw0, st1 = SYS ? r1 < Q : sw1;
+            const int own0 = valid && st0 ? dr0 : INT_MIN;
+            const int own1 = valid && st1 ? dr1 : INT_MIN;
+            const int known = SYS && valid ? (!sw0 ? 1 : 0) | (!sw1 ? 2 : 0) : 0;
             // pointer mode: the projections of this lane's two rows
             uint64_t pb0 = 0, pb1 = 0;
             if constexpr (!POOL) {
@@ -463,11 +483,7 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch)
                 const int src = owner < kWave ? owner : 0;
                 const int od0 = __shfl(own0, src), od1 = __shfl(own1, src);
                 const int og0 = __shfl(g0, src), og1 = __shfl(g1, src);
-                int orow = srow;                 // image row of the segment
-                if constexpr (SYS) {
-                    const int oa0 = __shfl(arow0, src), oa1 = __shfl(arow1, src);
-                    orow = (srow & 1) ? oa1 : oa0;
-                }
+                const int orow = srow;           // image row of the segment
                 int orel = sslot, oshift = 0;   // whole blocks: slot = block
                 if constexpr (CHUNK != kWhole) {
                     orel = __shfl(rel, src);
@@ -481,6 +497,11 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch)
                 const int sd = odd ? od1 : od0;
                 SegParam &s = sp[it];
                 s.on = sslot < NB && sd != INT_MIN;
+                s.known = false;
+                if constexpr (SYS) {
+                    const int okn = __shfl(known, src);
+                    s.known = s.on && ((okn >> (odd ? 1 : 0)) & 1);
+                }
                 const int dd = s.on ? sd : 0;
                 s.ring = (sslot < NB ? sslot : 0) * SS + srow * RS;
                 s.gbin = odd ? og1 : og0;
@@ -555,10 +576,23 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch)
                     const int cw = c + (AL ? s.mis : 0);     // column of word 2q
                     const bool in0 = s.on && (unsigned)cw < (unsigned)P;
                     const bool in1 = s.on && (unsigned)(cw - 1) < (unsigned)P;
-                    const uint32_t off0 = in0 ? (uint32_t)w * 8u : kOffNone;
-                    const uint32_t off1 = in1 ? (uint32_t)(w + 1) * 8u : kOffNone;
-                    const u32x2 w0 = __builtin_amdgcn_raw_buffer_load_b64(rin, off0, 0, 0);
-                    const u32x2 w1 = __builtin_amdgcn_raw_buffer_load_b64(rin, off1, 0, 0);
+                    const uint32_t off0 = in0 && !s.known ? (uint32_t)w * 8u : kOffNone;
+                    const uint32_t off1 = in1 && !s.known ? (uint32_t)(w + 1) * 8u : kOffNone;
+                    u32x2 w0 = __builtin_amdgcn_raw_buffer_load_b64(rin, off0, 0, 0);
+                    u32x2 w1 = __builtin_amdgcn_raw_buffer_load_b64(rin, off1, 0, 0);
+                    if constexpr (SYS) {
+                        // a known line's pixels from the image (words ascend
+                        // with the column); the other load of each pair is
+                        // disabled and reads zero
+                        const int wi = s.gbin + c;
+                        const bool k0 = in0 && s.known, k1 = in1 && s.known;
+                        const uint32_t oi0 = k0 ? (uint32_t)wi * 8u : kOffNone;
+                        const uint32_t oi1 = k1 ? (uint32_t)(wi - 1) * 8u : kOffNone;
+                        const u32x2 i0 = __builtin_amdgcn_raw_buffer_load_b64(rout, oi0, 0, 0);
+                        const u32x2 i1 = __builtin_amdgcn_raw_buffer_load_b64(rout, oi1, 0, 0);
+                        w0 = w0 | i0;
+                        w1 = w1 | i1;
+                    }
                     buf[it] = u32x4{w0.x, w0.y, w1.x, w1.y};
                 } else {
                     const uint64_t *bins = s.bins;
@@ -628,8 +662,9 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch)
                     bool in_chunk = true;
                     if constexpr (CHUNK != kWhole)
                         in_chunk = ((t < a.chunk.tiles ? store_in : store_past) >> it) & 1u;
-                    const bool both = s.on && in_chunk && c >= 0 && c + 1 < P;
-                    const bool last = s.on && in_chunk && c == P - 1;
+                    const bool put = s.on && !s.known && in_chunk;
+                    const bool both = put && c >= 0 && c + 1 < P;
+                    const bool last = put && c == P - 1;
                     if constexpr (POOL) {
                         const uint32_t off2 = both ? (uint32_t)(s.img + c) * 8u : kOffNone;
                         const uint32_t off1 = last ? (uint32_t)(s.img + c) * 8u : kOffNone;
@@ -675,6 +710,17 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch)
         // aligned loads: the previous tile's lines (16-byte pixels: its
         // first pixel per lane, the only one that can be held)
         u32x4 prev[AL ? NIT : 1];
+        // Systematic code: known lines are read up to a.sys_lead tiles
+        // behind their staged windows, so those tiles go in first (the
+        // swept rows' tiles before 0 lie before column 0 and stage zeros).
+        if constexpr (SYS) {
+            for (int tt = -a.sys_lead; tt < 0; ++tt) {
+                load_tile(tt, buf);
+                wave_sync();
+                stage_tile(tt, buf, prev);
+                wave_sync();
+            }
+        }
         if constexpr (AL && W == 1) load_tile(-1, prev);
         if constexpr (AL && W == 2) {
             u32x4 first[NIT * W];

@@ -1,5 +1,6 @@
 // Systematic-code decode launches: the lost data lines of every block rebuilt
-// from residual parity bins (the sweep of decode_body.h in its SYS form).
+// from the parity bins and the surviving lines (the sweep of decode_body.h in
+// its SYS form).
 #include "decode_body.h"
 
 namespace mj {
@@ -11,19 +12,20 @@ __global__ __launch_bounds__(kWave) void decode_sys_kernel(DecodeArgs a) {
         decode_batch<Q, kDecodeTile, true, kWhole, NBT, DecodeArgs, kStreamPolicy, true>(a, batch);
 }
 
+// The body compiled for half the slots (the full one spills: the known
+// lines' loads add to the row windows' registers).
 template <int Q>
 static hipError_t launch_sys_q(const DecodeArgs &a, int grid, hipStream_t s) {
-    constexpr int full = full_slots<Q>();
+    constexpr int half = half_slots<Q>();
+    if (a.nb > half) return hipErrorInvalidValue;
     const size_t lds = decode_lds_bytes(Q, a.nb, a.ring_stride);
-    if (full >= 2 && a.nb <= full / 2)
-        hipLaunchKernelGGL((decode_sys_kernel<Q, (full >= 2 ? full / 2 : 1)>), dim3(grid),
-                           dim3(kWave), lds, s, a);
-    else
-        hipLaunchKernelGGL((decode_sys_kernel<Q, full>), dim3(grid), dim3(kWave), lds, s, a);
+    hipLaunchKernelGGL((decode_sys_kernel<Q, half>), dim3(grid), dim3(kWave), lds, s, a);
     return hipGetLastError();
 }
 
-// Q: parity projections per block (the most lines that can be lost), 1..8.
+hipError_t launch_decode_sys_hi(int Q, const DecodeArgs &a, int grid, hipStream_t s);
+
+// Q: data lines per block, 1..15.
 hipError_t launch_decode_sys(int Q, const DecodeArgs &a, int grid, hipStream_t s) {
     switch (Q) {
         case 1: return launch_sys_q<1>(a, grid, s);
@@ -33,8 +35,7 @@ hipError_t launch_decode_sys(int Q, const DecodeArgs &a, int grid, hipStream_t s
         case 5: return launch_sys_q<5>(a, grid, s);
         case 6: return launch_sys_q<6>(a, grid, s);
         case 7: return launch_sys_q<7>(a, grid, s);
-        case 8: return launch_sys_q<8>(a, grid, s);
-        default: return hipErrorInvalidValue;
+        default: return launch_decode_sys_hi(Q, a, grid, s);
     }
 }
 

@@ -24,69 +24,45 @@ namespace mj {
 // column tile t, computed by one wavefront from its LDS tile.  `A` supplies
 // the geometry (EncodeArgs for one pool, EncodeClass for one class of a mixed
 // launch).
-//
-// RESID (A = ResidArgs): the residual pass of the systematic decode.  Lost
-// lines are staged as zeros, so a bin sums the surviving lines only; it is
-// XORed with the stored parity bin, which leaves the sum of the lost lines'
-// pixels on the bin's line.  Only the projections the decode reads (the
-// r-th surviving one in ascending p for the r-th lost line m_r) are
-// computed, and of those only the bins m_r*p - k, k in [0, P), it reads.
-template <int Q, class A, bool RESID, bool VERIFY = false>
+template <int Q, class A, bool VERIFY = false>
 __device__ __forceinline__ void encode_bins(const A &a, int64_t blk, int t, const uint64_t *tile,
-                                            int lane, uint32_t use, uint64_t row_of);
+                                            int lane, uint32_t use);
 
 // VERIFY (A = VerifyArgs): the bins of every surviving projection are
 // compared with the stored ones instead of being written.
-template <int Q, class A, bool RESID = false, bool VERIFY = false>
+template <int Q, class A, bool VERIFY = false>
 __device__ __forceinline__ void encode_item(const A &a, int64_t blk, int t, uint64_t *tile,
                                             int lane) {
     const int P = a.P, W = a.W, H = a.H, S = a.S;
     const int x0 = t * W;
     const uint64_t *img = a.images + blk * (int64_t)P * Q;
 
-    uint32_t lost = 0, use = 0;             // RESID: lost lines, projections read
-    uint64_t row_of = 0;                    // RESID: the lost line projection i serves, 4 bits each
-    if constexpr (RESID) {
-        const uint32_t mask = a.masks[blk];
-        lost = mask & ((1u << Q) - 1u);
-        if (!lost) return;                  // every line survived: nothing to rebuild
-        uint32_t left = lost;
-        for (int s = 0; s < a.n && left; ++s) {
-            const int id = a.id_sorted[s];
-            if ((mask >> (Q + id)) & 1u) continue;
-            use |= 1u << id;
-            row_of |= (uint64_t)__builtin_ctz(left) << (4 * id);
-            left &= left - 1u;
-        }
-        if (left) return;                   // too few projections: the decode reports it
-    }
+    uint32_t use = 0;                       // VERIFY: the projections checked
     if constexpr (VERIFY) {
         const uint32_t mask = a.masks ? a.masks[blk] : 0u;
         use = ~mask & ((1u << a.n) - 1u);
     }
 
-    // Stage image columns [x0 - H, x0 + W + H) of every row, zeros outside
-    // (and, RESID, zeros for the lost lines).
+    // Stage image columns [x0 - H, x0 + W + H) of every row, zeros outside.
 #pragma unroll
     for (int l = 0; l < Q; ++l) {
         const uint64_t *row = img + (int64_t)l * P;
-        const bool keep = !((lost >> l) & 1u);
         for (int c = lane; c < S; c += kWave) {
             const int col = x0 - H + c;
             uint64_t v = 0;
-            if (keep && (unsigned)col < (unsigned)P) v = row[col];
+            if ((unsigned)col < (unsigned)P) v = row[col];
             tile[l * S + c] = v;
         }
     }
     wave_sync();
-    encode_bins<Q, A, RESID, VERIFY>(a, blk, t, tile, lane, use, row_of);
+    encode_bins<Q, A, VERIFY>(a, blk, t, tile, lane, use);
 }
 
 // The bins of work item (blk, t) from the wave's staged LDS tile; ends with
 // the wave done reading the tile.
-template <int Q, class A, bool RESID, bool VERIFY>
+template <int Q, class A, bool VERIFY>
 __device__ __forceinline__ void encode_bins(const A &a, int64_t blk, int t, const uint64_t *tile,
-                                            int lane, uint32_t use, uint64_t row_of) {
+                                            int lane, uint32_t use) {
     const int P = a.P, W = a.W, H = a.H, S = a.S;
     const int x0 = t * W;
     // The bins whose row-0 crossing -b falls in [x0, x0 + W); the first tile
@@ -106,13 +82,6 @@ __device__ __forceinline__ void encode_bins(const A &a, int64_t blk, int t, cons
             if (!((use >> i) & 1u)) continue;
             src = a.par[i] + blk * a.proj_stride;
         }
-        if constexpr (RESID) {
-            if (!((use >> i) & 1u)) continue;
-            const int m = (int)((row_of >> (4 * i)) & 15u);
-            bh = min(bh, m * p);
-            bl = max(bl, m * p - P + 1);
-            src = a.par[i] + blk * a.proj_stride;
-        }
         uint64_t *dst = a.proj_in(i, slice);
         const int rstride = S + p;
         for (int b = bl + lane; b <= bh; b += kWave) {
@@ -123,7 +92,6 @@ __device__ __forceinline__ void encode_bins(const A &a, int64_t blk, int t, cons
                 if (v != src[b - bmin]) *a.status = MOJETTE_EINCONSISTENT;
                 continue;
             }
-            if constexpr (RESID) v ^= src[b - bmin];
             dst[(b - bmin) ^ a.bin_swap] = v;
         }
     }
@@ -174,7 +142,7 @@ __device__ __forceinline__ void encode_pipelined(const EncodeArgs &a, uint64_t *
         const int64_t blk = item / a.ntiles;
         const int t = (int)(item - blk * a.ntiles);
         if (item + nwaves < nitems) fetch(item + nwaves);
-        encode_bins<Q, EncodeArgs, false>(a, blk, t, tile, lane, 0, 0);
+        encode_bins<Q, EncodeArgs, false>(a, blk, t, tile, lane, 0);
     }
 }
 
@@ -208,23 +176,7 @@ __global__ __launch_bounds__(kWave *kEncodeWaves) void encode_kernel(EncodeArgs 
     }
 }
 
-// A mixed launch: items of every class, in the order of the class table
-// (heaviest items first), one wavefront per workgroup.
-template <int Q>
-__global__ __launch_bounds__(kWave *kEncodeWaves) void resid_kernel(ResidArgs a) {
-    extern __shared__ uint64_t lds[];
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wv = threadIdx.x >> 6;
-    uint64_t *tile = lds + (size_t)wv * Q * a.S;
-    const int64_t nitems = a.nblocks * a.ntiles;
-    const int64_t nwaves = (int64_t)gridDim.x * a.waves;
-    for (int64_t item = (int64_t)blockIdx.x * a.waves + wv; item < nitems; item += nwaves) {
-        const int64_t blk = item / a.ntiles;
-        const int t = (int)(item - blk * a.ntiles);
-        encode_item<Q, ResidArgs, true>(a, blk, t, tile, lane);
-    }
-}
-
+// The consistency check: every work item of every block, as the encode.
 template <int Q>
 __global__ __launch_bounds__(kWave *kEncodeWaves) void verify_kernel(VerifyArgs a) {
     extern __shared__ uint64_t lds[];
@@ -236,10 +188,12 @@ __global__ __launch_bounds__(kWave *kEncodeWaves) void verify_kernel(VerifyArgs 
     for (int64_t item = (int64_t)blockIdx.x * a.waves + wv; item < nitems; item += nwaves) {
         const int64_t blk = item / a.ntiles;
         const int t = (int)(item - blk * a.ntiles);
-        encode_item<Q, VerifyArgs, false, true>(a, blk, t, tile, lane);
+        encode_item<Q, VerifyArgs, true>(a, blk, t, tile, lane);
     }
 }
 
+// A mixed launch: items of every class, in the order of the class table
+// (heaviest items first), one wavefront per workgroup.
 template <int QMAX>
 __global__ __launch_bounds__(kWave) void encode_classes_kernel(EncodeClassTable tab) {
     extern __shared__ uint64_t lds[];
@@ -287,36 +241,6 @@ static hipError_t launch_q(const EncodeArgs &a, int grid, hipStream_t s) {
     hipLaunchKernelGGL(encode_kernel<Q>, dim3(grid), dim3(kWave * a.waves),
                        encode_lds_bytes(Q, a.S, a.waves), s, a);
     return hipGetLastError();
-}
-
-template <int Q>
-static hipError_t launch_resid_q(const ResidArgs &a, int grid, hipStream_t s) {
-    hipLaunchKernelGGL(resid_kernel<Q>, dim3(grid), dim3(kWave * a.waves),
-                       encode_lds_bytes(Q, a.S, a.waves), s, a);
-    return hipGetLastError();
-}
-
-// Data lines per block of the systematic code: 1..15 (the lines and the
-// parity projections share a 16-bit erasure mask).
-hipError_t launch_resid(const ResidArgs &a, int grid, hipStream_t s) {
-    switch (a.Q) {
-        case 1: return launch_resid_q<1>(a, grid, s);
-        case 2: return launch_resid_q<2>(a, grid, s);
-        case 3: return launch_resid_q<3>(a, grid, s);
-        case 4: return launch_resid_q<4>(a, grid, s);
-        case 5: return launch_resid_q<5>(a, grid, s);
-        case 6: return launch_resid_q<6>(a, grid, s);
-        case 7: return launch_resid_q<7>(a, grid, s);
-        case 8: return launch_resid_q<8>(a, grid, s);
-        case 9: return launch_resid_q<9>(a, grid, s);
-        case 10: return launch_resid_q<10>(a, grid, s);
-        case 11: return launch_resid_q<11>(a, grid, s);
-        case 12: return launch_resid_q<12>(a, grid, s);
-        case 13: return launch_resid_q<13>(a, grid, s);
-        case 14: return launch_resid_q<14>(a, grid, s);
-        case 15: return launch_resid_q<15>(a, grid, s);
-        default: return hipErrorInvalidValue;
-    }
 }
 
 template <int Q>

@@ -67,15 +67,6 @@ struct EncodeArgs {
     __device__ int kept_count(int i, int full) const { return keep_n[i] ? keep_n[i] : full; }
 };
 
-// Residual pass of the systematic decode: for every block with lost data
-// lines, the parity projections the decode will read, with the surviving
-// lines' pixels removed (XORed out), written at out[i] + blk*proj_stride.
-struct ResidArgs : EncodeArgs {
-    const uint64_t *par[kMaxDirs];   // parity projection i of block b: par[i] + b*proj_stride
-    const uint16_t *masks;           // bits 0..Q-1 lost lines, Q+i parity projection i lost
-    int32_t id_sorted[kMaxDirs];     // parity projections in ascending p
-};
-
 // Consistency check: every surviving projection recomputed from the image and
 // compared with the stored one (par[i] + b*proj_stride).
 struct VerifyArgs : EncodeArgs {
@@ -187,7 +178,7 @@ struct DecodeArgs {
     int32_t id_sorted[kMaxDirs];     // their indices in the caller's dirs
     ChunkInfo chunk;                 // chunked launches only
     int32_t keep_lo[kMaxDirs];       // projection i's first stored bin index (0: Eq. 2's first)
-    int32_t sys_rows;                // systematic decode: data lines per block (else unused)
+    int32_t sys_lead;                // systematic decode: tiles staged ahead of the sweep
     int32_t ring_mode;               // whole-block pool sweeps: 0 every block; 1 only blocks
                                      // whose survivor set's depth is <= ring_depth; 2 the others
     int32_t ring_depth;
@@ -261,7 +252,6 @@ size_t carry_lds_bytes(int state);
 bool carry_rows_in_registers(int state);
 
 hipError_t launch_encode(const EncodeArgs &a, int grid, hipStream_t s);
-hipError_t launch_resid(const ResidArgs &a, int grid, hipStream_t s);
 hipError_t launch_verify(const VerifyArgs &a, int grid, hipStream_t s);
 hipError_t launch_decode_sys(int Q, const DecodeArgs &a, int grid, hipStream_t s);
 hipError_t launch_encode_classes(int qmax, const EncodeClassTable &tab, size_t lds, int grid,
