@@ -27,6 +27,7 @@ constexpr int kMaxP = 1 << 24;                 // keeps every bin index inside i
 constexpr int kMaxAbsP = 1 << 16;
 constexpr int kEncodeGridCap = 256 * 64;       // workgroups; larger batches loop inside the kernel
 constexpr int kDecodeGridCap = 256 * 128;
+constexpr int kGatherRange = 256;              // blocks a deep-class wavefront scans (<= 512)
 constexpr int kMaxSysParity = 8;               // parity projections of the systematic code
 
 bool geometry_ok(const int32_t *dirs, int32_t n, int32_t P, int32_t Q) {
@@ -379,7 +380,9 @@ int launch_pool_whole(mj::DecodeArgs a, int Q, int nb_req, hipStream_t stream) {
         if ((int64_t)b.nb * b.proj_stride * 8 >= ((int64_t)1 << 31) ||
             (int64_t)b.nb * b.img_stride * 8 >= ((int64_t)1 << 31))
             return MOJETTE_ENOTSUP;
-        const int64_t batches = (b.nblocks + b.nb - 1) / b.nb;
+        // gathering launches: one wavefront per range of gather_range blocks
+        const int64_t per_wave = b.gather_range > 0 ? b.gather_range : b.nb;
+        const int64_t batches = (b.nblocks + per_wave - 1) / per_wave;
         const int grid = (int)std::min<int64_t>(batches, kDecodeGridCap);
         clear_stale_error();
         return status_of(mj::launch_decode(Q, mj::kLaunchPool, b, grid, stream));
@@ -412,8 +415,10 @@ int launch_pool_whole(mj::DecodeArgs a, int Q, int nb_req, hipStream_t stream) {
     pick_nb(m1);
     const int rc = go(m1);
     if (rc != MOJETTE_OK) return rc;
+    // the deep class is a few scattered blocks: gathered from ranges of 256
     a.ring_mode = 2;
     a.nb = pool_default_blocks(Q, a.ring_stride);
+    a.gather_range = kGatherRange;
     return go(a);
 }
 

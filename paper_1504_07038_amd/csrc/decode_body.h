@@ -136,14 +136,16 @@ __device__ __forceinline__ void sweep_pixel(const RowState<Q, T> &s,
 
 // Row window owned by one lane in store/load iteration `it`: segment
 // it*SPI + lane/LPS, words 2q, 2q+1 of the window, q = lane % LPS.
+// Offsets count pixels (words when W = 1).
 struct SegParam {
-    int ring;      // LDS word index of the segment's ring row (valid slots only)
-    int gbin;      // pool: word offset (in the wave's pool slice) of column 0's bin
+    int ring;      // LDS index of the segment's ring row (valid slots only)
+    int gbin;      // pool: offset (in the wave's pool slice) of column 0's bin;
+                   // systematic code, known line: of its column 0 in the image slice
                    // pointer mode: bin index of column 0 (jbase)
-    int col0;      // column of word 2q of the load window of tile 0
+    int col0;      // column of the lane's first word (pixel) of tile 0's load window
     int scol0;     // first column stored by this lane at tile 0 (window lag applied)
-    int mis;       // aligned loads: the row window's offset past a 128-byte line, in words
-    int img;       // word offset (in the wave's image slice) of the segment's row
+    int mis;       // aligned loads: the row window's offset past a 128-byte line
+    int img;       // offset (in the wave's image slice) of the segment's row
     const uint64_t *bins;   // pointer mode: the row's projection
     bool on;       // segment belongs to a block slot in use
     bool known;    // systematic code: a surviving line (staged from the image, not stored)
@@ -203,7 +205,10 @@ struct SegParam {
 // block pool sweeps only.
 template <int Q, int TW, bool POOL, int CHUNK, int NBT, class Args, int STPOL = kStreamPolicy,
           bool SYS = false, bool ALIGN = false, bool RCLS = false, int W = 1>
-__device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch) {
+__device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch,
+                                             const int64_t gather_blk = -1,
+                                             const int64_t gather_lo = 0,
+                                             const int64_t gather_hi = 0) {
     static_assert(W == 1 || (W == 2 && POOL && CHUNK == kWhole && !SYS && !RCLS),
                   "16-byte pixels: whole-block pool sweeps only");
     using T = PixT<W>;
@@ -228,16 +233,19 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch)
     int per = 1;                             // slots per block
     if constexpr (CHUNK != kWhole) per = a.chunk.nchunks - 1;
     const int64_t item = batch * NB + slot;
-    const int64_t blk = item / per;
+    // Gathered slots (ring class 2, see decode_deep_gather): the slot's block
+    // is given, within the wave's slice [gather_lo, gather_hi).
+    const bool gathered = RCLS && gather_blk >= 0;
+    const int64_t blk = gathered ? gather_blk : item / per;
     int chunk = 0, shift = 0;                // chunk index, its first column offset
     if constexpr (CHUNK != kWhole) {
         chunk = (int)(item - blk * per) + (CHUNK == kChunkC ? 1 : 0);
         shift = chunk * a.chunk.tiles * TW;
     }
-    const int64_t blk_lo = batch * NB / per;
+    const int64_t blk_lo = gathered ? gather_lo : batch * NB / per;
     const int rel = (int)(blk - blk_lo);
     const int RS = a.ring_stride;
-    const int SS = Q * RS + 1;              // words per block slot (odd)
+    const int SS = Q * RS + 1;              // pixels per block slot (odd)
     const int Rmask = a.R - 1;
     const int P = a.P;
     T *slot_base = lds + (size_t)(lane_used ? slot : 0) * SS;
@@ -246,7 +254,7 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch)
     const int QP = Q * P;
 
     {
-        const bool blk_ok = lane_used && blk < a.nblocks;
+        const bool blk_ok = lane_used && blk < (gathered ? gather_hi : a.nblocks);
         uint32_t mask = a.mask_uniform;
         if (blk_ok && a.masks) mask = a.masks[blk];
 
@@ -485,6 +493,11 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch)
                 const int og0 = __shfl(g0, src), og1 = __shfl(g1, src);
                 const int orow = srow;           // image row of the segment
                 int orel = sslot, oshift = 0;   // whole blocks: slot = block
+                if constexpr (RCLS) {
+                    // gathered slots: the owner's block, not the slot's index
+                    const int srel = __shfl(rel, src);
+                    if (gathered) orel = srel;
+                }
                 if constexpr (CHUNK != kWhole) {
                     orel = __shfl(rel, src);
                     oshift = __shfl(shift, src);
@@ -531,7 +544,8 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch)
 
         // Buffer descriptors of this wave's pool and image slices.
         const int64_t first = blk_lo;
-        const int64_t blk_hi = min(a.nblocks, (batch * NB + NB + per - 1) / per);
+        const int64_t blk_hi =
+            gathered ? gather_hi : min(a.nblocks, (batch * NB + NB + per - 1) / per);
         const int64_t nblk = blk_hi - first;
         __amdgpu_buffer_rsrc_t rin, rout;
         if constexpr (POOL) {
@@ -819,6 +833,88 @@ __global__ __launch_bounds__(kWave) void decode_kernel(DecodeArgs a) {
             a, batch);
 }
 
+// Ring class of block b for the whole-block pool sweeps split by ring
+// length: true when its survivor set reads more than a.ring_depth columns
+// behind a row's newest pixel (the depth rule of decode_batch), false for
+// the others and for undecodable blocks.
+template <int Q>
+__device__ __forceinline__ bool block_is_deep(const DecodeArgs &a, int64_t b) {
+    const uint32_t mask = a.masks ? a.masks[b] : a.mask_uniform;
+    int A[Q], pr[Q];
+    int cnt = 0, psum = 0;
+    for (int s = 0; s < a.n; ++s) {
+        const int id = a.id_sorted[s];
+        const int p = a.p_sorted[s];
+        if (!((mask >> id) & 1u) && cnt < Q) {
+#pragma unroll
+            for (int r = 0; r < Q; ++r) {
+                if (r == cnt) {
+                    A[r] = 2 * psum + cnt;
+                    pr[r] = p;
+                }
+            }
+            psum += p;
+            ++cnt;
+        }
+    }
+    if (cnt < Q) return false;
+    int depth = INT_MIN;
+#pragma unroll
+    for (int r = 0; r < Q; ++r)
+#pragma unroll
+        for (int l = 0; l < Q; ++l)
+            if (l != r) depth = max(depth, ceil_half(A[l] - A[r]) - 1 - (l - r) * pr[r]);
+    return depth > a.ring_depth;
+}
+
+constexpr int kGatherWords = 8;   // a gathering wavefront scans up to 8 x 64 blocks
+
+// The deep ring class (a.ring_mode 2), gathered: its blocks are few (13 of
+// the 495 survivor sets of the (12,8) code) and scattered, so instead of
+// sweeping batches of consecutive blocks, mostly empty, each wavefront scans
+// a.gather_range consecutive blocks for the class's members (one block per
+// lane and pass, ballot) and sweeps them a.nb at a time, every slot in use.
+template <int Q, int TW, int NBT>
+__global__ __launch_bounds__(kWave) void decode_deep_kernel(DecodeArgs a) {
+    constexpr int LPB = (Q + 1) / 2;
+    const int lane = threadIdx.x;
+    const int slot = lane / LPB;
+    const int SR = a.gather_range;
+    const int U = SR / kWave;
+    const int64_t nranges = (a.nblocks + SR - 1) / SR;
+    for (int64_t range = blockIdx.x; range < nranges; range += gridDim.x) {
+        const int64_t lo = range * SR, hi = min(a.nblocks, lo + SR);
+        uint64_t deep[kGatherWords];
+        int total = 0;
+#pragma unroll
+        for (int u = 0; u < kGatherWords; ++u) {
+            const int64_t b = lo + kWave * u + lane;
+            const bool d = u < U && b < hi && block_is_deep<Q>(a, b);
+            deep[u] = __ballot(d);
+            total += __popcll(deep[u]);
+        }
+        for (int base = 0; base < total; base += a.nb) {
+            const int idx = base + slot;
+            int64_t blk = hi;   // an empty slot
+            if (slot < a.nb && idx < total) {
+                int k = idx;
+#pragma unroll
+                for (int u = 0; u < kGatherWords; ++u) {
+                    const int c = __popcll(deep[u]);
+                    if (k >= 0 && k < c) {
+                        uint64_t m = deep[u];
+                        for (int i = 0; i < k; ++i) m &= m - 1;
+                        blk = lo + kWave * u + __builtin_ctzll(m);
+                    }
+                    k -= c;
+                }
+            }
+            decode_batch<Q, TW, true, kWhole, NBT, DecodeArgs, kStreamPolicy, false, false, true>(
+                a, 0, blk, lo, hi);
+        }
+    }
+}
+
 // Carry pass of the chunked decode.  For every block, with y_c the end state
 // of chunk c swept from a zero start (saved by the first sweep) and T the
 // transfer matrix of the block's survivor set, the exact start state of
@@ -1048,7 +1144,10 @@ static hipError_t launch_qn(int mode, const DecodeArgs &a, int grid, hipStream_t
                        dim3(kWave), lds, s, a)
             // the held words' registers leave room for 2 wavefronts per SIMD:
             // worth it only while the wavefront's slots are mostly in use
-            if (a.ring_mode != 0) {
+            if (a.ring_mode == 2 && a.gather_range > 0) {
+                hipLaunchKernelGGL((decode_deep_kernel<Q, kDecodeTile, NBT>), dim3(grid),
+                                   dim3(kWave), lds, s, a);
+            } else if (a.ring_mode != 0) {
                 if (kAlign && a.align && 2 * a.nb > NBT) MJ_POOL_LAUNCH(kAlign, true);
                 else MJ_POOL_LAUNCH(false, true);
             } else {

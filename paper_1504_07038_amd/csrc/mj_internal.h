@@ -183,6 +183,8 @@ struct DecodeArgs {
                                      // whose survivor set's depth is <= ring_depth; 2 the others
     int32_t ring_depth;
     int32_t align;                   // whole-block pool sweeps: whole-line loads where compiled
+    int32_t gather_range;            // ring_mode 2: blocks scanned per wavefront for members of
+                                     // the class (a multiple of 64), 0: every block in batches
     __device__ const uint64_t *proj_base(int64_t blk, int id) const {
         return pool ? pool + slots[blk] * proj_stride + off[id] : in[id];
     }

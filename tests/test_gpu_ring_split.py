@@ -91,3 +91,21 @@ def test_deep_shallow_and_mixed_batches(mj, n, Q, P, nb):
     mixed = np.array([by_depth[i][1] for i in rng.integers(0, len(by_depth), nb)],
                      dtype=np.uint16)
     run(mj, P, Q, dirs, mixed)
+
+
+def test_scattered_deep_blocks_at_range_edges(mj):
+    """The deep class is gathered from ranges of consecutive blocks: deep
+    blocks at the first and last positions of ranges, a dense cluster inside
+    one range, and the ragged last range, in a shallow batch."""
+    n, Q, P, nb = 12, 8, 128, 20000
+    dirs = synth.centered_dirs(n)
+    by_depth = masks_by_depth(dirs, Q)
+    shallow = [m for _, m in by_depth[:20]]
+    deep = [m for _, m in by_depth[-13:]]
+    masks = np.array([shallow[i % len(shallow)] for i in range(nb)], dtype=np.uint16)
+    at = [0, 1, 63, 64, 65, 127, 255, 256, 257, 511, 512, 767] + list(range(5000, 5030)) + \
+         [nb - 257, nb - 256, nb - 2, nb - 1]
+    for k, i in enumerate(at):
+        masks[i] = deep[k % len(deep)]
+    say(f"deep blocks at {len(at)} positions of {nb}")
+    run(mj, P, Q, dirs, masks)
