@@ -135,8 +135,8 @@ __device__ __forceinline__ void sweep_pixel(const RowState<Q, T> &s,
 }
 
 // Row window owned by one lane in store/load iteration `it`: segment
-// it*SPI + lane/LPS, words 2q, 2q+1 of the window, q = lane % LPS.
-// Offsets count pixels (words when W = 1).
+// it*SPI + lane/LPS, words 2q, 2q+1 of the window (16-byte pixels: pixels q
+// and q + TW/2), q = lane % LPS.  Offsets count pixels (words when W = 1).
 struct SegParam {
     int ring;      // LDS index of the segment's ring row (valid slots only)
     int gbin;      // pool: offset (in the wave's pool slice) of column 0's bin;
@@ -185,7 +185,7 @@ struct SegParam {
 // lines are known: their windows are staged into their rings from the image
 // instead of bins, so the sweep reads their pixels as it reads the lost
 // lines' (no pass removes them from the parity bins first).
-
+//
 // ALIGN (pool mode): each row's bins are loaded as the 128-byte line where
 // the tile's window starts, and the words of that line that belong to the
 // next tile are kept in registers until then, so no line is fetched for two
@@ -233,7 +233,7 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch,
     int per = 1;                             // slots per block
     if constexpr (CHUNK != kWhole) per = a.chunk.nchunks - 1;
     const int64_t item = batch * NB + slot;
-    // Gathered slots (ring class 2, see decode_deep_gather): the slot's block
+    // Gathered slots (ring class 2, see decode_deep_kernel): the slot's block
     // is given, within the wave's slice [gather_lo, gather_hi).
     const bool gathered = RCLS && gather_blk >= 0;
     const int64_t blk = gathered ? gather_blk : item / per;
