@@ -25,8 +25,12 @@ constexpr size_t kDecodeLdsLong = 26 * 1024;   // decode LDS per wavefront, long
 constexpr int64_t kScanWaveBudget = 1024;      // chunked decode: parallel carry below this many waves
 constexpr int kMaxP = 1 << 24;                 // keeps every bin index inside int32
 constexpr int kMaxAbsP = 1 << 16;
-constexpr int kEncodeGridCap = 256 * 64;       // workgroups; larger batches loop inside the kernel
-constexpr int kDecodeGridCap = 256 * 128;
+// Workgroups per launch; larger batches loop inside the kernel.  Measured on
+// 2^21 4 KB (6,4) blocks: the encode runs 5% faster with one work item per
+// wavefront (no loop) than with 2^14 workgroups, the decode 1% faster with
+// 2^16 workgroups (4 batches per wavefront at 2^15).
+constexpr int kEncodeGridCap = 1 << 19;
+constexpr int kDecodeGridCap = 1 << 16;
 constexpr int kGatherRange = 256;              // blocks a deep-class wavefront scans (<= 512)
 constexpr int kMaxSysParity = 8;               // parity projections of the systematic code
 
