@@ -127,6 +127,16 @@ bool encode_tiling(const int32_t *dirs, int32_t n, int32_t P, int32_t Q, mj::Enc
     int W = P;
     if ((size_t)(P + 2 * H) > cols_fit) W = (int)((cols_fit - 2 * H) / 64 * 64);
     if (max_w > 0 && W > max_w) W = max_w;
+    // Workgroups of several wavefronts whose tiles take more than 48 KB of
+    // LDS leave a CU two of them, 8 wavefronts; one wavefront per workgroup
+    // then keeps more resident.  Measured, 8 KB (12,8) blocks (13.6 KB
+    // tiles): one wavefront 2.31 ms, two 2.41, four 2.60; with smaller tiles
+    // four stay best (4 KB (6,4): 4.23 ms against 4.45 with two and 4.58
+    // with one; 16-byte pixels at P = 64: 4.49 against 4.65 with two).
+    {
+        const size_t tile = (size_t)Q * (W + 2 * H) * sizeof(uint64_t);
+        if ((size_t)waves * tile > 48 * 1024) waves = 1;
+    }
     a.waves = waves;
     a.W = W;
     a.H = H;
