@@ -431,7 +431,7 @@ def run_mixed(args):
         if sched[0] == "chunked":
             key = (tuple(d), Q, sched[1])
             if key not in plans:
-                plans[key] = mj.Plan(d, Q, sched[1])
+                plans[key] = mj.ChunkPlan(d, Q, sched[1])
             pl = plans[key]
             jd["plan"] = pl
             jd["workspace"] = torch.empty(max(1, pl.workspace_words(P, nb)), dtype=torch.int64,
@@ -559,7 +559,7 @@ def run_chunked(args):
     rows, ok_all = [], True
     for k, m, P, cols in ((4, 2, 32768, 256), (8, 4, 16384, 256)):
         dirs = synth.centered_dirs(k + m)
-        plan = mj.Plan(dirs, k, cols)
+        plan = mj.ChunkPlan(dirs, k, cols)
         for nb in (1, 256):
             words = mj.mojette_block_words(dirs, P, k)
             img = torch.empty(nb * P * k, dtype=torch.int64, device="cuda")

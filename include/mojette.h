@@ -250,6 +250,21 @@ int32_t mojette_decode_max_blocks_per_wave(const int32_t *dirs, int32_t n, int32
 int32_t mojette_decode_default_blocks_per_wave(const int32_t *dirs, int32_t n, int32_t P,
                                                int32_t Q);
 
+/* The launches mojette_decode_batch_tuned makes for nblocks blocks of this
+ * geometry (blocks_per_wave as there; 0 is mojette_decode_batch's own
+ * choice), computed on the host without launching anything.  Returns their
+ * number (1, or 2 when a large batch is split into ring classes) or a
+ * negative status (MOJETTE_EINVAL; MOJETTE_ENOTSUP when a wavefront's slice
+ * of the pools is beyond 32-bit byte offsets).  For launch t < cap, ring[t]
+ * receives its ring length in words, blocks[t] its blocks per wavefront and
+ * mode[t] what it sweeps: 0 every block, 1 the blocks whose survivor set
+ * fits the short ring, 2 the others (gathered from ranges of 256 blocks,
+ * which the split needs to address with 32-bit offsets; otherwise the batch
+ * is decoded in one launch).  Host arrays of cap entries, each may be NULL. */
+int32_t mojette_decode_batch_launches(const int32_t *dirs, int32_t n, int32_t P, int32_t Q,
+                                      int64_t nblocks, int32_t blocks_per_wave, int32_t *ring,
+                                      int32_t *blocks, int32_t *mode, int32_t cap);
+
 /*
  * Mixed batches: blocks of up to MOJETTE_MAX_CLASSES geometry classes (each
  * class: nblocks blocks of one P, Q and direction set) encoded or decoded in
@@ -303,7 +318,7 @@ int mojette_decode_classes(const mojette_class *classes, int32_t nclasses,
  * (MOJETTE_ENOTSUP otherwise); chunked jobs take any row count.  Same ownership, error and stream rules as the
  * batch calls; safe to record into a HIP graph.
  */
-typedef struct mojette_plan mojette_plan;   /* chunked decode, see below */
+typedef struct mojette_chunk_plan mojette_chunk_plan;   /* chunked decode, see below */
 
 typedef struct mojette_job {
     int32_t P, Q, n;
@@ -317,7 +332,7 @@ typedef struct mojette_job {
      * rows long enough to cut, the job's blocks are decoded in chunks (see
      * mojette_decode_batch_chunked) in launches of their own on the same
      * stream, using `workspace` (mojette_decode_chunked_workspace() words). */
-    const mojette_plan *plan;
+    const mojette_chunk_plan *plan;
     uint64_t *workspace;
 } mojette_job;
 
@@ -339,15 +354,15 @@ int mojette_decode_jobs(const mojette_job *jobs, int32_t njobs, int32_t *status,
  * Results are bit-identical to mojette_decode_batch.
  *
  * A plan holds the transfer matrices of every Q-subset of the directions for
- * one chunk length.  mojette_plan_create computes them on the host and
+ * one chunk length.  mojette_chunk_plan_create computes them on the host and
  * copies them to the current device: it allocates device memory and
  * synchronises, so it is not for use under graph capture.  It returns
  * MOJETTE_ENOTSUP if chunks of that length are shorter than the decode's
- * own lead-in.  mojette_plan_destroy frees the plan (NULL is a no-op).
+ * own lead-in.  mojette_chunk_plan_destroy frees the plan (NULL is a no-op).
  */
-int mojette_plan_create(const int32_t *dirs, int32_t n, int32_t Q, int32_t chunk_cols,
-                        mojette_plan **plan);
-int mojette_plan_destroy(mojette_plan *plan);
+int mojette_chunk_plan_create(const int32_t *dirs, int32_t n, int32_t Q, int32_t chunk_cols,
+                              mojette_chunk_plan **plan);
+int mojette_chunk_plan_destroy(mojette_chunk_plan *plan);
 
 /* Host only: the state width E (*state_cols) and transfer matrix of one
  * survivor set, directions p_sorted[0..Q) strictly ascending.  Row i of the
@@ -364,7 +379,8 @@ int64_t mojette_chunk_matrix(const int32_t *p_sorted, int32_t Q, int32_t chunk_c
  * P needs; 0 when P is too short to cut (the call then decodes whole
  * blocks).  It is non-decreasing in nblocks: a workspace sized for nblocks
  * serves every call on at most nblocks blocks.  -1 on bad arguments. */
-int64_t mojette_decode_chunked_workspace(const mojette_plan *plan, int32_t P, int64_t nblocks);
+int64_t mojette_decode_chunked_workspace(const mojette_chunk_plan *plan, int32_t P,
+                                         int64_t nblocks);
 
 /*
  * mojette_decode_batch with the plan's directions and row count, the sweep
@@ -373,7 +389,7 @@ int64_t mojette_decode_chunked_workspace(const mojette_plan *plan, int32_t P, in
  * caller, overwritten.  Three launches on `stream` (two when a block has
  * only two chunks); allocates nothing; safe to record into a HIP graph.
  */
-int mojette_decode_batch_chunked(const mojette_plan *plan, const uint64_t *projs,
+int mojette_decode_batch_chunked(const mojette_chunk_plan *plan, const uint64_t *projs,
                                  const uint16_t *erased, int64_t nblocks, int32_t P,
                                  uint64_t *images, int32_t *status, uint64_t *workspace,
                                  void *stream);

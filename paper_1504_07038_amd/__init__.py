@@ -63,7 +63,7 @@ class MojetteJob(ctypes.Structure):
 def make_jobs(jobs):
     """``jobs``: iterable of dicts with P, Q, dirs, nblocks, images, projs and
     optional slots (int64 device tensor), erased (int16 device tensor), plan
-    (a ``Plan``) and workspace (int64 device tensor)."""
+    (a ``ChunkPlan``) and workspace (int64 device tensor)."""
     jobs = list(jobs)
     arr = (MojetteJob * max(1, len(jobs)))()
     for c, j in enumerate(jobs):
@@ -145,13 +145,14 @@ def lib() -> ctypes.CDLL:
                                        ctypes.c_int),
         "mojette_decode_max_blocks_per_wave": ([vp, i32, i32, i32], i32),
         "mojette_decode_default_blocks_per_wave": ([vp, i32, i32, i32], i32),
+        "mojette_decode_batch_launches": ([vp, i32, i32, i32, i64, i32, vp, vp, vp, i32], i32),
         "mojette_classes_layout": ([vp, i32, vp, vp], ctypes.c_int),
         "mojette_encode_classes": ([vp, i32, vp, vp, vp], ctypes.c_int),
         "mojette_decode_classes": ([vp, i32, vp, vp, vp, vp, vp], ctypes.c_int),
         "mojette_encode_jobs": ([vp, i32, vp], ctypes.c_int),
         "mojette_decode_jobs": ([vp, i32, vp, vp], ctypes.c_int),
-        "mojette_plan_create": ([vp, i32, i32, i32, vp], ctypes.c_int),
-        "mojette_plan_destroy": ([vp], ctypes.c_int),
+        "mojette_chunk_plan_create": ([vp, i32, i32, i32, vp], ctypes.c_int),
+        "mojette_chunk_plan_destroy": ([vp], ctypes.c_int),
         "mojette_chunk_matrix": ([vp, i32, i32, vp, vp, i64], i64),
         "mojette_decode_chunked_workspace": ([vp, i32, i64], i64),
         "mojette_decode_batch_chunked": ([vp, vp, vp, i64, i32, vp, vp, vp, vp], ctypes.c_int),
@@ -195,10 +196,10 @@ def exported_symbols() -> list[str]:
         "mojette_trimmed_layout", "mojette_encode_batch_trimmed", "mojette_decode_batch_trimmed",
         "mojette_encode_batch_sys", "mojette_sys_workspace", "mojette_decode_batch_sys",
         "mojette_decode_batch_tuned", "mojette_decode_max_blocks_per_wave",
-        "mojette_decode_default_blocks_per_wave",
+        "mojette_decode_default_blocks_per_wave", "mojette_decode_batch_launches",
         "mojette_classes_layout", "mojette_encode_classes", "mojette_decode_classes",
-        "mojette_encode_jobs", "mojette_decode_jobs", "mojette_plan_create",
-        "mojette_plan_destroy", "mojette_chunk_matrix", "mojette_decode_chunked_workspace",
+        "mojette_encode_jobs", "mojette_decode_jobs", "mojette_chunk_plan_create",
+        "mojette_chunk_plan_destroy", "mojette_chunk_matrix", "mojette_decode_chunked_workspace",
         "mojette_decode_batch_chunked", "mojette_mlp_params", "mojette_mlp_forward",
         "mojette_mlp_grad_workspace", "mojette_mlp_grad", "mojette_mlp_adam",
         "mojette_fill_splitmix64", "mojette_copy_words",
@@ -426,6 +427,17 @@ def mojette_decode_max_blocks_per_wave(dirs, P: int, Q: int) -> int:
     return int(lib().mojette_decode_max_blocks_per_wave(arr, n, P, Q))
 
 
+def mojette_decode_batch_launches(dirs, P: int, Q: int, nblocks: int, blocks_per_wave: int = 0):
+    """The launches a batched decode makes, as (ring words, blocks per
+    wavefront, mode) per launch; raises on a negative status."""
+    arr, n = _i32_array(dirs)
+    ring, blocks, mode = (ctypes.c_int32 * 4)(), (ctypes.c_int32 * 4)(), (ctypes.c_int32 * 4)()
+    k = int(lib().mojette_decode_batch_launches(arr, n, P, Q, nblocks, blocks_per_wave, ring,
+                                                blocks, mode, 4))
+    _check(k if k < 0 else 0, "mojette_decode_batch_launches", True)
+    return [(ring[t], blocks[t], mode[t]) for t in range(k)]
+
+
 def mojette_decode_default_blocks_per_wave(dirs, P: int, Q: int) -> int:
     arr, n = _i32_array(dirs)
     return int(lib().mojette_decode_default_blocks_per_wave(arr, n, P, Q))
@@ -478,22 +490,22 @@ def mojette_decode_jobs(jobs, status=None, stream=None, check: bool = True) -> i
     return _check(rc, "mojette_decode_jobs", check)
 
 
-class Plan:
-    """``mojette_plan``: transfer matrices of the chunked decode for one code
+class ChunkPlan:
+    """``mojette_chunk_plan``: transfer matrices of the chunked decode for one code
     (directions, Q) and one chunk length.  Creating it allocates device memory
     and synchronises; ``close()`` (or garbage collection) frees it."""
 
     def __init__(self, dirs, Q: int, chunk_cols: int):
         arr, n = _i32_array(dirs)
         h = ctypes.c_void_p(0)
-        rc = lib().mojette_plan_create(arr, n, Q, chunk_cols, ctypes.addressof(h))
-        _check(rc, "mojette_plan_create", True)
+        rc = lib().mojette_chunk_plan_create(arr, n, Q, chunk_cols, ctypes.addressof(h))
+        _check(rc, "mojette_chunk_plan_create", True)
         self.handle = h.value
         self.dirs, self.Q, self.chunk_cols = [int(p) for p in dirs], int(Q), int(chunk_cols)
 
     def close(self) -> None:
         if self.handle:
-            lib().mojette_plan_destroy(self.handle)
+            lib().mojette_chunk_plan_destroy(self.handle)
             self.handle = None
 
     def __del__(self):
@@ -506,7 +518,7 @@ class Plan:
         return int(lib().mojette_decode_chunked_workspace(self.handle, P, nblocks))
 
 
-mojette_plan_create = Plan
+mojette_chunk_plan_create = ChunkPlan
 
 
 def mojette_chunk_matrix(p_sorted, Q: int, chunk_cols: int):
@@ -526,11 +538,11 @@ def mojette_chunk_matrix(p_sorted, Q: int, chunk_cols: int):
     return E.value, rows[:need].reshape(d, rw) if d else rows[:0].reshape(0, 0)
 
 
-def mojette_decode_chunked_workspace(plan: Plan, P: int, nblocks: int) -> int:
+def mojette_decode_chunked_workspace(plan: ChunkPlan, P: int, nblocks: int) -> int:
     return plan.workspace_words(P, nblocks)
 
 
-def mojette_decode_batch_chunked(plan: Plan, projs, erased, nblocks: int, P: int, images,
+def mojette_decode_batch_chunked(plan: ChunkPlan, projs, erased, nblocks: int, P: int, images,
                                  workspace, status=None, stream=None, check: bool = True) -> int:
     import torch
 

@@ -378,7 +378,11 @@ static int device_cus() {
 // taken only while, with the deep sets drawn uniformly, at most a quarter
 // of its batches would (the 128-bit (6,4) geometry, 1 deep set in 15 at 12
 // blocks per wavefront, ran 1,380 against 1,823 GB/s split).
-int launch_pool_whole(mj::DecodeArgs a, int Q, int nb_req, hipStream_t stream) {
+// The launches of a whole-block pool decode (see launch_pool_whole), in
+// order, without launching them.  MOJETTE_ENOTSUP when a wave's slice is
+// beyond 32-bit byte offsets even in one launch.
+int plan_pool_whole(mj::DecodeArgs a, int Q, int nb_req, std::vector<mj::DecodeArgs> &out) {
+    out.clear();
     auto pick_nb = [&](mj::DecodeArgs &b) {
         if (nb_req > 0) {
             b.nb = std::min(mj::decode_max_blocks_per_wave(Q), nb_req);
@@ -387,19 +391,19 @@ int launch_pool_whole(mj::DecodeArgs a, int Q, int nb_req, hipStream_t stream) {
             b.nb = pool_default_blocks(Q, b.ring_stride);
         }
     };
-    auto go = [&](mj::DecodeArgs b) {
+    // A wave addresses its slice of the pool and of the images (its nb
+    // blocks, or the gather_range blocks it scans) with 32-bit byte offsets.
+    auto slice_fits = [](const mj::DecodeArgs &b) {
+        const int64_t span = std::max<int64_t>(b.nb, b.gather_range);
+        return span * b.proj_stride * 8 < ((int64_t)1 << 31) &&
+               span * b.img_stride * 8 < ((int64_t)1 << 31);
+    };
+    auto add = [&](mj::DecodeArgs b) {
         // whole-line loads pay with the shortest rings only
         b.align = b.R == 2 * mj::kDecodeTile;
-        // a wave's slice of the pool and of the images: 32-bit byte offsets
-        if ((int64_t)b.nb * b.proj_stride * 8 >= ((int64_t)1 << 31) ||
-            (int64_t)b.nb * b.img_stride * 8 >= ((int64_t)1 << 31))
-            return MOJETTE_ENOTSUP;
-        // gathering launches: one wavefront per range of gather_range blocks
-        const int64_t per_wave = b.gather_range > 0 ? b.gather_range : b.nb;
-        const int64_t batches = (b.nblocks + per_wave - 1) / per_wave;
-        const int grid = (int)std::min<int64_t>(batches, kDecodeGridCap);
-        clear_stale_error();
-        return status_of(mj::launch_decode(Q, mj::kLaunchPool, b, grid, stream));
+        if (!slice_fits(b)) return MOJETTE_ENOTSUP;
+        out.push_back(b);
+        return MOJETTE_OK;
     };
     std::vector<int> sp(a.p_sorted, a.p_sorted + a.n);
     int common = -1;
@@ -414,11 +418,17 @@ int launch_pool_whole(mj::DecodeArgs a, int Q, int nb_req, hipStream_t stream) {
         const int64_t batches = (b.nblocks + b.nb - 1) / b.nb;
         const int nb2 = pool_default_blocks(Q, a.ring_stride);
         split = batches >= 2 * per_cu * device_cus() && 1.0 - std::pow(1.0 - deep, nb2) <= 0.25;
+        // the gathered launch's slices span kGatherRange blocks: blocks too
+        // large for 32-bit offsets over that span stay in one launch
+        mj::DecodeArgs g = a;
+        g.nb = nb2;
+        g.gather_range = kGatherRange;
+        if (!slice_fits(g)) split = false;
     }
     if (!split) {
         a.ring_mode = 0;
         pick_nb(a);
-        return go(a);
+        return add(a);
     }
     // the short ring serves sets whose depth is at most common - TW - 1
     a.ring_depth = common - mj::kDecodeTile - 1;
@@ -427,13 +437,29 @@ int launch_pool_whole(mj::DecodeArgs a, int Q, int nb_req, hipStream_t stream) {
     m1.ring_stride = common + 1;
     m1.ring_mode = 1;
     pick_nb(m1);
-    const int rc = go(m1);
+    const int rc = add(m1);
     if (rc != MOJETTE_OK) return rc;
     // the deep class is a few scattered blocks: gathered from ranges of 256
     a.ring_mode = 2;
     a.nb = pool_default_blocks(Q, a.ring_stride);
     a.gather_range = kGatherRange;
-    return go(a);
+    return add(a);
+}
+
+int launch_pool_whole(const mj::DecodeArgs &a, int Q, int nb_req, hipStream_t stream) {
+    std::vector<mj::DecodeArgs> launches;
+    const int rc = plan_pool_whole(a, Q, nb_req, launches);
+    if (rc != MOJETTE_OK) return rc;
+    for (const mj::DecodeArgs &b : launches) {
+        // gathering launches: one wavefront per range of gather_range blocks
+        const int64_t per_wave = b.gather_range > 0 ? b.gather_range : b.nb;
+        const int64_t batches = (b.nblocks + per_wave - 1) / per_wave;
+        const int grid = (int)std::min<int64_t>(batches, kDecodeGridCap);
+        clear_stale_error();
+        const int st = status_of(mj::launch_decode(Q, mj::kLaunchPool, b, grid, stream));
+        if (st != MOJETTE_OK) return st;
+    }
+    return MOJETTE_OK;
 }
 
 // Checks a class table and returns, per class, block words and pool offsets.
@@ -839,7 +865,7 @@ int mojette_decode_batch_sys(uint64_t *images, const uint64_t *parity, const uin
 
 // ---- chunked decode of long rows -------------------------------------------
 
-struct mojette_plan {
+struct mojette_chunk_plan {
     int32_t n, Q, tiles, max_cols, R, nsets;
     int32_t npow;            // matrices per set: T, T^2, ..., T^(2^(npow-1))
     int32_t dirs[MOJETTE_MAX_DIRS];
@@ -849,7 +875,7 @@ struct mojette_plan {
     uint64_t *tmat;          // device
 };
 
-static void plan_free(mojette_plan *pl) {
+static void plan_free(mojette_chunk_plan *pl) {
     if (!pl) return;
     if (pl->lut) (void)hipFree(pl->lut);
     if (pl->state_cols) (void)hipFree(pl->state_cols);
@@ -858,8 +884,8 @@ static void plan_free(mojette_plan *pl) {
     delete pl;
 }
 
-int mojette_plan_create(const int32_t *dirs, int32_t n, int32_t Q, int32_t chunk_cols,
-                        mojette_plan **plan) {
+int mojette_chunk_plan_create(const int32_t *dirs, int32_t n, int32_t Q, int32_t chunk_cols,
+                        mojette_chunk_plan **plan) {
     if (!plan) return MOJETTE_EINVAL;
     *plan = nullptr;
     if (!geometry_ok(dirs, n, 1, Q) || n < Q || chunk_cols < 1) return MOJETTE_EINVAL;
@@ -943,7 +969,7 @@ int mojette_plan_create(const int32_t *dirs, int32_t n, int32_t Q, int32_t chunk
     if (R < 0) return MOJETTE_EINVAL;
     while (R < max_cols + TW) R <<= 1;   // a chunk's start state and its first tile of bins
     if (tmat.empty()) tmat.push_back(0);
-    auto *pl = new (std::nothrow) mojette_plan{};
+    auto *pl = new (std::nothrow) mojette_chunk_plan{};
     if (!pl) return MOJETTE_ENOMEM;
     pl->n = n;
     pl->Q = Q;
@@ -988,18 +1014,18 @@ int64_t mojette_chunk_matrix(const int32_t *p_sorted, int32_t Q, int32_t chunk_c
     return (int64_t)T.size();
 }
 
-int mojette_plan_destroy(mojette_plan *plan) {
+int mojette_chunk_plan_destroy(mojette_chunk_plan *plan) {
     plan_free(plan);
     return MOJETTE_OK;
 }
 
-static int plan_chunks(const mojette_plan *pl, int32_t P) {
+static int plan_chunks(const mojette_chunk_plan *pl, int32_t P) {
     return std::max(1, (P / mj::kDecodeTile) / pl->tiles);
 }
 
 // Steps of the parallel carry over `per` chunk boundaries, or 0 when the
 // sequential carry runs (one boundary, or not enough powers in the plan).
-static int scan_steps(const mojette_plan *pl, int per, int64_t nblocks) {
+static int scan_steps(const mojette_chunk_plan *pl, int per, int64_t nblocks) {
     if (per < 2 || pl->npow < 2) return 0;
     int steps = 0;
     while ((1 << steps) < per) ++steps;
@@ -1012,7 +1038,7 @@ static int scan_steps(const mojette_plan *pl, int per, int64_t nblocks) {
     return nblocks * waves <= kScanWaveBudget ? steps : 0;
 }
 
-int64_t mojette_decode_chunked_workspace(const mojette_plan *plan, int32_t P, int64_t nblocks) {
+int64_t mojette_decode_chunked_workspace(const mojette_chunk_plan *plan, int32_t P, int64_t nblocks) {
     if (!plan || P < 1 || P > kMaxP || nblocks < 0) return -1;
     const int nchunks = plan_chunks(plan, P);
     if (nchunks < 2) return 0;
@@ -1027,7 +1053,7 @@ int64_t mojette_decode_chunked_workspace(const mojette_plan *plan, int32_t P, in
 
 // The three launches of a chunked decode of one geometry: `a` holds the
 // geometry and buffers (pool mode, or pointer mode with slots when gathering).
-static int chunked_launch(const mojette_plan *plan, int nchunks, mj::DecodeArgs &a, int Q,
+static int chunked_launch(const mojette_chunk_plan *plan, int nchunks, mj::DecodeArgs &a, int Q,
                           bool gather, uint64_t *workspace, hipStream_t s) {
     a.R = std::max(a.R, plan->R);
     a.ring_stride = a.R + 1;
@@ -1075,14 +1101,14 @@ static int chunked_launch(const mojette_plan *plan, int nchunks, mj::DecodeArgs 
                                        a, grid, s));
 }
 
-static bool plan_matches(const mojette_plan *plan, const int32_t *dirs, int32_t n, int32_t Q) {
+static bool plan_matches(const mojette_chunk_plan *plan, const int32_t *dirs, int32_t n, int32_t Q) {
     if (!plan || plan->n != n || plan->Q != Q) return false;
     for (int i = 0; i < n; ++i)
         if (plan->dirs[i] != dirs[i]) return false;
     return true;
 }
 
-int mojette_decode_batch_chunked(const mojette_plan *plan, const uint64_t *projs,
+int mojette_decode_batch_chunked(const mojette_chunk_plan *plan, const uint64_t *projs,
                                  const uint16_t *erased, int64_t nblocks, int32_t P,
                                  uint64_t *images, int32_t *status, uint64_t *workspace,
                                  void *stream) {
@@ -1170,6 +1196,30 @@ int32_t mojette_decode_default_blocks_per_wave(const int32_t *dirs, int32_t n, i
     mj::DecodeArgs a{};
     if (decode_setup(dirs, n, P, Q, a) != MOJETTE_OK) return -1;
     return pool_default_blocks(Q, main_ring_stride(a, Q));
+}
+
+int32_t mojette_decode_batch_launches(const int32_t *dirs, int32_t n, int32_t P, int32_t Q,
+                                      int64_t nblocks, int32_t blocks_per_wave, int32_t *ring,
+                                      int32_t *blocks, int32_t *mode, int32_t cap) {
+    if (nblocks < 1 || blocks_per_wave < 0 || cap < 0 || !geometry_ok(dirs, n, P, Q))
+        return MOJETTE_EINVAL;
+    mj::DecodeArgs a{};
+    const int rc = decode_setup(dirs, n, P, Q, a);
+    if (rc != MOJETTE_OK) return rc;
+    int64_t words = 0;
+    for (int i = 0; i < n; ++i) words += mojette_proj_size(dirs[i], P, Q);
+    a.proj_stride = words;
+    a.img_stride = (int64_t)P * Q;
+    a.nblocks = nblocks;
+    std::vector<mj::DecodeArgs> launches;
+    const int st = plan_pool_whole(a, Q, blocks_per_wave, launches);
+    if (st != MOJETTE_OK) return st;
+    for (int t = 0; t < (int)launches.size() && t < cap; ++t) {
+        if (ring) ring[t] = launches[t].R;
+        if (blocks) blocks[t] = launches[t].nb;
+        if (mode) mode[t] = launches[t].ring_mode;
+    }
+    return (int32_t)launches.size();
 }
 
 int mojette_classes_layout(const mojette_class *classes, int32_t nclasses, int64_t *image_words,
@@ -1392,7 +1442,7 @@ static int decode_jobs_chunked_merged(const mojette_job *jobs, const std::vector
         mj::DecodeChunkClass &d = tab.cls[k];
         int rc = decode_setup(j.dirs, j.n, j.P, j.Q, d);
         if (rc != MOJETTE_OK) return rc;
-        const mojette_plan *pl = j.plan;
+        const mojette_chunk_plan *pl = j.plan;
         d.R = std::max(d.R, pl->R);
         d.ring_stride = d.R + 1;
         d.nb = std::max(1, mj::decode_max_blocks_per_wave(j.Q) / 2);

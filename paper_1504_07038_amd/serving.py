@@ -222,7 +222,7 @@ class Server:
             if chunk_min_P and g.P >= chunk_min_P:
                 key = (tuple(g.dirs), g.Q)
                 if key not in self.plans:
-                    self.plans[key] = mj.Plan(g.dirs, g.Q, chunk_cols)
+                    self.plans[key] = mj.ChunkPlan(g.dirs, g.Q, chunk_cols)
                 w = self.plans[key].workspace_words(g.P, cap)
             ws_words.append(w)
         fixed = sum((depth + 2) * c * g.img_words * 8 for c, g in zip(caps, self.geos))

@@ -101,7 +101,7 @@ class Bench:
     def plan(self, w: Workload, cols: int):
         key = (tuple(w.dirs), w.k, cols)
         if key not in self.plans:
-            self.plans[key] = mj.Plan(w.dirs, w.k, cols)
+            self.plans[key] = mj.ChunkPlan(w.dirs, w.k, cols)
         return self.plans[key]
 
     def prepare(self, w: Workload):

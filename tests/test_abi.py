@@ -144,3 +144,25 @@ def test_one_hip_runtime_even_when_the_library_loads_first():
                          timeout=300)
     assert out.returncode == 0, out.stderr
     assert out.stdout.strip().splitlines()[-1] == "1"
+
+
+def test_decode_launch_plan_split_and_32bit_slices(mj):
+    """A large batch of the (12,8) code is decoded in two ring classes (a
+    short-ring launch, then the deep blocks gathered from ranges of 256
+    blocks); when blocks are so long that 256 of them pass 32-bit byte
+    offsets, the batch stays in one launch, which still addresses its own
+    few blocks with 32-bit offsets."""
+    dirs = list(range(-6, 6))
+    two = mj.mojette_decode_batch_launches(dirs, 128, 8, 1 << 19)
+    assert [m for _, _, m in two] == [1, 2]
+    assert two[0][0] < two[1][0]                     # short ring first
+    assert mj.mojette_decode_batch_launches(dirs, 128, 8, 64)[0][2] == 0   # small batch: one
+    # 12P + 252 words per block slice: 256 slices pass 2^31 bytes from P = 87,361 on
+    P = 90000
+    assert 256 * mj.mojette_block_words(dirs, P, 8) * 8 >= 1 << 31
+    one = mj.mojette_decode_batch_launches(dirs, P, 8, 1 << 19)
+    assert len(one) == 1 and one[0][2] == 0
+    assert one[0][1] * mj.mojette_block_words(dirs, P, 8) * 8 < 1 << 31
+    # a wave slice of even a few blocks beyond 32-bit offsets is refused
+    with pytest.raises(mj.MojetteError):
+        mj.mojette_decode_batch_launches([-1, 0, 1], 1 << 28, 2, 4, 2)

@@ -56,7 +56,7 @@ def test_chunked_decode_matches_oracle(mj, orc, P, Q, dirs, nb, cols):
     masks = synth.erasure_masks(41 + P, nb, n, (0, n - Q))
     enc = orc.encode_blocks(imgs, P, Q, dirs)
     src = poisoned(orc, enc, masks, P, Q, dirs)
-    plan = mj.Plan(dirs, Q, cols)
+    plan = mj.ChunkPlan(dirs, Q, cols)
     ws_words = plan.workspace_words(P, nb)
     assert ws_words > 0
     d_src, d_mask = to_dev(src), masks_to_dev(masks)
@@ -79,7 +79,7 @@ def test_chunked_decode_matches_oracle(mj, orc, P, Q, dirs, nb, cols):
 
 def test_chunked_short_rows_fall_back_and_status(mj, orc):
     dirs, Q = synth.centered_dirs(6), 4
-    plan = mj.Plan(dirs, Q, 256)
+    plan = mj.ChunkPlan(dirs, Q, 256)
     # too short to cut: no workspace, whole-block decode
     P, nb = 200, 8
     assert plan.workspace_words(P, nb) == 0
@@ -113,7 +113,7 @@ def test_chunked_short_rows_fall_back_and_status(mj, orc):
 
 def test_chunked_decode_graph_replay(mj, orc):
     dirs, Q, P, nb = synth.centered_dirs(6), 4, 4000, 16
-    plan = mj.Plan(dirs, Q, 128)
+    plan = mj.ChunkPlan(dirs, Q, 128)
     imgs = synth.block_images(9, 0, nb, P, Q)
     masks = synth.erasure_masks(10, nb, 6, (0, 2))
     enc = orc.encode_blocks(imgs, P, Q, dirs)
@@ -169,7 +169,7 @@ def test_jobs_mix_chunked_and_whole_with_slots(mj, orc):
         job = dict(P=P, Q=Q, dirs=dirs, nblocks=nb, images=d_out, projs=d_proj, slots=d_slots,
                    erased=masks_to_dev(masks))
         if cols:
-            plan = mj.Plan(dirs, Q, cols)
+            plan = mj.ChunkPlan(dirs, Q, cols)
             plans.append(plan)
             job["plan"] = plan
             job["workspace"] = torch.empty(plan.workspace_words(P, nb), dtype=torch.int64,
@@ -198,7 +198,7 @@ def test_workspace_serves_every_smaller_batch(mj):
     may choose the parallel carry (two buffers) where N blocks would not."""
     for dirs, Q, P, cols in ((synth.centered_dirs(6), 4, 1218, 128),
                              (synth.centered_dirs(12), 8, 4096, 256)):
-        plan = mj.Plan(dirs, Q, cols)
+        plan = mj.ChunkPlan(dirs, Q, cols)
         per = (P // 16) // ((cols + 15) // 16) - 1
         stride = Q * max(1, plan.workspace_words(P, 1) // (2 * per * Q))
         prev = 0

@@ -11,7 +11,7 @@ import pytest
 
 import oracle
 import synth
-from tests.gpuutil import masks_to_dev, say, to_dev, to_np
+from tests.gpuutil import mask_depth, masks_to_dev, poison_erased_dev, say, to_dev, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -226,7 +226,14 @@ def test_hip_graph_replay(mj):
 
 
 def full_size_case(mj, P, Q, n, nblocks, ner, seed):
+    """Encode and decode at the full batch size, in the launches the library
+    picks for it (ring classes and the gathered long-ring launch included),
+    from a pool whose erased projections are overwritten on the device: the
+    round trip over every block, encode and decode against the oracle on a
+    sample that holds the first and last blocks, random ones and blocks of
+    the deepest survivor set present."""
     dirs = synth.centered_dirs(n)
+    sizes = [oracle.proj_size(p, 1, P, Q) for p in dirs]
     words = mj.mojette_block_words(dirs, P, Q)
     say(f"full size: {nblocks} blocks P={P} Q={Q} n={n}")
     d_img = torch.empty(nblocks * Q * P, dtype=torch.int64, device="cuda")
@@ -237,19 +244,30 @@ def full_size_case(mj, P, Q, n, nblocks, ner, seed):
     d_out = torch.empty_like(d_img)
     d_status = torch.zeros(1, dtype=torch.int32, device="cuda")
     mj.mojette_encode_batch(d_img, nblocks, P, Q, dirs, d_proj)
+    rng = np.random.default_rng(seed)
+    depths = {int(m): mask_depth(int(m), dirs, Q) for m in np.unique(masks)}
+    dmax = max(depths.values())
+    deep_masks = np.array([m for m, d in depths.items() if d == dmax], dtype=np.uint16)
+    deepest = np.flatnonzero(np.isin(masks, deep_masks))
+    sample = np.unique(np.concatenate([[0, nblocks - 1], rng.integers(0, nblocks, 48),
+                                       deepest[:8], deepest[-8:]]))
+    idx = torch.from_numpy(sample).cuda()
+    proj2 = d_proj.view(nblocks, words)
+    torch.cuda.synchronize()
+    got = to_np(proj2[idx])                              # encode, before any bin is overwritten
+    imgs = synth.sample_images(seed, sample, P, Q)
+    want = oracle.encode_blocks(imgs, P, Q, dirs)
+    assert np.array_equal(got.reshape(len(sample), words), want)
+    poison_erased_dev(d_proj, masks, sizes)
     mj.mojette_decode_batch(d_proj, d_mask, nblocks, P, Q, dirs, d_out, d_status)
     torch.cuda.synchronize()
     assert int(d_status.item()) == 0
     assert torch.equal(d_out, d_img)          # round trip over every block
-    rng = np.random.default_rng(seed)
-    sample = np.unique(np.concatenate([[0, nblocks - 1], rng.integers(0, nblocks, 48)]))
-    imgs = synth.sample_images(seed, sample, P, Q)
-    want = oracle.encode_blocks(imgs, P, Q, dirs)
-    proj2 = d_proj.view(nblocks, words)
-    got = to_np(proj2[torch.from_numpy(sample).cuda()])
-    assert np.array_equal(got.reshape(len(sample), words), want)
-    dec = oracle.decode_blocks(want, masks[sample], P, Q, dirs)
+    src = to_np(proj2[idx]).reshape(len(sample), words)
+    assert np.array_equal(src, poison_erased(want, masks[sample], P, Q, dirs))
+    dec = oracle.decode_blocks(src, masks[sample], P, Q, dirs)
     assert np.array_equal(dec, imgs)
+    assert np.array_equal(to_np(d_out.view(nblocks, -1)[idx]).reshape(len(sample), Q, P), dec)
     del d_img, d_proj, d_out
     torch.cuda.empty_cache()
 

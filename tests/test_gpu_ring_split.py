@@ -10,7 +10,8 @@ import pytest
 
 import oracle
 import synth
-from tests.gpuutil import masks_to_dev, say, to_dev, to_np
+from tests.gpuutil import (POISON_WORD, mask_depth, masks_to_dev, poison_erased_dev, say,
+                           survivor_depth, to_np)
 
 pytestmark = pytest.mark.gpu
 
@@ -27,53 +28,51 @@ def mj():
     return mj
 
 
-def depth(ps_sorted_used):
-    """Deepest read behind a row's newest pixel for the used survivors (the
-    r-th smallest p rebuilds row r): max ceil((A_l - A_r)/2) - 1 - (l-r) p_r."""
-    Q = len(ps_sorted_used)
-    A, s = [], 0
-    for r in range(Q):
-        A.append(2 * s + r)
-        s += ps_sorted_used[r]
-    best = 0
-    for r in range(Q):
-        for l in range(Q):
-            if l != r:
-                d = A[l] - A[r]
-                ch = (d + 1) // 2 if d >= 0 else -((-d) // 2)
-                best = max(best, ch - 1 - (l - r) * ps_sorted_used[r])
-    return best
-
-
 def masks_by_depth(dirs, Q):
     n = len(dirs)
     out = []
     for keep in itertools.combinations(range(n), Q):
         used = sorted(dirs[i] for i in keep)
         mask = sum(1 << i for i in range(n) if i not in keep)
-        out.append((depth(used), mask))
+        out.append((survivor_depth(used), mask))
     return sorted(out)
 
 
 def run(mj, P, Q, dirs, masks):
-    """Round trip of every block on the device, the oracle on a sample.  The
-    batches are large enough for the library to split them."""
+    """Round trip of every block on the device from pools whose erased
+    projections are overwritten, the oracle on a sample that holds the first,
+    middle and last blocks and the deepest blocks of the batch (those of the
+    gathered long-ring launch when the library splits it).  The batches are
+    large enough for the library to split them."""
     nb = len(masks)
+    sizes = [oracle.proj_size(p, 1, P, Q) for p in dirs]
     words = mj.mojette_block_words(dirs, P, Q)
     d_img = torch.empty(nb * Q * P, dtype=torch.int64, device="cuda")
     mj.mojette_fill_splitmix64(d_img, d_img.numel(), 900 + nb)
     d_proj = torch.empty(nb * words, dtype=torch.int64, device="cuda")
     mj.mojette_encode_batch(d_img, nb, P, Q, dirs, d_proj)
+    depths = {int(m): mask_depth(int(m), dirs, Q) for m in np.unique(masks)}
+    dmax = max(depths.values())
+    deepest = np.flatnonzero([depths[int(m)] == dmax for m in masks])
+    pick = np.unique(np.concatenate([[0, 1, nb // 2, nb - 1], deepest[:3], deepest[-3:]]))
+    idx = torch.from_numpy(pick).cuda()
+    torch.cuda.synchronize()
+    enc = to_np(d_proj.view(nb, words)[idx])          # before the erased bins are overwritten
+    poison_erased_dev(d_proj, masks, sizes)
     d_out = torch.full((nb * Q * P,), -1, dtype=torch.int64, device="cuda")
     st = torch.zeros(1, dtype=torch.int32, device="cuda")
     mj.mojette_decode_batch(d_proj, masks_to_dev(masks), nb, P, Q, dirs, d_out, st)
     torch.cuda.synchronize()
     assert int(st.item()) == 0
     assert torch.equal(d_out, d_img)
-    pick = np.array([0, 1, nb // 2, nb - 1])
-    idx = torch.from_numpy(pick).cuda()
-    enc = to_np(d_proj.view(nb, words)[idx])
-    want = oracle.decode_blocks(enc, masks[pick], P, Q, dirs)
+    src = to_np(d_proj.view(nb, words)[idx])
+    off = np.cumsum([0] + sizes)
+    for k, b in enumerate(pick):                     # the device pool really is poisoned
+        for i in range(len(dirs)):
+            if (int(masks[b]) >> i) & 1:
+                assert (src[k, off[i]:off[i + 1]] == np.uint64(POISON_WORD)).all()
+    want = oracle.decode_blocks(src, masks[pick], P, Q, dirs)
+    assert np.array_equal(want, oracle.decode_blocks(enc, masks[pick], P, Q, dirs))
     assert np.array_equal(to_np(d_out.view(nb, -1)[idx]).reshape(len(pick), Q, P), want)
 
 
