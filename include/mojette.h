@@ -48,6 +48,7 @@ extern "C" {
 #define MOJETTE_ENOMEM (-4)        /* host-side bookkeeping could not allocate */
 #define MOJETTE_EINCONSISTENT (-5) /* projections that no image has (mojette_verify_batch) */
 #define MOJETTE_ENOTSUP (-6)       /* geometry beyond the kernels' LDS limits */
+#define MOJETTE_ESCRATCH (-7)      /* beyond the fixed scratch memory (..._noalloc call) */
 
 #define MOJETTE_MAX_DIRS 16
 #define MOJETTE_MAX_ROWS 16
@@ -393,6 +394,27 @@ int mojette_decode_batch_chunked(const mojette_chunk_plan *plan, const uint64_t 
                                  const uint16_t *erased, int64_t nblocks, int32_t P,
                                  uint64_t *images, int32_t *status, uint64_t *workspace,
                                  void *stream);
+
+/*
+ * mojette_decode_batch_chunked for callers that cannot allocate device
+ * memory or pass a workspace (code under HIP graph capture, serving loops,
+ * harnesses that forbid hipMalloc).  The workspace is a fixed array of
+ * MOJETTE_SCRATCH_WORDS 64-bit words (64 MiB) in the library's device
+ * memory, which each GPU the library runs on holds until the process ends.
+ * The call allocates nothing; its first call on a device looks up that
+ * device's array (no allocation, no synchronisation).  Arguments and results
+ * as for mojette_decode_batch_chunked.  A call whose
+ * mojette_decode_chunked_workspace(plan, P, nblocks) exceeds
+ * MOJETTE_SCRATCH_WORDS returns MOJETTE_ESCRATCH before anything is enqueued
+ * (decode fewer blocks per call).  Every call on a GPU shares that GPU's
+ * array and leaves its contents behind: calls that may overlap on one GPU
+ * (on concurrent streams or threads) race and must be serialised by the
+ * caller.
+ */
+#define MOJETTE_SCRATCH_WORDS ((int64_t)1 << 23)
+int mojette_decode_batch_chunked_noalloc(const mojette_chunk_plan *plan, const uint64_t *projs,
+                                         const uint16_t *erased, int64_t nblocks, int32_t P,
+                                         uint64_t *images, int32_t *status, void *stream);
 
 /*
  * Cost model of the schedule autotuner (not part of the paper's method: it

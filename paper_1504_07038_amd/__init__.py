@@ -25,6 +25,8 @@ MOJETTE_EHIP = -3
 MOJETTE_ENOMEM = -4
 MOJETTE_EINCONSISTENT = -5
 MOJETTE_ENOTSUP = -6
+MOJETTE_ESCRATCH = -7
+MOJETTE_SCRATCH_WORDS = 1 << 23
 MAX_DIRS = 16
 MAX_ROWS = 16
 
@@ -156,6 +158,8 @@ def lib() -> ctypes.CDLL:
         "mojette_chunk_matrix": ([vp, i32, i32, vp, vp, i64], i64),
         "mojette_decode_chunked_workspace": ([vp, i32, i64], i64),
         "mojette_decode_batch_chunked": ([vp, vp, vp, i64, i32, vp, vp, vp, vp], ctypes.c_int),
+        "mojette_decode_batch_chunked_noalloc": ([vp, vp, vp, i64, i32, vp, vp, vp],
+                                                 ctypes.c_int),
         "mojette_mlp_params": ([i32, i32], i32),
         "mojette_mlp_forward": ([vp, i32, i32, vp, i64, vp, vp], ctypes.c_int),
         "mojette_mlp_grad_workspace": ([i32, i32, i64], i64),
@@ -200,7 +204,8 @@ def exported_symbols() -> list[str]:
         "mojette_classes_layout", "mojette_encode_classes", "mojette_decode_classes",
         "mojette_encode_jobs", "mojette_decode_jobs", "mojette_chunk_plan_create",
         "mojette_chunk_plan_destroy", "mojette_chunk_matrix", "mojette_decode_chunked_workspace",
-        "mojette_decode_batch_chunked", "mojette_mlp_params", "mojette_mlp_forward",
+        "mojette_decode_batch_chunked", "mojette_decode_batch_chunked_noalloc",
+        "mojette_mlp_params", "mojette_mlp_forward",
         "mojette_mlp_grad_workspace", "mojette_mlp_grad", "mojette_mlp_adam",
         "mojette_fill_splitmix64", "mojette_copy_words",
     ]
@@ -561,6 +566,25 @@ def mojette_decode_batch_chunked(plan: ChunkPlan, projs, erased, nblocks: int, P
                                             _word_tensor(images, "images"),
                                             _dev_ptr(status, "status"), ws, _stream(stream))
     return _check(rc, "mojette_decode_batch_chunked", check)
+
+
+def mojette_decode_batch_chunked_noalloc(plan: ChunkPlan, projs, erased, nblocks: int, P: int,
+                                         images, status=None, stream=None,
+                                         check: bool = True) -> int:
+    """mojette_decode_batch_chunked with the library's fixed scratch memory
+    as its workspace (no allocation; MOJETTE_ESCRATCH beyond
+    MOJETTE_SCRATCH_WORDS words of workspace)."""
+    import torch
+
+    if erased is not None and erased.dtype not in (torch.int16, torch.uint16):
+        raise ValueError("erased must be 16-bit masks")
+    if status is not None and status.dtype != torch.int32:
+        raise ValueError("status must be int32")
+    rc = lib().mojette_decode_batch_chunked_noalloc(plan.handle, _word_tensor(projs, "projs"),
+                                                    _dev_ptr(erased, "erased"), nblocks, P,
+                                                    _word_tensor(images, "images"),
+                                                    _dev_ptr(status, "status"), _stream(stream))
+    return _check(rc, "mojette_decode_batch_chunked_noalloc", check)
 
 
 def _f32_tensor(t, name: str) -> int:

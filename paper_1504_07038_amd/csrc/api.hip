@@ -512,6 +512,7 @@ const char *mojette_strerror(int status) {
         case MOJETTE_ENOMEM: return "out of host memory";
         case MOJETTE_ENOTSUP: return "geometry exceeds the kernels' LDS limits";
         case MOJETTE_EINCONSISTENT: return "projections disagree with the image";
+        case MOJETTE_ESCRATCH: return "request exceeds the library's fixed scratch memory";
         default: return "unknown status";
     }
 }
