@@ -828,7 +828,7 @@ def plain_vs_batched(mj, torch, np, d_img, d_proj, masks, P, Q, dirs, words, nb,
         lat = []
         for a in dec_args:
             t = time.perf_counter()
-            rc = L.mojette_decode(a[0], a[1], a[2], dirs_arr, n, P, Q, a[3], sp)
+            rc = L.mojette_decode(a[0], a[1], a[2], dirs_arr, n, P, Q, a[3], 0, sp)
             if sync_each:
                 torch.cuda.synchronize()
                 lat.append((time.perf_counter() - t) * 1e6)

@@ -93,14 +93,24 @@ int mojette_encode(const uint64_t *image, int32_t P, int32_t Q, const int32_t *d
  *   proj_ids  host, m distinct indices into dirs.
  *   dirs, n   the code's directions, as given to mojette_encode.
  *   image_out device, Q*P words.
+ *   flags     0 or MOJETTE_VERIFY.  With MOJETTE_VERIFY the call checks
+ *             consistency (Section 2.2: projections that are not the
+ *             projections of any image leave bins with a nonzero residue):
+ *             every given projection, all of its Eq. 2 bins, is recomputed
+ *             from the decoded image and compared; the call then waits for
+ *             the result (it is synchronous, not for graph capture) and
+ *             returns MOJETTE_EINCONSISTENT on any difference.  Verified
+ *             decodes on one device take turns on a device word of the
+ *             library's.
  * m >= Q is required (Katz with q_i = 1: any Q of the n projections
  * reconstruct, Section 2.3); with m > Q the Q survivors of smallest p are
  * used.  Returns MOJETTE_OK, MOJETTE_EINVAL, MOJETTE_ENOTRECON,
- * MOJETTE_ENOTSUP or MOJETTE_EHIP.
+ * MOJETTE_ENOTSUP, MOJETTE_EHIP or (verified) MOJETTE_EINCONSISTENT.
  */
+#define MOJETTE_VERIFY 1u
 int mojette_decode(const uint64_t *const *proj, const int32_t *proj_ids, int32_t m,
                    const int32_t *dirs, int32_t n, int32_t P, int32_t Q, uint64_t *image_out,
-                   void *stream);
+                   uint32_t flags, void *stream);
 
 /*
  * Forward transform of nblocks blocks of one geometry in one launch.
@@ -343,6 +353,91 @@ int mojette_encode_jobs(const mojette_job *jobs, int32_t njobs, void *stream);
 /* Inverse transform (Section 2.2) of every block of every job; status as for
  * mojette_decode_batch. */
 int mojette_decode_jobs(const mojette_job *jobs, int32_t njobs, int32_t *status, void *stream);
+
+/*
+ * Descriptor-driven batched calls: any number of blocks, each with its own
+ * code and row length, in one call.  A plan holds the codes (geometries:
+ * Q = k data lines, n projections along (p_i, 1), Section 2.3) and, per
+ * code, the schedule of its launches.  Each block is described by a device
+ * descriptor (mojette_block) that names its code (geom_id), its row length
+ * P, its erasure mask and where its image and its projections sit in one
+ * device word pool: the image is Q x P words from image_off (row-major, row l
+ * = data packet l), the n projections are back to back from proj_off
+ * (projection i, mojette_proj_size(dirs[i], P, Q) bins, at proj_off +
+ * sum_{i' < i} B_i').  Blocks may come in any order and interleave codes and
+ * row lengths.
+ *
+ * A call first groups the blocks by (code, P) on the device, in the caller's
+ * workspace (mojette_workspace_size bytes), then runs the transform of every
+ * block in one persistent launch (per row count when the plan's row counts
+ * have no combined kernel), longest rows first.  Calls allocate nothing,
+ * never synchronise and are safe to record into a HIP graph.  At most 2,048
+ * distinct (geom_id, P) pairs per call; the blocks of pairs beyond that are
+ * not transformed and MOJETTE_ENOTSUP is stored to *status.
+ */
+typedef struct mojette_geom {
+    int32_t Q;                        /* rows = data packets, 1..16 */
+    int32_t n;                        /* projections, Q..16 */
+    int32_t dirs[MOJETTE_MAX_DIRS];   /* p of each projection (q = 1), distinct, |p| <= 32767 */
+} mojette_geom;
+
+/* Schedule of one code (zero fields: the library's choice).  An autotuner
+ * fills these from measurements. */
+typedef struct mojette_tune {
+    int32_t decode_blocks_per_wave;   /* blocks swept by one decode wavefront (>= 1) */
+    int32_t decode_ring_split;        /* 1: survivor sets that read shallowly get a short ring and
+                                         more blocks per wavefront (their own classes); -1: never;
+                                         0: the library's choice (split where 90% of sets fit) */
+    int32_t encode_tile_cols;         /* encode tile width cap, a multiple of 64 */
+    int32_t reserved;
+} mojette_tune;
+
+/* A block of a descriptor-driven call (device memory, 24 bytes). */
+typedef struct mojette_block {
+    uint64_t image_off;               /* word offset of the block's image in the pool */
+    uint64_t proj_off;                /* word offset of its first projection in the pool */
+    uint32_t P;                       /* pixels per row, 1..2^24 with P*Q <= 2^30 */
+    uint16_t geom_id;                 /* index into the plan's codes */
+    uint16_t erasure_mask;            /* decode: bit i set = projection i lost */
+} mojette_block;
+
+typedef struct mojette_plan mojette_plan;
+
+/* Creates a plan over ngeoms codes (1..1024).  tune: NULL or ngeoms entries.
+ * Checks every code (EINVAL: bad Q, n, duplicate or out-of-range
+ * directions; ENOTSUP: beyond the kernels' LDS limits), computes each
+ * code's decode rings on the host and copies the code table to the current
+ * device: it allocates device memory and synchronises, so it is not for
+ * use under graph capture.  The plan is used on that device only. */
+int mojette_plan_create(const mojette_geom *geoms, int32_t ngeoms, const mojette_tune *tune,
+                        mojette_plan **plan);
+/* Frees the plan (NULL is a no-op). */
+int mojette_plan_destroy(mojette_plan *plan);
+
+/* Workspace bytes a call on up to nblocks blocks needs (non-decreasing in
+ * nblocks), or -1 on bad arguments.  About 1 MB plus 8 bytes per block. */
+int64_t mojette_workspace_size(const mojette_plan *plan, int64_t nblocks);
+
+/* Forward transform (Section 2.1, Eq. 1) of every described block: reads
+ * each block's image, writes its n projections.  blocks: device, nblocks
+ * descriptors; pool: device words holding every image and projection;
+ * workspace: device, mojette_workspace_size(plan, nblocks) bytes, 256-byte
+ * aligned, overwritten.  status: device int32 or NULL, receives
+ * MOJETTE_EINVAL for a descriptor with a bad geom_id or P (that block is
+ * skipped) and MOJETTE_ENOTSUP as above; never cleared by the call.
+ * Returns MOJETTE_OK, MOJETTE_EINVAL (bad arguments) or MOJETTE_EHIP. */
+int mojette_encode_batched(const mojette_plan *plan, const mojette_block *blocks,
+                           int64_t nblocks, uint64_t *pool, void *workspace, int32_t *status,
+                           void *stream);
+
+/* Inverse transform (Section 2.2) of every described block from the
+ * projections its erasure mask leaves (bins of erased projections are never
+ * read), writing its image.  A block with fewer than Q survivors is left
+ * unwritten and MOJETTE_ENOTRECON is stored to *status.  Other arguments as
+ * for mojette_encode_batched. */
+int mojette_decode_batched(const mojette_plan *plan, const mojette_block *blocks,
+                           int64_t nblocks, uint64_t *pool, void *workspace, int32_t *status,
+                           void *stream);
 
 /*
  * Chunked decode of long rows (the inverse of Section 2.2, cut into chunks).

@@ -27,6 +27,7 @@ MOJETTE_EINCONSISTENT = -5
 MOJETTE_ENOTSUP = -6
 MOJETTE_ESCRATCH = -7
 MOJETTE_SCRATCH_WORDS = 1 << 23
+MOJETTE_VERIFY = 1
 MAX_DIRS = 16
 MAX_ROWS = 16
 
@@ -90,6 +91,44 @@ def make_jobs(jobs):
     return arr, len(jobs)
 
 
+class MojetteGeom(ctypes.Structure):
+    """``mojette_geom``: one code (Q rows, n directions) of a plan."""
+
+    _fields_ = [("Q", ctypes.c_int32), ("n", ctypes.c_int32), ("dirs", ctypes.c_int32 * MAX_DIRS)]
+
+
+class MojetteTune(ctypes.Structure):
+    """``mojette_tune``: the schedule of one code (zero: the library's choice)."""
+
+    _fields_ = [("decode_blocks_per_wave", ctypes.c_int32), ("decode_ring_split", ctypes.c_int32),
+                ("encode_tile_cols", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+def block_dtype():
+    """numpy dtype of ``mojette_block`` (24 bytes)."""
+    import numpy as np
+
+    return np.dtype([("image_off", "<u8"), ("proj_off", "<u8"), ("P", "<u4"),
+                     ("geom_id", "<u2"), ("erasure_mask", "<u2")])
+
+
+def make_blocks(image_off, proj_off, P, geom_id, erasure_mask=None):
+    """Descriptors from per-block arrays -> a uint8 torch tensor on the device
+    (nblocks x 24 bytes) ready for the batched calls."""
+    import numpy as np
+    import torch
+
+    n = len(P)
+    arr = np.zeros(n, dtype=block_dtype())
+    arr["image_off"] = image_off
+    arr["proj_off"] = proj_off
+    arr["P"] = P
+    arr["geom_id"] = geom_id
+    if erasure_mask is not None:
+        arr["erasure_mask"] = erasure_mask
+    return torch.from_numpy(arr.view(np.uint8).copy()).to("cuda")
+
+
 class MojetteError(RuntimeError):
     def __init__(self, status: int, where: str):
         msg = f"{where}: {strerror(status)} ({status})"
@@ -128,7 +167,7 @@ def lib() -> ctypes.CDLL:
         "mojette_block_words": ([vp, i32, i32, i32], i64),
         "mojette_decode_ring": ([vp, i32, i32, i32], i32),
         "mojette_encode": ([vp, i32, i32, vp, i32, vp, vp], ctypes.c_int),
-        "mojette_decode": ([vp, vp, i32, vp, i32, i32, i32, vp, vp], ctypes.c_int),
+        "mojette_decode": ([vp, vp, i32, vp, i32, i32, i32, vp, ctypes.c_uint32, vp], ctypes.c_int),
         "mojette_encode_batch": ([vp, i64, i32, i32, vp, i32, vp, vp], ctypes.c_int),
         "mojette_decode_batch": ([vp, vp, i64, i32, i32, vp, i32, vp, vp, vp], ctypes.c_int),
         "mojette_encode_batch_wide": ([vp, i64, i32, i32, vp, i32, vp, vp], ctypes.c_int),
@@ -158,6 +197,11 @@ def lib() -> ctypes.CDLL:
         "mojette_chunk_matrix": ([vp, i32, i32, vp, vp, i64], i64),
         "mojette_decode_chunked_workspace": ([vp, i32, i64], i64),
         "mojette_decode_batch_chunked": ([vp, vp, vp, i64, i32, vp, vp, vp, vp], ctypes.c_int),
+        "mojette_plan_create": ([vp, i32, vp, vp], ctypes.c_int),
+        "mojette_plan_destroy": ([vp], ctypes.c_int),
+        "mojette_workspace_size": ([vp, i64], i64),
+        "mojette_encode_batched": ([vp, vp, i64, vp, vp, vp, vp], ctypes.c_int),
+        "mojette_decode_batched": ([vp, vp, i64, vp, vp, vp, vp], ctypes.c_int),
         "mojette_decode_batch_chunked_noalloc": ([vp, vp, vp, i64, i32, vp, vp, vp],
                                                  ctypes.c_int),
         "mojette_mlp_params": ([i32, i32], i32),
@@ -205,6 +249,8 @@ def exported_symbols() -> list[str]:
         "mojette_encode_jobs", "mojette_decode_jobs", "mojette_chunk_plan_create",
         "mojette_chunk_plan_destroy", "mojette_chunk_matrix", "mojette_decode_chunked_workspace",
         "mojette_decode_batch_chunked", "mojette_decode_batch_chunked_noalloc",
+        "mojette_plan_create", "mojette_plan_destroy", "mojette_workspace_size",
+        "mojette_encode_batched", "mojette_decode_batched",
         "mojette_mlp_params", "mojette_mlp_forward",
         "mojette_mlp_grad_workspace", "mojette_mlp_grad", "mojette_mlp_adam",
         "mojette_fill_splitmix64", "mojette_copy_words",
@@ -286,12 +332,15 @@ def mojette_encode(image, P: int, Q: int, dirs, proj_out, stream=None, check: bo
 
 
 def mojette_decode(proj, proj_ids, dirs, P: int, Q: int, image_out, stream=None,
-                   check: bool = True) -> int:
+                   check: bool = True, verify: bool = False) -> int:
+    """One block from m >= Q projections; verify=True sets MOJETTE_VERIFY (the
+    call then checks every given projection against the decoded image and
+    waits for the verdict)."""
     arr, n = _i32_array(dirs)
     ids, m = _i32_array(proj_ids)
     ptrs = (ctypes.c_void_p * max(1, len(proj)))(*[_word_tensor(t, "proj") for t in proj])
     rc = lib().mojette_decode(ptrs, ids, m, arr, n, P, Q, _word_tensor(image_out, "image_out"),
-                              _stream(stream))
+                              MOJETTE_VERIFY if verify else 0, _stream(stream))
     return _check(rc, "mojette_decode", check)
 
 
@@ -585,6 +634,86 @@ def mojette_decode_batch_chunked_noalloc(plan: ChunkPlan, projs, erased, nblocks
                                                     _word_tensor(images, "images"),
                                                     _dev_ptr(status, "status"), _stream(stream))
     return _check(rc, "mojette_decode_batch_chunked_noalloc", check)
+
+
+class GeomPlan:
+    """``mojette_plan``: the codes of the descriptor-driven batched calls and
+    their schedules.  ``geoms``: list of (Q, dirs); ``tune``: None or one dict
+    per code with any of the ``mojette_tune`` fields.  Creating it allocates
+    device memory and synchronises; ``close()`` (or garbage collection)
+    frees it."""
+
+    def __init__(self, geoms, tune=None):
+        geoms = list(geoms)
+        arr = (MojetteGeom * max(1, len(geoms)))()
+        for g, (Q, dirs) in enumerate(geoms):
+            arr[g].Q, arr[g].n = int(Q), len(dirs)
+            for i, p in enumerate(dirs):
+                arr[g].dirs[i] = int(p)
+        tarr = None
+        if tune is not None:
+            tarr = (MojetteTune * max(1, len(geoms)))()
+            for g, t in enumerate(tune):
+                for k, v in (t or {}).items():
+                    setattr(tarr[g], k, int(v))
+        h = ctypes.c_void_p(0)
+        rc = lib().mojette_plan_create(arr, len(geoms), tarr, ctypes.addressof(h))
+        _check(rc, "mojette_plan_create", True)
+        self.handle = h.value
+        self.geoms = [(int(Q), [int(p) for p in dirs]) for Q, dirs in geoms]
+
+    def close(self) -> None:
+        if self.handle:
+            lib().mojette_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace_bytes(self, nblocks: int) -> int:
+        return int(lib().mojette_workspace_size(self.handle, nblocks))
+
+    def workspace(self, nblocks: int):
+        import torch
+
+        return torch.empty(max(1, self.workspace_bytes(nblocks)), dtype=torch.uint8, device="cuda")
+
+
+mojette_plan_create = GeomPlan
+
+
+def mojette_workspace_size(plan: GeomPlan, nblocks: int) -> int:
+    return plan.workspace_bytes(nblocks)
+
+
+def _desc_args(plan, blocks, nblocks, pool, workspace, status):
+    import torch
+
+    if blocks.dtype != torch.uint8 or blocks.numel() < 24 * nblocks:
+        raise ValueError("blocks must be a uint8 tensor of nblocks descriptors (24 bytes each)")
+    if workspace.dtype != torch.uint8 or workspace.numel() < plan.workspace_bytes(nblocks):
+        raise ValueError(f"workspace must hold {plan.workspace_bytes(nblocks)} bytes")
+    if status is not None and status.dtype != torch.int32:
+        raise ValueError("status must be int32")
+    return (plan.handle, _dev_ptr(blocks, "blocks"), nblocks, _word_tensor(pool, "pool"),
+            _dev_ptr(workspace, "workspace"), _dev_ptr(status, "status"))
+
+
+def mojette_encode_batched(plan: GeomPlan, blocks, nblocks: int, pool, workspace, status=None,
+                           stream=None, check: bool = True) -> int:
+    rc = lib().mojette_encode_batched(*_desc_args(plan, blocks, nblocks, pool, workspace, status),
+                                      _stream(stream))
+    return _check(rc, "mojette_encode_batched", check)
+
+
+def mojette_decode_batched(plan: GeomPlan, blocks, nblocks: int, pool, workspace, status=None,
+                           stream=None, check: bool = True) -> int:
+    rc = lib().mojette_decode_batched(*_desc_args(plan, blocks, nblocks, pool, workspace, status),
+                                      _stream(stream))
+    return _check(rc, "mojette_decode_batched", check)
 
 
 def _f32_tensor(t, name: str) -> int:

@@ -16,7 +16,7 @@ OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmojette.so")
 SOURCES = ["api.hip", "chunk.hip", "encode.hip", "decode_single.hip", "decode_single_hi.hip",
            "decode_classes.hip", "decode_chunks.hip", "decode_sys.hip", "decode_sys_hi.hip",
-           "decode_wide.hip", "mlp.hip", "synth.hip", "noalloc.hip"]
+           "decode_wide.hip", "mlp.hip", "synth.hip", "noalloc.hip", "batched.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -622,10 +622,71 @@ int mojette_encode_batch_trimmed(const uint64_t *images, int64_t nblocks, int32_
     return encode_batch_impl(images, nblocks, P, Q, dirs, n, projs, stream, 0, f, c);
 }
 
+// The consistency verdict of a verified one-block decode: a device word per
+// device (its address looked up once per device), written by the check and
+// read back; verified decodes on one device take turns on it.
+static __device__ int32_t verify_word[1];
+
+static int32_t *verify_word_on_current_device() {
+    static std::map<int, int32_t *> ptrs;
+    int dev = 0;
+    const hipError_t ge = hipGetDevice(&dev);
+    if (ge != hipSuccess) {
+        mj::hip_status(ge);
+        return nullptr;
+    }
+    auto it = ptrs.find(dev);
+    if (it != ptrs.end()) return it->second;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(verify_word));
+    if (e != hipSuccess || !ptr) {
+        mj::hip_status(e != hipSuccess ? e : hipErrorInvalidSymbol);
+        return nullptr;
+    }
+    return ptrs[dev] = static_cast<int32_t *>(ptr);
+}
+
+// Recomputes every given projection from the decoded image and compares all
+// its bins (the consistency check of Section 2.2); waits for the result.
+static int verify_one_block(const uint64_t *const *proj, const int32_t *proj_ids, int32_t m,
+                            const int32_t *dirs, int32_t n, int32_t P, int32_t Q,
+                            const uint64_t *image, hipStream_t stream) {
+    static std::mutex mu;
+    std::lock_guard<std::mutex> g(mu);
+    mj::VerifyArgs a{};
+    if (!encode_tiling(dirs, n, P, Q, a)) return MOJETTE_ENOTSUP;
+    uint32_t have = 0;
+    for (int t = 0; t < m; ++t) {
+        a.par[proj_ids[t]] = proj[t];
+        have |= 1u << proj_ids[t];
+    }
+    a.images = image;
+    a.proj_stride = 0;
+    a.nblocks = 1;
+    a.masks = nullptr;
+    a.mask_uniform = ~have & ((1u << n) - 1u);
+    int32_t *word = verify_word_on_current_device();
+    if (!word) return MOJETTE_EHIP;
+    a.status = word;
+    const int32_t zero = 0;
+    int32_t verdict = 0;
+    hipError_t e = hipMemcpyAsync(word, &zero, sizeof zero, hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess) return mj::hip_status(e);
+    const int grid = (int)std::min<int64_t>((a.ntiles + a.waves - 1) / a.waves, kEncodeGridCap);
+    clear_stale_error();
+    const int rc = status_of(mj::launch_verify(a, grid, stream));
+    if (rc != MOJETTE_OK) return rc;
+    e = hipMemcpyAsync(&verdict, word, sizeof verdict, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return mj::hip_status(e);
+    return verdict;
+}
+
 int mojette_decode(const uint64_t *const *proj, const int32_t *proj_ids, int32_t m,
                    const int32_t *dirs, int32_t n, int32_t P, int32_t Q, uint64_t *image_out,
-                   void *stream) {
+                   uint32_t flags, void *stream) {
     if (!image_out || !geometry_ok(dirs, n, P, Q) || m < 0 || m > n) return MOJETTE_EINVAL;
+    if (flags & ~(uint32_t)MOJETTE_VERIFY) return MOJETTE_EINVAL;
     if (m > 0 && (!proj || !proj_ids)) return MOJETTE_EINVAL;
     mj::DecodeArgs a{};
     uint32_t have = 0;
@@ -648,7 +709,9 @@ int mojette_decode(const uint64_t *const *proj, const int32_t *proj_ids, int32_t
     a.nblocks = 1;
     a.nb = 1;   // one block: one slot
     clear_stale_error();
-    return status_of(mj::launch_decode(Q, mj::kLaunchPointers, a, 1, (hipStream_t)stream));
+    const int st = status_of(mj::launch_decode(Q, mj::kLaunchPointers, a, 1, (hipStream_t)stream));
+    if (st != MOJETTE_OK || !(flags & MOJETTE_VERIFY)) return st;
+    return verify_one_block(proj, proj_ids, m, dirs, n, P, Q, image_out, (hipStream_t)stream);
 }
 
 static int decode_batch_impl(const uint64_t *projs, const uint16_t *erased, int64_t nblocks,
@@ -1636,6 +1699,187 @@ int mojette_decode_classes(const mojette_class *classes, int32_t nclasses,
     const int rc = classes_to_jobs(classes, nclasses, images, projs, erased, jobs);
     if (rc != MOJETTE_OK) return rc;
     return mojette_decode_jobs(jobs.data(), nclasses, status, stream);
+}
+
+// ---- plans over geometries and descriptor-driven calls -----------------------
+
+struct mojette_plan {
+    std::vector<mj::GeomDev> geoms;   // host copy of the code table
+    mj::GeomDev *d_geoms;             // device
+    unsigned qmask;                   // row counts of the codes
+    int qmax;
+    size_t dec_lds, enc_lds;          // dynamic LDS of the transform launches
+    int dev;                          // device the table lives on
+};
+
+// Blocks per decode wavefront of a descriptor class: the library's choice
+// for the ring (or the tuned count), within the share of LDS a workgroup of
+// a mixed launch gets and the half-slot bodies the launch is compiled for.
+static int desc_blocks(int Q, int ring_stride, int tuned) {
+    int nb = tuned > 0 ? std::min(tuned, mj::decode_max_blocks_per_wave(Q))
+                       : default_blocks(Q, ring_stride);
+    while (nb > 1 && mj::decode_lds_bytes(Q, nb, ring_stride) > kMixedDecodeLds) --nb;
+    return std::min(nb, std::max(1, mj::decode_max_blocks_per_wave(Q) / 2));
+}
+
+int mojette_plan_create(const mojette_geom *geoms, int32_t ngeoms, const mojette_tune *tune,
+                        mojette_plan **plan) {
+    if (!plan) return MOJETTE_EINVAL;
+    *plan = nullptr;
+    if (!geoms || ngeoms < 1 || ngeoms > 1024) return MOJETTE_EINVAL;
+    std::vector<mj::GeomDev> tab(ngeoms);
+    unsigned qmask = 0;
+    int qmax = 0;
+    size_t dec_lds = 0, enc_lds = 0;
+    for (int gi = 0; gi < ngeoms; ++gi) {
+        const mojette_geom &gm = geoms[gi];
+        const int Q = gm.Q, n = gm.n;
+        if (!geometry_ok(gm.dirs, n, 1, Q) || n < Q) return MOJETTE_EINVAL;
+        mj::GeomDev &g = tab[gi];
+        g = mj::GeomDev{};
+        g.Q = Q;
+        g.n = n;
+        int maxabs = 0;
+        for (int i = 0; i < n; ++i) {
+            if (gm.dirs[i] < -32767 || gm.dirs[i] > 32767) return MOJETTE_EINVAL;
+            g.dirs[i] = gm.dirs[i];
+            g.sumabs += std::abs(gm.dirs[i]);
+            maxabs = std::max(maxabs, std::abs(gm.dirs[i]));
+        }
+        std::vector<int> order(n);
+        for (int i = 0; i < n; ++i) order[i] = i;
+        std::sort(order.begin(), order.end(),
+                  [&](int x, int y) { return gm.dirs[x] < gm.dirs[y]; });
+        std::vector<int> sp(n);
+        for (int s = 0; s < n; ++s) {
+            sp[s] = gm.dirs[order[s]];
+            g.p_sorted[s] = (int16_t)sp[s];
+            g.id_sorted[s] = (int8_t)order[s];
+        }
+        const mojette_tune *t = tune ? &tune[gi] : nullptr;
+        // encode: tiles of at most enc_w columns beside the halo, within LDS
+        g.H = (Q - 1) * maxabs;
+        int w = t && t->encode_tile_cols > 0 ? t->encode_tile_cols : kEncodeTileCols;
+        if (w % 64 != 0) return MOJETTE_EINVAL;
+        while (w > 64 && (size_t)Q * (w + 2 * g.H) * 8 > kLdsLimit) w -= 64;
+        if ((size_t)Q * (w + 2 * g.H) * 8 > kLdsLimit) return MOJETTE_ENOTSUP;
+        g.enc_w = w;
+        enc_lds = std::max(enc_lds, (size_t)Q * (w + 2 * g.H) * 8);
+        // decode: the full ring and, where a shorter ring serves most
+        // survivor sets, a short-ring class for them
+        int common = -1;
+        double deep = 1;
+        const int R = ring_length(sp, Q, &common, &deep);
+        if (R < 0) return MOJETTE_EINVAL;
+        const int tuned_nb = t ? t->decode_blocks_per_wave : 0;
+        if (tuned_nb < 0) return MOJETTE_EINVAL;
+        g.R = R;
+        g.nb = desc_blocks(Q, R + 1, tuned_nb);
+        if (mj::decode_lds_bytes(Q, g.nb, R + 1) > kLdsLimit) return MOJETTE_ENOTSUP;
+        dec_lds = std::max(dec_lds, mj::decode_lds_bytes(Q, g.nb, R + 1));
+        const int split = t ? t->decode_ring_split : 0;
+        if (split >= 0 && common > 0 && common < R) {
+            g.R_short = common;
+            g.depth_short = common - mj::kDecodeTile - 1;
+            g.nb_short = desc_blocks(Q, common + 1, tuned_nb);
+            dec_lds = std::max(dec_lds, mj::decode_lds_bytes(Q, g.nb_short, common + 1));
+        }
+        qmask |= 1u << Q;
+        qmax = std::max(qmax, Q);
+    }
+    auto *pl = new (std::nothrow) mojette_plan{};
+    if (!pl) return MOJETTE_ENOMEM;
+    pl->geoms = tab;
+    pl->qmask = qmask;
+    pl->qmax = qmax;
+    pl->dec_lds = dec_lds;
+    pl->enc_lds = enc_lds;
+    hipError_t e = hipGetDevice(&pl->dev);
+    if (e == hipSuccess) e = hipMalloc((void **)&pl->d_geoms, tab.size() * sizeof(mj::GeomDev));
+    if (e == hipSuccess)
+        e = hipMemcpy(pl->d_geoms, tab.data(), tab.size() * sizeof(mj::GeomDev),
+                      hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        mj::hip_status(e);
+        if (pl->d_geoms) (void)hipFree(pl->d_geoms);
+        delete pl;
+        return MOJETTE_EHIP;
+    }
+    *plan = pl;
+    return MOJETTE_OK;
+}
+
+int mojette_plan_destroy(mojette_plan *plan) {
+    if (!plan) return MOJETTE_OK;
+    if (plan->d_geoms) (void)hipFree(plan->d_geoms);
+    delete plan;
+    return MOJETTE_OK;
+}
+
+int64_t mojette_workspace_size(const mojette_plan *plan, int64_t nblocks) {
+    if (!plan || nblocks < 0 || nblocks > INT32_MAX) return -1;
+    return (int64_t)mj::DescWorkspace::bytes(nblocks);
+}
+
+// Checks a descriptor-driven call and fills what the bucket kernels need.
+static int desc_call(const mojette_plan *plan, const mojette_block *blocks, int64_t nblocks,
+                     uint64_t *pool, void *workspace, int32_t *status, bool decode,
+                     mj::DescCall &c) {
+    if (!plan || nblocks < 0 || nblocks > INT32_MAX) return MOJETTE_EINVAL;
+    if (nblocks > 0 && (!blocks || !pool || !workspace)) return MOJETTE_EINVAL;
+    if (((uintptr_t)workspace & 255) != 0) return MOJETTE_EINVAL;
+    c = mj::DescCall{};
+    c.desc = blocks;
+    c.nblocks = nblocks;
+    c.geoms = plan->d_geoms;
+    c.ngeoms = (int32_t)plan->geoms.size();
+    c.ws = static_cast<uint8_t *>(workspace);
+    c.pool = pool;
+    c.status = status;
+    c.decode = decode ? 1 : 0;
+    c.group_by_q = decode && !mj::decode_desc_supported(plan->qmask) ? 1 : 0;
+    return MOJETTE_OK;
+}
+
+int mojette_encode_batched(const mojette_plan *plan, const mojette_block *blocks,
+                           int64_t nblocks, uint64_t *pool, void *workspace, int32_t *status,
+                           void *stream) {
+    mj::DescCall c;
+    int rc = desc_call(plan, blocks, nblocks, pool, workspace, status, false, c);
+    if (rc != MOJETTE_OK || nblocks == 0) return rc;
+    const hipStream_t s = (hipStream_t)stream;
+    clear_stale_error();
+    if ((rc = status_of(mj::launch_desc_buckets(c, s))) != MOJETTE_OK) return rc;
+    // work items are (block, tile): a grid that loops over them
+    const int grid = (int)std::min<int64_t>(kEncodeGridCap, std::max<int64_t>(1, nblocks * 8));
+    return status_of(mj::launch_encode_desc(plan->qmax, c, 0, plan->enc_lds, grid, s));
+}
+
+int mojette_decode_batched(const mojette_plan *plan, const mojette_block *blocks,
+                           int64_t nblocks, uint64_t *pool, void *workspace, int32_t *status,
+                           void *stream) {
+    mj::DescCall c;
+    int rc = desc_call(plan, blocks, nblocks, pool, workspace, status, true, c);
+    if (rc != MOJETTE_OK || nblocks == 0) return rc;
+    const hipStream_t s = (hipStream_t)stream;
+    clear_stale_error();
+    if ((rc = status_of(mj::launch_desc_buckets(c, s))) != MOJETTE_OK) return rc;
+    // at most one batch per block: a grid of that many (capped) loops over them
+    const int grid = (int)std::min<int64_t>(kDecodeGridCap, nblocks);
+    if (!c.group_by_q)
+        return status_of(mj::launch_decode_desc(plan->qmask, c, 0, plan->dec_lds, grid, s));
+    for (int q = 1; q <= kMaxRows; ++q) {
+        if (!((plan->qmask >> q) & 1u)) continue;
+        size_t lds = 0;
+        for (const mj::GeomDev &g : plan->geoms) {
+            if (g.Q != q) continue;
+            lds = std::max(lds, mj::decode_lds_bytes(q, g.nb, g.R + 1));
+            if (g.R_short > 0) lds = std::max(lds, mj::decode_lds_bytes(q, g.nb_short, g.R_short + 1));
+        }
+        if ((rc = status_of(mj::launch_decode_desc(1u << q, c, q, lds, grid, s))) != MOJETTE_OK)
+            return rc;
+    }
+    return MOJETTE_OK;
 }
 
 }  // extern "C"

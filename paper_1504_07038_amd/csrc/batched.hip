@@ -1,0 +1,436 @@
+// Descriptor-driven batched calls on gfx950: the bucket kernels that group
+// the described blocks into classes of equal (code, row length, decode ring
+// class) in the caller's workspace, and the decode launch over those
+// classes.  The encode launch over the same classes is in encode.hip.
+//
+// Bucketing is four short launches:
+//   clear    zeroes the hash table of class keys and the header;
+//   count    one thread per descriptor checks it, finds its class key (the
+//            decode also checks that Q projections survive and sorts the
+//            survivor set into the short- or full-ring class of its code),
+//            inserts the key into an open-addressing hash table, and takes
+//            its rank within the class (one atomic per distinct key per
+//            wavefront);
+//   layout   one workgroup compacts the table into a class list sorted by
+//            launch group, longest rows first, and fills each class's launch
+//            parameters and the prefix sums of blocks and work items;
+//   scatter  places every block in its class's segment of the index list
+//            (its place is its class's start plus its rank, so no second
+//            round of atomics is needed).
+// The transform launches then walk the work items of one group, class by
+// class in that order; every block of a class has the same geometry, so a
+// wavefront's slots share the sweep of the whole-block decode.
+#include "decode_body.h"
+
+namespace mj {
+
+namespace {
+
+constexpr int kLayoutThreads = 1024;
+
+__device__ __forceinline__ uint64_t class_key(int geom, int ring, uint32_t P) {
+    return ((uint64_t)(geom + 1) << 32) | ((uint64_t)ring << 31) | P;   // never 0
+}
+
+// Fibonacci hashing (Knuth, TAOCP vol. 3, 6.4): the top bits of key * 2^64/phi.
+__device__ __forceinline__ uint32_t slot_hash(uint64_t key) {
+    return (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> 52) & (kDescSlots - 1);
+}
+
+// The deepest read behind a row's newest pixel for the survivor set of
+// `mask` (the Q survivors of smallest p, the r-th rebuilding row r):
+// max over rows r != l of ceil((A_l - A_r)/2) - 1 - (l - r) p_r, with
+// A_r = 2 (p_0 + ... + p_{r-1}) + r.
+__device__ int survivor_depth(const GeomDev &g, uint32_t mask) {
+    int ps[kMaxRows], A[kMaxRows];
+    int cnt = 0, psum = 0;
+    for (int s = 0; s < g.n && cnt < g.Q; ++s) {
+        if ((mask >> g.id_sorted[s]) & 1u) continue;
+        ps[cnt] = g.p_sorted[s];
+        A[cnt] = 2 * psum + cnt;
+        psum += g.p_sorted[s];
+        ++cnt;
+    }
+    int depth = 0;
+    for (int r = 0; r < cnt; ++r)
+        for (int l = 0; l < cnt; ++l)
+            if (l != r) depth = max(depth, ceil_half(A[l] - A[r]) - 1 - (l - r) * ps[r]);
+    return depth;
+}
+
+__global__ void desc_clear_kernel(uint8_t *ws) {
+    uint64_t *keys = reinterpret_cast<uint64_t *>(ws + DescWorkspace::kKeys);
+    uint32_t *counts = reinterpret_cast<uint32_t *>(ws + DescWorkspace::kCounts);
+    for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < kDescSlots;
+         s += gridDim.x * blockDim.x) {
+        keys[s] = 0;
+        counts[s] = 0;
+    }
+    if (blockIdx.x == 0 && threadIdx.x < sizeof(DescHeader) / 4)
+        reinterpret_cast<uint32_t *>(ws + DescWorkspace::kHeader)[threadIdx.x] = 0;
+}
+
+// Inserts `key` (or finds it) and returns its slot, -1 if the table is full.
+__device__ int insert_key(uint64_t *keys, uint64_t key) {
+    uint32_t h = slot_hash(key);
+    for (int probe = 0; probe < kDescSlots; ++probe) {
+        const uint64_t seen = __atomic_load_n(&keys[h], __ATOMIC_RELAXED);
+        if (seen == key) return (int)h;
+        if (seen == 0) {
+            const uint64_t prev = atomicCAS((unsigned long long *)&keys[h], 0ull,
+                                            (unsigned long long)key);
+            if (prev == 0 || prev == key) return (int)h;
+        }
+        h = (h + 1) & (kDescSlots - 1);
+    }
+    return -1;
+}
+
+__global__ __launch_bounds__(256) void desc_count_kernel(DescCall c) {
+    uint64_t *keys = reinterpret_cast<uint64_t *>(c.ws + DescWorkspace::kKeys);
+    uint32_t *counts = reinterpret_cast<uint32_t *>(c.ws + DescWorkspace::kCounts);
+    int2 *slot_of = reinterpret_cast<int2 *>(c.ws + DescWorkspace::kSlotOf);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    // every lane of a wavefront runs the same number of rounds (ballots below)
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~(kWave - 1));
+         base < c.nblocks; base += stride) {
+        const int64_t i = base + lane;
+        int st = MOJETTE_OK;
+        uint64_t key = 0;
+        if (i < c.nblocks) {
+            const mojette_block b = c.desc[i];
+            if (b.geom_id >= c.ngeoms || b.P < 1 || b.P > (uint32_t)kDescMaxP) {
+                st = MOJETTE_EINVAL;
+            } else {
+                const GeomDev &g = c.geoms[b.geom_id];
+                int ring = 0;
+                if ((int64_t)b.P * g.Q > ((int64_t)1 << 30)) {
+                    st = MOJETTE_EINVAL;
+                } else if (c.decode) {
+                    const uint32_t all = (1u << g.n) - 1u;
+                    if (__builtin_popcount(~(uint32_t)b.erasure_mask & all) < g.Q)
+                        st = MOJETTE_ENOTRECON;
+                    else if (g.R_short > 0 &&
+                             survivor_depth(g, b.erasure_mask) <= g.depth_short)
+                        ring = 1;
+                }
+                if (st == MOJETTE_OK) key = class_key(b.geom_id, ring, b.P);
+            }
+        }
+        // one insertion and one count per distinct key of the wavefront
+        int slot = -1, rank = 0;
+        uint64_t todo = __ballot(key != 0);
+        while (todo) {
+            const int leader = __builtin_ctzll(todo);
+            const uint64_t lk = __shfl(key, leader);
+            const uint64_t same = __ballot(key == lk);
+            int ls = -1;
+            uint32_t base_rank = 0;
+            if (lane == leader) {
+                ls = insert_key(keys, lk);
+                if (ls >= 0) base_rank = atomicAdd(&counts[ls], (uint32_t)__popcll(same));
+            }
+            ls = __shfl(ls, leader);
+            base_rank = __shfl(base_rank, leader);
+            if (key == lk) {
+                slot = ls;
+                rank = (int)base_rank + __popcll(same & ((1ull << lane) - 1ull));
+            }
+            todo &= ~same;
+        }
+        if (key != 0 && slot < 0) st = MOJETTE_ENOTSUP;
+        if (i < c.nblocks) slot_of[i] = make_int2(st == MOJETTE_OK ? slot : -1, rank);
+        if (st != MOJETTE_OK && c.status) *c.status = st;
+    }
+}
+
+__device__ __forceinline__ int64_t class_weight_items(const DescCall &c, const GeomDev &g,
+                                                      int ring, int P, int64_t count, int &nb,
+                                                      int &W) {
+    if (c.decode) {
+        nb = ring ? g.nb_short : g.nb;
+        return (count + nb - 1) / nb;
+    }
+    W = min(g.enc_w, P);
+    return count * ((P + W - 1) / W);
+}
+
+__global__ __launch_bounds__(kLayoutThreads) void desc_layout_kernel(DescCall c) {
+    __shared__ uint64_t order[kDescSlots];   // sort keys: group, longest rows first, slot
+    __shared__ int64_t scan[kLayoutThreads];
+    __shared__ int nclasses;
+    const uint64_t *keys = reinterpret_cast<const uint64_t *>(c.ws + DescWorkspace::kKeys);
+    const uint32_t *counts = reinterpret_cast<const uint32_t *>(c.ws + DescWorkspace::kCounts);
+    int32_t *slot_class = reinterpret_cast<int32_t *>(c.ws + DescWorkspace::kSlotClass);
+    int64_t *seg_start = reinterpret_cast<int64_t *>(c.ws + DescWorkspace::kSegStart);
+    int64_t *first_item = reinterpret_cast<int64_t *>(c.ws + DescWorkspace::kFirstItem);
+    DescHeader &hd = *reinterpret_cast<DescHeader *>(c.ws + DescWorkspace::kHeader);
+    const int tid = threadIdx.x;
+    constexpr int PER = kDescSlots / kLayoutThreads;
+
+    // 1. compact the occupied slots (in slot order) into sort keys
+    int occ = 0;
+    for (int k = 0; k < PER; ++k) occ += keys[tid * PER + k] != 0 && counts[tid * PER + k] > 0;
+    scan[tid] = occ;
+    __syncthreads();
+    for (int off = 1; off < kLayoutThreads; off <<= 1) {   // inclusive scan (Hillis-Steele)
+        const int64_t v = tid >= off ? scan[tid - off] : 0;
+        __syncthreads();
+        scan[tid] += v;
+        __syncthreads();
+    }
+    int at = (int)scan[tid] - occ;
+    if (tid == kLayoutThreads - 1) nclasses = (int)scan[tid];
+    for (int k = 0; k < PER; ++k) {
+        const int s = tid * PER + k;
+        const uint64_t key = keys[s];
+        if (key == 0 || counts[s] == 0) continue;
+        const int geom = (int)(key >> 32) - 1;
+        const uint32_t P = (uint32_t)key & 0x7FFFFFFFu;
+        const int Q = c.geoms[geom].Q;
+        const uint64_t group = c.group_by_q ? (uint64_t)Q : 0;
+        // ascending: group, then P descending, then Q descending, then slot
+        order[at++] = (group << 59) | ((uint64_t)(0x1FFFFFFu - P) << 34) |
+                      ((uint64_t)(0xFF - Q) << 26) | (uint64_t)s;
+    }
+    __syncthreads();
+    const int nc = nclasses;
+    int n2 = 1;
+    while (n2 < nc) n2 <<= 1;
+    for (int s = nc + tid; s < n2; s += kLayoutThreads) order[s] = ~0ull;
+    __syncthreads();
+    // 2. bitonic sort of the n2 keys
+    for (int k = 2; k <= n2; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = tid; i < n2; i += kLayoutThreads) {
+                const int ixj = i ^ j;
+                if (ixj > i) {
+                    const uint64_t a = order[i], b = order[ixj];
+                    const bool up = (i & k) == 0;
+                    if ((a > b) == up) {
+                        order[i] = b;
+                        order[ixj] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    // 3. per class (sorted): blocks and work items, scanned in order
+    constexpr int CPT = kDescSlots / kLayoutThreads;   // classes per thread, consecutive
+    int64_t my_blocks[CPT], my_items[CPT];
+    int64_t tb = 0, ti = 0;
+    for (int k = 0; k < CPT; ++k) {
+        const int ci = tid * CPT + k;
+        my_blocks[k] = my_items[k] = 0;
+        if (ci >= nc) continue;
+        const int s = (int)(order[ci] & (kDescSlots - 1));
+        const uint64_t key = keys[s];
+        const int geom = (int)(key >> 32) - 1;
+        const int ring = (int)((key >> 31) & 1);
+        const int P = (int)(key & 0x7FFFFFFFu);
+        int nb = 1, W = 1;
+        my_blocks[k] = counts[s];
+        my_items[k] = class_weight_items(c, c.geoms[geom], ring, P, counts[s], nb, W);
+        tb += my_blocks[k];
+        ti += my_items[k];
+    }
+    // exclusive scans of blocks and items over threads (two passes of one buffer)
+    int64_t blocks_before = 0, items_before = 0;
+    for (int pass = 0; pass < 2; ++pass) {
+        scan[tid] = pass == 0 ? tb : ti;
+        __syncthreads();
+        for (int off = 1; off < kLayoutThreads; off <<= 1) {
+            const int64_t v = tid >= off ? scan[tid - off] : 0;
+            __syncthreads();
+            scan[tid] += v;
+            __syncthreads();
+        }
+        const int64_t excl = scan[tid] - (pass == 0 ? tb : ti);
+        if (pass == 0) blocks_before = excl; else items_before = excl;
+        if (pass == 0 && tid == kLayoutThreads - 1) seg_start[nc] = scan[tid];
+        if (pass == 1 && tid == kLayoutThreads - 1) first_item[nc] = scan[tid];
+        __syncthreads();
+    }
+    int32_t *idx = reinterpret_cast<int32_t *>(c.ws + DescWorkspace::idx_at(c.nblocks));
+    for (int k = 0; k < CPT; ++k) {
+        const int ci = tid * CPT + k;
+        if (ci >= nc) continue;
+        const int s = (int)(order[ci] & (kDescSlots - 1));
+        const uint64_t key = keys[s];
+        const int geom = (int)(key >> 32) - 1;
+        const int ring = (int)((key >> 31) & 1);
+        const int P = (int)(key & 0x7FFFFFFFu);
+        const GeomDev &g = c.geoms[geom];
+        slot_class[s] = ci;
+        seg_start[ci] = blocks_before;
+        first_item[ci] = items_before;
+        int nb = 1, W = 1;
+        class_weight_items(c, g, ring, P, counts[s], nb, W);
+        int32_t off[kMaxDirs];
+        int32_t o = 0;
+        for (int i = 0; i < g.n; ++i) {
+            off[i] = o;
+            o += proj_bins(g.dirs[i], P, g.Q);
+        }
+        if (c.decode) {
+            DecodeDesc &d = reinterpret_cast<DecodeDesc *>(c.ws + DescWorkspace::kClasses)[ci];
+            d.desc = c.desc;
+            d.idx = idx + blocks_before;
+            d.pool = c.pool;
+            d.status = c.status;
+            d.images = nullptr;
+            d.masks = nullptr;
+            d.slots = nullptr;
+            d.nblocks = my_blocks[k];
+            d.proj_stride = o;
+            d.img_stride = (int64_t)P * g.Q;
+            d.P = P;
+            d.Q = g.Q;
+            d.n = g.n;
+            d.nb = nb;
+            d.R = ring ? g.R_short : g.R;
+            d.ring_stride = d.R + 1;
+            d.mask_uniform = 0;
+            for (int i = 0; i < kMaxDirs; ++i) {
+                d.off[i] = i < g.n ? off[i] : 0;
+                d.p_sorted[i] = g.p_sorted[i];
+                d.id_sorted[i] = g.id_sorted[i];
+            }
+        } else {
+            EncodeDesc &e = reinterpret_cast<EncodeDesc *>(c.ws + DescWorkspace::kClasses)[ci];
+            e.desc = c.desc;
+            e.idx = idx + blocks_before;
+            e.pool = c.pool;
+            e.nblocks = my_blocks[k];
+            e.P = P;
+            e.Q = g.Q;
+            e.n = g.n;
+            e.W = W;
+            e.H = g.H;
+            e.S = W + 2 * g.H;
+            e.ntiles = (P + W - 1) / W;
+            e.bin_swap = 0;
+            for (int i = 0; i < kMaxDirs; ++i) {
+                e.off[i] = i < g.n ? off[i] : 0;
+                e.p[i] = (int16_t)(i < g.n ? g.dirs[i] : 0);
+            }
+        }
+        blocks_before += my_blocks[k];
+        items_before += my_items[k];
+        // launch groups: where the group of consecutive classes changes
+        const int grp = (int)(order[ci] >> 59);
+        if (ci == 0 || (int)(order[ci - 1] >> 59) != grp) hd.range[2 * grp] = first_item[ci];
+        if (ci == nc - 1 || (int)(order[ci + 1] >> 59) != grp)
+            hd.range[2 * grp + 1] = first_item[ci] + my_items[k];
+    }
+    if (tid == 0) hd.nclasses = nc;
+}
+
+__global__ __launch_bounds__(256) void desc_scatter_kernel(DescCall c) {
+    const int2 *slot_of = reinterpret_cast<const int2 *>(c.ws + DescWorkspace::kSlotOf);
+    const int32_t *slot_class = reinterpret_cast<const int32_t *>(c.ws + DescWorkspace::kSlotClass);
+    const int64_t *seg_start = reinterpret_cast<const int64_t *>(c.ws + DescWorkspace::kSegStart);
+    int32_t *idx = reinterpret_cast<int32_t *>(c.ws + DescWorkspace::idx_at(c.nblocks));
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < c.nblocks;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int2 sr = slot_of[i];
+        if (sr.x < 0) continue;
+        idx[seg_start[slot_class[sr.x]] + sr.y] = (int32_t)i;
+    }
+}
+
+// The decode of the work items of launch group g: batches of every class of
+// the group, in class order, one wavefront per workgroup.  QMASK has bit Q
+// set for every row count the launch may meet (only those bodies are
+// compiled in); bodies are compiled for half the block slots.
+template <unsigned QMASK>
+__global__ __launch_bounds__(kWave) void decode_desc_kernel(const uint8_t *ws, int g) {
+    const DescHeader &hd = *reinterpret_cast<const DescHeader *>(ws + DescWorkspace::kHeader);
+    const int64_t *first = reinterpret_cast<const int64_t *>(ws + DescWorkspace::kFirstItem);
+    const DecodeDesc *cls = reinterpret_cast<const DecodeDesc *>(ws + DescWorkspace::kClasses);
+    const int64_t lo = hd.range[2 * g], hi = hd.range[2 * g + 1];
+    const int nc = hd.nclasses;
+    for (int64_t item = lo + blockIdx.x; item < hi; item += gridDim.x) {
+        int c0 = 0, c1 = nc;
+        while (c1 - c0 > 1) {
+            const int m = (c0 + c1) >> 1;
+            if (first[m] <= item) c0 = m; else c1 = m;
+        }
+        const DecodeDesc &a = cls[c0];
+        const int64_t batch = item - first[c0];
+        switch (a.Q) {
+#define MJ_DEC_CASE(QQ)                                                                    \
+    case QQ:                                                                               \
+        if constexpr ((QMASK >> QQ) & 1u)                                                 \
+            decode_batch<QQ, kDecodeTile, false, kWhole, half_slots<QQ>(), DecodeDesc, 0>( \
+                a, batch);                                                                 \
+        break;
+            MJ_DEC_CASE(1) MJ_DEC_CASE(2) MJ_DEC_CASE(3) MJ_DEC_CASE(4)
+            MJ_DEC_CASE(5) MJ_DEC_CASE(6) MJ_DEC_CASE(7) MJ_DEC_CASE(8)
+            MJ_DEC_CASE(9) MJ_DEC_CASE(10) MJ_DEC_CASE(11) MJ_DEC_CASE(12)
+            MJ_DEC_CASE(13) MJ_DEC_CASE(14) MJ_DEC_CASE(15) MJ_DEC_CASE(16)
+#undef MJ_DEC_CASE
+            default: break;
+        }
+    }
+}
+
+constexpr unsigned qbit(int q) { return 1u << q; }
+
+}  // namespace
+
+hipError_t launch_desc_buckets(const DescCall &c, hipStream_t s) {
+    hipLaunchKernelGGL(desc_clear_kernel, dim3(kDescSlots / 256), dim3(256), 0, s, c.ws);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((c.nblocks + 255) / 256, 4096));
+    hipLaunchKernelGGL(desc_count_kernel, dim3(grid), dim3(256), 0, s, c);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(desc_layout_kernel, dim3(1), dim3(kLayoutThreads), 0, s, c);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(desc_scatter_kernel, dim3(grid), dim3(256), 0, s, c);
+    return hipGetLastError();
+}
+
+// Row-count sets with a combined descriptor decode kernel: every single row
+// count, and the (4,2)+(8,4) and (4,2)+(6,3)+(8,4)+(12,4) code families.
+bool decode_desc_supported(unsigned qmask) {
+    if (qmask && !(qmask & (qmask - 1))) return true;
+    return qmask == (qbit(4) | qbit(8)) || qmask == (qbit(4) | qbit(6) | qbit(8) | qbit(12));
+}
+
+hipError_t launch_decode_desc(unsigned qmask, const DescCall &c, int g, size_t lds, int grid,
+                              hipStream_t s) {
+    const uint8_t *ws = c.ws;
+#define MJ_LAUNCH(M) \
+    hipLaunchKernelGGL((decode_desc_kernel<M>), dim3(grid), dim3(kWave), lds, s, ws, g)
+    switch (qmask) {
+        case qbit(1): MJ_LAUNCH(qbit(1)); break;
+        case qbit(2): MJ_LAUNCH(qbit(2)); break;
+        case qbit(3): MJ_LAUNCH(qbit(3)); break;
+        case qbit(4): MJ_LAUNCH(qbit(4)); break;
+        case qbit(5): MJ_LAUNCH(qbit(5)); break;
+        case qbit(6): MJ_LAUNCH(qbit(6)); break;
+        case qbit(7): MJ_LAUNCH(qbit(7)); break;
+        case qbit(8): MJ_LAUNCH(qbit(8)); break;
+        case qbit(9): MJ_LAUNCH(qbit(9)); break;
+        case qbit(10): MJ_LAUNCH(qbit(10)); break;
+        case qbit(11): MJ_LAUNCH(qbit(11)); break;
+        case qbit(12): MJ_LAUNCH(qbit(12)); break;
+        case qbit(13): MJ_LAUNCH(qbit(13)); break;
+        case qbit(14): MJ_LAUNCH(qbit(14)); break;
+        case qbit(15): MJ_LAUNCH(qbit(15)); break;
+        case qbit(16): MJ_LAUNCH(qbit(16)); break;
+        case qbit(4) | qbit(8): MJ_LAUNCH(qbit(4) | qbit(8)); break;
+        case qbit(4) | qbit(6) | qbit(8) | qbit(12):
+            MJ_LAUNCH(qbit(4) | qbit(6) | qbit(8) | qbit(12));
+            break;
+        default: return hipErrorInvalidValue;
+    }
+#undef MJ_LAUNCH
+    return hipGetLastError();
+}
+
+}  // namespace mj

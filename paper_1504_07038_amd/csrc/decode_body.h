@@ -63,6 +63,15 @@ __device__ __forceinline__ int ceil_half(int x) { return x >= 0 ? (x + 1) / 2 : 
 template <class T>
 constexpr bool kIsDecodeArgs = std::is_same<T, DecodeArgs>::value;
 
+// Descriptor-driven classes (DecodeDesc) find a block's mask, bins and image
+// through its descriptor; the other argument types through their pools.
+template <class T, class = void>
+struct IsDesc : std::false_type {};
+template <class T>
+struct IsDesc<T, std::void_t<decltype(T::kDesc)>> : std::bool_constant<T::kDesc> {};
+template <class T>
+constexpr bool kIsDesc = IsDesc<T>::value;
+
 __device__ __forceinline__ int wave_max(int v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
@@ -147,6 +156,7 @@ struct SegParam {
     int mis;       // aligned loads: the row window's offset past a 128-byte line
     int img;       // offset (in the wave's image slice) of the segment's row
     const uint64_t *bins;   // pointer mode: the row's projection
+    uint64_t *dst;          // descriptor classes: the segment's image row
     bool on;       // segment belongs to a block slot in use
     bool known;    // systematic code: a surviving line (staged from the image, not stored)
 };
@@ -256,7 +266,11 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch,
     {
         const bool blk_ok = lane_used && blk < (gathered ? gather_hi : a.nblocks);
         uint32_t mask = a.mask_uniform;
-        if (blk_ok && a.masks) mask = a.masks[blk];
+        if constexpr (kIsDesc<Args>) {
+            if (blk_ok) mask = a.mask_of(blk);
+        } else {
+            if (blk_ok && a.masks) mask = a.masks[blk];
+        }
 
         // Survivors in ascending p; row r takes the r-th.
         int p0 = 0, p1 = 0, id0 = 0, id1 = 0, A0 = 0, A1 = 0;
@@ -474,12 +488,14 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch,
             const int own0 = valid && st0 ? dr0 : INT_MIN;
             const int own1 = valid && st1 ? dr1 : INT_MIN;
             const int known = SYS && valid ? (!sw0 ? 1 : 0) | (!sw1 ? 2 : 0) : 0;
-            // pointer mode: the projections of this lane's two rows
-            uint64_t pb0 = 0, pb1 = 0;
+            // pointer mode: the projections of this lane's two rows (and,
+            // for descriptor classes, its block's image)
+            uint64_t pb0 = 0, pb1 = 0, ib = 0;
             if constexpr (!POOL) {
                 if (valid) {
                     pb0 = (uint64_t)a.proj_base(blk, id0);
                     pb1 = (uint64_t)a.proj_base(blk, id1);
+                    if constexpr (kIsDesc<Args>) ib = (uint64_t)a.image_of(blk);
                 }
             }
 #pragma unroll
@@ -519,6 +535,7 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch,
                 s.ring = (sslot < NB ? sslot : 0) * SS + srow * RS;
                 s.gbin = odd ? og1 : og0;
                 s.bins = nullptr;
+                s.dst = nullptr;
                 if constexpr (!POOL) {
                     // both rows' pointers come over; the requester picks
                     const uint32_t lo0 = __shfl((uint32_t)pb0, src);
@@ -527,6 +544,11 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch,
                     const uint32_t hi1 = __shfl((uint32_t)(pb1 >> 32), src);
                     s.bins = (const uint64_t *)(odd ? (((uint64_t)hi1 << 32) | lo1)
                                                     : (((uint64_t)hi0 << 32) | lo0));
+                    if constexpr (kIsDesc<Args>) {
+                        const uint32_t ilo = __shfl((uint32_t)ib, src);
+                        const uint32_t ihi = __shfl((uint32_t)(ib >> 32), src);
+                        s.dst = (uint64_t *)(((uint64_t)ihi << 32) | ilo) + orow * P;
+                    }
                 }
                 s.col0 = dd + TW - 1 - (W == 1 ? 2 * q : q) + oshift;
                 // the window of tile t starts at word gbin - col0 - 2q - TW*t
@@ -690,7 +712,11 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch,
                             __builtin_amdgcn_raw_buffer_store_b64(
                                 u32x2{(uint32_t)w0, (uint32_t)(w0 >> 32)}, rout, off1, 0, STPOL);
                     } else {
-                        uint64_t *dst = a.images + first * a.img_stride + s.img;
+                        uint64_t *dst;
+                        if constexpr (kIsDesc<Args>)
+                            dst = s.dst;
+                        else
+                            dst = a.images + first * a.img_stride + s.img;
                         if (both) {
                             store_pair(dst + c, w0, w1);
                         } else if (last) {

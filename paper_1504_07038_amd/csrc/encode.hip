@@ -35,11 +35,11 @@ __device__ __forceinline__ void encode_item(const A &a, int64_t blk, int t, uint
                                             int lane) {
     const int P = a.P, W = a.W, H = a.H, S = a.S;
     const int x0 = t * W;
-    const uint64_t *img = a.images + blk * (int64_t)P * Q;
+    const uint64_t *img = a.image_of(blk);
 
     uint32_t use = 0;                       // VERIFY: the projections checked
     if constexpr (VERIFY) {
-        const uint32_t mask = a.masks ? a.masks[blk] : 0u;
+        const uint32_t mask = a.masks ? a.masks[blk] : a.mask_uniform;
         use = ~mask & ((1u << a.n) - 1u);
     }
 
@@ -219,6 +219,58 @@ __global__ __launch_bounds__(kWave) void encode_classes_kernel(EncodeClassTable 
             default: break;
         }
     }
+}
+
+// A descriptor-driven launch: the items of the classes of launch group g
+// (heaviest first), read from the call's workspace, one wavefront per
+// workgroup; the grid loops until the group's items are done.
+template <int QMAX>
+__global__ __launch_bounds__(kWave) void encode_desc_kernel(const uint8_t *ws, int g) {
+    extern __shared__ uint64_t lds[];
+    const int lane = threadIdx.x;
+    const DescHeader &hd = *reinterpret_cast<const DescHeader *>(ws + DescWorkspace::kHeader);
+    const int64_t *first = reinterpret_cast<const int64_t *>(ws + DescWorkspace::kFirstItem);
+    const EncodeDesc *cls = reinterpret_cast<const EncodeDesc *>(ws + DescWorkspace::kClasses);
+    const int64_t lo = hd.range[2 * g], hi = hd.range[2 * g + 1];
+    const int nc = hd.nclasses;
+    for (int64_t item = lo + blockIdx.x; item < hi; item += gridDim.x) {
+        // the class holding the item: the last c with first[c] <= item
+        int c0 = 0, c1 = nc;
+        while (c1 - c0 > 1) {
+            const int m = (c0 + c1) >> 1;
+            if (first[m] <= item) c0 = m; else c1 = m;
+        }
+        const EncodeDesc &a = cls[c0];
+        const int64_t local = item - first[c0];
+        const int64_t blk = local / a.ntiles;
+        const int t = (int)(local - blk * a.ntiles);
+        switch (a.Q) {
+#define MJ_ENC_CASE(QQ)                                      \
+    case QQ:                                                 \
+        if constexpr (QQ <= QMAX) encode_item<QQ>(a, blk, t, lds, lane); \
+        break;
+            MJ_ENC_CASE(1) MJ_ENC_CASE(2) MJ_ENC_CASE(3) MJ_ENC_CASE(4)
+            MJ_ENC_CASE(5) MJ_ENC_CASE(6) MJ_ENC_CASE(7) MJ_ENC_CASE(8)
+            MJ_ENC_CASE(9) MJ_ENC_CASE(10) MJ_ENC_CASE(11) MJ_ENC_CASE(12)
+            MJ_ENC_CASE(13) MJ_ENC_CASE(14) MJ_ENC_CASE(15) MJ_ENC_CASE(16)
+#undef MJ_ENC_CASE
+            default: break;
+        }
+    }
+}
+
+hipError_t launch_encode_desc(int qmax, const DescCall &c, int g, size_t lds, int grid,
+                              hipStream_t s) {
+    const uint8_t *ws = c.ws;
+    if (qmax <= 4)
+        hipLaunchKernelGGL(encode_desc_kernel<4>, dim3(grid), dim3(kWave), lds, s, ws, g);
+    else if (qmax <= 8)
+        hipLaunchKernelGGL(encode_desc_kernel<8>, dim3(grid), dim3(kWave), lds, s, ws, g);
+    else if (qmax <= 12)
+        hipLaunchKernelGGL(encode_desc_kernel<12>, dim3(grid), dim3(kWave), lds, s, ws, g);
+    else
+        hipLaunchKernelGGL(encode_desc_kernel<16>, dim3(grid), dim3(kWave), lds, s, ws, g);
+    return hipGetLastError();
 }
 
 hipError_t launch_encode_classes(int qmax, const EncodeClassTable &tab, size_t lds, int grid,

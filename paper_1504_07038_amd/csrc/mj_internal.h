@@ -65,6 +65,7 @@ struct EncodeArgs {
     }
     __device__ int kept_first(int i) const { return keep_lo[i]; }
     __device__ int kept_count(int i, int full) const { return keep_n[i] ? keep_n[i] : full; }
+    __device__ const uint64_t *image_of(int64_t blk) const { return images + blk * (int64_t)P * Q; }
 };
 
 // Consistency check: every surviving projection recomputed from the image and
@@ -72,6 +73,7 @@ struct EncodeArgs {
 struct VerifyArgs : EncodeArgs {
     const uint64_t *par[kMaxDirs];
     const uint16_t *masks;           // bit i: projection i lost (not checked); may be null
+    uint32_t mask_uniform;           // the mask of every block when masks is null
     int32_t *status;
 };
 
@@ -95,6 +97,7 @@ struct EncodeClass {
     }
     __device__ int kept_first(int) const { return 0; }      // mixed launches keep every bin
     __device__ int kept_count(int, int full) const { return full; }
+    __device__ const uint64_t *image_of(int64_t blk) const { return images + blk * (int64_t)P * Q; }
 };
 
 constexpr int kMaxClasses = MOJETTE_MAX_CLASSES;
@@ -218,6 +221,124 @@ struct DecodeClassTable {
     int64_t first_item[kMaxClasses + 1];   // batches of class c: [first_item[c], first_item[c+1])
     int32_t nclasses;
 };
+
+// ---- descriptor-driven batched calls ----------------------------------------
+// Blocks are described by device descriptors (mojette_block): each names its
+// code (geom_id into the plan's geometry table), its row length P, where its
+// image and projections sit in one word pool, and its erasure mask.  A call
+// first sorts the blocks into classes of equal (code, P, decode ring class)
+// on the device (bucket kernels, in the caller's workspace), then one
+// persistent launch walks the classes' work items, heaviest first.
+
+// One code of a plan, as the device kernels read it.
+struct GeomDev {
+    int32_t Q, n;
+    int32_t sumabs;                  // sum of |p_i|: projection offsets are P-dependent
+    int32_t H;                       // encode halo, (Q-1) * max |p|
+    int32_t enc_w;                   // encode tile width cap (columns)
+    int32_t R, nb;                   // decode ring and blocks per wavefront, full ring
+    int32_t R_short, nb_short;       // short-ring class (0: none)
+    int32_t depth_short;             // survivor sets of depth <= this take the short ring
+    int32_t dirs[kMaxDirs];          // in the caller's order
+    int16_t p_sorted[kMaxDirs];      // ascending
+    int8_t id_sorted[kMaxDirs];
+};
+
+constexpr int kDescSlots = 4096;     // hash slots = most classes per call
+constexpr int kDescMaxP = 1 << 24;
+
+// One class of a descriptor-driven decode: field names follow DecodeClass so
+// that the same per-batch body serves it (pointer mode: a block's bins and
+// image are found through its descriptor).
+struct DecodeDesc {
+    const mojette_block *desc;
+    const int32_t *idx;              // the class's blocks: descriptor indices
+    uint64_t *pool;
+    int32_t *status;
+    uint64_t *images;                // unused (images are found per block)
+    const uint16_t *masks;           // unused (masks come with the descriptors)
+    const int64_t *slots;            // unused
+    int64_t nblocks;
+    int64_t proj_stride, img_stride;
+    int32_t P, Q, n, nb, R, ring_stride;
+    uint32_t mask_uniform;
+    int32_t off[kMaxDirs];
+    int16_t p_sorted[kMaxDirs];
+    int8_t id_sorted[kMaxDirs];
+    static constexpr bool kDesc = true;
+    __device__ const mojette_block &block(int64_t blk) const { return desc[idx[blk]]; }
+    __device__ const uint64_t *proj_base(int64_t blk, int id) const {
+        return pool + block(blk).proj_off + off[id];
+    }
+    __device__ uint64_t *image_of(int64_t blk) const { return pool + block(blk).image_off; }
+    __device__ uint32_t mask_of(int64_t blk) const { return block(blk).erasure_mask; }
+    __device__ int kept_first(int) const { return 0; }
+};
+
+// One class of a descriptor-driven encode (fields as EncodeClass).
+struct EncodeDesc {
+    const mojette_block *desc;
+    const int32_t *idx;
+    uint64_t *pool;
+    int64_t nblocks;
+    int32_t P, Q, n, W, H, S, ntiles;
+    int32_t bin_swap;                // always 0
+    int32_t off[kMaxDirs];
+    int16_t p[kMaxDirs];
+    __device__ int dir(int i) const { return p[i]; }
+    __device__ const mojette_block &block(int64_t blk) const { return desc[idx[blk]]; }
+    __device__ int64_t slice(int64_t blk) const { return (int64_t)block(blk).proj_off; }
+    __device__ uint64_t *proj_in(int i, int64_t slice) const { return pool + slice + off[i]; }
+    __device__ int kept_first(int) const { return 0; }
+    __device__ int kept_count(int, int full) const { return full; }
+    __device__ const uint64_t *image_of(int64_t blk) const { return pool + block(blk).image_off; }
+};
+
+// Workspace of a descriptor-driven call (byte offsets from its start; the
+// layout depends on nblocks only).
+struct DescWorkspace {
+    static constexpr size_t kHeader = 0;           // DescHeader
+    static constexpr size_t kKeys = 512;           // kDescSlots uint64 keys (0: empty)
+    static constexpr size_t kCounts = kKeys + 8 * kDescSlots;      // uint32 per slot
+    static constexpr size_t kSlotClass = kCounts + 4 * kDescSlots; // int32 per slot
+    static constexpr size_t kSegStart = kSlotClass + 4 * kDescSlots;  // int64 per class + 1
+    static constexpr size_t kFirstItem = kSegStart + 8 * (kDescSlots + 8); // int64 per class + 1
+    static constexpr size_t kClasses = kFirstItem + 8 * (kDescSlots + 8);
+    static constexpr size_t kClassBytes =
+        sizeof(DecodeDesc) > sizeof(EncodeDesc) ? sizeof(DecodeDesc) : sizeof(EncodeDesc);
+    static constexpr size_t kSlotOf = (kClasses + kClassBytes * kDescSlots + 255) / 256 * 256;
+    // per block: (slot, rank) as int2, then the index list (int32)
+    __host__ __device__ static size_t idx_at(int64_t nblocks) { return kSlotOf + (size_t)(8 * nblocks + 255) / 256 * 256; }
+    __host__ __device__ static size_t bytes(int64_t nblocks) { return idx_at(nblocks) + (size_t)(4 * nblocks + 255) / 256 * 256; }
+};
+
+struct DescHeader {   // at most DescWorkspace::kKeys bytes
+    int32_t nclasses;
+    int32_t error;                   // a status stored by the bucket kernels (table full)
+    int64_t range[2 * (kMaxRows + 1)];   // items of launch group g: [range[2g], range[2g+1])
+};
+
+// What the bucket kernels need of a call.
+struct DescCall {
+    const mojette_block *desc;
+    int64_t nblocks;
+    const GeomDev *geoms;
+    int32_t ngeoms;
+    uint8_t *ws;
+    uint64_t *pool;
+    int32_t *status;
+    int32_t decode;                  // 1: decode classes (ring classes, survivor check)
+    int32_t group_by_q;              // 1: one launch group per row count, else one group
+};
+
+hipError_t launch_desc_buckets(const DescCall &c, hipStream_t s);
+// One launch of a descriptor-driven decode or encode over launch group g
+// (every class when the call has one group; the classes of Q = g otherwise).
+hipError_t launch_decode_desc(unsigned qmask, const DescCall &c, int g, size_t lds, int grid,
+                              hipStream_t s);
+bool decode_desc_supported(unsigned qmask);
+hipError_t launch_encode_desc(int qmax, const DescCall &c, int g, size_t lds, int grid,
+                              hipStream_t s);
 
 // Status of a HIP call as a library status code; a failure is remembered for
 // mojette_last_hip_error() on the calling thread.

@@ -73,11 +73,13 @@ def test_argument_errors_before_any_launch(mj):
     assert L.mojette_encode(fake, 8, 2, dirs, 17, outs, None) == mj.MOJETTE_EINVAL
     ids = (ctypes.c_int32 * 2)(0, 0)
     projs = (ctypes.c_void_p * 2)(0x1000, 0x2000)
-    assert L.mojette_decode(projs, ids, 2, dirs, 3, 8, 2, fake, None) == mj.MOJETTE_EINVAL
+    assert L.mojette_decode(projs, ids, 2, dirs, 3, 8, 2, fake, 0, None) == mj.MOJETTE_EINVAL
     ids2 = (ctypes.c_int32 * 2)(0, 3)
-    assert L.mojette_decode(projs, ids2, 2, dirs, 3, 8, 2, fake, None) == mj.MOJETTE_EINVAL
+    assert L.mojette_decode(projs, ids2, 2, dirs, 3, 8, 2, fake, 0, None) == mj.MOJETTE_EINVAL
     ids3 = (ctypes.c_int32 * 1)(1)
-    assert L.mojette_decode(projs, ids3, 1, dirs, 3, 8, 2, fake, None) == mj.MOJETTE_ENOTRECON
+    assert L.mojette_decode(projs, ids3, 1, dirs, 3, 8, 2, fake, 0, None) == mj.MOJETTE_ENOTRECON
+    ids4 = (ctypes.c_int32 * 2)(0, 1)
+    assert L.mojette_decode(projs, ids4, 2, dirs, 3, 8, 2, fake, 2, None) == mj.MOJETTE_EINVAL  # unknown flag
     assert L.mojette_encode_batch(fake, -1, 8, 2, dirs, 3, fake, None) == mj.MOJETTE_EINVAL
     assert L.mojette_encode_batch(fake, 0, 8, 2, dirs, 3, fake, None) == mj.MOJETTE_OK
     assert L.mojette_decode_batch(fake, None, 0, 8, 2, dirs, 3, fake, None, None) == mj.MOJETTE_OK
@@ -166,3 +168,38 @@ def test_decode_launch_plan_split_and_32bit_slices(mj):
     # a wave slice of even a few blocks beyond 32-bit offsets is refused
     with pytest.raises(mj.MojetteError):
         mj.mojette_decode_batch_launches([-1, 0, 1], 1 << 28, 2, 4, 2)
+
+
+def test_geometry_plan_argument_errors(mj):
+    """mojette_plan_create checks every code on the host before it touches a
+    device; the batched calls check their arguments before any launch."""
+    L = mj.lib()
+    h = ctypes.c_void_p(0)
+
+    def create(geoms, tune=None):
+        arr = (mj.MojetteGeom * max(1, len(geoms)))()
+        for g, (Q, dirs) in enumerate(geoms):
+            arr[g].Q, arr[g].n = Q, len(dirs)
+            for i, p in enumerate(dirs):
+                arr[g].dirs[i] = p
+        t = None
+        if tune is not None:
+            t = (mj.MojetteTune * len(geoms))()
+            for g, d in enumerate(tune):
+                for k, v in d.items():
+                    setattr(t[g], k, v)
+        return L.mojette_plan_create(arr, len(geoms), t, ctypes.addressof(h))
+
+    assert create([]) == mj.MOJETTE_EINVAL
+    assert create([(4, [-1, 0, 0, 2, 3])]) == mj.MOJETTE_EINVAL        # duplicate direction
+    assert create([(4, [-1, 0, 1])]) == mj.MOJETTE_EINVAL              # n < Q
+    assert create([(17, list(range(16)))]) == mj.MOJETTE_EINVAL         # Q > 16
+    assert create([(2, [0, 40000])]) == mj.MOJETTE_EINVAL              # |p| too large
+    assert create([(4, [-3, -2, -1, 0, 1, 2])], [{"encode_tile_cols": 100}]) == mj.MOJETTE_EINVAL
+    assert create([(4, [-3, -2, -1, 0, 1, 2])], [{"decode_blocks_per_wave": -2}]) == mj.MOJETTE_EINVAL
+    assert h.value is None
+    assert L.mojette_workspace_size(None, 10) == -1
+    fake = ctypes.c_void_p(0x1000)
+    assert L.mojette_encode_batched(None, fake, 1, fake, fake, None, None) == mj.MOJETTE_EINVAL
+    assert L.mojette_decode_batched(None, fake, 1, fake, fake, None, None) == mj.MOJETTE_EINVAL
+    assert ctypes.sizeof(mj.MojetteGeom) == 72 and mj.block_dtype().itemsize == 24

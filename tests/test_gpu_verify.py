@@ -94,3 +94,33 @@ def test_verify_full_size_4k(mj):
     assert int(vst.item()) == -5
     del d_img, d_proj, d_out
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("P,Q,n", [(128, 4, 6), (60, 8, 12), (9, 2, 3)])
+def test_single_block_decode_with_verify_flag(mj, P, Q, n):
+    """mojette_decode with MOJETTE_VERIFY: clean projections give OK and the
+    image; one corrupted bit in any bin of any given projection gives
+    MOJETTE_EINCONSISTENT exactly when the oracle's peeling check (verify)
+    flags the same inputs."""
+    dirs = synth.centered_dirs(n)
+    img = synth.block_images(P + Q, 0, 1, P, Q)[0]
+    projs = oracle.forward(img, [(p, 1) for p in dirs])
+    rng = np.random.default_rng(P)
+    for m in (Q, n):
+        ids = sorted(int(i) for i in rng.permutation(n)[:m])
+        d_projs = [to_dev(projs[i]) for i in ids]
+        out = torch.zeros(Q * P, dtype=torch.int64, device="cuda")
+        assert mj.mojette_decode(d_projs, ids, dirs, P, Q, out, verify=True) == 0
+        assert np.array_equal(to_np(out).reshape(Q, P), img)
+        for trial in range(6):
+            t = int(rng.integers(0, m))
+            j = int(rng.integers(0, projs[ids[t]].size))
+            bad = [p.copy() for p in projs]
+            bad[ids[t]][j] ^= np.uint64(1) << np.uint64(int(rng.integers(0, 64)))
+            # the oracle's check on the same survivors (erased ones left out)
+            st_orc, _ = oracle.inverse([bad[i] for i in ids], [(dirs[i], 1) for i in ids], P, Q,
+                                       verify=True)
+            d_bad = [to_dev(bad[i]) for i in ids]
+            rc = mj.mojette_decode(d_bad, ids, dirs, P, Q, out, verify=True, check=False)
+            say(f"verify m={m} proj {ids[t]} bin {j}: library {rc}, oracle {st_orc}")
+            assert rc == (mj.MOJETTE_EINCONSISTENT if st_orc == oracle.EINCONSISTENT else 0)
