@@ -44,7 +44,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="4k_6_4", choices=sorted(WORKLOADS) + ["mixed", "serving", "tune", "chunked", "sys"])
-    ap.add_argument("--mixed-blocks", type=int, default=50000,
+    ap.add_argument("--mixed-budget-gib", type=float, default=70.0,
+                    help="mixed workload: device memory for the projections of one chunk")
+    ap.add_argument("--mixed-blocks", type=int, default=500000,
                     help="blocks of the mixed workload (16 size x code classes)")
     ap.add_argument("--qps", default="10000,20000,50000,100000,200000,500000,1000000,2000000",
                     help="serving: comma-separated arrival rates (requests/s)")
@@ -60,6 +62,11 @@ def parse():
                     help="summarise two rocprofv3 --pmc runs into profiles/traffic_*.json")
     ap.add_argument("--pmc-command", default="", help="command recorded with --pmc-summary")
     return ap.parse_args()
+
+
+def log(msg: str) -> None:
+    """Progress of a long run, on stderr."""
+    print(msg, file=sys.stderr, flush=True)
 
 
 def pct(xs, q):
@@ -383,12 +390,18 @@ def train_cost_model(codes):
 
 
 def run_mixed(args):
-    """The mixed workload: blocks of 4 KB, 8 KB, 64 KB and 1 MB under the
-    (4,2), (6,3), (8,4) and (12,4) codes (16 classes), erasures per block
-    uniform in 0..m.  One step = one encode launch over every class plus the
-    decode of every class, each class decoded with the schedule the learned
-    cost model picks (whole blocks, or chunked long rows), the whole step
-    captured in one HIP graph and replayed."""
+    """The batched uneven workload: --mixed-blocks blocks (500k by default),
+    each of a size uniform over {4 KB, 8 KB, 64 KB, 1 MB} and a code uniform
+    over (4,2), (6,3), (8,4), (12,4) (P = ceil(size / 8k), the last row
+    zero-padded), erasures per block uniform in 0..m then a uniform subset.
+    The images of every block stay resident in HBM; their projections go
+    through a buffer of --mixed-budget-gib, so the blocks run as chunks (in
+    block order) whose projections fit it: per chunk one descriptor-driven
+    encode and one decode (each a persistent launch after its bucket
+    kernels), decoding back into the images' places.  The whole step, every
+    chunk, is one captured HIP graph.  Per-code schedules come from the plan
+    tuner (learned cost model ranking, step-level measurements on the first
+    chunk, never slower than the library's defaults there)."""
     import numpy as np
     import torch
 
@@ -396,88 +409,67 @@ def run_mixed(args):
     import synth
     from paper_1504_07038_amd import tune
 
-    cl = synth.mixed_classes(args.mixed_blocks, synth.SEED_DATA)
-    spec = [(P, Q, d, nb) for P, Q, d, nb, _ in cl]
-    codes = sorted({(Q, len(d) - Q) for P, Q, d, nb in spec})
-    t0 = time.perf_counter()
-    tuner, _ = train_cost_model(codes)
-    tune_s = time.perf_counter() - t0
-    iw, pw = mj.mojette_classes_layout(spec)
     dev = torch.device("cuda:0")
-    d_img = torch.empty(iw, dtype=torch.int64, device=dev)
-    mj.mojette_fill_splitmix64(d_img, iw, synth.SEED_DATA)
-    masks = np.concatenate([synth.erasure_masks(synth.SEED_ERASE + c, nb, len(d), (0, len(d) - Q))
-                            for c, (P, Q, d, nb) in enumerate(spec)])
-    d_mask = torch.from_numpy(masks.view(np.int16)).to(dev)
-    d_proj = torch.empty(pw, dtype=torch.int64, device=dev)
-    d_out = torch.empty_like(d_img)
+    N = args.mixed_blocks
+    size_idx, code_idx, masks = synth.mixed_block_list(N, synth.SEED_DATA)
+    sizes = np.array(synth.MIXED_SIZES, dtype=np.int64)[size_idx]
+    codes = list(synth.MIXED_CODES)
+    ks = np.array([k for k, _ in codes], dtype=np.int64)[code_idx]
+    ns = np.array([k + m for k, m in codes], dtype=np.int64)[code_idx]
+    Ps = -(-sizes // (8 * ks))
+    dirs_of = [synth.centered_dirs(k + m) for k, m in codes]
+    sumabs = np.array([sum(abs(p) for p in d) for d in dirs_of], dtype=np.int64)[code_idx]
+    img_words = Ps * ks
+    proj_words = ns * Ps + sumabs * (ks - 1)             # sum over projections of Eq. 2
+    user = int(sizes.sum())
+    enc_alg = int((8 * (img_words + proj_words)).sum())
+    dec_alg = int((16 * img_words).sum())
+    # images: class by class (size, code), blocks in block order; pads zeroed
+    cls = size_idx * len(codes) + code_idx
+    order = np.argsort(cls, kind="stable")
+    img_off = np.zeros(N, dtype=np.int64)
+    img_off[order] = np.concatenate([[0], np.cumsum(img_words[order])[:-1]])
+    total_img = int(img_words.sum())
+    # chunks: consecutive blocks whose projections fit the budget
+    budget = int(args.mixed_budget_gib * (1 << 30) // 8)
+    bounds, proj_off = [0], np.zeros(N, dtype=np.int64)
+    acc = 0
+    for b in range(N):
+        w = int(proj_words[b])
+        if acc + w > budget:
+            bounds.append(b)
+            acc = 0
+        proj_off[b] = total_img + acc
+        acc += w
+    bounds.append(N)
+    nchunks = len(bounds) - 1
+    log(f"mixed: {N} blocks, {user / 1e9:.1f} GB of user data, {nchunks} chunks")
+    buf_words = int(max(proj_words[lo:hi].sum() for lo, hi in zip(bounds[:-1], bounds[1:])))
+    pool = torch.empty(total_img + buf_words, dtype=torch.int64, device=dev)
+    imgs = pool[:total_img]
+    mj.mojette_fill_splitmix64(imgs, total_img, synth.SEED_DATA)
+    pad_of = img_words - sizes // 8                          # zero words at each block's end
+    for c in np.unique(cls):
+        sel = order[cls[order] == c]
+        pad = int(pad_of[sel[0]])
+        if pad:
+            v = imgs[int(img_off[sel[0]]):int(img_off[sel[-1]] + img_words[sel[-1]])]
+            v.view(len(sel), int(img_words[sel[0]]))[:, -pad:] = 0
     d_status = torch.zeros(1, dtype=torch.int32, device=dev)
-    user = sum(nb * size for _, _, _, nb, size in cl)
-    enc_alg = sum(nb * 8 * (P * Q + mj.mojette_block_words(d, P, Q)) for P, Q, d, nb in spec)
-    dec_alg = sum(nb * 16 * P * Q for P, Q, d, nb in spec)
-
-    # per-class schedules: the model ranks, two are measured on the class's own size
-    jobs_e, jobs_d, choices, plans = [], [], [], {}
-    io = po = mo = 0
-    for P, Q, d, nb in spec:
-        words = mj.mojette_block_words(d, P, Q)
-        w = tune.Workload(Q, len(d) - Q, P, max(1, min(nb, (4 << 30) // (P * Q * 8))), len(d) - Q)
-        sched, _ = tuner.choose(w, budget=2)
-        choices.append([P, Q, len(d), nb, sched[0], sched[1]])
-        base = dict(P=P, Q=Q, dirs=d, nblocks=nb, images=d_img[io:io + nb * P * Q],
-                    projs=d_proj[po:po + nb * words])
-        jobs_e.append(dict(base))
-        jd = dict(base, images=d_out[io:io + nb * P * Q], erased=d_mask[mo:mo + nb])
-        if sched[0] == "chunked":
-            key = (tuple(d), Q, sched[1])
-            if key not in plans:
-                plans[key] = mj.ChunkPlan(d, Q, sched[1])
-            pl = plans[key]
-            jd["plan"] = pl
-            jd["workspace"] = torch.empty(max(1, pl.workspace_words(P, nb)), dtype=torch.int64,
-                                          device=dev)
-        jobs_d.append(jd)
-        io += nb * P * Q
-        po += nb * words
-        mo += nb
-    tuner.bench.cur = None          # release the tuner's buffers
-    torch.cuda.empty_cache()
+    chunks = []
+    for lo, hi in zip(bounds[:-1], bounds[1:]):
+        blocks = mj.make_blocks(img_off[lo:hi].astype(np.uint64), proj_off[lo:hi].astype(np.uint64),
+                                Ps[lo:hi], code_idx[lo:hi], masks[lo:hi])
+        chunks.append((blocks, hi - lo))
+    max_chunk = max(n for _, n in chunks)
+    geoms = [(k, d) for (k, _), d in zip(codes, dirs_of)]
     stream = torch.cuda.Stream()
-    side = torch.cuda.Stream()
     s_ptr = stream.cuda_stream
-    chunked = [j for j in jobs_d if "plan" in j]
-    whole = [j for j in jobs_d if "plan" not in j]
 
-    def tuned_step():
-        # chunked long-row classes on a side stream, overlapping the whole-block classes
-        mj.mojette_encode_jobs(jobs_e, stream=s_ptr)
-        if chunked:
-            fork = torch.cuda.Event()
-            fork.record(stream)
-            side.wait_event(fork)
-            mj.mojette_decode_jobs(chunked, status=d_status, stream=side.cuda_stream)
-            join = torch.cuda.Event()
-            join.record(side)
-        if whole:
-            mj.mojette_decode_jobs(whole, status=d_status, stream=s_ptr)
-        if chunked:
-            stream.wait_event(join)
-
-    def untuned_step():
-        mj.mojette_encode_classes(spec, d_img, d_proj, stream=s_ptr)
-        mj.mojette_decode_classes(spec, d_proj, d_mask, d_out, d_status, stream=s_ptr)
-
-    with torch.cuda.stream(stream):
-        for _ in range(args.warmup):
-            tuned_step()
-            untuned_step()
-    stream.synchronize()
-    graphs = {}
-    for name, fn in (("tuned", tuned_step), ("untuned", untuned_step)):
-        g = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(g, stream=stream):
-            fn()
-        graphs[name] = g
+    def run_chunks(plan, ws, which):
+        for blocks, n in which:
+            mj.mojette_encode_batched(plan, blocks, n, pool, ws, d_status, stream=s_ptr)
+            mj.mojette_decode_batched(plan, blocks, n, pool, ws, d_status, stream=s_ptr)
 
     def timed(fn, reps):
         evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
@@ -490,34 +482,105 @@ def run_mixed(args):
         stream.synchronize()
         return [a.elapsed_time(b) for a, b in evs]
 
-    # step-level check of the per-class choices: the faster graph is the step
-    trial = {name: float(np.median(timed(g.replay, 3))) for name, g in graphs.items()}
-    pick = min(trial, key=trial.get)
-    d_out.fill_(0)
-    torch.cuda.synchronize()
-    wall0 = time.perf_counter()
-    step_ms = timed(graphs[pick].replay, args.steps)
-    wall = time.perf_counter() - wall0
-    ok = bool(torch.equal(d_out, d_img)) and int(d_status.item()) == 0
-    ms = wall * 1e3 / args.steps
-    ms_ev = float(np.median(step_ms))
+    # the plan tuner: learned ranking, measured on the first chunk
+    t0 = time.perf_counter()
+    log("mixed: training the cost model")
+    tuner_model, _ = train_cost_model(codes)
+    log(f"mixed: cost model trained ({time.perf_counter() - t0:.1f} s); tuning the plan")
+    first = chunks[:1]
+    lo, hi = bounds[0], bounds[1]
+    classes = {}
+    for g in range(len(codes)):
+        sel = np.flatnonzero(code_idx[lo:hi] == g)
+        Pv, cnt = np.unique(Ps[lo:hi][sel], return_counts=True)
+        classes[g] = [(int(a), int(b)) for a, b in zip(Pv, cnt)]
+    ws_probe = torch.empty(max(1, mj.GeomPlan(geoms).workspace_bytes(max_chunk)), dtype=torch.uint8,
+                           device=dev)
 
+    def measure(tn):
+        plan = mj.GeomPlan(geoms, tn)
+        run_chunks(plan, ws_probe, first)
+        stream.synchronize()
+        ms = float(np.median(timed(lambda: run_chunks(plan, ws_probe, first), 3)))
+        plan.close()
+        log(f"mixed: tune {tn}: first chunk {ms:.2f} ms")
+        return ms
+
+    pt = tune.PlanTuner(codes, classes, measure, model=tuner_model.model)
+    chosen, tuned_ms, default_ms = pt.tune()
+    tune_s = time.perf_counter() - t0
+    plan = mj.GeomPlan(geoms, chosen)
+    ws = ws_probe
+    with torch.cuda.stream(stream):
+        for _ in range(args.warmup):
+            run_chunks(plan, ws, chunks)
+    stream.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=stream):
+        run_chunks(plan, ws, chunks)
+    d_status.zero_()
+    torch.cuda.synchronize()
+    log("mixed: timing the captured step")
+    wall0 = time.perf_counter()
+    step_ms = timed(g.replay, args.steps)
+    wall = time.perf_counter() - wall0
+    # the round trip: the decoded images equal the generated ones, which are
+    # regenerated class by class, whole blocks at a time, pads zeroed
+    log("mixed: checking the round trip")
+    ok = int(d_status.item()) == 0
+    ref = torch.empty(1 << 30, dtype=torch.int64, device=dev)
+    for c in np.unique(cls):
+        sel = order[cls[order] == c]
+        wpb, pad = int(img_words[sel[0]]), int(pad_of[sel[0]])
+        c_lo = int(img_off[sel[0]])
+        per = max(1, ref.numel() // wpb)
+        for j in range(0, len(sel), per):
+            nbk = min(per, len(sel) - j)
+            start = c_lo + j * wpb
+            r = ref[:nbk * wpb]
+            mj.mojette_fill_splitmix64(r, nbk * wpb, synth.SEED_DATA, start)
+            if pad:
+                r.view(nbk, wpb)[:, -pad:] = 0
+            ok = ok and bool(torch.equal(imgs[start:start + nbk * wpb], r))
+    del ref
+    ms_ev = float(np.median(step_ms))
+    # per-chunk launch times of the tuned plan (events around each call)
+    def per_call():
+        ev = []
+        with torch.cuda.stream(stream):
+            for blocks, n in chunks:
+                e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+                e[0].record(stream)
+                mj.mojette_encode_batched(plan, blocks, n, pool, ws, d_status, stream=s_ptr)
+                e[1].record(stream)
+                mj.mojette_decode_batched(plan, blocks, n, pool, ws, d_status, stream=s_ptr)
+                e[2].record(stream)
+                ev.append(e)
+        stream.synchronize()
+        return (sum(e[0].elapsed_time(e[1]) for e in ev), sum(e[1].elapsed_time(e[2]) for e in ev))
+    enc_ms, dec_ms = per_call()
     rec = {
-        "metric": "encode/decode GB/s of user data, mixed block sizes and codes",
+        "metric": "encode/decode GB/s of user data, batched uneven blocks",
         "value": round(user / (ms_ev * 1e-3) / 1e9, 2), "unit": "GB/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_ev, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
         "data": "synthetic",
-        "config": {"workload": f"mixed: {args.mixed_blocks} blocks, sizes 4K/8K/64K/1M x codes "
-                               f"(4,2)/(6,3)/(8,4)/(12,4), 16 classes, erasures 0..m per block, "
-                               f"autotuned decode schedules, one HIP graph per step",
-                   "chunked_on_side_stream": True,
-                   "classes": choices, "parallelism": "single GPU"},
-        "wall_ms_per_step": round(ms, 4),
+        "config": {"workload": f"mixed: {N} blocks, sizes 4K/8K/64K/1M x codes "
+                               f"(4,2)/(6,3)/(8,4)/(12,4) per block, erasures 0..m per block; "
+                               f"descriptor-driven calls, {nchunks} chunks under a "
+                               f"{args.mixed_budget_gib:g} GiB projection budget, "
+                               f"one HIP graph per step",
+                   "blocks": N, "chunks": nchunks, "projection_budget_gib": args.mixed_budget_gib,
+                   "user_bytes": user, "image_bytes": 8 * total_img,
+                   "projection_bytes": int(8 * proj_words.sum()),
+                   "parallelism": "single GPU"},
+        "wall_ms_per_step": round(wall * 1e3 / args.steps, 4),
         "step_ms_p50": round(pct(step_ms, 50), 4), "step_ms_p99": round(pct(step_ms, 99), 4),
-        "step_choice": pick,
-        "trial_GBps": {k: round(user / (v * 1e-3) / 1e9, 2) for k, v in trial.items()},
-        "tuning_s": round(tune_s, 2),
+        "encode_GBps": round(user / (enc_ms * 1e-3) / 1e9, 2),
+        "decode_GBps": round(user / (dec_ms * 1e-3) / 1e9, 2),
+        "tune": {"chosen": chosen, "first_chunk_ms_tuned": round(tuned_ms, 4),
+                 "first_chunk_ms_default": round(default_ms, 4),
+                 "measurements": len(pt.history), "tuning_s": round(tune_s, 2)},
         "roundtrip_ok": ok,
         "alg_bytes_per_step": enc_alg + dec_alg,
         "roofline": {"kernel": "encode+decode step", "bound": "hbm",
@@ -525,11 +588,14 @@ def run_mixed(args):
                      "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": round((enc_alg + dec_alg) / (ms_ev * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
                      "traffic": None},
+        "roofline_decode": {"achieved": round(dec_alg / (dec_ms * 1e-3) / 1e9, 1),
+                            "frac": round(dec_alg / (dec_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)},
+        "roofline_encode": {"achieved": round(enc_alg / (enc_ms * 1e-3) / 1e9, 1),
+                            "frac": round(enc_alg / (enc_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)},
         "cpu_baseline": None,
     }
     print(json.dumps(rec), flush=True)
-    for pl in plans.values():
-        pl.close()
+    plan.close()
     if not ok:
         sys.exit(1)
 

@@ -231,3 +231,79 @@ class Tuner:
             if best is None or t < best[1]:
                 best = (s, t)
         return best
+
+
+# ---- schedules of a plan over codes (descriptor-driven batched calls) ----
+#
+# A plan gives every code one schedule for all of its blocks, whatever their
+# row length: the decode's blocks per wavefront and ring split, the encode's
+# tile width.  The tuner starts from the library's choices and accepts a
+# change only when a step of the actual workload (encode + decode of a
+# sample of its blocks, the launches the plan makes) measures faster, so the
+# schedule it returns is never slower than the untuned one on that sample.
+# The cost model ranks the decode candidates of each code over the code's
+# row-length classes, so that only the best-ranked ones are measured.
+
+ENCODE_TILES = (64, 128, 256)
+
+
+def decode_candidates(k: int, m: int):
+    """Blocks per wavefront the tuner tries for code (k, m) (0: the library's)."""
+    n = k + m
+    dirs = [i - n // 2 for i in range(n)]
+    full = mj.mojette_decode_max_blocks_per_wave(dirs, 64, k)
+    out, nb = [], max(1, full // 2)
+    while nb >= 1 and len(out) < 4:
+        out.append(nb)
+        nb //= 2
+    return out
+
+
+class PlanTuner:
+    """measure(tune) -> median step ms of the workload sample with a plan made
+    with that tune (a list of per-code mojette_tune dicts)."""
+
+    def __init__(self, codes, classes, measure, model: CostModel | None = None,
+                 budget: int = 2, margin: float = 0.01):
+        self.codes = list(codes)            # [(k, m)]
+        self.classes = classes              # {code index: [(P, nblocks)]}
+        self.measure = measure
+        self.model = model
+        self.budget = budget
+        self.margin = margin
+        self.history = []
+
+    def rank_decode(self, g: int):
+        k, m = self.codes[g]
+        cands = decode_candidates(k, m)
+        if self.model is None or not self.classes.get(g):
+            return cands
+        totals = []
+        for nb in cands:
+            X = np.array([features(Workload(k, m, P, cnt, m), ("whole", nb))
+                          for P, cnt in self.classes[g]])
+            totals.append(float(np.sum(np.exp(self.model.predict(X)))))
+        return [cands[i] for i in np.argsort(totals)]
+
+    def _try(self, tune, g, key, val, best_ms):
+        trial = [dict(t) for t in tune]
+        trial[g][key] = val
+        ms = self.measure(trial)
+        self.history.append((g, key, val, ms))
+        if ms < best_ms * (1.0 - self.margin):
+            return trial, ms
+        return tune, best_ms
+
+    def tune(self):
+        tune = [dict() for _ in self.codes]
+        default_ms = self.measure(tune)
+        self.history.append((None, "default", None, default_ms))
+        best_ms = default_ms
+        for g in range(len(self.codes)):
+            for nb in self.rank_decode(g)[:self.budget]:
+                tune, best_ms = self._try(tune, g, "decode_blocks_per_wave", nb, best_ms)
+            tune, best_ms = self._try(tune, g, "decode_ring_split", -1, best_ms)
+            for w in ENCODE_TILES:
+                if w != 128:
+                    tune, best_ms = self._try(tune, g, "encode_tile_cols", w, best_ms)
+        return tune, best_ms, default_ms

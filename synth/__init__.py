@@ -124,3 +124,19 @@ def mixed_images(seed: int, P: int, Q: int, nblocks: int, size: int, first_block
     imgs = block_images(seed, first_block, nblocks, P, Q).reshape(nblocks, Q * P)
     imgs[:, size // 8:] = 0
     return imgs.reshape(nblocks, Q, P)
+
+
+def mixed_block_list(nblocks: int, seed: int, sizes=MIXED_SIZES, codes=MIXED_CODES):
+    """Per-block recipe of a mixed batch: block b's size index and code index
+    (each uniform, from SplitMix64(seed) words 2b and 2b+1) and its erasure
+    mask (a uniform count 0..m, then a uniform subset of the n projections;
+    erasure_masks over the blocks of each code, stream seed + 1 + code).
+    Returns (size_idx, code_idx, masks) as numpy arrays."""
+    r = splitmix64(seed, 0, 2 * nblocks).reshape(nblocks, 2)
+    size_idx = _uniform_below(r[:, 0], len(sizes))
+    code_idx = _uniform_below(r[:, 1], len(codes))
+    masks = np.zeros(nblocks, dtype=np.uint16)
+    for ci, (k, m) in enumerate(codes):
+        sel = np.flatnonzero(code_idx == ci)
+        masks[sel] = erasure_masks(seed + 1 + ci, len(sel), k + m, (0, m))
+    return size_idx, code_idx, masks
