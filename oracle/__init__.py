@@ -75,6 +75,8 @@ def _load():
     lib.orc_katz.restype = i32
     lib.orc_forward.argtypes = [i32, u64, vp, i32, i32, vp, vp, i32, vp, vp]
     lib.orc_forward.restype = i32
+    lib.orc_forward_count.argtypes = [i32, u64, vp, i32, i32, vp, vp, i32, vp, vp, vp]
+    lib.orc_forward_count.restype = i32
     lib.orc_inverse.argtypes = [i32, u64, vp, vp, vp, vp, i32, i32, i32, vp, i32, vp]
     lib.orc_inverse.restype = i32
     lib.orc_inverse_kept.argtypes = [i32, u64, vp, vp, vp, vp, i32, i32, i32, vp, vp, vp, i32,
@@ -114,8 +116,10 @@ def _dir_arrays(dirs):
     return p, q
 
 
-def forward(image: np.ndarray, dirs, kind: int = XOR, mod: int = 0) -> list[np.ndarray]:
-    """Eq. 1 for every direction (p, q) in ``dirs``; ``image`` is (Q, P) uint64."""
+def forward(image: np.ndarray, dirs, kind: int = XOR, mod: int = 0, return_ops: bool = False):
+    """Eq. 1 for every direction (p, q) in ``dirs``; ``image`` is (Q, P) uint64.
+    With ``return_ops`` also the number of group additions that combine two
+    pixels (a bin's first pixel is a copy)."""
     img = np.ascontiguousarray(image, dtype=np.uint64)
     Q, P = img.shape
     p, q = _dir_arrays(dirs)
@@ -124,11 +128,13 @@ def forward(image: np.ndarray, dirs, kind: int = XOR, mod: int = 0) -> list[np.n
     if sizes:
         off[1:] = np.cumsum(sizes)[:-1]
     flat = np.zeros(max(1, sum(sizes)), dtype=np.uint64)
-    rc = _load().orc_forward(kind, mod, _ptr(img), P, Q, _ptr(p), _ptr(q), len(sizes),
-                             _ptr(flat), _ptr(off))
+    ops = ctypes.c_int64(0)
+    rc = _load().orc_forward_count(kind, mod, _ptr(img), P, Q, _ptr(p), _ptr(q), len(sizes),
+                                   _ptr(flat), _ptr(off), ctypes.addressof(ops))
     if rc != OK:
         raise ValueError(f"orc_forward failed: {rc}")
-    return [flat[o:o + s].copy() for o, s in zip(off, sizes)]
+    out = [flat[o:o + s].copy() for o, s in zip(off, sizes)]
+    return (out, int(ops.value)) if return_ops else out
 
 
 def inverse(projs, dirs, P: int, Q: int, kind: int = XOR, mod: int = 0,

@@ -106,13 +106,38 @@ int32_t orc_katz(int32_t P, int32_t Q, const int32_t *p, const int32_t *q, int32
  * line passes through it (the Iverson bracket of Eq. 1 selects exactly that
  * bin).
  */
+int32_t orc_forward_count(int32_t kind, uint64_t mod, const uint64_t *image, int32_t P,
+                          int32_t Q, const int32_t *p, const int32_t *q, int32_t n,
+                          uint64_t *proj, const int64_t *proj_off, int64_t *ops);
+
 int32_t orc_forward(int32_t kind, uint64_t mod, const uint64_t *image, int32_t P, int32_t Q,
                     const int32_t *p, const int32_t *q, int32_t n, uint64_t *proj,
                     const int64_t *proj_off) {
+    return orc_forward_count(kind, mod, image, P, Q, p, q, n, proj, proj_off, NULL);
+}
+
+/*
+ * Eq. 1 as orc_forward, also counting in *ops (if not NULL) the group
+ * additions that combine two pixels: a pixel added to a bin that already
+ * holds one.  The first pixel of a bin is a copy, so a bin of c pixels costs
+ * c - 1 additions (Section 3.1: at most k - 1 XORs per bin, none at the
+ * edges).
+ */
+int32_t orc_forward_count(int32_t kind, uint64_t mod, const uint64_t *image, int32_t P,
+                          int32_t Q, const int32_t *p, const int32_t *q, int32_t n,
+                          uint64_t *proj, const int64_t *proj_off, int64_t *ops) {
     if (!grp_ok(kind, mod) || P <= 0 || Q <= 0 || n < 0) return ORC_EINVAL;
+    int64_t total = 0;
     for (int32_t i = 0; i < n; i++) {
         int64_t B = orc_proj_size(p[i], q[i], P, Q);
         for (int64_t j = 0; j < B; j++) proj[proj_off[i] + j] = 0;
+        total += B;
+    }
+    unsigned char *seen = NULL;
+    if (ops) {
+        *ops = 0;
+        seen = (unsigned char *)calloc(total > 0 ? (size_t)total : 1, 1);
+        if (!seen) return ORC_ENOMEM;
     }
     for (int32_t l = 0; l < Q; l++) {
         for (int32_t k = 0; k < P; k++) {
@@ -122,9 +147,14 @@ int32_t orc_forward(int32_t kind, uint64_t mod, const uint64_t *image, int32_t P
                 int64_t j = b - orc_bin_min(p[i], q[i], P, Q);
                 uint64_t *bin = &proj[proj_off[i] + j];
                 *bin = grp_add(kind, mod, *bin, f);
+                if (seen) {
+                    if (seen[proj_off[i] + j]) ++*ops;
+                    seen[proj_off[i] + j] = 1;
+                }
             }
         }
     }
+    free(seen);
     return ORC_OK;
 }
 

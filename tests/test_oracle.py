@@ -325,3 +325,25 @@ def test_ops_count(orc):
     projs = orc.forward(img, dirs)
     rc, out, ops = orc.inverse(projs, dirs, P, Q, return_ops=True)
     assert rc == orc.OK and ops == len(dirs) * P * Q
+
+
+@pytest.mark.parametrize("P,Q,n,want", [(128, 4, 6, 2277), (256, 4, 6, 4581), (128, 8, 12, 10500),
+                                        (1, 1, 1, 0), (7, 3, 5, None), (40, 5, 9, None)])
+def test_encode_xor_count(orc, P, Q, n, want):
+    """Encoding costs n*P*Q - sum(B_i) XORs: every pixel lands in one bin of
+    every projection, and a bin's first pixel is a copy (Section 3.1: at
+    most k - 1 XORs per bin, none at the edge bins, which hold one pixel).
+    The counts for the 4 KB and 8 KB codes were worked out by hand from
+    Eq. 2 when the scope was surveyed: 6*512 - 795, 6*1024 - 1563,
+    12*1024 - 1788."""
+    dirs = [(i - n // 2, 1) for i in range(n)]
+    img = synth.block_images(P * Q + n, 0, 1, P, Q)[0]
+    projs, ops = orc.forward(img, dirs, return_ops=True)
+    sizes = [orc.proj_size(p, q, P, Q) for p, q in dirs]
+    assert ops == n * P * Q - sum(sizes)
+    if want is not None:
+        assert ops == want
+    # the count does not depend on the values; the projections are unchanged
+    assert all(np.array_equal(a, b) for a, b in zip(projs, orc.forward(img, dirs)))
+    _, ops0 = orc.forward(np.zeros_like(img), dirs, return_ops=True)
+    assert ops0 == ops
