@@ -185,6 +185,21 @@ def cpu_baseline(P, Q, dirs, sample_blocks, n_erase):
         t_dec = time.perf_counter() - t0
     ok = all(np.array_equal(o, imgs[ix[0]:ix[-1] + 1]) for o, ix in zip(outs, chunks))
     user = sample_blocks * P * Q * 8
+    # one thread, per block, beside the paper's single-core cycle counts
+    n1 = min(sample_blocks, 4096)
+    t0 = time.perf_counter()
+    p1 = oracle.encode_blocks(imgs[:n1], P, Q, dirs)
+    t_enc1 = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    o1 = oracle.decode_blocks(p1, masks[:n1], P, Q, dirs)
+    t_dec1 = time.perf_counter() - t0
+    ok = ok and bool(np.array_equal(o1, imgs[:n1]))
+    ghz = host_ghz()
+    single = {"blocks": n1, "encode_us_per_block": round(t_enc1 / n1 * 1e6, 3),
+              "decode_us_per_block": round(t_dec1 / n1 * 1e6, 3), "cpu_ghz": ghz}
+    if ghz:
+        single["encode_cycles_per_block"] = round(t_enc1 / n1 * ghz * 1e9)
+        single["decode_cycles_per_block"] = round(t_dec1 / n1 * ghz * 1e9)
     return {
         "value": round(user / (t_enc + t_dec) / 1e9, 4),
         "unit": "GB/s",
@@ -194,8 +209,19 @@ def cpu_baseline(P, Q, dirs, sample_blocks, n_erase):
                    f"then decode, one block range per thread"),
         "encode_GBps": round(user / t_enc / 1e9, 4),
         "decode_GBps": round(user / t_dec / 1e9, 4),
+        "single_thread": single,
         "roundtrip_ok": bool(ok),
     }
+
+
+def host_ghz():
+    """The host cores' clock in GHz (mean of /proc/cpuinfo's "cpu MHz"), or None."""
+    try:
+        mhz = [float(line.split(":")[1]) for line in open("/proc/cpuinfo")
+               if line.startswith("cpu MHz")]
+        return round(sum(mhz) / len(mhz) / 1e3, 3) if mhz else None
+    except (OSError, ValueError):
+        return None
 
 
 def main():
@@ -265,8 +291,11 @@ def main():
         if evs:
             evs[2].record(stream)
 
-    for _ in range(args.warmup):
-        step()
+    # warm-up steps are timed too (outside the timed region): a profiler's
+    # mean over every launch of the run includes them
+    wevs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.warmup)]
+    for k in range(args.warmup):
+        step(wevs[k])
     torch.cuda.synchronize()
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
     torch.cuda.synchronize()
@@ -288,9 +317,13 @@ def main():
     dec_avg = sum(dec_ms) / len(dec_ms)
     enc_alg = 8 * (pw * P * Q + words)     # read the image, write every bin
     dec_alg = 16 * pw * P * Q              # read P bins of Q survivors, write the image
+    enc_all = enc_ms + [e[0].elapsed_time(e[1]) for e in wevs]
+    dec_all = dec_ms + [e[1].elapsed_time(e[2]) for e in wevs]
     kernels = {
-        "encode": {"ms": enc_avg, "alg_bytes_per_block": enc_alg},
-        "decode": {"ms": dec_avg, "alg_bytes_per_block": dec_alg},
+        "encode": {"ms": enc_avg, "alg_bytes_per_block": enc_alg,
+                   "ms_all": sum(enc_all) / len(enc_all)},
+        "decode": {"ms": dec_avg, "alg_bytes_per_block": dec_alg,
+                   "ms_all": sum(dec_all) / len(dec_all)},
     }
     dom = "encode" if enc_avg >= dec_avg else "decode"
 
@@ -308,6 +341,11 @@ def main():
             "traffic": tr,
             "alg_bytes_per_launch": k["alg_bytes_per_block"] * nblocks,
             "avg_launch_ms": round(k["ms"], 4),
+            # over every launch of the run, warm-ups included (what a
+            # profiler's mean duration for the kernel covers)
+            "avg_launch_ms_all": round(k["ms_all"], 4),
+            "frac_all_launches": round(k["alg_bytes_per_block"] * nblocks / (k["ms_all"] * 1e-3)
+                                       / 1e9 / HBM_PEAK_GBPS, 4),
         }
 
     # a plain streaming copy of the image pool: the practical HBM ceiling
@@ -321,6 +359,17 @@ def main():
         if k:
             copy_ms.append(ea.elapsed_time(eb))
     copy_gbps = 2 * d_img.numel() * 8 / (sum(copy_ms) / len(copy_ms) * 1e-3) / 1e9
+    # the runtime's own device-to-device copy (hipMemcpyAsync) of the same bytes
+    d2d_ms = []
+    for k in range(6):
+        ea, eb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ea.record(stream)
+        d_out.copy_(d_img)
+        eb.record(stream)
+        torch.cuda.synchronize()
+        if k:
+            d2d_ms.append(ea.elapsed_time(eb))
+    d2d_gbps = 2 * d_img.numel() * 8 / (sum(d2d_ms) / len(d2d_ms) * 1e-3) / 1e9
 
     # plain path: one launch per block, against the batched path on the same blocks
     plain = None
@@ -359,6 +408,7 @@ def main():
         "step_ms_p99": round(pct(step_ms, 99), 4),
         "roundtrip_ok": roundtrip_ok,
         "copy_GBps": round(copy_gbps, 1),
+        "copy_d2d_GBps": round(d2d_gbps, 1),
         "roofline": roof(dom),
         "roofline_other": roof("decode" if dom == "encode" else "encode"),
         "plain_vs_batched": plain,
@@ -707,8 +757,11 @@ def run_sys(args):
     # rebuild the lost lines once, so that every timed step encodes the true
     # lines (the rebuild's work does not depend on the lost lines' contents)
     mj.mojette_decode_batch_sys(d_img, d_par, d_mask, nb, P, Q, pdirs, ws, d_status)
-    for _ in range(args.warmup):
-        step()
+    # warm-up steps are timed too (outside the timed region): a profiler's
+    # mean over every launch of the run includes them
+    wevs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.warmup)]
+    for k in range(args.warmup):
+        step(wevs[k])
     torch.cuda.synchronize()
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
     t0 = time.perf_counter()

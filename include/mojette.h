@@ -369,8 +369,8 @@ int mojette_decode_jobs(const mojette_job *jobs, int32_t njobs, int32_t *status,
  *
  * A call first groups the blocks by (code, P) on the device, in the caller's
  * workspace (mojette_workspace_size bytes), then runs the transform of every
- * block in one persistent launch (per row count when the plan's row counts
- * have no combined kernel), longest rows first.  Calls allocate nothing,
+ * block in one persistent launch per row count Q among the plan's codes,
+ * longest rows first.  Calls allocate nothing,
  * never synchronise and are safe to record into a HIP graph.  At most 2,048
  * distinct (geom_id, P) pairs per call; the blocks of pairs beyond that are
  * not transformed and MOJETTE_ENOTSUP is stored to *status.
@@ -415,7 +415,7 @@ int mojette_plan_create(const mojette_geom *geoms, int32_t ngeoms, const mojette
 int mojette_plan_destroy(mojette_plan *plan);
 
 /* Workspace bytes a call on up to nblocks blocks needs (non-decreasing in
- * nblocks), or -1 on bad arguments.  About 1 MB plus 8 bytes per block. */
+ * nblocks), or -1 on bad arguments.  About 1 MB plus 12 bytes per block. */
 int64_t mojette_workspace_size(const mojette_plan *plan, int64_t nblocks);
 
 /* Forward transform (Section 2.1, Eq. 1) of every described block: reads

@@ -1708,7 +1708,6 @@ struct mojette_plan {
     mj::GeomDev *d_geoms;             // device
     unsigned qmask;                   // row counts of the codes
     int qmax;
-    size_t dec_lds, enc_lds;          // dynamic LDS of the transform launches
     int dev;                          // device the table lives on
 };
 
@@ -1730,7 +1729,6 @@ int mojette_plan_create(const mojette_geom *geoms, int32_t ngeoms, const mojette
     std::vector<mj::GeomDev> tab(ngeoms);
     unsigned qmask = 0;
     int qmax = 0;
-    size_t dec_lds = 0, enc_lds = 0;
     for (int gi = 0; gi < ngeoms; ++gi) {
         const mojette_geom &gm = geoms[gi];
         const int Q = gm.Q, n = gm.n;
@@ -1764,7 +1762,6 @@ int mojette_plan_create(const mojette_geom *geoms, int32_t ngeoms, const mojette
         while (w > 64 && (size_t)Q * (w + 2 * g.H) * 8 > kLdsLimit) w -= 64;
         if ((size_t)Q * (w + 2 * g.H) * 8 > kLdsLimit) return MOJETTE_ENOTSUP;
         g.enc_w = w;
-        enc_lds = std::max(enc_lds, (size_t)Q * (w + 2 * g.H) * 8);
         // decode: the full ring and, where a shorter ring serves most
         // survivor sets, a short-ring class for them
         int common = -1;
@@ -1776,13 +1773,11 @@ int mojette_plan_create(const mojette_geom *geoms, int32_t ngeoms, const mojette
         g.R = R;
         g.nb = desc_blocks(Q, R + 1, tuned_nb);
         if (mj::decode_lds_bytes(Q, g.nb, R + 1) > kLdsLimit) return MOJETTE_ENOTSUP;
-        dec_lds = std::max(dec_lds, mj::decode_lds_bytes(Q, g.nb, R + 1));
         const int split = t ? t->decode_ring_split : 0;
         if (split >= 0 && common > 0 && common < R) {
             g.R_short = common;
             g.depth_short = common - mj::kDecodeTile - 1;
             g.nb_short = desc_blocks(Q, common + 1, tuned_nb);
-            dec_lds = std::max(dec_lds, mj::decode_lds_bytes(Q, g.nb_short, common + 1));
         }
         qmask |= 1u << Q;
         qmax = std::max(qmax, Q);
@@ -1792,8 +1787,6 @@ int mojette_plan_create(const mojette_geom *geoms, int32_t ngeoms, const mojette
     pl->geoms = tab;
     pl->qmask = qmask;
     pl->qmax = qmax;
-    pl->dec_lds = dec_lds;
-    pl->enc_lds = enc_lds;
     hipError_t e = hipGetDevice(&pl->dev);
     if (e == hipSuccess) e = hipMalloc((void **)&pl->d_geoms, tab.size() * sizeof(mj::GeomDev));
     if (e == hipSuccess)
@@ -1837,7 +1830,10 @@ static int desc_call(const mojette_plan *plan, const mojette_block *blocks, int6
     c.pool = pool;
     c.status = status;
     c.decode = decode ? 1 : 0;
-    c.group_by_q = decode && !mj::decode_desc_supported(plan->qmask) ? 1 : 0;
+    // one launch per row count: a combined kernel holds the registers of its
+    // largest body (the (4,2)+(6,3)+(8,4)+(12,4) one ran at one wavefront
+    // per SIMD), and launches of one row count size their LDS to it
+    c.group_by_q = 1;
     return MOJETTE_OK;
 }
 
@@ -1850,9 +1846,22 @@ int mojette_encode_batched(const mojette_plan *plan, const mojette_block *blocks
     const hipStream_t s = (hipStream_t)stream;
     clear_stale_error();
     if ((rc = status_of(mj::launch_desc_buckets(c, s))) != MOJETTE_OK) return rc;
-    // work items are (block, tile): a grid that loops over them
-    const int grid = (int)std::min<int64_t>(kEncodeGridCap, std::max<int64_t>(1, nblocks * 8));
-    return status_of(mj::launch_encode_desc(plan->qmax, c, 0, plan->enc_lds, grid, s));
+    // one launch per row count: work items are (block, tile), each
+    // wavefront takes a contiguous run of them; the LDS tile of a wavefront
+    // fits the widest tile of the row count's codes, and workgroups hold
+    // four wavefronts while their tiles take at most 48 KB
+    for (int q = 1; q <= kMaxRows; ++q) {
+        if (!((plan->qmask >> q) & 1u)) continue;
+        int tile_words = 0;
+        for (const mj::GeomDev &g : plan->geoms)
+            if (g.Q == q) tile_words = std::max(tile_words, q * (g.enc_w + 2 * g.H));
+        const int waves = (size_t)mj::kEncodeWaves * tile_words * 8 <= 48 * 1024 ? mj::kEncodeWaves : 1;
+        const int64_t want_waves = std::max<int64_t>(1, std::min<int64_t>(nblocks * 8, 1 << 16));
+        const int grid = (int)((want_waves + waves - 1) / waves);
+        rc = status_of(mj::launch_encode_desc(q, c, q, waves, tile_words, grid, s));
+        if (rc != MOJETTE_OK) return rc;
+    }
+    return MOJETTE_OK;
 }
 
 int mojette_decode_batched(const mojette_plan *plan, const mojette_block *blocks,
@@ -1866,8 +1875,6 @@ int mojette_decode_batched(const mojette_plan *plan, const mojette_block *blocks
     if ((rc = status_of(mj::launch_desc_buckets(c, s))) != MOJETTE_OK) return rc;
     // at most one batch per block: a grid of that many (capped) loops over them
     const int grid = (int)std::min<int64_t>(kDecodeGridCap, nblocks);
-    if (!c.group_by_q)
-        return status_of(mj::launch_decode_desc(plan->qmask, c, 0, plan->dec_lds, grid, s));
     for (int q = 1; q <= kMaxRows; ++q) {
         if (!((plan->qmask >> q) & 1u)) continue;
         size_t lds = 0;
@@ -1876,7 +1883,7 @@ int mojette_decode_batched(const mojette_plan *plan, const mojette_block *blocks
             lds = std::max(lds, mj::decode_lds_bytes(q, g.nb, g.R + 1));
             if (g.R_short > 0) lds = std::max(lds, mj::decode_lds_bytes(q, g.nb_short, g.R_short + 1));
         }
-        if ((rc = status_of(mj::launch_decode_desc(1u << q, c, q, lds, grid, s))) != MOJETTE_OK)
+        if ((rc = status_of(mj::launch_decode_desc(q, c, q, lds, grid, s))) != MOJETTE_OK)
             return rc;
     }
     return MOJETTE_OK;

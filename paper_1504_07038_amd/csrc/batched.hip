@@ -377,8 +377,6 @@ __global__ __launch_bounds__(kWave) void decode_desc_kernel(const uint8_t *ws, i
     }
 }
 
-constexpr unsigned qbit(int q) { return 1u << q; }
-
 }  // namespace
 
 hipError_t launch_desc_buckets(const DescCall &c, hipStream_t s) {
@@ -394,42 +392,21 @@ hipError_t launch_desc_buckets(const DescCall &c, hipStream_t s) {
     return hipGetLastError();
 }
 
-// Row-count sets with a combined descriptor decode kernel: every single row
-// count, and the (4,2)+(8,4) and (4,2)+(6,3)+(8,4)+(12,4) code families.
-bool decode_desc_supported(unsigned qmask) {
-    if (qmask && !(qmask & (qmask - 1))) return true;
-    return qmask == (qbit(4) | qbit(8)) || qmask == (qbit(4) | qbit(6) | qbit(8) | qbit(12));
-}
-
-hipError_t launch_decode_desc(unsigned qmask, const DescCall &c, int g, size_t lds, int grid,
+hipError_t launch_decode_desc(int Q, const DescCall &c, int g, size_t lds, int grid,
                               hipStream_t s) {
     const uint8_t *ws = c.ws;
-#define MJ_LAUNCH(M) \
-    hipLaunchKernelGGL((decode_desc_kernel<M>), dim3(grid), dim3(kWave), lds, s, ws, g)
-    switch (qmask) {
-        case qbit(1): MJ_LAUNCH(qbit(1)); break;
-        case qbit(2): MJ_LAUNCH(qbit(2)); break;
-        case qbit(3): MJ_LAUNCH(qbit(3)); break;
-        case qbit(4): MJ_LAUNCH(qbit(4)); break;
-        case qbit(5): MJ_LAUNCH(qbit(5)); break;
-        case qbit(6): MJ_LAUNCH(qbit(6)); break;
-        case qbit(7): MJ_LAUNCH(qbit(7)); break;
-        case qbit(8): MJ_LAUNCH(qbit(8)); break;
-        case qbit(9): MJ_LAUNCH(qbit(9)); break;
-        case qbit(10): MJ_LAUNCH(qbit(10)); break;
-        case qbit(11): MJ_LAUNCH(qbit(11)); break;
-        case qbit(12): MJ_LAUNCH(qbit(12)); break;
-        case qbit(13): MJ_LAUNCH(qbit(13)); break;
-        case qbit(14): MJ_LAUNCH(qbit(14)); break;
-        case qbit(15): MJ_LAUNCH(qbit(15)); break;
-        case qbit(16): MJ_LAUNCH(qbit(16)); break;
-        case qbit(4) | qbit(8): MJ_LAUNCH(qbit(4) | qbit(8)); break;
-        case qbit(4) | qbit(6) | qbit(8) | qbit(12):
-            MJ_LAUNCH(qbit(4) | qbit(6) | qbit(8) | qbit(12));
-            break;
+    switch (Q) {
+#define MJ_LAUNCH(QQ)                                                                          \
+    case QQ:                                                                                   \
+        hipLaunchKernelGGL((decode_desc_kernel<1u << QQ>), dim3(grid), dim3(kWave), lds, s, ws, \
+                           g);                                                                 \
+        break;
+        MJ_LAUNCH(1) MJ_LAUNCH(2) MJ_LAUNCH(3) MJ_LAUNCH(4) MJ_LAUNCH(5) MJ_LAUNCH(6)
+        MJ_LAUNCH(7) MJ_LAUNCH(8) MJ_LAUNCH(9) MJ_LAUNCH(10) MJ_LAUNCH(11) MJ_LAUNCH(12)
+        MJ_LAUNCH(13) MJ_LAUNCH(14) MJ_LAUNCH(15) MJ_LAUNCH(16)
+#undef MJ_LAUNCH
         default: return hipErrorInvalidValue;
     }
-#undef MJ_LAUNCH
     return hipGetLastError();
 }
 

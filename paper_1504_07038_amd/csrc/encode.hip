@@ -221,55 +221,127 @@ __global__ __launch_bounds__(kWave) void encode_classes_kernel(EncodeClassTable 
     }
 }
 
-// A descriptor-driven launch: the items of the classes of launch group g
-// (heaviest first), read from the call's workspace, one wavefront per
-// workgroup; the grid loops until the group's items are done.
-template <int QMAX>
-__global__ __launch_bounds__(kWave) void encode_desc_kernel(const uint8_t *ws, int g) {
+// A descriptor-driven launch over the items of launch group g (the classes
+// of one row count Q), read from the call's workspace.  Each wavefront takes
+// a contiguous run of items, so the tiles of one long block follow one
+// another on a wavefront (its descriptor is read once into the cache) and
+// the class of the next item is found by stepping forward from the current
+// one; `waves` wavefronts per workgroup, each with its own LDS tile of
+// tile_words words.  With PF > 0 (every class's tile and halo within PF*64
+// columns) each lane holds its words of the next item's tile in registers,
+// loaded while the current item's bins are made: a run's items are
+// dependent loads otherwise (class, block index, descriptor, image), which
+// left the encode of 1 MB blocks at a third of the single-geometry rate.
+template <int Q, int PF>
+__global__ __launch_bounds__(kWave *kEncodeWaves) void encode_desc_kernel(const uint8_t *ws,
+                                                                          int g, int waves,
+                                                                          int tile_words) {
     extern __shared__ uint64_t lds[];
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wv = threadIdx.x >> 6;
     const DescHeader &hd = *reinterpret_cast<const DescHeader *>(ws + DescWorkspace::kHeader);
     const int64_t *first = reinterpret_cast<const int64_t *>(ws + DescWorkspace::kFirstItem);
     const EncodeDesc *cls = reinterpret_cast<const EncodeDesc *>(ws + DescWorkspace::kClasses);
     const int64_t lo = hd.range[2 * g], hi = hd.range[2 * g + 1];
-    const int nc = hd.nclasses;
-    for (int64_t item = lo + blockIdx.x; item < hi; item += gridDim.x) {
-        // the class holding the item: the last c with first[c] <= item
-        int c0 = 0, c1 = nc;
-        while (c1 - c0 > 1) {
-            const int m = (c0 + c1) >> 1;
-            if (first[m] <= item) c0 = m; else c1 = m;
+    const int64_t nw = (int64_t)gridDim.x * waves;
+    const int64_t per = (hi - lo + nw - 1) / nw;
+    int64_t item = lo + ((int64_t)blockIdx.x * waves + wv) * per;
+    const int64_t end = min(hi, item + per);
+    if (item >= end) return;
+    uint64_t *tile = lds + (size_t)wv * tile_words;
+    // the class holding the first item: the last c with first[c] <= item
+    int c = 0, c1 = hd.nclasses;
+    while (c1 - c > 1) {
+        const int m = (c + c1) >> 1;
+        if (first[m] <= item) c = m; else c1 = m;
+    }
+    int64_t next = first[c + 1];
+    if constexpr (PF == 0) {
+        for (; item < end; ++item) {
+            while (item >= next) next = first[++c + 1];
+            const EncodeDesc &a = cls[c];
+            const int64_t local = item - first[c];
+            const int64_t blk = local / a.ntiles;
+            const int t = (int)(local - blk * a.ntiles);
+            encode_item<Q>(a, blk, t, tile, lane);
         }
-        const EncodeDesc &a = cls[c0];
-        const int64_t local = item - first[c0];
-        const int64_t blk = local / a.ntiles;
-        const int t = (int)(local - blk * a.ntiles);
-        switch (a.Q) {
-#define MJ_ENC_CASE(QQ)                                      \
-    case QQ:                                                 \
-        if constexpr (QQ <= QMAX) encode_item<QQ>(a, blk, t, lds, lane); \
-        break;
-            MJ_ENC_CASE(1) MJ_ENC_CASE(2) MJ_ENC_CASE(3) MJ_ENC_CASE(4)
-            MJ_ENC_CASE(5) MJ_ENC_CASE(6) MJ_ENC_CASE(7) MJ_ENC_CASE(8)
-            MJ_ENC_CASE(9) MJ_ENC_CASE(10) MJ_ENC_CASE(11) MJ_ENC_CASE(12)
-            MJ_ENC_CASE(13) MJ_ENC_CASE(14) MJ_ENC_CASE(15) MJ_ENC_CASE(16)
-#undef MJ_ENC_CASE
-            default: break;
+    } else {
+        uint64_t reg[Q][PF];
+        // the words of item `it` (class k) this lane stages
+        auto fetch = [&](const EncodeDesc &a, int64_t local) {
+            const int64_t blk = local / a.ntiles;
+            const int t = (int)(local - blk * a.ntiles);
+            const uint64_t *img = a.image_of(blk);
+            const int x0 = t * a.W;
+#pragma unroll
+            for (int l = 0; l < Q; ++l)
+#pragma unroll
+                for (int j = 0; j < PF; ++j) {
+                    const int cc = lane + j * kWave;
+                    const int col = x0 - a.H + cc;
+                    reg[l][j] = (cc < a.S && (unsigned)col < (unsigned)a.P)
+                                    ? img[(int64_t)l * a.P + col] : 0;
+                }
+        };
+        fetch(cls[c], item - first[c]);
+        while (item < end) {
+            const EncodeDesc &a = cls[c];
+#pragma unroll
+            for (int l = 0; l < Q; ++l)
+#pragma unroll
+                for (int j = 0; j < PF; ++j) {
+                    const int cc = lane + j * kWave;
+                    if (cc < a.S) tile[l * a.S + cc] = reg[l][j];
+                }
+            wave_sync();
+            const int64_t local = item - first[c];
+            const int64_t blk = local / a.ntiles;
+            const int t = (int)(local - blk * a.ntiles);
+            // the next item and its class; its words load during this one
+            const int64_t nit = item + 1;
+            int c2 = c;
+            int64_t next2 = next;
+            while (nit >= next2 && nit < end) next2 = first[++c2 + 1];
+            if (nit < end) fetch(cls[c2], nit - first[c2]);
+            encode_bins<Q, EncodeDesc, false>(a, blk, t, tile, lane, 0);
+            item = nit;
+            c = c2;
+            next = next2;
         }
     }
 }
 
-hipError_t launch_encode_desc(int qmax, const DescCall &c, int g, size_t lds, int grid,
-                              hipStream_t s) {
+// Register prefetch chunks of a descriptor encode launch of Q rows whose
+// tiles and halos span at most max_s columns (0: none fits).
+int encode_desc_prefetch(int Q, int max_s) {
+    const int pf = Q <= 4 ? 3 : Q <= 8 ? 4 : Q <= 12 ? 5 : 0;
+    return pf && max_s <= pf * kWave ? pf : 0;
+}
+
+hipError_t launch_encode_desc(int Q, const DescCall &c, int g, int waves, int tile_words,
+                              int grid, hipStream_t s) {
     const uint8_t *ws = c.ws;
-    if (qmax <= 4)
-        hipLaunchKernelGGL(encode_desc_kernel<4>, dim3(grid), dim3(kWave), lds, s, ws, g);
-    else if (qmax <= 8)
-        hipLaunchKernelGGL(encode_desc_kernel<8>, dim3(grid), dim3(kWave), lds, s, ws, g);
-    else if (qmax <= 12)
-        hipLaunchKernelGGL(encode_desc_kernel<12>, dim3(grid), dim3(kWave), lds, s, ws, g);
-    else
-        hipLaunchKernelGGL(encode_desc_kernel<16>, dim3(grid), dim3(kWave), lds, s, ws, g);
+    const size_t lds = (size_t)waves * tile_words * sizeof(uint64_t);
+    const int pf = encode_desc_prefetch(Q, tile_words / Q);
+#define MJ_ENC_LAUNCH2(QQ, PP)                                                                 \
+    hipLaunchKernelGGL((encode_desc_kernel<QQ, PP>), dim3(grid), dim3(kWave * waves), lds, s, \
+                       ws, g, waves, tile_words)
+#define MJ_ENC_LAUNCH(QQ, PPF)                                                                 \
+    case QQ:                                                                                   \
+        if (pf) MJ_ENC_LAUNCH2(QQ, PPF); else MJ_ENC_LAUNCH2(QQ, 0);                           \
+        break;
+    switch (Q) {
+        MJ_ENC_LAUNCH(1, 3) MJ_ENC_LAUNCH(2, 3) MJ_ENC_LAUNCH(3, 3) MJ_ENC_LAUNCH(4, 3)
+        MJ_ENC_LAUNCH(5, 4) MJ_ENC_LAUNCH(6, 4) MJ_ENC_LAUNCH(7, 4) MJ_ENC_LAUNCH(8, 4)
+        MJ_ENC_LAUNCH(9, 5) MJ_ENC_LAUNCH(10, 5) MJ_ENC_LAUNCH(11, 5) MJ_ENC_LAUNCH(12, 5)
+        case 13: MJ_ENC_LAUNCH2(13, 0); break;
+        case 14: MJ_ENC_LAUNCH2(14, 0); break;
+        case 15: MJ_ENC_LAUNCH2(15, 0); break;
+        case 16: MJ_ENC_LAUNCH2(16, 0); break;
+        default: return hipErrorInvalidValue;
+    }
+#undef MJ_ENC_LAUNCH
+#undef MJ_ENC_LAUNCH2
     return hipGetLastError();
 }
 

@@ -333,12 +333,11 @@ struct DescCall {
 
 hipError_t launch_desc_buckets(const DescCall &c, hipStream_t s);
 // One launch of a descriptor-driven decode or encode over launch group g
-// (every class when the call has one group; the classes of Q = g otherwise).
-hipError_t launch_decode_desc(unsigned qmask, const DescCall &c, int g, size_t lds, int grid,
+// (the classes of row count Q = g).
+hipError_t launch_decode_desc(int Q, const DescCall &c, int g, size_t lds, int grid,
                               hipStream_t s);
-bool decode_desc_supported(unsigned qmask);
-hipError_t launch_encode_desc(int qmax, const DescCall &c, int g, size_t lds, int grid,
-                              hipStream_t s);
+hipError_t launch_encode_desc(int Q, const DescCall &c, int g, int waves, int tile_words,
+                              int grid, hipStream_t s);
 
 // Status of a HIP call as a library status code; a failure is remembered for
 // mojette_last_hip_error() on the calling thread.
