@@ -15,10 +15,13 @@ an output ring per class (where reads land):
   - a read needs a resident object of its class and a row of the output ring;
   - an iteration takes at most `cap` requests of each kind per class.
 Every loop turn retires the iterations whose completion event has fired,
-admits what has arrived and fits, and launches ONE scatter-encode and ONE
-gather-decode job launch for every class with work (the job API of
-``mojette.h``; 16 classes per launch), up to `depth` iterations in flight, so
-requests join while earlier ones are still running on the device.
+admits what has arrived and fits, and issues ONE descriptor-driven encode
+call for every write and ONE descriptor-driven decode call for every
+short-row read of every class (a 24-byte descriptor per request: where its
+image and its arena slot sit in the server's one word pool, its row length,
+code and erasure mask), plus chunked decode jobs for the long-row reads on
+side streams, up to `depth` iterations in flight, so requests join while
+earlier ones are still running on the device.
 
 Latency is arrival to the GPU completion event of the request's iteration,
 read on the GPU clock from a start event that had completed before the host
@@ -172,16 +175,18 @@ class SlotStore:
 
 
 class _Class(SlotStore):
-    """Device buffers of one class on top of its slot bookkeeping."""
+    """Device buffers of one class (views into the server's word pool, at the
+    given word offsets) on top of its slot bookkeeping."""
 
-    def __init__(self, geo: Geometry, slots: int, cap: int, depth: int, dev, torch):
+    def __init__(self, geo: Geometry, slots: int, cap: int, depth: int, pool, offs):
         super().__init__(slots)
         self.geo = geo
         self.cap = cap
         self.pay = 2 * cap
-        self.arena = torch.empty(slots * geo.words, dtype=torch.int64, device=dev)
-        self.payload = torch.empty(self.pay * geo.img_words, dtype=torch.int64, device=dev)
-        self.out = torch.empty(depth * cap * geo.img_words, dtype=torch.int64, device=dev)
+        self.arena_off, self.payload_off, self.out_off = offs
+        self.arena = pool[self.arena_off:self.arena_off + slots * geo.words]
+        self.payload = pool[self.payload_off:self.payload_off + self.pay * geo.img_words]
+        self.out = pool[self.out_off:self.out_off + depth * cap * geo.img_words]
         self.arena_ptr = self.arena.data_ptr()
         self.payload_ptr = self.payload.data_ptr()
         self.out_ptr = self.out.data_ptr()
@@ -199,7 +204,8 @@ class Server:
 
     def __init__(self, budget_bytes: int = 64 << 30, depth: int = 3, seed: int = 1,
                  geos=None, prefill: float = 0.5, per_iter_bytes: int = 16 << 20,
-                 chunk_min_P: int = 1024, chunk_cols: int = 256, side_streams: int = 3):
+                 chunk_min_P: int = 1024, chunk_cols: int = 256, side_streams: int = 3,
+                 chunk_max_reads: int = 512):
         import torch
 
         self.torch = torch
@@ -225,23 +231,50 @@ class Server:
                     self.plans[key] = mj.ChunkPlan(g.dirs, g.Q, chunk_cols)
                 w = self.plans[key].workspace_words(g.P, cap)
             ws_words.append(w)
+        # Writes and whole-block reads go through the descriptor-driven calls:
+        # one plan over the codes, a descriptor per request (24 bytes) staged
+        # with the slot lists, one workspace (the calls run in stream order).
+        codes = []
+        for g in self.geos:
+            if (g.Q, tuple(g.dirs)) not in codes:
+                codes.append((g.Q, tuple(g.dirs)))
+        self.geom_id = [codes.index((g.Q, tuple(g.dirs))) for g in self.geos]
+        self.plan = mj.GeomPlan([(q, list(d)) for q, d in codes])
+        self.max_desc = 2 * sum(caps)
+        desc_words = 3 * self.max_desc
+        stage_words += desc_words
+        ws_bytes = self.plan.workspace_bytes(self.max_desc)
         fixed = sum((depth + 2) * c * g.img_words * 8 for c, g in zip(caps, self.geos))
-        fixed += 2 * depth * stage_words * 8 + depth * 8 * sum(ws_words)
+        fixed += 2 * depth * stage_words * 8 + depth * 8 * sum(ws_words) + ws_bytes
         if fixed >= budget_bytes:
             raise ValueError("budget too small for the payload pools and output rings")
         share = (budget_bytes - fixed) // len(self.geos)
-        self.cs = []
+        # one word pool holds every class's arena, payload pool and output ring
+        layout, at = [], 0
         for c, (g, cap) in enumerate(zip(self.geos, caps)):
             slots = share // (g.words * 8)
             if slots < 2 * cap:
                 raise ValueError(f"budget leaves class {c} fewer than {2 * cap} slots")
-            st = _Class(g, int(slots), cap, depth, self.dev, torch)
+            offs = (at, at + slots * g.words, at + slots * g.words + 2 * cap * g.img_words)
+            at = offs[2] + depth * cap * g.img_words
+            layout.append((int(slots), offs))
+        self.pool = torch.empty(at, dtype=torch.int64, device=self.dev)
+        self.ws = torch.empty(max(1, ws_bytes), dtype=torch.uint8, device=self.dev)
+        self.cs = []
+        for c, (g, cap) in enumerate(zip(self.geos, caps)):
+            slots, offs = layout[c]
+            st = _Class(g, slots, cap, depth, self.pool, offs)
             st.plan = self.plans.get((tuple(g.dirs), g.Q)) if ws_words[c] else None
             st.ws_words = ws_words[c]
             st.ws = (torch.empty(depth * ws_words[c], dtype=torch.int64, device=self.dev)
                      if ws_words[c] else None)
             self.cs.append(st)
         self.side = [torch.cuda.Stream() for _ in range(side_streams)]
+        # Long-row reads are chunked only in iterations of at most this many
+        # reads: a chunked read halves one read's latency at twice the sweep
+        # work, which pays while an iteration leaves the chip idle; a large
+        # iteration fills it with whole-block sweeps, in the one decode call.
+        self.chunk_max_reads = chunk_max_reads
         for c, st in enumerate(self.cs):
             mj.mojette_fill_splitmix64(st.payload, st.payload.numel(), seed * 1000 + c,
                                        stream=self.stream_ptr)
@@ -259,9 +292,9 @@ class Server:
 
     @property
     def budget_used(self) -> int:
-        b = (self.h_stage.numel() + self.d_stage.numel()) * 8
+        b = (self.h_stage.numel() + self.d_stage.numel()) * 8 + self.ws.numel()
+        b += self.pool.numel() * 8
         for st in self.cs:
-            b += (st.arena.numel() + st.payload.numel() + st.out.numel()) * 8
             b += st.ws.numel() * 8 if st.ws is not None else 0
         return b
 
@@ -317,38 +350,66 @@ class Server:
                 st.push_resident(slots, np.arange(b))
                 want -= b
 
+    def _descriptors(self, at: int, entries) -> int:
+        """Write descriptors (image_off, proj_off, P | geom_id | mask) at word
+        `at` of the host stage; entries: (class, image word offsets, slots,
+        masks or None).  Returns the number written."""
+        hs = self.h_np
+        k0 = 0
+        for c, img_off, slots, masks in entries:
+            st = self.cs[c]
+            k = len(slots)
+            d = hs[at + 3 * k0:at + 3 * (k0 + k)].reshape(k, 3)
+            d[:, 0] = img_off
+            d[:, 1] = st.arena_off + slots * st.geo.words
+            w = np.full(k, st.geo.P | (self.geom_id[c] << 32), dtype=np.int64)
+            if masks is not None:
+                w |= masks.astype(np.int64) << 48
+            d[:, 2] = w
+            k0 += k
+        return k0
+
     def _launch(self, writes, reads, trace: Trace):
-        """Stage slot lists and masks, copy them over, launch, record the
-        completion event.  writes: (class, ids, slots, first payload row);
-        reads: (class, ids, slots)."""
+        """Stage descriptors, slot lists and masks, copy them over, launch,
+        record the completion event.  writes: (class, ids, slots, first
+        payload row); reads: (class, ids, slots).  Writes and whole-block
+        reads are one descriptor-driven encode and one decode over every
+        class; long-row reads are chunked decode jobs on side streams."""
         torch = self.torch
         ring = self.iter_no % self.depth
         self.iter_no += 1
         base = ring * self.stage_words
-        pos = base
         hs = self.h_np
-        wl, rl = [], []
+        wd, rd, rl = [], [], []
         for c, ids, slots, row0 in writes:
-            k = len(slots)
             st = self.cs[c]
-            hs[pos:pos + k] = slots
-            wl.append((c, k, st.payload_ptr + row0 * st.geo.img_words * 8,
-                       self.d_stage_ptr + pos * 8, None))
-            pos += k
+            img = st.payload_off + (row0 + np.arange(len(slots))) * st.geo.img_words
+            wd.append((c, img, slots, None))
+        chunking = sum(len(r[2]) for r in reads) <= self.chunk_max_reads
         for c, ids, slots in reads:
-            k = len(slots)
             st = self.cs[c]
+            if st.plan is None or not chunking:
+                img = st.out_off + (ring * st.cap + np.arange(len(slots))) * st.geo.img_words
+                rd.append((c, img, slots, trace.mask[ids]))
+        nw = self._descriptors(base, wd)
+        nr = self._descriptors(base + 3 * nw, rd)
+        pos = base + 3 * (nw + nr)
+        for c, ids, slots in reads:
+            st = self.cs[c]
+            if st.plan is None or not chunking:
+                continue
+            k = len(slots)
             hs[pos:pos + k] = slots
-            nw = (k + 3) // 4
-            hs[pos + k + nw - 1] = 0
-            hs[pos + k:pos + k + nw].view(np.uint16)[:k] = trace.mask[ids]
+            nmw = (k + 3) // 4
+            hs[pos + k + nmw - 1] = 0
+            hs[pos + k:pos + k + nmw].view(np.uint16)[:k] = trace.mask[ids]
             out = st.out_ptr + ring * st.cap * st.geo.img_words * 8
             rl.append((c, k, out, self.d_stage_ptr + pos * 8, self.d_stage_ptr + (pos + k) * 8))
-            pos += k + nw
+            pos += k + nmw
         begin = torch.cuda.Event(enable_timing=True)
         done = torch.cuda.Event(enable_timing=True)
-        chunked = [e for e in rl if self.cs[e[0]].plan is not None]
-        whole = [e for e in rl if self.cs[e[0]].plan is None]
+        chunked = rl
+        stage_u8 = self.d_stage.view(torch.uint8)
         with torch.cuda.stream(self.stream):
             begin.record(self.stream)
             self.d_stage[base:pos].copy_(self.h_stage[base:pos], non_blocking=True)
@@ -368,10 +429,14 @@ class Server:
                     ev = torch.cuda.Event()
                     ev.record(side)
                     joins.append(ev)
-            if wl:
-                self._run_jobs("w", wl)
-            if whole:
-                self._run_jobs("r", whole)
+            if nw:
+                d = stage_u8[8 * base:8 * (base + 3 * nw)]
+                mj.mojette_encode_batched(self.plan, d, nw, self.pool, self.ws, self.status,
+                                          stream=self.stream_ptr)
+            if nr:
+                d = stage_u8[8 * (base + 3 * nw):8 * (base + 3 * (nw + nr))]
+                mj.mojette_decode_batched(self.plan, d, nr, self.pool, self.ws, self.status,
+                                          stream=self.stream_ptr)
             for ev in joins:
                 self.stream.wait_event(ev)
             done.record(self.stream)

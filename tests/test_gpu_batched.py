@@ -325,3 +325,45 @@ def test_graph_replay(mj):
         torch.cuda.synchronize()
         assert torch.equal(got, d_pool)
     plan.close()
+
+
+def test_mixed_workload_recipe_sample(mj):
+    """The mixed workload's recipe (sizes 4K/8K/64K/1M, codes (4,2), (6,3),
+    (8,4), (12,4), erasures 0..m per block), a few thousand blocks in block
+    order through the descriptor calls with erased projections poisoned,
+    padded last rows included: round trip of every block, and encode and
+    decode against the oracle on a sample that holds every class present."""
+    N = 3000
+    size_idx, code_idx, masks = synth.mixed_block_list(N, synth.SEED_DATA)
+    codes = [(k, synth.centered_dirs(k + m)) for k, m in synth.MIXED_CODES]
+    sizes = np.array(synth.MIXED_SIZES)[size_idx]
+    # keep the 1 MB blocks few: every fourth of them
+    keep = np.flatnonzero((sizes < (1 << 20)) | (np.arange(N) % 4 == 0))
+    size_idx, code_idx, masks, sizes = size_idx[keep], code_idx[keep], masks[keep], sizes[keep]
+    Ps = np.array([-(-int(s) // (8 * codes[g][0])) for s, g in zip(sizes, code_idx)])
+    say(f"mixed recipe sample: {len(keep)} blocks, {int(sizes.sum()) >> 20} MiB")
+    lay, imgs, src, dec, st = run_round_trip(mj, codes, code_idx, Ps, masks, 600)
+    assert st == 0
+    for b in range(len(keep)):
+        o = int(lay.img_off[b])
+        assert np.array_equal(dec[o:o + imgs[b].size], imgs[b].ravel()), b
+    # oracle on one block of every (size, code) class present
+    for key in sorted(set(zip(size_idx.tolist(), code_idx.tolist()))):
+        b = int(np.flatnonzero((size_idx == key[0]) & (code_idx == key[1]))[0])
+        Q, dirs = codes[code_idx[b]]
+        P = int(Ps[b])
+        words = sum(oracle.proj_size(p, 1, P, Q) for p in dirs)
+        o = int(lay.proj_off[b])
+        want_enc = oracle.encode_blocks(imgs[b][None], P, Q, dirs)[0]
+        got_src = src[o:o + words]
+        keep_bins = np.ones(words, dtype=bool)
+        off = 0
+        for i, p in enumerate(dirs):
+            s = oracle.proj_size(p, 1, P, Q)
+            if (int(masks[b]) >> i) & 1:
+                keep_bins[off:off + s] = False
+            off += s
+        assert np.array_equal(got_src[keep_bins], want_enc[keep_bins]), key
+        want = oracle.decode_blocks(got_src[None], masks[b:b + 1], P, Q, dirs)[0]
+        oi = int(lay.img_off[b])
+        assert np.array_equal(dec[oi:oi + imgs[b].size].reshape(Q, P), want), key

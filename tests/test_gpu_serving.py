@@ -36,15 +36,18 @@ def alone_decode(mj, projs, mask, g):
     return out
 
 
-@pytest.mark.parametrize("budget_mib,prefill,qps", [(3072, 0.5, 100000), (640, 1.0, 200000)])
-def test_serving_mix_matches_alone_and_oracle(mj, orc, budget_mib, prefill, qps):
+@pytest.mark.parametrize("budget_mib,prefill,qps,chunk_max",
+                         [(3072, 0.5, 100000, 512), (640, 1.0, 200000, 512),
+                          (3072, 0.5, 100000, 0)])   # the last: long rows never chunked
+def test_serving_mix_matches_alone_and_oracle(mj, orc, budget_mib, prefill, qps, chunk_max):
     from paper_1504_07038_amd import serving
 
     seed = 11
     geos = serving.geometries(per_octave=1)
-    say(f"serving: budget {budget_mib} MiB, prefill {prefill}, qps {qps}, {len(geos)} classes")
+    say(f"serving: budget {budget_mib} MiB, prefill {prefill}, qps {qps}, {len(geos)} classes, "
+        f"chunked reads up to {chunk_max} per iteration")
     srv = serving.Server(budget_bytes=budget_mib << 20, depth=3, seed=seed, geos=geos,
-                         prefill=prefill, per_iter_bytes=2 << 20)
+                         prefill=prefill, per_iter_bytes=2 << 20, chunk_max_reads=chunk_max)
     assert srv.budget_used <= budget_mib << 20
     tr = serving.make_trace(qps, 0.05, geos, seed=3)
     N = len(tr.arrival)
