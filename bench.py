@@ -43,7 +43,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="4k_6_4", choices=sorted(WORKLOADS) + ["mixed", "serving", "tune", "chunked", "sys"])
+    ap.add_argument("--workload", default="4k_6_4", choices=sorted(WORKLOADS) + ["mixed", "serving", "tune", "chunked", "sys",
+                                                   "two_corner"])
     ap.add_argument("--mixed-budget-gib", type=float, default=70.0,
                     help="mixed workload: device memory for the projections of one chunk")
     ap.add_argument("--mixed-blocks", type=int, default=500000,
@@ -247,6 +248,9 @@ def main():
         return
     if args.workload == "sys":
         run_sys(args)
+        return
+    if args.workload == "two_corner":
+        run_two_corner(args)
         return
 
     import numpy as np
@@ -646,6 +650,71 @@ def run_mixed(args):
     }
     print(json.dumps(rec), flush=True)
     plan.close()
+    if not ok:
+        sys.exit(1)
+
+
+def run_two_corner(args):
+    """The two-corner decode (every block swept from both ends) against the
+    one-sided sweep of mojette_decode_batch, HIP events: 8 KB (12,8) blocks
+    at 2^19 (4 erasures), the 64 KB blocks of the (4,2), (6,3), (8,4), (12,4)
+    codes (10,000 each, erasures 0..m), and 1 MB (4,2) blocks alone and 256
+    at a time."""
+    import numpy as np
+    import torch
+
+    import paper_1504_07038_amd as mj
+    import synth
+
+    dev = torch.device("cuda:0")
+    rows = []
+
+    def timed(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            torch.cuda.synchronize()
+            ts.append(a.elapsed_time(b))
+        return float(np.median(ts))
+
+    cases = [("8 KB (12,8)", 128, 8, 4, 1 << 19, 4)]
+    for k, m in synth.MIXED_CODES:
+        cases.append((f"64 KB ({k},{m})", -(-65536 // (8 * k)), k, m, 10000, (0, m)))
+    cases += [("1 MB (4,2), one block", 32768, 4, 2, 1, 2), ("1 MB (4,2), 256 blocks", 32768, 4, 2, 256, 2)]
+    ok = True
+    for name, P, Q, m, nb, ner in cases:
+        dirs = synth.centered_dirs(Q + m)
+        words = mj.mojette_block_words(dirs, P, Q)
+        img = torch.empty(nb * P * Q, dtype=torch.int64, device=dev)
+        mj.mojette_fill_splitmix64(img, img.numel(), synth.SEED_DATA)
+        proj = torch.empty(nb * words, dtype=torch.int64, device=dev)
+        mj.mojette_encode_batch(img, nb, P, Q, dirs, proj)
+        masks = synth.erasure_masks(synth.SEED_ERASE, nb, Q + m, ner)
+        d_mask = torch.from_numpy(masks.view(np.int16)).to(dev)
+        out1, out2 = torch.empty_like(img), torch.empty_like(img)
+        t1 = timed(lambda: mj.mojette_decode_batch(proj, d_mask, nb, P, Q, dirs, out1))
+        t2 = timed(lambda: mj.mojette_decode_batch_two_corner(proj, d_mask, nb, P, Q, dirs, out2))
+        same = bool(torch.equal(out1, img)) and bool(torch.equal(out2, img))
+        ok = ok and same
+        user = nb * P * Q * 8
+        rows.append({"case": name, "blocks": nb, "P": P, "Q": Q,
+                     "one_sided_ms": round(t1, 4), "two_corner_ms": round(t2, 4),
+                     "one_sided_GBps": round(user / (t1 * 1e-3) / 1e9, 1),
+                     "two_corner_GBps": round(user / (t2 * 1e-3) / 1e9, 1),
+                     "speedup": round(t1 / t2, 3), "identical": same})
+        log(f"two-corner: {rows[-1]}")
+        del img, proj, out1, out2
+        torch.cuda.empty_cache()
+    rec = {"metric": "decode time, two-corner against one-sided sweep", "value": None,
+           "unit": "ms", "n_gpus": 1, "higher_is_better": False, "dtype": "u64",
+           "data": "synthetic", "config": {"workload": "two_corner", "parallelism": "single GPU"},
+           "rows": rows, "roundtrip_ok": ok, "roofline": None, "cpu_baseline": None}
+    print(json.dumps(rec), flush=True)
     if not ok:
         sys.exit(1)
 

@@ -250,6 +250,25 @@ int mojette_decode_batch_tuned(const uint64_t *projs, const uint16_t *erased, in
                                uint64_t *images, int32_t *status, int32_t blocks_per_wave,
                                void *stream);
 
+/*
+ * mojette_decode_batch with a shallower reconstruction path (Section 2.2:
+ * the path is fixed in advance and may propagate from the corners of the
+ * image toward its center).  Every block is swept from both ends at once:
+ * from column 0 as in mojette_decode_batch, and from column P-1 as the same
+ * sweep of the column-mirrored block (whose projections are those along
+ * (-p, 1), bins in reverse order; its rows take the survivors in ascending
+ * -p).  Each sweep stops once every row has reached the middle column, so
+ * a block's dependency chain is about half as deep (about P half-steps
+ * instead of 2P); the work is the same, plus the columns both sweeps reach.
+ * Results are bit-identical to mojette_decode_batch.  blocks_per_wave as for
+ * mojette_decode_batch_tuned (two slots per block).  Arguments, layouts and
+ * errors as for mojette_decode_batch.
+ */
+int mojette_decode_batch_two_corner(const uint64_t *projs, const uint16_t *erased,
+                                    int64_t nblocks, int32_t P, int32_t Q, const int32_t *dirs,
+                                    int32_t n, uint64_t *images, int32_t *status,
+                                    int32_t blocks_per_wave, void *stream);
+
 /* Blocks per decode wavefront for this geometry: the most that fit in LDS,
  * and the library's own choice for mojette_decode_batch (all the lanes
  * allow when their rings take at most 34 KB of LDS, else at most half of

@@ -184,6 +184,8 @@ def lib() -> ctypes.CDLL:
                                       ctypes.c_int),
         "mojette_decode_batch_tuned": ([vp, vp, i64, i32, i32, vp, i32, vp, vp, i32, vp],
                                        ctypes.c_int),
+        "mojette_decode_batch_two_corner": ([vp, vp, i64, i32, i32, vp, i32, vp, vp, i32, vp],
+                                            ctypes.c_int),
         "mojette_decode_max_blocks_per_wave": ([vp, i32, i32, i32], i32),
         "mojette_decode_default_blocks_per_wave": ([vp, i32, i32, i32], i32),
         "mojette_decode_batch_launches": ([vp, i32, i32, i32, i64, i32, vp, vp, vp, i32], i32),
@@ -243,7 +245,8 @@ def exported_symbols() -> list[str]:
         "mojette_encode_batch_wide", "mojette_decode_batch_wide", "mojette_verify_batch",
         "mojette_trimmed_layout", "mojette_encode_batch_trimmed", "mojette_decode_batch_trimmed",
         "mojette_encode_batch_sys", "mojette_sys_workspace", "mojette_decode_batch_sys",
-        "mojette_decode_batch_tuned", "mojette_decode_max_blocks_per_wave",
+        "mojette_decode_batch_tuned", "mojette_decode_batch_two_corner",
+        "mojette_decode_max_blocks_per_wave",
         "mojette_decode_default_blocks_per_wave", "mojette_decode_batch_launches",
         "mojette_classes_layout", "mojette_encode_classes", "mojette_decode_classes",
         "mojette_encode_jobs", "mojette_decode_jobs", "mojette_chunk_plan_create",
@@ -474,6 +477,24 @@ def mojette_decode_batch_tuned(projs, erased, nblocks: int, P: int, Q: int, dirs
                                           _dev_ptr(status, "status"), blocks_per_wave,
                                           _stream(stream))
     return _check(rc, "mojette_decode_batch_tuned", check)
+
+
+def mojette_decode_batch_two_corner(projs, erased, nblocks: int, P: int, Q: int, dirs, images,
+                                    status=None, blocks_per_wave: int = 0, stream=None,
+                                    check: bool = True) -> int:
+    """mojette_decode_batch swept from both ends of every block (half the
+    dependency chain, the same words)."""
+    import torch
+
+    arr, n = _i32_array(dirs)
+    if erased is not None and erased.dtype not in (torch.int16, torch.uint16):
+        raise ValueError("erased must be 16-bit masks")
+    rc = lib().mojette_decode_batch_two_corner(_word_tensor(projs, "projs"),
+                                               _dev_ptr(erased, "erased"), nblocks, P, Q, arr, n,
+                                               _word_tensor(images, "images"),
+                                               _dev_ptr(status, "status"), blocks_per_wave,
+                                               _stream(stream))
+    return _check(rc, "mojette_decode_batch_two_corner", check)
 
 
 def mojette_decode_max_blocks_per_wave(dirs, P: int, Q: int) -> int:

@@ -1205,6 +1205,53 @@ int mojette_decode_batch_chunked(const mojette_chunk_plan *plan, const uint64_t 
     return chunked_launch(plan, nchunks, a, Q, false, workspace, (hipStream_t)stream);
 }
 
+int mojette_decode_batch_two_corner(const uint64_t *projs, const uint16_t *erased,
+                                    int64_t nblocks, int32_t P, int32_t Q, const int32_t *dirs,
+                                    int32_t n, uint64_t *images, int32_t *status,
+                                    int32_t blocks_per_wave, void *stream) {
+    if (nblocks < 0 || blocks_per_wave < 0 || !geometry_ok(dirs, n, P, Q)) return MOJETTE_EINVAL;
+    if (nblocks == 0) return MOJETTE_OK;
+    if (!projs || !images) return MOJETTE_EINVAL;
+    mj::DecodeArgs a{};
+    int rc = decode_setup(dirs, n, P, Q, a);
+    if (rc != MOJETTE_OK) return rc;
+    // the mirrored sweeps take the survivors in ascending -p: the ring
+    // covers the survivor sets of the negated directions too
+    std::vector<int> neg(n);
+    for (int s = 0; s < n; ++s) neg[s] = -a.p_sorted[n - 1 - s];
+    const int Rn = ring_length(neg, Q);
+    if (Rn < 0) return MOJETTE_EINVAL;
+    a.R = std::max(a.R, Rn);
+    a.ring_stride = a.R + 1;
+    // two slots per block: the half-slot body, within the LDS share
+    const int half = std::max(1, mj::decode_max_blocks_per_wave(Q) / 2);
+    a.nb = blocks_per_wave > 0 ? std::min(blocks_per_wave, half) : default_blocks(Q, a.ring_stride);
+    a.nb = std::min(a.nb, half);
+    while (a.nb > 1 && mj::decode_lds_bytes(Q, a.nb, a.ring_stride) > kLdsLimit) --a.nb;
+    if (mj::decode_lds_bytes(Q, a.nb, a.ring_stride) > kLdsLimit) return MOJETTE_ENOTSUP;
+    int64_t off = 0;
+    for (int i = 0; i < n; ++i) {
+        a.off[i] = (int32_t)off;
+        off += mojette_proj_size(dirs[i], P, Q);
+    }
+    a.pool = projs;
+    a.proj_stride = off;
+    a.images = images;
+    a.img_stride = (int64_t)P * Q;
+    a.masks = erased;
+    a.mask_uniform = 0;
+    a.status = status;
+    a.nblocks = nblocks;
+    // a wave's slots span nb/2 + 1 blocks, addressed with 32-bit offsets
+    const int64_t span = a.nb / 2 + 1;
+    if (span * a.proj_stride * 8 >= ((int64_t)1 << 31) || span * a.img_stride * 8 >= ((int64_t)1 << 31))
+        return MOJETTE_ENOTSUP;
+    const int64_t batches = (2 * nblocks + a.nb - 1) / a.nb;
+    const int grid = (int)std::min<int64_t>(batches, kDecodeGridCap);
+    clear_stale_error();
+    return status_of(mj::launch_decode(Q, mj::kLaunchTwoCorner, a, grid, (hipStream_t)stream));
+}
+
 int mojette_decode_batch_tuned(const uint64_t *projs, const uint16_t *erased, int64_t nblocks,
                                int32_t P, int32_t Q, const int32_t *dirs, int32_t n,
                                uint64_t *images, int32_t *status, int32_t blocks_per_wave,

@@ -166,6 +166,8 @@ struct SegParam {
     int img;       // offset (in the wave's image slice) of the segment's row
     const uint64_t *bins;   // pointer mode: the row's projection
     uint64_t *dst;          // descriptor classes: the segment's image row
+    int last;      // two-corner sweeps: the last column computed in the row
+    bool mir;      // two-corner sweeps: the row belongs to a mirrored sweep
     bool on;       // segment belongs to a block slot in use
     bool known;    // systematic code: a surviving line (staged from the image, not stored)
 };
@@ -183,6 +185,21 @@ struct SegParam {
 //            of every row) to the workspace;
 //   kChunkC  chunk c >= 1, from its exact start state read from the
 //            workspace; stores its image windows.
+//   kTwoCorner  (pool mode, whole blocks) two slots per block: side 0
+//            sweeps from column 0, side 1 from column P-1.  The image read
+//            from its right end is the column-mirror of the image, whose
+//            projections are those along (-p, 1) with their bins in reverse
+//            order (bin j of direction p is bin B-1-j of direction -p of the
+//            mirror), so side 1 is the same sweep on the mirrored block: its
+//            rows take the survivors in ascending -p, it loads its bins in
+//            ascending order and stores its pixels at mirrored columns.  A
+//            sweep stopped after any number of tiles has computed a set of
+//            pixels that holds every pixel each of them depends on (all are
+//            earlier in the sweep), and both are exact.  Each side sweeps
+//            until every row has reached the middle column from its end,
+//            about half the tiles of a whole sweep, then stores the pixels
+//            it has computed; columns both reach are stored twice with the
+//            same words.  The dependency chain of a block is about halved.
 //
 // NBT is the most block slots the body is compiled for (a.nb <= NBT): the
 // full 64 / ceil(Q/2), or half of it when long rings leave LDS for no more,
@@ -250,17 +267,20 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch,
     // Slot -> (block, chunk).  A wave's slots cover consecutive blocks
     // [blk_lo, blk_hi]; `rel` is the slot's block relative to blk_lo.
     int per = 1;                             // slots per block
-    if constexpr (CHUNK != kWhole) per = a.chunk.nchunks - 1;
+    if constexpr (CHUNK == kChunkA || CHUNK == kChunkC) per = a.chunk.nchunks - 1;
+    if constexpr (CHUNK == kTwoCorner) per = 2;
     const int64_t item = batch * NB + slot;
     // Gathered slots (ring class 2, see decode_deep_kernel): the slot's block
     // is given, within the wave's slice [gather_lo, gather_hi).
     const bool gathered = RCLS && gather_blk >= 0;
     const int64_t blk = gathered ? gather_blk : item / per;
     int chunk = 0, shift = 0;                // chunk index, its first column offset
-    if constexpr (CHUNK != kWhole) {
+    if constexpr (CHUNK == kChunkA || CHUNK == kChunkC) {
         chunk = (int)(item - blk * per) + (CHUNK == kChunkC ? 1 : 0);
         shift = chunk * a.chunk.tiles * TW;
     }
+    // two-corner sweeps: side 1 sweeps the column-mirrored block
+    const bool mir = CHUNK == kTwoCorner && (item - blk * per) == 1;
     const int64_t blk_lo = gathered ? gather_lo : batch * NB / per;
     const int rel = (int)(blk - blk_lo);
     const int RS = a.ring_stride;
@@ -310,8 +330,10 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch,
         }
         int A_next = 0;                     // SYS: A of sweep row cnt
         for (int s = 0; s < a.n; ++s) {
-            const int id = a.id_sorted[s];
-            const int p = a.p_sorted[s];
+            // the mirrored block's directions, -p, ascend in reverse order
+            const int sx = mir ? a.n - 1 - s : s;
+            const int id = a.id_sorted[sx];
+            const int p = mir ? -a.p_sorted[sx] : a.p_sorted[sx];
             if (!((mask >> (pbase + id)) & 1u) && cnt < nrows) {
                 int A = 2 * psum + cnt;
                 if constexpr (SYS) {
@@ -346,7 +368,8 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch,
         }
         if (valid && cnt < nrows) {
             // reported once per block: by its whole sweep or its first chunk
-            if (blk_ok && j == 0 && a.status && (CHUNK == kWhole || (CHUNK == kChunkA && chunk == 0)))
+            if (blk_ok && j == 0 && a.status &&
+                (CHUNK == kWhole || (CHUNK == kChunkA && chunk == 0) || (CHUNK == kTwoCorner && !mir)))
                 a.status[0] = MOJETTE_ENOTRECON;
             valid = false;
         }
@@ -386,7 +409,7 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch,
         }
         // Chunked sweeps: the state width E of this survivor set.
         int E = 0;
-        if constexpr (CHUNK != kWhole) {
+        if constexpr (CHUNK == kChunkA || CHUNK == kChunkC) {
             if (valid) E = a.chunk.state_cols[a.chunk.lut[used]];
         }
         // Half-step of pixel (k, r) within the block: h = 2k - A_r + A_max.
@@ -414,6 +437,12 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch,
                      : chunk < a.chunk.nchunks - 1 ? a.chunk.tiles
                                                    : ntiles_all - first_tile;
             first_last = chunk == a.chunk.nchunks - 1 ? 2 : 0;
+        } else if constexpr (CHUNK == kTwoCorner) {
+            // every row reaches column H (side 0) or P - H (side 1, from its
+            // end) once the sweep has passed the row with the largest skew
+            const int H = (P + 1) / 2;
+            const int half = mir ? P - H : H;
+            ntiles = valid ? min(ntiles_all, (half - dmin + TW - 1) / TW) : 0;
         }
         const int ntiles_wave = wave_max(ntiles);
 
@@ -448,6 +477,12 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch,
             Y.d = Y.on ? -((A_max - Ay - 1) >> 1) : 0;   // (Ay - A_max + 1)/2, exact
             jb0 = r0 * p0 - (bin_offset(p0, P, Q) + a.kept_first(id0));
             jb1 = r1 * p1 - (bin_offset(p1, P, Q) + a.kept_first(id1));
+            if (mir) {
+                // bin j of the mirrored block's projection is bin B-1-j of the
+                // stored one: column 0's bin, whose index then ascends with c
+                jb0 = proj_bins(p0, P, Q) - 1 - jb0;
+                jb1 = proj_bins(p1, P, Q) - 1 - jb1;
+            }
         }
 
         // Per-iteration row windows, from the lanes that own their rows.
@@ -523,7 +558,8 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch,
                     const int srel = __shfl(rel, src);
                     if (gathered) orel = srel;
                 }
-                if constexpr (CHUNK != kWhole) {
+                if constexpr (CHUNK == kTwoCorner) orel = __shfl(rel, src);
+                if constexpr (CHUNK == kChunkA || CHUNK == kChunkC) {
                     orel = __shfl(rel, src);
                     oshift = __shfl(shift, src);
                     const int ofl = __shfl(first_last, src);
@@ -541,6 +577,13 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch,
                     s.known = s.on && ((okn >> (odd ? 1 : 0)) & 1);
                 }
                 const int dd = s.on ? sd : 0;
+                s.mir = false;
+                s.last = INT_MAX;
+                if constexpr (CHUNK == kTwoCorner) {
+                    s.mir = __shfl(mir ? 1 : 0, src) != 0;
+                    // the last column the sweep computes in this row
+                    s.last = ntiles_wave * TW + dd - 1;
+                }
                 s.ring = (sslot < NB ? sslot : 0) * SS + srow * RS;
                 s.gbin = odd ? og1 : og0;
                 s.bins = nullptr;
@@ -617,12 +660,20 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch,
                     // pixels of the others whatever their bins hold, so the
                     // lines a row's window covers before column 0 and past
                     // column P-1 are never fetched.
-                    const int w = s.gbin - c - (AL ? s.mis : 0);
+                    int w = s.gbin - c - (AL ? s.mis : 0);
+                    int wn = w + 1;                           // the word of column cw - 1
+                    if constexpr (CHUNK == kTwoCorner) {
+                        // a mirrored sweep's bins ascend with its column
+                        if (s.mir) {
+                            w = s.gbin + c;
+                            wn = w - 1;
+                        }
+                    }
                     const int cw = c + (AL ? s.mis : 0);     // column of word 2q
                     const bool in0 = s.on && (unsigned)cw < (unsigned)P;
                     const bool in1 = s.on && (unsigned)(cw - 1) < (unsigned)P;
                     const uint32_t off0 = in0 && !s.known ? (uint32_t)w * 8u : kOffNone;
-                    const uint32_t off1 = in1 && !s.known ? (uint32_t)(w + 1) * 8u : kOffNone;
+                    const uint32_t off1 = in1 && !s.known ? (uint32_t)wn * 8u : kOffNone;
                     u32x2 w0 = __builtin_amdgcn_raw_buffer_load_b64(rin, off0, 0, 0);
                     u32x2 w1 = __builtin_amdgcn_raw_buffer_load_b64(rin, off1, 0, 0);
                     if constexpr (SYS) {
@@ -684,7 +735,7 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch,
         // Stores the completed TW-aligned window of every row at the end of
         // tile t: columns t*TW + scol0 and the next one (16-byte pixels:
         // t*TW + scol0 and TW/2 columns further).
-        auto store_tile = [&](int t) {
+        auto store_tile = [&](int t, bool flush = false) {
 #pragma unroll
             for (int it = 0; it < NIT; ++it) {
                 const SegParam &s = sp[it];
@@ -705,19 +756,39 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch,
                 } else {
                     const uint64_t w0 = row[c & Rmask], w1 = row[(c + 1) & Rmask];
                     bool in_chunk = true;
-                    if constexpr (CHUNK != kWhole)
+                    if constexpr (CHUNK == kChunkA || CHUNK == kChunkC)
                         in_chunk = ((t < a.chunk.tiles ? store_in : store_past) >> it) & 1u;
                     const bool put = s.on && !s.known && in_chunk;
-                    const bool both = put && c >= 0 && c + 1 < P;
-                    const bool last = put && c == P - 1;
+                    // the last column to store: P - 1, or (a two-corner
+                    // sweep's final store) the last one it computed
+                    int hi = P - 1;
+                    if constexpr (CHUNK == kTwoCorner) {
+                        if (flush) hi = min(hi, s.last);
+                    }
+                    const bool both = put && c >= 0 && c + 1 <= hi;
+                    const bool last = put && c >= 0 && c == hi;
                     if constexpr (POOL) {
-                        const uint32_t off2 = both ? (uint32_t)(s.img + c) * 8u : kOffNone;
-                        const uint32_t off1 = last ? (uint32_t)(s.img + c) * 8u : kOffNone;
+                        // a mirrored sweep's columns c, c+1 are the block's
+                        // columns P-1-c, P-2-c: the pair goes in reverse
+                        int cp = c, cs = c;
+                        uint64_t lo = w0, hi2 = w1;
+                        if constexpr (CHUNK == kTwoCorner) {
+                            if (s.mir) {
+                                cp = P - 2 - c;
+                                cs = P - 1 - c;
+                                lo = w1;
+                                hi2 = w0;
+                            }
+                        }
+                        const uint32_t off2 = both ? (uint32_t)(s.img + cp) * 8u : kOffNone;
+                        const uint32_t off1 = last ? (uint32_t)(s.img + cs) * 8u : kOffNone;
                         __builtin_amdgcn_raw_buffer_store_b128(
-                            u32x4{(uint32_t)w0, (uint32_t)(w0 >> 32), (uint32_t)w1,
-                                  (uint32_t)(w1 >> 32)},
+                            u32x4{(uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi2,
+                                  (uint32_t)(hi2 >> 32)},
                             rout, off2, 0, STPOL);
-                        if (P & 1)   // only an odd row length leaves a single last word
+                        // only an odd row length leaves a single last word
+                        // (and a two-corner sweep's last computed column)
+                        if ((P & 1) || CHUNK == kTwoCorner)
                             __builtin_amdgcn_raw_buffer_store_b64(
                                 u32x2{(uint32_t)w0, (uint32_t)(w0 >> 32)}, rout, off1, 0, STPOL);
                     } else {
@@ -838,6 +909,9 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch,
                 advance(t, buf, 1);
             }
         }
+        // A two-corner sweep stops before its rows' last windows are
+        // complete: the pixels it computed in them go out now.
+        if constexpr (CHUNK == kTwoCorner) store_tile(ntiles_wave, true);
         // The end state of a chunk: the last E pixels of every row.
         if constexpr (CHUNK == kChunkA) {
             if (valid) {
@@ -861,7 +935,7 @@ constexpr int half_slots() { return kWave / ((Q + 1) / 2) >= 2 ? kWave / ((Q + 1
 template <int Q, int TW, bool POOL, int CHUNK, int NBT, bool ALIGN = false, bool RCLS = false,
           int W = 1>
 __global__ __launch_bounds__(kWave) void decode_kernel(DecodeArgs a) {
-    const int64_t per = CHUNK == kWhole ? 1 : a.chunk.nchunks - 1;
+    const int64_t per = CHUNK == kWhole ? 1 : CHUNK == kTwoCorner ? 2 : a.chunk.nchunks - 1;
     const int64_t nbatches = (a.nblocks * per + a.nb - 1) / a.nb;
     for (int64_t batch = blockIdx.x; batch < nbatches; batch += gridDim.x)
         decode_batch<Q, TW, POOL, CHUNK, NBT, DecodeArgs, kStreamPolicy, false, ALIGN, RCLS, W>(
@@ -1222,6 +1296,10 @@ static hipError_t launch_chunk(int mode, const DecodeArgs &a, int grid, hipStrea
             break;
         case kLaunchChunkCGather:
             hipLaunchKernelGGL((decode_kernel<Q, kDecodeTile, false, kChunkC, NBT>), dim3(grid),
+                               dim3(kWave), lds, s, a);
+            break;
+        case kLaunchTwoCorner:
+            hipLaunchKernelGGL((decode_kernel<Q, kDecodeTile, true, kTwoCorner, NBT>), dim3(grid),
                                dim3(kWave), lds, s, a);
             break;
         default: return hipErrorInvalidValue;

@@ -125,6 +125,7 @@ struct EncodeClassTable {
 constexpr int kWhole = 0;     // sweep whole blocks
 constexpr int kChunkA = 1;    // sweep chunks from zero states, save end states
 constexpr int kChunkC = 2;    // sweep chunks from exact start states
+constexpr int kTwoCorner = 3; // sweep each block from both ends, each sweep half-way
 
 constexpr int kCarryMaxState = 2048;   // most state words (Q * E) the carry pass handles
 
@@ -156,6 +157,7 @@ constexpr int kLaunchChunkA = 2;     // pool, first chunk sweep
 constexpr int kLaunchChunkC = 3;     // pool, final chunk sweep
 constexpr int kLaunchChunkAGather = 4;   // projection slices at slots, first chunk sweep
 constexpr int kLaunchChunkCGather = 5;   // projection slices at slots, final chunk sweep
+constexpr int kLaunchTwoCorner = 8;      // whole blocks from a pool, swept from both ends
 
 struct DecodeArgs {
     // Pool mode (batches): block b's n projections start at word
