@@ -686,6 +686,9 @@ def run_two_corner(args):
     for k, m in synth.MIXED_CODES:
         cases.append((f"64 KB ({k},{m})", -(-65536 // (8 * k)), k, m, 10000, (0, m)))
     cases += [("1 MB (4,2), one block", 32768, 4, 2, 1, 2), ("1 MB (4,2), 256 blocks", 32768, 4, 2, 256, 2)]
+    # the 1 MB classes of one chunk of the mixed workload (about 10,000 per code)
+    for k, m in synth.MIXED_CODES:
+        cases.append((f"1 MB ({k},{m}), 10,000 blocks", -(-(1 << 20) // (8 * k)), k, m, 10000, (0, m)))
     ok = True
     for name, P, Q, m, nb, ner in cases:
         dirs = synth.centered_dirs(Q + m)
@@ -898,7 +901,7 @@ def run_tune(args):
             for nb in (1, 8, 128, 2048):
                 if nb * P * k * 8 <= (256 << 20):
                     held.append(tune.Workload(k, m, P, nb, m))
-    rows, r_best, r_def = [], [], []
+    rows, r_best, r_def, r_rule = [], [], [], []
     n_model = n_all = 0
     for w in held:
         times = tuner.measure_all(w)
@@ -907,6 +910,7 @@ def run_tune(args):
         t_def = times[tune.default_schedule(w)]
         r_best.append(t / times[best_s])
         r_def.append(t_def / t)
+        r_rule.append(times[tune.rule_schedule(w)] / t)
         n_model += 2
         n_all += len(times)
         rows.append([w.k, w.m, w.P, w.nblocks, list(s), round(t, 4), list(best_s),
@@ -922,6 +926,7 @@ def run_tune(args):
                                "{128, 512, 2048, 8192} x blocks {1, 8, 128, 2048}",
                    "parallelism": "single GPU"},
         "model_vs_exhaustive": round(gm(r_best), 4),
+        "rule_over_model": round(gm(r_rule), 4),
         "measurements_model": n_model, "measurements_exhaustive": n_all,
         "training_points": sum(len(v) for v in table.values()),
         "train_s": round(train_s, 2), "final_loss": tuner.model.losses[-1],

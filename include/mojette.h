@@ -408,7 +408,8 @@ typedef struct mojette_tune {
                                          more blocks per wavefront (their own classes); -1: never;
                                          0: the library's choice (split where 90% of sets fit) */
     int32_t encode_tile_cols;         /* encode tile width cap, a multiple of 64 */
-    int32_t reserved;
+    int32_t decode_two_corner_min_P;  /* blocks of at least this row length are decoded from
+                                         both ends (mojette_decode_batch_two_corner); 0: none */
 } mojette_tune;
 
 /* A block of a descriptor-driven call (device memory, 24 bytes). */

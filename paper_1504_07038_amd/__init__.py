@@ -101,7 +101,8 @@ class MojetteTune(ctypes.Structure):
     """``mojette_tune``: the schedule of one code (zero: the library's choice)."""
 
     _fields_ = [("decode_blocks_per_wave", ctypes.c_int32), ("decode_ring_split", ctypes.c_int32),
-                ("encode_tile_cols", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("encode_tile_cols", ctypes.c_int32),
+                ("decode_two_corner_min_P", ctypes.c_int32)]
 
 
 def block_dtype():

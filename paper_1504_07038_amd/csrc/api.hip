@@ -1826,6 +1826,19 @@ int mojette_plan_create(const mojette_geom *geoms, int32_t ngeoms, const mojette
             g.depth_short = common - mj::kDecodeTile - 1;
             g.nb_short = desc_blocks(Q, common + 1, tuned_nb);
         }
+        // rows decoded from both ends: their ring covers the survivor sets
+        // of the negated directions too; two slots per block
+        g.two_min_P = t ? t->decode_two_corner_min_P : 0;
+        if (g.two_min_P < 0) return MOJETTE_EINVAL;
+        if (g.two_min_P > 0) {
+            std::vector<int> neg(n);
+            for (int s = 0; s < n; ++s) neg[s] = -sp[n - 1 - s];
+            const int Rn = ring_length(neg, Q);
+            if (Rn < 0) return MOJETTE_EINVAL;
+            g.R_two = std::max(R, Rn);
+            g.nb_two = desc_blocks(Q, g.R_two + 1, tuned_nb);
+            if (mj::decode_lds_bytes(Q, g.nb_two, g.R_two + 1) > kLdsLimit) return MOJETTE_ENOTSUP;
+        }
         qmask |= 1u << Q;
         qmax = std::max(qmax, Q);
     }
@@ -1920,18 +1933,28 @@ int mojette_decode_batched(const mojette_plan *plan, const mojette_block *blocks
     const hipStream_t s = (hipStream_t)stream;
     clear_stale_error();
     if ((rc = status_of(mj::launch_desc_buckets(c, s))) != MOJETTE_OK) return rc;
-    // at most one batch per block: a grid of that many (capped) loops over them
-    const int grid = (int)std::min<int64_t>(kDecodeGridCap, nblocks);
-    for (int q = 1; q <= kMaxRows; ++q) {
-        if (!((plan->qmask >> q) & 1u)) continue;
-        size_t lds = 0;
-        for (const mj::GeomDev &g : plan->geoms) {
-            if (g.Q != q) continue;
-            lds = std::max(lds, mj::decode_lds_bytes(q, g.nb, g.R + 1));
-            if (g.R_short > 0) lds = std::max(lds, mj::decode_lds_bytes(q, g.nb_short, g.R_short + 1));
+    // at most two batches per block: a grid of that many (capped) loops over them
+    const int grid = (int)std::min<int64_t>(kDecodeGridCap, 2 * nblocks);
+    for (int two = 0; two < 2; ++two) {
+        for (int q = 1; q <= kMaxRows; ++q) {
+            if (!((plan->qmask >> q) & 1u)) continue;
+            size_t lds = 0;
+            for (const mj::GeomDev &g : plan->geoms) {
+                if (g.Q != q) continue;
+                if (two) {
+                    if (g.two_min_P > 0)
+                        lds = std::max(lds, mj::decode_lds_bytes(q, g.nb_two, g.R_two + 1));
+                    continue;
+                }
+                lds = std::max(lds, mj::decode_lds_bytes(q, g.nb, g.R + 1));
+                if (g.R_short > 0)
+                    lds = std::max(lds, mj::decode_lds_bytes(q, g.nb_short, g.R_short + 1));
+            }
+            if (lds == 0) continue;   // no code of this row count decodes from both ends
+            const int grp = q + (two ? mj::kTwoGroup : 0);
+            rc = status_of(mj::launch_decode_desc(q, two != 0, c, grp, lds, grid, s));
+            if (rc != MOJETTE_OK) return rc;
         }
-        if ((rc = status_of(mj::launch_decode_desc(q, c, q, lds, grid, s))) != MOJETTE_OK)
-            return rc;
     }
     return MOJETTE_OK;
 }

@@ -109,9 +109,10 @@ __global__ __launch_bounds__(256) void desc_count_kernel(DescCall c) {
                     st = MOJETTE_EINVAL;
                 } else if (c.decode) {
                     const uint32_t all = (1u << g.n) - 1u;
+                    const bool two = g.two_min_P > 0 && (int)b.P >= g.two_min_P;
                     if (__builtin_popcount(~(uint32_t)b.erasure_mask & all) < g.Q)
                         st = MOJETTE_ENOTRECON;
-                    else if (g.R_short > 0 &&
+                    else if (!two && g.R_short > 0 &&
                              survivor_depth(g, b.erasure_mask) <= g.depth_short)
                         ring = 1;
                 }
@@ -145,10 +146,19 @@ __global__ __launch_bounds__(256) void desc_count_kernel(DescCall c) {
     }
 }
 
+// Whether blocks of row length P of code g decode from both ends.
+__device__ __forceinline__ bool two_corner(const DescCall &c, const GeomDev &g, int P) {
+    return c.decode && g.two_min_P > 0 && P >= g.two_min_P;
+}
+
 __device__ __forceinline__ int64_t class_weight_items(const DescCall &c, const GeomDev &g,
                                                       int ring, int P, int64_t count, int &nb,
                                                       int &W) {
     if (c.decode) {
+        if (two_corner(c, g, P)) {
+            nb = g.nb_two;
+            return (2 * count + nb - 1) / nb;   // two slots per block
+        }
         nb = ring ? g.nb_short : g.nb;
         return (count + nb - 1) / nb;
     }
@@ -189,10 +199,11 @@ __global__ __launch_bounds__(kLayoutThreads) void desc_layout_kernel(DescCall c)
         const int geom = (int)(key >> 32) - 1;
         const uint32_t P = (uint32_t)key & 0x7FFFFFFFu;
         const int Q = c.geoms[geom].Q;
-        const uint64_t group = c.group_by_q ? (uint64_t)Q : 0;
+        const int two = two_corner(c, c.geoms[geom], (int)P) ? kTwoGroup : 0;
+        const uint64_t group = c.group_by_q ? (uint64_t)(Q + two) : 0;
         // ascending: group, then P descending, then Q descending, then slot
-        order[at++] = (group << 59) | ((uint64_t)(0x1FFFFFFu - P) << 34) |
-                      ((uint64_t)(0xFF - Q) << 26) | (uint64_t)s;
+        order[at++] = (group << 58) | ((uint64_t)(0x1FFFFFFu - P) << 33) |
+                      ((uint64_t)(0xFF - Q) << 25) | (uint64_t)s;
     }
     __syncthreads();
     const int nc = nclasses;
@@ -290,7 +301,7 @@ __global__ __launch_bounds__(kLayoutThreads) void desc_layout_kernel(DescCall c)
             d.Q = g.Q;
             d.n = g.n;
             d.nb = nb;
-            d.R = ring ? g.R_short : g.R;
+            d.R = two_corner(c, g, P) ? g.R_two : ring ? g.R_short : g.R;
             d.ring_stride = d.R + 1;
             d.mask_uniform = 0;
             for (int i = 0; i < kMaxDirs; ++i) {
@@ -320,9 +331,9 @@ __global__ __launch_bounds__(kLayoutThreads) void desc_layout_kernel(DescCall c)
         blocks_before += my_blocks[k];
         items_before += my_items[k];
         // launch groups: where the group of consecutive classes changes
-        const int grp = (int)(order[ci] >> 59);
-        if (ci == 0 || (int)(order[ci - 1] >> 59) != grp) hd.range[2 * grp] = first_item[ci];
-        if (ci == nc - 1 || (int)(order[ci + 1] >> 59) != grp)
+        const int grp = (int)(order[ci] >> 58);
+        if (ci == 0 || (int)(order[ci - 1] >> 58) != grp) hd.range[2 * grp] = first_item[ci];
+        if (ci == nc - 1 || (int)(order[ci + 1] >> 58) != grp)
             hd.range[2 * grp + 1] = first_item[ci] + my_items[k];
     }
     if (tid == 0) hd.nclasses = nc;
@@ -345,7 +356,7 @@ __global__ __launch_bounds__(256) void desc_scatter_kernel(DescCall c) {
 // the group, in class order, one wavefront per workgroup.  QMASK has bit Q
 // set for every row count the launch may meet (only those bodies are
 // compiled in); bodies are compiled for half the block slots.
-template <unsigned QMASK>
+template <unsigned QMASK, int CH>
 __global__ __launch_bounds__(kWave) void decode_desc_kernel(const uint8_t *ws, int g) {
     const DescHeader &hd = *reinterpret_cast<const DescHeader *>(ws + DescWorkspace::kHeader);
     const int64_t *first = reinterpret_cast<const int64_t *>(ws + DescWorkspace::kFirstItem);
@@ -364,7 +375,7 @@ __global__ __launch_bounds__(kWave) void decode_desc_kernel(const uint8_t *ws, i
 #define MJ_DEC_CASE(QQ)                                                                    \
     case QQ:                                                                               \
         if constexpr ((QMASK >> QQ) & 1u)                                                 \
-            decode_batch<QQ, kDecodeTile, false, kWhole, half_slots<QQ>(), DecodeDesc, 0>( \
+            decode_batch<QQ, kDecodeTile, false, CH, half_slots<QQ>(), DecodeDesc, 0>(    \
                 a, batch);                                                                 \
         break;
             MJ_DEC_CASE(1) MJ_DEC_CASE(2) MJ_DEC_CASE(3) MJ_DEC_CASE(4)
@@ -392,14 +403,18 @@ hipError_t launch_desc_buckets(const DescCall &c, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_decode_desc(int Q, const DescCall &c, int g, size_t lds, int grid,
+hipError_t launch_decode_desc(int Q, bool two, const DescCall &c, int g, size_t lds, int grid,
                               hipStream_t s) {
     const uint8_t *ws = c.ws;
     switch (Q) {
 #define MJ_LAUNCH(QQ)                                                                          \
     case QQ:                                                                                   \
-        hipLaunchKernelGGL((decode_desc_kernel<1u << QQ>), dim3(grid), dim3(kWave), lds, s, ws, \
-                           g);                                                                 \
+        if (two)                                                                               \
+            hipLaunchKernelGGL((decode_desc_kernel<1u << QQ, kTwoCorner>), dim3(grid),          \
+                               dim3(kWave), lds, s, ws, g);                                    \
+        else                                                                                   \
+            hipLaunchKernelGGL((decode_desc_kernel<1u << QQ, kWhole>), dim3(grid), dim3(kWave), \
+                               lds, s, ws, g);                                                 \
         break;
         MJ_LAUNCH(1) MJ_LAUNCH(2) MJ_LAUNCH(3) MJ_LAUNCH(4) MJ_LAUNCH(5) MJ_LAUNCH(6)
         MJ_LAUNCH(7) MJ_LAUNCH(8) MJ_LAUNCH(9) MJ_LAUNCH(10) MJ_LAUNCH(11) MJ_LAUNCH(12)

@@ -693,8 +693,10 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch,
                 } else {
                     const uint64_t *bins = s.bins;
                     const int c0 = min(max(c, 0), P - 1), c1 = min(max(c - 1, 0), P - 1);
-                    const uint64_t w0 = s.on ? bins[s.gbin - c0] : 0;
-                    const uint64_t w1 = s.on ? bins[s.gbin - c1] : 0;
+                    // a mirrored sweep's bins ascend with its column
+                    const int sg = CHUNK == kTwoCorner && s.mir ? -1 : 1;
+                    const uint64_t w0 = s.on ? bins[s.gbin - sg * c0] : 0;
+                    const uint64_t w1 = s.on ? bins[s.gbin - sg * c1] : 0;
                     buf[it] = u32x4{(uint32_t)w0, (uint32_t)(w0 >> 32), (uint32_t)w1,
                                     (uint32_t)(w1 >> 32)};
                 }
@@ -797,7 +799,14 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch,
                             dst = s.dst;
                         else
                             dst = a.images + first * a.img_stride + s.img;
-                        if (both) {
+                        if (CHUNK == kTwoCorner && s.mir) {
+                            // the mirrored columns c, c+1: P-1-c, P-2-c
+                            if (both) {
+                                store_pair(dst + (P - 2 - c), w1, w0);
+                            } else if (last) {
+                                dst[P - 1 - c] = w0;
+                            }
+                        } else if (both) {
                             store_pair(dst + c, w0, w1);
                         } else if (last) {
                             dst[c] = w0;

@@ -241,6 +241,8 @@ struct GeomDev {
     int32_t R, nb;                   // decode ring and blocks per wavefront, full ring
     int32_t R_short, nb_short;       // short-ring class (0: none)
     int32_t depth_short;             // survivor sets of depth <= this take the short ring
+    int32_t two_min_P;               // rows at least this long decode from both ends (0: never)
+    int32_t R_two, nb_two;           // their ring (both direction orders) and blocks per wave
     int32_t dirs[kMaxDirs];          // in the caller's order
     int16_t p_sorted[kMaxDirs];      // ascending
     int8_t id_sorted[kMaxDirs];
@@ -300,7 +302,7 @@ struct EncodeDesc {
 // layout depends on nblocks only).
 struct DescWorkspace {
     static constexpr size_t kHeader = 0;           // DescHeader
-    static constexpr size_t kKeys = 512;           // kDescSlots uint64 keys (0: empty)
+    static constexpr size_t kKeys = 1024;          // kDescSlots uint64 keys (0: empty)
     static constexpr size_t kCounts = kKeys + 8 * kDescSlots;      // uint32 per slot
     static constexpr size_t kSlotClass = kCounts + 4 * kDescSlots; // int32 per slot
     static constexpr size_t kSegStart = kSlotClass + 4 * kDescSlots;  // int64 per class + 1
@@ -314,10 +316,15 @@ struct DescWorkspace {
     __host__ __device__ static size_t bytes(int64_t nblocks) { return idx_at(nblocks) + (size_t)(4 * nblocks + 255) / 256 * 256; }
 };
 
+// Launch groups: row count Q, plus kTwoGroup for the classes decoded from
+// both ends.
+constexpr int kTwoGroup = kMaxRows + 1;
+constexpr int kDescGroups = 2 * kTwoGroup;
+
 struct DescHeader {   // at most DescWorkspace::kKeys bytes
     int32_t nclasses;
     int32_t error;                   // a status stored by the bucket kernels (table full)
-    int64_t range[2 * (kMaxRows + 1)];   // items of launch group g: [range[2g], range[2g+1])
+    int64_t range[2 * kDescGroups];  // items of launch group g: [range[2g], range[2g+1])
 };
 
 // What the bucket kernels need of a call.
@@ -336,7 +343,7 @@ struct DescCall {
 hipError_t launch_desc_buckets(const DescCall &c, hipStream_t s);
 // One launch of a descriptor-driven decode or encode over launch group g
 // (the classes of row count Q = g).
-hipError_t launch_decode_desc(int Q, const DescCall &c, int g, size_t lds, int grid,
+hipError_t launch_decode_desc(int Q, bool two, const DescCall &c, int g, size_t lds, int grid,
                               hipStream_t s);
 hipError_t launch_encode_desc(int Q, const DescCall &c, int g, int waves, int tile_words,
                               int grid, hipStream_t s);

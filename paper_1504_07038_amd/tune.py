@@ -4,6 +4,8 @@ A decode workload is a code (k, m), a row length P, a batch of nblocks
 blocks and a number of erasures per block.  Its schedules:
   ("whole", nb)      every block swept whole, nb blocks per wavefront
                      (mojette_decode_batch_tuned);
+  ("two_corner", 0)  every block swept from both ends, half the chain
+                     (mojette_decode_batch_two_corner);
   ("chunked", cols)  the sweep of every block cut into chunks of about cols
                      columns (mojette_decode_batch_chunked).
 The best one depends on the workload: few long blocks want chunks, many
@@ -27,7 +29,7 @@ import paper_1504_07038_amd as mj
 
 TILE = 16                          # decode tile width (columns)
 CHUNK_COLS = (128, 256, 512, 1024, 2048)
-N_FEATURES = 8
+N_FEATURES = 9
 
 
 @dataclass(frozen=True)
@@ -57,10 +59,19 @@ def candidates(w: Workload):
         if ("whole", nb) not in out:
             out.append(("whole", nb))
         nb //= 2
+    out.append(("two_corner", 0))
     for cols in CHUNK_COLS:
         if (w.P // TILE) // (cols // TILE) >= 2:
             out.append(("chunked", cols))
     return out
+
+
+def rule_schedule(w: Workload):
+    """A two-line rule for comparison with the learned model: chunks of 256
+    columns for a few long blocks, the library's default otherwise."""
+    if w.nblocks <= 32 and w.P >= 1024:
+        return ("chunked", 256)
+    return default_schedule(w)
 
 
 def default_schedule(w: Workload):
@@ -79,6 +90,11 @@ def features(w: Workload, s) -> np.ndarray:
     if kind == "whole":
         f[5] = math.log2(val) / 5.0
         f[7] = math.log2(max(1, math.ceil(w.nblocks / val))) / 8.0   # wavefronts
+    elif kind == "two_corner":
+        f[8] = 1.0
+        half = max(1, mj.mojette_decode_max_blocks_per_wave(w.dirs, w.P, w.k) // 2)
+        f[5] = math.log2(half) / 5.0
+        f[7] = math.log2(max(1, math.ceil(2 * w.nblocks / half))) / 8.0
     else:
         f[6] = math.log2(val) / 8.0
         chunks = (w.P // TILE) // (val // TILE)
@@ -129,6 +145,10 @@ class Bench:
         if kind == "whole":
             def call():
                 mj.mojette_decode_batch_tuned(proj, d_mask, w.nblocks, w.P, w.k, w.dirs, out, val)
+        elif kind == "two_corner":
+            def call():
+                mj.mojette_decode_batch_two_corner(proj, d_mask, w.nblocks, w.P, w.k, w.dirs, out,
+                                                   blocks_per_wave=val)
         else:
             plan = self.plan(w, val)
             ws = torch.empty(max(1, plan.workspace_words(w.P, w.nblocks)), dtype=torch.int64,
@@ -236,8 +256,8 @@ class Tuner:
 # ---- schedules of a plan over codes (descriptor-driven batched calls) ----
 #
 # A plan gives every code one schedule for all of its blocks, whatever their
-# row length: the decode's blocks per wavefront and ring split, the encode's
-# tile width.  The tuner starts from the library's choices and accepts a
+# row length: the decode's blocks per wavefront, ring split and the row
+# length from which blocks decode from both ends, the encode's tile width.  The tuner starts from the library's choices and accepts a
 # change only when a step of the actual workload (encode + decode of a
 # sample of its blocks, the launches the plan makes) measures faster, so the
 # schedule it returns is never slower than the untuned one on that sample.
@@ -245,6 +265,7 @@ class Tuner:
 # row-length classes, so that only the best-ranked ones are measured.
 
 ENCODE_TILES = (64, 128, 256)
+TWO_CORNER_MIN_P = (8192, 1024)    # rows at least this long decode from both ends
 
 
 def decode_candidates(k: int, m: int):
@@ -303,6 +324,8 @@ class PlanTuner:
             for nb in self.rank_decode(g)[:self.budget]:
                 tune, best_ms = self._try(tune, g, "decode_blocks_per_wave", nb, best_ms)
             tune, best_ms = self._try(tune, g, "decode_ring_split", -1, best_ms)
+            for pmin in TWO_CORNER_MIN_P:
+                tune, best_ms = self._try(tune, g, "decode_two_corner_min_P", pmin, best_ms)
             for w in ENCODE_TILES:
                 if w != 128:
                     tune, best_ms = self._try(tune, g, "encode_tile_cols", w, best_ms)

@@ -367,3 +367,31 @@ def test_mixed_workload_recipe_sample(mj):
         want = oracle.decode_blocks(got_src[None], masks[b:b + 1], P, Q, dirs)[0]
         oi = int(lay.img_off[b])
         assert np.array_equal(dec[oi:oi + imgs[b].size].reshape(Q, P), want), key
+
+
+@pytest.mark.parametrize("min_p", [1, 100, 1000])
+def test_two_corner_classes(mj, min_p):
+    """Codes whose rows of at least min_p columns decode from both ends
+    (mojette_tune.decode_two_corner_min_P): interleaved codes and row lengths,
+    poisoned erasures, against the oracle."""
+    rng = np.random.default_rng(min_p)
+    nb = 700
+    geom = rng.integers(0, len(CODES), nb)
+    Ps = rng.choice([1, 3, 17, 99, 100, 128, 300, 999, 1000, 1366, 2048], nb)
+    masks = np.zeros(nb, dtype=np.uint16)
+    for b in range(nb):
+        Q, dirs = CODES[geom[b]]
+        masks[b] = synth.erasure_masks(20 + b, 1, len(dirs), (0, len(dirs) - Q))[0]
+    tune = [{"decode_two_corner_min_P": min_p} for _ in CODES]
+    lay, imgs, src, dec, st = run_round_trip(mj, CODES, geom, Ps, masks, 700 + min_p, tune=tune)
+    assert st == 0
+    for b in range(nb):
+        o = int(lay.img_off[b])
+        assert np.array_equal(dec[o:o + imgs[b].size], imgs[b].ravel()), (b, int(Ps[b]))
+    for b in rng.choice(nb, 30, replace=False):
+        Q, dirs = CODES[geom[b]]
+        o = int(lay.proj_off[b])
+        words = sum(oracle.proj_size(p, 1, int(Ps[b]), Q) for p in dirs)
+        want = oracle.decode_blocks(src[o:o + words][None], masks[b:b + 1], int(Ps[b]), Q, dirs)
+        oi = int(lay.img_off[b])
+        assert np.array_equal(dec[oi:oi + imgs[b].size].reshape(want[0].shape), want[0])

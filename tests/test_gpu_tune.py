@@ -52,20 +52,24 @@ def test_learned_model_tunes_held_out_workloads(tune):
     tuner.model = model
     say(f"tune: {len(X)} training points, final loss {loss:.4f} (standardised log ms)")
     assert model.losses[-1] < model.losses[0]
-    r_best, r_default, r_model, n_meas = [], [], [], 0
+    r_best, r_default, r_model, r_rule, n_meas = [], [], [], [], 0
     for w in held:
         times = table[w]
         best = min(times.values())
         t_def = times[tune.default_schedule(w)]
+        t_rule = times[tune.rule_schedule(w)]
         s, t_mod = tuner.choose(w, budget=2, times=times)
         n_meas += 2
         r_best.append(t_mod / best)
         r_default.append(t_def / t_mod)
         r_model.append(t_def / best)
+        r_rule.append(t_rule / t_mod)
     gm = lambda a: float(math.exp(np.mean(np.log(a))))
     say(f"tune: held-out {len(held)} workloads; model/exhaustive {gm(r_best):.3f}, "
         f"default/model {gm(r_default):.2f}x, default/exhaustive {gm(r_model):.2f}x, "
+        f"two-line rule/model {gm(r_rule):.2f}x, "
         f"measurements {n_meas} vs {sum(len(table[w]) for w in held)}")
     assert gm(r_best) < 1.15          # within 15% of exhaustive tuning
     assert gm(r_default) > 1.5        # well ahead of the untuned default
+    assert gm(r_rule) > 1.0           # and ahead of a two-line rule on P and nblocks
     assert n_meas < sum(len(table[w]) for w in held)
