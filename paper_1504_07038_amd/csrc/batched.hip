@@ -325,7 +325,7 @@ __global__ __launch_bounds__(kLayoutThreads) void desc_layout_kernel(DescCall c)
             e.bin_swap = 0;
             for (int i = 0; i < kMaxDirs; ++i) {
                 e.off[i] = i < g.n ? off[i] : 0;
-                e.p[i] = (int16_t)(i < g.n ? g.dirs[i] : 0);
+                e.p[i] = i < g.n ? g.dirs[i] : 0;
             }
         }
         blocks_before += my_blocks[k];

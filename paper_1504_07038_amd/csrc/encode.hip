@@ -238,7 +238,10 @@ __global__ __launch_bounds__(kWave *kEncodeWaves) void encode_desc_kernel(const 
                                                                           int tile_words) {
     extern __shared__ uint64_t lds[];
     const int lane = threadIdx.x & (kWave - 1);
-    const int wv = threadIdx.x >> 6;
+    // the wavefront's index, uniform across it: the item, its class and the
+    // class's fields then live in scalar registers (scalar loads), not in
+    // vector loads that share the vector memory counter with the image loads
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const DescHeader &hd = *reinterpret_cast<const DescHeader *>(ws + DescWorkspace::kHeader);
     const int64_t *first = reinterpret_cast<const int64_t *>(ws + DescWorkspace::kFirstItem);
     const EncodeDesc *cls = reinterpret_cast<const EncodeDesc *>(ws + DescWorkspace::kClasses);

@@ -267,8 +267,8 @@ struct DecodeDesc {
     int32_t P, Q, n, nb, R, ring_stride;
     uint32_t mask_uniform;
     int32_t off[kMaxDirs];
-    int16_t p_sorted[kMaxDirs];
-    int8_t id_sorted[kMaxDirs];
+    int32_t p_sorted[kMaxDirs];      // 32-bit: read with scalar loads
+    int32_t id_sorted[kMaxDirs];
     static constexpr bool kDesc = true;
     __device__ const mojette_block &block(int64_t blk) const { return desc[idx[blk]]; }
     __device__ const uint64_t *proj_base(int64_t blk, int id) const {
@@ -288,7 +288,7 @@ struct EncodeDesc {
     int32_t P, Q, n, W, H, S, ntiles;
     int32_t bin_swap;                // always 0
     int32_t off[kMaxDirs];
-    int16_t p[kMaxDirs];
+    int32_t p[kMaxDirs];             // 32-bit: read with scalar loads
     __device__ int dir(int i) const { return p[i]; }
     __device__ const mojette_block &block(int64_t blk) const { return desc[idx[blk]]; }
     __device__ int64_t slice(int64_t blk) const { return (int64_t)block(blk).proj_off; }

@@ -239,7 +239,10 @@ class Server:
             if (g.Q, tuple(g.dirs)) not in codes:
                 codes.append((g.Q, tuple(g.dirs)))
         self.geom_id = [codes.index((g.Q, tuple(g.dirs))) for g in self.geos]
-        self.plan = mj.GeomPlan([(q, list(d)) for q, d in codes])
+        # long rows that are not chunked decode from both ends in the
+        # descriptor call (half the chain of a whole-block sweep, the same work)
+        two = [{"decode_two_corner_min_P": chunk_min_P} for _ in codes] if chunk_min_P else None
+        self.plan = mj.GeomPlan([(q, list(d)) for q, d in codes], two)
         self.max_desc = 2 * sum(caps)
         desc_words = 3 * self.max_desc
         stage_words += desc_words
@@ -270,12 +273,14 @@ class Server:
                      if ws_words[c] else None)
             self.cs.append(st)
         self.side = [torch.cuda.Stream() for _ in range(side_streams)]
-        # Long-row reads are chunked in iterations of at most this many reads
-        # (by default all): a whole-block sweep of a 1 MB object takes ~8 ms
-        # however many share the chip, so every iteration that holds one
-        # would wait for it (measured: with whole-block long rows in
-        # iterations of more than 512 reads the loop saturated at 89 GB/s,
-        # against 188 GB/s at 1M requests/s chunked).
+        # Long-row reads are chunked in iterations of at most this many
+        # reads (by default all): chunks cut a read's latency the most (a
+        # 1 MB read in ~0.2 ms) at twice the sweep work.  Above the limit
+        # long rows decode from both ends in the descriptor call, half the
+        # chain of a one-sided sweep (~8 ms for a 1 MB object however many
+        # share the chip).  Measured, sustained rate of the loop: always
+        # chunked 188 GB/s at 1M requests/s; both ends above 1,024 reads
+        # 93 GB/s at 500k; one-sided above 512 reads 89 GB/s.
         self.chunk_max_reads = chunk_max_reads
         for c, st in enumerate(self.cs):
             mj.mojette_fill_splitmix64(st.payload, st.payload.numel(), seed * 1000 + c,
