@@ -193,7 +193,15 @@ int mojette_decode_batch_wide(const uint64_t *projs, const uint16_t *erased, int
  * mojette_encode_batch_trimmed / mojette_decode_batch_trimmed: as the
  *   batched calls, projections in the trimmed layout (block b's slice at
  *   word b * mojette_trimmed_layout()).
+ *
+ * The layout is tied to the reconstruction path above: another decoder
+ * (another assignment of projections to rows) may need bins it leaves out.
+ * mojette_trimmed_path returns MOJETTE_TRIMMED_PATH, the number of that path
+ * in this library; a store keeps it beside a trimmed pool and reads the pool
+ * back only with a library that returns the same number.
  */
+#define MOJETTE_TRIMMED_PATH 1
+int32_t mojette_trimmed_path(void);
 int64_t mojette_trimmed_layout(const int32_t *dirs, int32_t n, int32_t P, int32_t Q,
                                int64_t *first, int64_t *count);
 int mojette_encode_batch_trimmed(const uint64_t *images, int64_t nblocks, int32_t P, int32_t Q,
@@ -394,10 +402,28 @@ int mojette_decode_jobs(const mojette_job *jobs, int32_t njobs, int32_t *status,
  * distinct (geom_id, P) pairs per call; the blocks of pairs beyond that are
  * not transformed and MOJETTE_ENOTSUP is stored to *status.
  */
+/* Layout options of a code (mojette_geom.flags), one at most:
+ * MOJETTE_GEOM_WIDE     128-bit pixels and bins (Section 3.1), as the _wide
+ *                       batch calls lay them out: a block's P counts 16-byte
+ *                       pixels, its image is Q x 2P words (pixel k of a row
+ *                       at words 2k, 2k+1, low word first), projection i
+ *                       holds mojette_proj_size(dirs[i], P, Q) 16-byte bins
+ *                       (twice as many words); image_off and proj_off still
+ *                       count words.  2P <= 2^24, |p| <= 16383.
+ * MOJETTE_GEOM_TRIMMED  never-used bins left out (Section 2.3), as the
+ *                       _trimmed batch calls lay them out: projection i
+ *                       holds only its kept bins (mojette_trimmed_layout),
+ *                       the projections back to back.  Tied to this
+ *                       library's reconstruction path (MOJETTE_TRIMMED_PATH);
+ *                       not with decode_two_corner_min_P. */
+#define MOJETTE_GEOM_WIDE 1u
+#define MOJETTE_GEOM_TRIMMED 2u
+
 typedef struct mojette_geom {
     int32_t Q;                        /* rows = data packets, 1..16 */
     int32_t n;                        /* projections, Q..16 */
     int32_t dirs[MOJETTE_MAX_DIRS];   /* p of each projection (q = 1), distinct, |p| <= 32767 */
+    uint32_t flags;                   /* 0 or one MOJETTE_GEOM_* layout option */
 } mojette_geom;
 
 /* Schedule of one code (zero fields: the library's choice).  An autotuner
@@ -425,7 +451,8 @@ typedef struct mojette_plan mojette_plan;
 
 /* Creates a plan over ngeoms codes (1..1024).  tune: NULL or ngeoms entries.
  * Checks every code (EINVAL: bad Q, n, duplicate or out-of-range
- * directions; ENOTSUP: beyond the kernels' LDS limits), computes each
+ * directions, unknown or combined flags, a trimmed code asked to decode
+ * from both ends; ENOTSUP: beyond the kernels' LDS limits), computes each
  * code's decode rings on the host and copies the code table to the current
  * device: it allocates device memory and synchronises, so it is not for
  * use under graph capture.  The plan is used on that device only. */
@@ -435,7 +462,7 @@ int mojette_plan_create(const mojette_geom *geoms, int32_t ngeoms, const mojette
 int mojette_plan_destroy(mojette_plan *plan);
 
 /* Workspace bytes a call on up to nblocks blocks needs (non-decreasing in
- * nblocks), or -1 on bad arguments.  About 1 MB plus 12 bytes per block. */
+ * nblocks), or -1 on bad arguments.  About 1.6 MB plus 12 bytes per block. */
 int64_t mojette_workspace_size(const mojette_plan *plan, int64_t nblocks);
 
 /* Forward transform (Section 2.1, Eq. 1) of every described block: reads

@@ -28,6 +28,9 @@ MOJETTE_ENOTSUP = -6
 MOJETTE_ESCRATCH = -7
 MOJETTE_SCRATCH_WORDS = 1 << 23
 MOJETTE_VERIFY = 1
+MOJETTE_TRIMMED_PATH = 1   # reconstruction path the trimmed layout is tied to
+GEOM_WIDE = 1      # mojette_geom.flags: 128-bit pixels and bins
+GEOM_TRIMMED = 2   # mojette_geom.flags: never-used bins left out
 MAX_DIRS = 16
 MAX_ROWS = 16
 
@@ -94,7 +97,8 @@ def make_jobs(jobs):
 class MojetteGeom(ctypes.Structure):
     """``mojette_geom``: one code (Q rows, n directions) of a plan."""
 
-    _fields_ = [("Q", ctypes.c_int32), ("n", ctypes.c_int32), ("dirs", ctypes.c_int32 * MAX_DIRS)]
+    _fields_ = [("Q", ctypes.c_int32), ("n", ctypes.c_int32), ("dirs", ctypes.c_int32 * MAX_DIRS),
+                ("flags", ctypes.c_uint32)]
 
 
 class MojetteTune(ctypes.Structure):
@@ -174,6 +178,7 @@ def lib() -> ctypes.CDLL:
         "mojette_encode_batch_wide": ([vp, i64, i32, i32, vp, i32, vp, vp], ctypes.c_int),
         "mojette_verify_batch": ([vp, vp, i64, i32, i32, vp, i32, vp, vp, vp], ctypes.c_int),
         "mojette_trimmed_layout": ([vp, i32, i32, i32, vp, vp], i64),
+        "mojette_trimmed_path": ([], i32),
         "mojette_encode_batch_sys": ([vp, i64, i32, i32, vp, i32, vp, vp], ctypes.c_int),
         "mojette_sys_workspace": ([vp, i32, i32, i32, i64], i64),
         "mojette_decode_batch_sys": ([vp, vp, vp, i64, i32, i32, vp, i32, vp, vp, vp],
@@ -244,7 +249,8 @@ def exported_symbols() -> list[str]:
         "mojette_bin_offset", "mojette_block_words", "mojette_decode_ring", "mojette_encode",
         "mojette_decode", "mojette_encode_batch", "mojette_decode_batch",
         "mojette_encode_batch_wide", "mojette_decode_batch_wide", "mojette_verify_batch",
-        "mojette_trimmed_layout", "mojette_encode_batch_trimmed", "mojette_decode_batch_trimmed",
+        "mojette_trimmed_layout", "mojette_trimmed_path", "mojette_encode_batch_trimmed",
+        "mojette_decode_batch_trimmed",
         "mojette_encode_batch_sys", "mojette_sys_workspace", "mojette_decode_batch_sys",
         "mojette_decode_batch_tuned", "mojette_decode_batch_two_corner",
         "mojette_decode_max_blocks_per_wave",
@@ -403,6 +409,13 @@ def mojette_decode_batch_wide(projs, erased, nblocks: int, P: int, Q: int, dirs,
     rc = lib().mojette_decode_batch_wide(_word_tensor(projs, "projs"), er, nblocks, P, Q, arr,
                                          n, _word_tensor(images, "images"), st, _stream(stream))
     return _check(rc, "mojette_decode_batch_wide", check)
+
+
+def mojette_trimmed_path() -> int:
+    """Number of the reconstruction path the trimmed layout follows in this
+    library (a pool written by the trimmed calls decodes only with a library
+    that returns the same number)."""
+    return int(lib().mojette_trimmed_path())
 
 
 def mojette_trimmed_layout(dirs, P: int, Q: int):
@@ -660,16 +673,17 @@ def mojette_decode_batch_chunked_noalloc(plan: ChunkPlan, projs, erased, nblocks
 
 class GeomPlan:
     """``mojette_plan``: the codes of the descriptor-driven batched calls and
-    their schedules.  ``geoms``: list of (Q, dirs); ``tune``: None or one dict
-    per code with any of the ``mojette_tune`` fields.  Creating it allocates
-    device memory and synchronises; ``close()`` (or garbage collection)
-    frees it."""
+    their schedules.  ``geoms``: list of (Q, dirs) or (Q, dirs, flags) with
+    flags 0, GEOM_WIDE (128-bit pixels) or GEOM_TRIMMED (never-used bins
+    left out); ``tune``: None or one dict per code with any of the
+    ``mojette_tune`` fields.  Creating it allocates device memory and
+    synchronises; ``close()`` (or garbage collection) frees it."""
 
     def __init__(self, geoms, tune=None):
-        geoms = list(geoms)
+        geoms = [tuple(g) if len(g) == 3 else (g[0], g[1], 0) for g in geoms]
         arr = (MojetteGeom * max(1, len(geoms)))()
-        for g, (Q, dirs) in enumerate(geoms):
-            arr[g].Q, arr[g].n = int(Q), len(dirs)
+        for g, (Q, dirs, flags) in enumerate(geoms):
+            arr[g].Q, arr[g].n, arr[g].flags = int(Q), len(dirs), int(flags)
             for i, p in enumerate(dirs):
                 arr[g].dirs[i] = int(p)
         tarr = None
@@ -682,7 +696,8 @@ class GeomPlan:
         rc = lib().mojette_plan_create(arr, len(geoms), tarr, ctypes.addressof(h))
         _check(rc, "mojette_plan_create", True)
         self.handle = h.value
-        self.geoms = [(int(Q), [int(p) for p in dirs]) for Q, dirs in geoms]
+        self.geoms = [(int(Q), [int(p) for p in dirs]) for Q, dirs, _ in geoms]
+        self.flags = [int(f) for _, _, f in geoms]
 
     def close(self) -> None:
         if self.handle:

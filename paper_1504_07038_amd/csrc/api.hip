@@ -601,6 +601,8 @@ int mojette_encode_batch_wide(const uint64_t *images, int64_t nblocks, int32_t P
     return encode_batch_impl(images, nblocks, 2 * P, Q, dirs2, n, projs, stream, 1);
 }
 
+int32_t mojette_trimmed_path(void) { return MOJETTE_TRIMMED_PATH; }
+
 int64_t mojette_trimmed_layout(const int32_t *dirs, int32_t n, int32_t P, int32_t Q,
                                int64_t *first, int64_t *count) {
     int32_t f[kMaxDirs], c[kMaxDirs];
@@ -1780,28 +1782,47 @@ int mojette_plan_create(const mojette_geom *geoms, int32_t ngeoms, const mojette
         const mojette_geom &gm = geoms[gi];
         const int Q = gm.Q, n = gm.n;
         if (!geometry_ok(gm.dirs, n, 1, Q) || n < Q) return MOJETTE_EINVAL;
+        if (gm.flags != 0 && gm.flags != MOJETTE_GEOM_WIDE && gm.flags != MOJETTE_GEOM_TRIMMED)
+            return MOJETTE_EINVAL;
+        const mojette_tune *t = tune ? &tune[gi] : nullptr;
         mj::GeomDev &g = tab[gi];
         g = mj::GeomDev{};
         g.Q = Q;
         g.n = n;
+        // 128-bit pixels: the word image of 2P columns, directions 2p
+        g.pshift = gm.flags == MOJETTE_GEOM_WIDE ? 1 : 0;
+        const int plim = 32767 >> g.pshift;
+        int dirs[kMaxDirs];
         int maxabs = 0;
         for (int i = 0; i < n; ++i) {
-            if (gm.dirs[i] < -32767 || gm.dirs[i] > 32767) return MOJETTE_EINVAL;
-            g.dirs[i] = gm.dirs[i];
-            g.sumabs += std::abs(gm.dirs[i]);
-            maxabs = std::max(maxabs, std::abs(gm.dirs[i]));
+            if (gm.dirs[i] < -plim || gm.dirs[i] > plim) return MOJETTE_EINVAL;
+            dirs[i] = gm.dirs[i] * (1 << g.pshift);
+            g.dirs[i] = dirs[i];
+            g.sumabs += std::abs(dirs[i]);
+            maxabs = std::max(maxabs, std::abs(dirs[i]));
+        }
+        // the bins each projection keeps (independent of P but for their
+        // number, P + rows * |p|; the reading of kept_layout)
+        for (int i = 0; i < kMaxDirs; ++i) g.keep_rows[i] = -1;
+        if (gm.flags == MOJETTE_GEOM_TRIMMED) {
+            if (t && t->decode_two_corner_min_P > 0) return MOJETTE_EINVAL;
+            int32_t first[kMaxDirs], count[kMaxDirs];
+            const int P1 = 1;
+            if (!kept_layout(gm.dirs, n, P1, Q, first, count)) return MOJETTE_EINVAL;
+            for (int i = 0; i < n; ++i) {
+                g.keep_lo[i] = first[i];
+                g.keep_rows[i] = gm.dirs[i] ? (count[i] - P1) / std::abs(gm.dirs[i]) : 0;
+            }
         }
         std::vector<int> order(n);
         for (int i = 0; i < n; ++i) order[i] = i;
-        std::sort(order.begin(), order.end(),
-                  [&](int x, int y) { return gm.dirs[x] < gm.dirs[y]; });
+        std::sort(order.begin(), order.end(), [&](int x, int y) { return dirs[x] < dirs[y]; });
         std::vector<int> sp(n);
         for (int s = 0; s < n; ++s) {
-            sp[s] = gm.dirs[order[s]];
+            sp[s] = dirs[order[s]];
             g.p_sorted[s] = (int16_t)sp[s];
             g.id_sorted[s] = (int8_t)order[s];
         }
-        const mojette_tune *t = tune ? &tune[gi] : nullptr;
         // encode: tiles of at most enc_w columns beside the halo, within LDS
         g.H = (Q - 1) * maxabs;
         int w = t && t->encode_tile_cols > 0 ? t->encode_tile_cols : kEncodeTileCols;
@@ -1828,8 +1849,10 @@ int mojette_plan_create(const mojette_geom *geoms, int32_t ngeoms, const mojette
         }
         // rows decoded from both ends: their ring covers the survivor sets
         // of the negated directions too; two slots per block
+        // rows counted in words, as the descriptors' rows are classed
         g.two_min_P = t ? t->decode_two_corner_min_P : 0;
-        if (g.two_min_P < 0) return MOJETTE_EINVAL;
+        if (g.two_min_P < 0 || g.two_min_P > (mj::kDescMaxP >> g.pshift)) return MOJETTE_EINVAL;
+        g.two_min_P <<= g.pshift;
         if (g.two_min_P > 0) {
             std::vector<int> neg(n);
             for (int s = 0; s < n; ++s) neg[s] = -sp[n - 1 - s];

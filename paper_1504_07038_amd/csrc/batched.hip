@@ -100,23 +100,26 @@ __global__ __launch_bounds__(256) void desc_count_kernel(DescCall c) {
         uint64_t key = 0;
         if (i < c.nblocks) {
             const mojette_block b = c.desc[i];
-            if (b.geom_id >= c.ngeoms || b.P < 1 || b.P > (uint32_t)kDescMaxP) {
+            if (b.geom_id >= c.ngeoms || b.P < 1 ||
+                b.P > (uint32_t)(kDescMaxP >> c.geoms[b.geom_id].pshift)) {
                 st = MOJETTE_EINVAL;
             } else {
                 const GeomDev &g = c.geoms[b.geom_id];
+                // the row in words: 2P for 128-bit pixels
+                const uint32_t Pw = b.P << g.pshift;
                 int ring = 0;
-                if ((int64_t)b.P * g.Q > ((int64_t)1 << 30)) {
+                if ((int64_t)Pw * g.Q > ((int64_t)1 << 30)) {
                     st = MOJETTE_EINVAL;
                 } else if (c.decode) {
                     const uint32_t all = (1u << g.n) - 1u;
-                    const bool two = g.two_min_P > 0 && (int)b.P >= g.two_min_P;
+                    const bool two = g.two_min_P > 0 && (int)Pw >= g.two_min_P;
                     if (__builtin_popcount(~(uint32_t)b.erasure_mask & all) < g.Q)
                         st = MOJETTE_ENOTRECON;
                     else if (!two && g.R_short > 0 &&
                              survivor_depth(g, b.erasure_mask) <= g.depth_short)
                         ring = 1;
                 }
-                if (st == MOJETTE_OK) key = class_key(b.geom_id, ring, b.P);
+                if (st == MOJETTE_OK) key = class_key(b.geom_id, ring, Pw);
             }
         }
         // one insertion and one count per distinct key of the wavefront
@@ -279,11 +282,13 @@ __global__ __launch_bounds__(kLayoutThreads) void desc_layout_kernel(DescCall c)
         first_item[ci] = items_before;
         int nb = 1, W = 1;
         class_weight_items(c, g, ring, P, counts[s], nb, W);
-        int32_t off[kMaxDirs];
+        // projection i's stored bins: Eq. 2's, or the kept ones
+        int32_t off[kMaxDirs], kept[kMaxDirs];
         int32_t o = 0;
         for (int i = 0; i < g.n; ++i) {
             off[i] = o;
-            o += proj_bins(g.dirs[i], P, g.Q);
+            kept[i] = g.keep_rows[i] < 0 ? 0 : P + g.keep_rows[i] * abs(g.dirs[i]);
+            o += kept[i] ? kept[i] : proj_bins(g.dirs[i], P, g.Q);
         }
         if (c.decode) {
             DecodeDesc &d = reinterpret_cast<DecodeDesc *>(c.ws + DescWorkspace::kClasses)[ci];
@@ -304,10 +309,12 @@ __global__ __launch_bounds__(kLayoutThreads) void desc_layout_kernel(DescCall c)
             d.R = two_corner(c, g, P) ? g.R_two : ring ? g.R_short : g.R;
             d.ring_stride = d.R + 1;
             d.mask_uniform = 0;
+            d.bin_swap = g.pshift;
             for (int i = 0; i < kMaxDirs; ++i) {
                 d.off[i] = i < g.n ? off[i] : 0;
                 d.p_sorted[i] = g.p_sorted[i];
                 d.id_sorted[i] = g.id_sorted[i];
+                d.keep_lo[i] = i < g.n && kept[i] ? g.keep_lo[i] : 0;
             }
         } else {
             EncodeDesc &e = reinterpret_cast<EncodeDesc *>(c.ws + DescWorkspace::kClasses)[ci];
@@ -322,10 +329,12 @@ __global__ __launch_bounds__(kLayoutThreads) void desc_layout_kernel(DescCall c)
             e.H = g.H;
             e.S = W + 2 * g.H;
             e.ntiles = (P + W - 1) / W;
-            e.bin_swap = 0;
+            e.bin_swap = g.pshift;
             for (int i = 0; i < kMaxDirs; ++i) {
                 e.off[i] = i < g.n ? off[i] : 0;
                 e.p[i] = i < g.n ? g.dirs[i] : 0;
+                e.keep_lo[i] = i < g.n && kept[i] ? g.keep_lo[i] : 0;
+                e.keep_n[i] = i < g.n ? kept[i] : 0;
             }
         }
         blocks_before += my_blocks[k];

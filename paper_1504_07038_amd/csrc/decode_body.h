@@ -695,8 +695,11 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch,
                     const int c0 = min(max(c, 0), P - 1), c1 = min(max(c - 1, 0), P - 1);
                     // a mirrored sweep's bins ascend with its column
                     const int sg = CHUNK == kTwoCorner && s.mir ? -1 : 1;
-                    const uint64_t w0 = s.on ? bins[s.gbin - sg * c0] : 0;
-                    const uint64_t w1 = s.on ? bins[s.gbin - sg * c1] : 0;
+                    // descriptor classes of 128-bit pixels: word bin j at word j ^ 1
+                    int swap = 0;
+                    if constexpr (kIsDesc<Args>) swap = a.bin_swap;
+                    const uint64_t w0 = s.on ? bins[(s.gbin - sg * c0) ^ swap] : 0;
+                    const uint64_t w1 = s.on ? bins[(s.gbin - sg * c1) ^ swap] : 0;
                     buf[it] = u32x4{(uint32_t)w0, (uint32_t)(w0 >> 32), (uint32_t)w1,
                                     (uint32_t)(w1 >> 32)};
                 }

@@ -243,6 +243,14 @@ struct GeomDev {
     int32_t depth_short;             // survivor sets of depth <= this take the short ring
     int32_t two_min_P;               // rows at least this long decode from both ends (0: never)
     int32_t R_two, nb_two;           // their ring (both direction orders) and blocks per wave
+    // 128-bit pixels (MOJETTE_GEOM_WIDE) run as the word image of 2P columns
+    // with the directions doubled (dirs, p_sorted below hold 2p), and word
+    // bin j stored at word j ^ 1: pshift = 1, else 0
+    int32_t pshift;
+    // never-used bins left out (MOJETTE_GEOM_TRIMMED): projection i keeps
+    // P + keep_rows[i] * |p_i| bins from index keep_lo[i] on; keep_rows[i]
+    // < 0: all of Eq. 2's bins
+    int32_t keep_lo[kMaxDirs], keep_rows[kMaxDirs];
     int32_t dirs[kMaxDirs];          // in the caller's order
     int16_t p_sorted[kMaxDirs];      // ascending
     int8_t id_sorted[kMaxDirs];
@@ -269,6 +277,8 @@ struct DecodeDesc {
     int32_t off[kMaxDirs];
     int32_t p_sorted[kMaxDirs];      // 32-bit: read with scalar loads
     int32_t id_sorted[kMaxDirs];
+    int32_t bin_swap;                // 1: bin j of a projection is stored at word j ^ 1
+    int32_t keep_lo[kMaxDirs];       // index of projection i's first stored bin
     static constexpr bool kDesc = true;
     __device__ const mojette_block &block(int64_t blk) const { return desc[idx[blk]]; }
     __device__ const uint64_t *proj_base(int64_t blk, int id) const {
@@ -276,7 +286,7 @@ struct DecodeDesc {
     }
     __device__ uint64_t *image_of(int64_t blk) const { return pool + block(blk).image_off; }
     __device__ uint32_t mask_of(int64_t blk) const { return block(blk).erasure_mask; }
-    __device__ int kept_first(int) const { return 0; }
+    __device__ int kept_first(int i) const { return keep_lo[i]; }
 };
 
 // One class of a descriptor-driven encode (fields as EncodeClass).
@@ -286,15 +296,16 @@ struct EncodeDesc {
     uint64_t *pool;
     int64_t nblocks;
     int32_t P, Q, n, W, H, S, ntiles;
-    int32_t bin_swap;                // always 0
+    int32_t bin_swap;                // 1: word bin j stored at word j ^ 1 (128-bit pixels)
     int32_t off[kMaxDirs];
     int32_t p[kMaxDirs];             // 32-bit: read with scalar loads
+    int32_t keep_lo[kMaxDirs], keep_n[kMaxDirs];   // stored bins (keep_n 0: all)
     __device__ int dir(int i) const { return p[i]; }
     __device__ const mojette_block &block(int64_t blk) const { return desc[idx[blk]]; }
     __device__ int64_t slice(int64_t blk) const { return (int64_t)block(blk).proj_off; }
     __device__ uint64_t *proj_in(int i, int64_t slice) const { return pool + slice + off[i]; }
-    __device__ int kept_first(int) const { return 0; }
-    __device__ int kept_count(int, int full) const { return full; }
+    __device__ int kept_first(int i) const { return keep_lo[i]; }
+    __device__ int kept_count(int i, int full) const { return keep_n[i] ? keep_n[i] : full; }
     __device__ const uint64_t *image_of(int64_t blk) const { return pool + block(blk).image_off; }
 };
 

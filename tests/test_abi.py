@@ -178,8 +178,10 @@ def test_geometry_plan_argument_errors(mj):
 
     def create(geoms, tune=None):
         arr = (mj.MojetteGeom * max(1, len(geoms)))()
-        for g, (Q, dirs) in enumerate(geoms):
+        for g, geo in enumerate(geoms):
+            Q, dirs = geo[0], geo[1]
             arr[g].Q, arr[g].n = Q, len(dirs)
+            arr[g].flags = geo[2] if len(geo) > 2 else 0
             for i, p in enumerate(dirs):
                 arr[g].dirs[i] = p
         t = None
@@ -197,9 +199,21 @@ def test_geometry_plan_argument_errors(mj):
     assert create([(2, [0, 40000])]) == mj.MOJETTE_EINVAL              # |p| too large
     assert create([(4, [-3, -2, -1, 0, 1, 2])], [{"encode_tile_cols": 100}]) == mj.MOJETTE_EINVAL
     assert create([(4, [-3, -2, -1, 0, 1, 2])], [{"decode_blocks_per_wave": -2}]) == mj.MOJETTE_EINVAL
+    six = [-3, -2, -1, 0, 1, 2]
+    assert create([(4, six, mj.GEOM_WIDE | mj.GEOM_TRIMMED)]) == mj.MOJETTE_EINVAL   # combined
+    assert create([(4, six, 4)]) == mj.MOJETTE_EINVAL                              # unknown flag
+    assert create([(2, [0, 20000], mj.GEOM_WIDE)]) == mj.MOJETTE_EINVAL             # 2|p| too large
+    assert create([(4, six, mj.GEOM_TRIMMED)],
+                  [{"decode_two_corner_min_P": 512}]) == mj.MOJETTE_EINVAL          # trimmed, both ends
     assert h.value is None
     assert L.mojette_workspace_size(None, 10) == -1
     fake = ctypes.c_void_p(0x1000)
     assert L.mojette_encode_batched(None, fake, 1, fake, fake, None, None) == mj.MOJETTE_EINVAL
     assert L.mojette_decode_batched(None, fake, 1, fake, fake, None, None) == mj.MOJETTE_EINVAL
-    assert ctypes.sizeof(mj.MojetteGeom) == 72 and mj.block_dtype().itemsize == 24
+    assert ctypes.sizeof(mj.MojetteGeom) == 76 and mj.block_dtype().itemsize == 24
+
+
+def test_trimmed_layout_names_its_reconstruction_path(mj):
+    text = open(os.path.join(ROOT, "include", "mojette.h")).read()
+    val = int(re.search(r"#define MOJETTE_TRIMMED_PATH (\d+)", text).group(1))
+    assert mj.mojette_trimmed_path() == val == mj.MOJETTE_TRIMMED_PATH
