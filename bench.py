@@ -53,6 +53,8 @@ def parse():
                     help="serving: comma-separated arrival rates (requests/s)")
     ap.add_argument("--serve-seconds", type=float, default=2.0,
                     help="serving: arrival window per rate")
+    ap.add_argument("--serve-long-reads", default="chunked", choices=["chunked", "both_ends"],
+                    help="serving: how reads of long rows are decoded")
     ap.add_argument("--serve-budget-gib", type=float, default=64.0,
                     help="serving: HBM budget of the store (arenas, payloads, outputs)")
     ap.add_argument("--plain-blocks", type=int, default=1024)
@@ -945,7 +947,8 @@ def run_serving(args):
     geos = serving.geometries()
     t_setup = time.perf_counter()
     srv = serving.Server(budget_bytes=int(args.serve_budget_gib * (1 << 30)), depth=3,
-                         seed=synth.SEED_DATA, geos=geos, prefill=0.5, per_iter_bytes=64 << 20)
+                         seed=synth.SEED_DATA, geos=geos, prefill=0.5, per_iter_bytes=64 << 20,
+                         long_reads=args.serve_long_reads)
     setup_s = time.perf_counter() - t_setup
     # warm-up: a short run at a low rate (first launches of every kernel variant)
     srv.run(serving.make_trace(20000, 0.2, geos, seed=99), max_wall=60)
@@ -959,8 +962,10 @@ def run_serving(args):
         sweep.append(s)
     ok = int(srv.status.item()) == 0
     # the sustained rate: the highest offered rate whose completions kept pace
-    # with arrivals (span within 10% of the arrival window)
-    kept = [s for s in sweep if s["span_s"] <= 1.1 * args.serve_seconds]
+    # with arrivals: span within 10% of the arrival window and p99 latency
+    # under 100 ms (no queue built up during the window)
+    kept = [s for s in sweep
+            if s["span_s"] <= 1.1 * args.serve_seconds and s["p99_us"] <= 100e3]
     best = max(kept, key=lambda s: s["GBps"]) if kept else max(sweep, key=lambda s: s["GBps"])
     rec = {
         "metric": "serving: sustained user GB/s under Poisson arrivals, with p50/p99 latency",
@@ -970,7 +975,8 @@ def run_serving(args):
         "config": {"workload": "serving: Poisson arrivals, 70% degraded reads (0..m erasures) / "
                                "30% writes, sizes 2^U[12,20] B rounded to 8k, codes (4,2)/(8,4), "
                                f"{len(geos)} size x code classes, {args.serve_budget_gib:g} GiB "
-                               "HBM budget, up to 3 iterations in flight",
+                               "HBM budget, up to 3 iterations in flight, long-row reads "
+                               f"{args.serve_long_reads}",
                    "parallelism": "single GPU"},
         "best_point": {k: best[k] for k in ("qps", "p50_us", "p99_us", "GBps")},
         "sweep": sweep, "setup_s": round(setup_s, 2), "status_ok": ok,

@@ -36,18 +36,21 @@ def alone_decode(mj, projs, mask, g):
     return out
 
 
-@pytest.mark.parametrize("budget_mib,prefill,qps,chunk_max",
-                         [(3072, 0.5, 100000, 512), (640, 1.0, 200000, 512),
-                          (3072, 0.5, 100000, 0)])   # the last: long rows never chunked
-def test_serving_mix_matches_alone_and_oracle(mj, orc, budget_mib, prefill, qps, chunk_max):
+@pytest.mark.parametrize("budget_mib,prefill,qps,chunk_max,long_reads",
+                         [(3072, 0.5, 100000, 512, "chunked"), (640, 1.0, 200000, 512, "chunked"),
+                          (3072, 0.5, 100000, 0, "chunked"),     # long rows never chunked
+                          (3072, 0.5, 200000, 512, "both_ends")])
+def test_serving_mix_matches_alone_and_oracle(mj, orc, budget_mib, prefill, qps, chunk_max,
+                                              long_reads):
     from paper_1504_07038_amd import serving
 
     seed = 11
     geos = serving.geometries(per_octave=1)
     say(f"serving: budget {budget_mib} MiB, prefill {prefill}, qps {qps}, {len(geos)} classes, "
-        f"chunked reads up to {chunk_max} per iteration")
+        f"chunked reads up to {chunk_max} per iteration, long reads {long_reads}")
     srv = serving.Server(budget_bytes=budget_mib << 20, depth=3, seed=seed, geos=geos,
-                         prefill=prefill, per_iter_bytes=2 << 20, chunk_max_reads=chunk_max)
+                         prefill=prefill, per_iter_bytes=2 << 20, chunk_max_reads=chunk_max,
+                         long_reads=long_reads)
     assert srv.budget_used <= budget_mib << 20
     tr = serving.make_trace(qps, 0.05, geos, seed=3)
     N = len(tr.arrival)
