@@ -292,9 +292,9 @@ __global__ __launch_bounds__(kLayoutThreads) void desc_layout_kernel(DescCall c)
         }
         if (c.decode) {
             DecodeDesc &d = reinterpret_cast<DecodeDesc *>(c.ws + DescWorkspace::kClasses)[ci];
-            d.desc = c.desc;
-            d.idx = idx + blocks_before;
-            d.pool = c.pool;
+            d.desc = (global_block *)c.desc;
+            d.idx = (global_i32 *)(idx + blocks_before);
+            d.pool = (global_u64 *)c.pool;
             d.status = c.status;
             d.images = nullptr;
             d.masks = nullptr;
@@ -318,9 +318,9 @@ __global__ __launch_bounds__(kLayoutThreads) void desc_layout_kernel(DescCall c)
             }
         } else {
             EncodeDesc &e = reinterpret_cast<EncodeDesc *>(c.ws + DescWorkspace::kClasses)[ci];
-            e.desc = c.desc;
-            e.idx = idx + blocks_before;
-            e.pool = c.pool;
+            e.desc = (global_block *)c.desc;
+            e.idx = (global_i32 *)(idx + blocks_before);
+            e.pool = (global_u64 *)c.pool;
             e.nblocks = my_blocks[k];
             e.P = P;
             e.Q = g.Q;
@@ -366,7 +366,7 @@ __global__ __launch_bounds__(256) void desc_scatter_kernel(DescCall c) {
 // set for every row count the launch may meet (only those bodies are
 // compiled in); bodies are compiled for half the block slots.
 template <unsigned QMASK, int CH>
-__global__ __launch_bounds__(kWave) void decode_desc_kernel(const uint8_t *ws, int g) {
+__global__ __launch_bounds__(kWave) void decode_desc_kernel(const uint8_t *__restrict__ ws, int g) {
     const DescHeader &hd = *reinterpret_cast<const DescHeader *>(ws + DescWorkspace::kHeader);
     const int64_t *first = reinterpret_cast<const int64_t *>(ws + DescWorkspace::kFirstItem);
     const DecodeDesc *cls = reinterpret_cast<const DecodeDesc *>(ws + DescWorkspace::kClasses);

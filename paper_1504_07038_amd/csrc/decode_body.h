@@ -101,6 +101,10 @@ struct __attribute__((aligned(8))) WordPair {
 __device__ __forceinline__ void store_pair(uint64_t *dst, uint64_t lo, uint64_t hi) {
     *reinterpret_cast<WordPair *>(dst) = WordPair{lo, hi};
 }
+typedef uint64_t u64x2_a8 __attribute__((ext_vector_type(2), aligned(8)));
+__device__ __forceinline__ void store_pair(global_u64 *dst, uint64_t lo, uint64_t hi) {
+    *reinterpret_cast<__attribute__((address_space(1))) u64x2_a8 *>(dst) = u64x2_a8{lo, hi};
+}
 
 // A 16-byte pixel or bin (Section 3.1's 128-bit pixels): word 0 is the low
 // half.  XOR acts on each word.
@@ -130,7 +134,9 @@ struct RowState {
 
 // Reconstructs column k0 + i of one row: the bin staged in the row's slot
 // XOR the other rows' pixels on the same line, zero outside the image.
-template <int Q, class T>
+// EDGE: the column may lie outside the image (else the whole tile of every
+// row of the wavefront is inside it and nothing needs zeroing).
+template <int Q, bool EDGE, class T>
 __device__ __forceinline__ void sweep_pixel(const RowState<Q, T> &s,
                                             const int (&o)[RowState<Q, T>::QM], int k0, int i,
                                             int Rmask, int P) {
@@ -148,7 +154,7 @@ __device__ __forceinline__ void sweep_pixel(const RowState<Q, T> &s,
     T v = own;
 #pragma unroll
     for (int m = 0; m < Q - 1; ++m) v ^= dv[m];
-    if ((unsigned)k >= (unsigned)P) v = pix_zero<T>();
+    if (EDGE && (unsigned)k >= (unsigned)P) v = pix_zero<T>();
     s.ring[k & Rmask] = v;
 }
 
@@ -164,8 +170,8 @@ struct SegParam {
     int scol0;     // first column stored by this lane at tile 0 (window lag applied)
     int mis;       // aligned loads: the row window's offset past a 128-byte line
     int img;       // offset (in the wave's image slice) of the segment's row
-    const uint64_t *bins;   // pointer mode: the row's projection
-    uint64_t *dst;          // descriptor classes: the segment's image row
+    const global_u64 *bins; // pointer mode: the row's projection
+    global_u64 *dst;        // descriptor classes: the segment's image row
     int last;      // two-corner sweeps: the last column computed in the row
     bool mir;      // two-corner sweeps: the row belongs to a mirrored sweep
     bool on;       // segment belongs to a block slot in use
@@ -287,6 +293,12 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch,
     const int SS = Q * RS + 1;              // pixels per block slot (odd)
     const int Rmask = a.R - 1;
     const int P = a.P;
+    // descriptor classes of 128-bit pixels: word bin j stored at word j ^ 1.
+    // Read once: the class table is global memory that the loop's stores
+    // might alias, so a field read inside it is a vector load each time
+    // (and its wait would also wait for the bins loaded ahead).
+    int bswap = 0;
+    if constexpr (kIsDesc<Args>) bswap = __builtin_amdgcn_readfirstlane(a.bin_swap);
     T *slot_base = lds + (size_t)(lane_used ? slot : 0) * SS;
     const int r0 = 2 * j, r1 = 2 * j + 1;   // this lane's rows
     const int q = lane % LPS;
@@ -594,12 +606,12 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch,
                     const uint32_t hi0 = __shfl((uint32_t)(pb0 >> 32), src);
                     const uint32_t lo1 = __shfl((uint32_t)pb1, src);
                     const uint32_t hi1 = __shfl((uint32_t)(pb1 >> 32), src);
-                    s.bins = (const uint64_t *)(odd ? (((uint64_t)hi1 << 32) | lo1)
+                    s.bins = (const global_u64 *)(odd ? (((uint64_t)hi1 << 32) | lo1)
                                                     : (((uint64_t)hi0 << 32) | lo0));
                     if constexpr (kIsDesc<Args>) {
                         const uint32_t ilo = __shfl((uint32_t)ib, src);
                         const uint32_t ihi = __shfl((uint32_t)(ib >> 32), src);
-                        s.dst = (uint64_t *)(((uint64_t)ihi << 32) | ilo) + orow * P;
+                        s.dst = (global_u64 *)(((uint64_t)ihi << 32) | ilo) + orow * P;
                     }
                 }
                 s.col0 = dd + TW - 1 - (W == 1 ? 2 * q : q) + oshift;
@@ -691,15 +703,12 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch,
                     }
                     buf[it] = u32x4{w0.x, w0.y, w1.x, w1.y};
                 } else {
-                    const uint64_t *bins = s.bins;
+                    const global_u64 *bins = s.bins;
                     const int c0 = min(max(c, 0), P - 1), c1 = min(max(c - 1, 0), P - 1);
                     // a mirrored sweep's bins ascend with its column
                     const int sg = CHUNK == kTwoCorner && s.mir ? -1 : 1;
-                    // descriptor classes of 128-bit pixels: word bin j at word j ^ 1
-                    int swap = 0;
-                    if constexpr (kIsDesc<Args>) swap = a.bin_swap;
-                    const uint64_t w0 = s.on ? bins[(s.gbin - sg * c0) ^ swap] : 0;
-                    const uint64_t w1 = s.on ? bins[(s.gbin - sg * c1) ^ swap] : 0;
+                    const uint64_t w0 = s.on ? bins[(s.gbin - sg * c0) ^ bswap] : 0;
+                    const uint64_t w1 = s.on ? bins[(s.gbin - sg * c1) ^ bswap] : 0;
                     buf[it] = u32x4{(uint32_t)w0, (uint32_t)(w0 >> 32), (uint32_t)w1,
                                     (uint32_t)(w1 >> 32)};
                 }
@@ -797,11 +806,11 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch,
                             __builtin_amdgcn_raw_buffer_store_b64(
                                 u32x2{(uint32_t)w0, (uint32_t)(w0 >> 32)}, rout, off1, 0, STPOL);
                     } else {
-                        uint64_t *dst;
+                        global_u64 *dst;
                         if constexpr (kIsDesc<Args>)
                             dst = s.dst;
                         else
-                            dst = a.images + first * a.img_stride + s.img;
+                            dst = (global_u64 *)(a.images + first * a.img_stride + s.img);
                         if (CHUNK == kTwoCorner && s.mir) {
                             // the mirrored columns c, c+1: P-1-c, P-2-c
                             if (both) {
@@ -880,12 +889,26 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch,
                 ox[m] = kx + X.delta[m];
                 oy[m] = ky + Y.delta[m];
             }
+            // a tile inside the image for every row of the wavefront (most
+            // tiles of a long row) zeroes nothing
+            const bool in_x = !X.on || (kx >= 0 && kx + TW <= P);
+            const bool in_y = !Y.on || (ky >= 0 && ky + TW <= P);
+            if (__all(in_x && in_y)) {
 #pragma unroll
-            for (int i = 0; i < TW; ++i) {
-                sweep_pixel<Q>(X, ox, kx, i, Rmask, P);
-                wave_sync();
-                sweep_pixel<Q>(Y, oy, ky, i, Rmask, P);
-                wave_sync();
+                for (int i = 0; i < TW; ++i) {
+                    sweep_pixel<Q, false>(X, ox, kx, i, Rmask, P);
+                    wave_sync();
+                    sweep_pixel<Q, false>(Y, oy, ky, i, Rmask, P);
+                    wave_sync();
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < TW; ++i) {
+                    sweep_pixel<Q, true>(X, ox, kx, i, Rmask, P);
+                    wave_sync();
+                    sweep_pixel<Q, true>(Y, oy, ky, i, Rmask, P);
+                    wave_sync();
+                }
             }
             store_tile(t);
             wave_sync();

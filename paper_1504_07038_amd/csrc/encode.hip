@@ -233,7 +233,7 @@ __global__ __launch_bounds__(kWave) void encode_classes_kernel(EncodeClassTable 
 // dependent loads otherwise (class, block index, descriptor, image), which
 // left the encode of 1 MB blocks at a third of the single-geometry rate.
 template <int Q, int PF>
-__global__ __launch_bounds__(kWave *kEncodeWaves) void encode_desc_kernel(const uint8_t *ws,
+__global__ __launch_bounds__(kWave *kEncodeWaves) void encode_desc_kernel(const uint8_t *__restrict__ ws,
                                                                           int g, int waves,
                                                                           int tile_words) {
     extern __shared__ uint64_t lds[];

@@ -25,6 +25,14 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Device memory addressed through a pointer read from a table in memory:
+// held in the global address space, so that the accesses through it are
+// global instructions rather than flat ones (flat ones also count against
+// the LDS wait counter, so every wait for an LDS read would wait for them).
+typedef __attribute__((address_space(1))) uint64_t global_u64;
+typedef __attribute__((address_space(1))) const mojette_block global_block;
+typedef __attribute__((address_space(1))) const int32_t global_i32;
+
 // Smallest line position b = -k + l*p over a P x Q image (q = 1).
 __host__ __device__ inline int32_t bin_offset(int32_t p, int32_t P, int32_t Q) {
     int32_t m = (Q - 1) * p;
@@ -263,9 +271,9 @@ constexpr int kDescMaxP = 1 << 24;
 // that the same per-batch body serves it (pointer mode: a block's bins and
 // image are found through its descriptor).
 struct DecodeDesc {
-    const mojette_block *desc;
-    const int32_t *idx;              // the class's blocks: descriptor indices
-    uint64_t *pool;
+    global_block *desc;
+    global_i32 *idx;                 // the class's blocks: descriptor indices
+    global_u64 *pool;
     int32_t *status;
     uint64_t *images;                // unused (images are found per block)
     const uint16_t *masks;           // unused (masks come with the descriptors)
@@ -280,20 +288,24 @@ struct DecodeDesc {
     int32_t bin_swap;                // 1: bin j of a projection is stored at word j ^ 1
     int32_t keep_lo[kMaxDirs];       // index of projection i's first stored bin
     static constexpr bool kDesc = true;
-    __device__ const mojette_block &block(int64_t blk) const { return desc[idx[blk]]; }
-    __device__ const uint64_t *proj_base(int64_t blk, int id) const {
-        return pool + block(blk).proj_off + off[id];
+    __device__ const mojette_block &block(int64_t blk) const {
+        return *(const mojette_block *)(desc + idx[blk]);
     }
-    __device__ uint64_t *image_of(int64_t blk) const { return pool + block(blk).image_off; }
+    __device__ const uint64_t *proj_base(int64_t blk, int id) const {
+        return (const uint64_t *)(pool + block(blk).proj_off + off[id]);
+    }
+    __device__ uint64_t *image_of(int64_t blk) const {
+        return (uint64_t *)(pool + block(blk).image_off);
+    }
     __device__ uint32_t mask_of(int64_t blk) const { return block(blk).erasure_mask; }
     __device__ int kept_first(int i) const { return keep_lo[i]; }
 };
 
 // One class of a descriptor-driven encode (fields as EncodeClass).
 struct EncodeDesc {
-    const mojette_block *desc;
-    const int32_t *idx;
-    uint64_t *pool;
+    global_block *desc;
+    global_i32 *idx;
+    global_u64 *pool;
     int64_t nblocks;
     int32_t P, Q, n, W, H, S, ntiles;
     int32_t bin_swap;                // 1: word bin j stored at word j ^ 1 (128-bit pixels)
@@ -301,12 +313,18 @@ struct EncodeDesc {
     int32_t p[kMaxDirs];             // 32-bit: read with scalar loads
     int32_t keep_lo[kMaxDirs], keep_n[kMaxDirs];   // stored bins (keep_n 0: all)
     __device__ int dir(int i) const { return p[i]; }
-    __device__ const mojette_block &block(int64_t blk) const { return desc[idx[blk]]; }
+    __device__ const mojette_block &block(int64_t blk) const {
+        return *(const mojette_block *)(desc + idx[blk]);
+    }
     __device__ int64_t slice(int64_t blk) const { return (int64_t)block(blk).proj_off; }
-    __device__ uint64_t *proj_in(int i, int64_t slice) const { return pool + slice + off[i]; }
+    __device__ uint64_t *proj_in(int i, int64_t slice) const {
+        return (uint64_t *)(pool + slice + off[i]);
+    }
     __device__ int kept_first(int i) const { return keep_lo[i]; }
     __device__ int kept_count(int i, int full) const { return keep_n[i] ? keep_n[i] : full; }
-    __device__ const uint64_t *image_of(int64_t blk) const { return pool + block(blk).image_off; }
+    __device__ const uint64_t *image_of(int64_t blk) const {
+        return (const uint64_t *)(pool + block(blk).image_off);
+    }
 };
 
 // Workspace of a descriptor-driven call (byte offsets from its start; the
