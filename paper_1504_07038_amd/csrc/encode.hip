@@ -26,7 +26,7 @@ namespace mj {
 // launch).
 template <int Q, class A, bool VERIFY = false>
 __device__ __forceinline__ void encode_bins(const A &a, int64_t blk, int t, const uint64_t *tile,
-                                            int lane, uint32_t use);
+                                            int lane, uint32_t use, int64_t slice_in = -1);
 
 // VERIFY (A = VerifyArgs): the bins of every surviving projection are
 // compared with the stored ones instead of being written.
@@ -60,16 +60,18 @@ __device__ __forceinline__ void encode_item(const A &a, int64_t blk, int t, uint
 
 // The bins of work item (blk, t) from the wave's staged LDS tile; ends with
 // the wave done reading the tile.
+// `slice`: the block's projection slice when the caller has it (else -1).
 template <int Q, class A, bool VERIFY>
 __device__ __forceinline__ void encode_bins(const A &a, int64_t blk, int t, const uint64_t *tile,
-                                            int lane, uint32_t use) {
+                                            int lane, uint32_t use, int64_t slice_in) {
     const int P = a.P, W = a.W, H = a.H, S = a.S;
     const int x0 = t * W;
     // The bins whose row-0 crossing -b falls in [x0, x0 + W); the first tile
     // also takes the edge bins with -b < 0, the last those with -b >= P.
     const bool first = (t == 0), last = (t == a.ntiles - 1);
     const int base = H - x0;
-    const int64_t slice = a.slice(blk);   // read once: the stores below cannot alias it
+    // read once: the stores below cannot alias it
+    const int64_t slice = slice_in >= 0 ? slice_in : a.slice(blk);
     for (int i = 0; i < a.n; ++i) {
         const int p = a.dir(i);
         // the stored bins: all of Eq. 2's, or the kept ones (Section 2.3)
@@ -270,11 +272,24 @@ __global__ __launch_bounds__(kWave *kEncodeWaves) void encode_desc_kernel(const 
         }
     } else {
         uint64_t reg[Q][PF];
-        // the words of item `it` (class k) this lane stages
-        auto fetch = [&](const EncodeDesc &a, int64_t local) {
+        // The block of the item being fetched (class, index), its image and
+        // projection slice: consecutive items are mostly tiles of one block,
+        // whose descriptor is then not read again (two dependent loads
+        // before the image loads could issue).
+        int f_c = -1;
+        int64_t f_blk = -1, f_slice = 0;
+        const uint64_t *f_img = nullptr;
+        auto fetch = [&](int cc, const EncodeDesc &a, int64_t local) {
             const int64_t blk = local / a.ntiles;
             const int t = (int)(local - blk * a.ntiles);
-            const uint64_t *img = a.image_of(blk);
+            if (cc != f_c || blk != f_blk) {
+                const mojette_block &b = a.block(blk);
+                f_c = cc;
+                f_blk = blk;
+                f_img = (const uint64_t *)(a.pool + b.image_off);
+                f_slice = (int64_t)b.proj_off;
+            }
+            const uint64_t *img = f_img;
             const int x0 = t * a.W;
 #pragma unroll
             for (int l = 0; l < Q; ++l)
@@ -286,9 +301,10 @@ __global__ __launch_bounds__(kWave *kEncodeWaves) void encode_desc_kernel(const 
                                     ? img[(int64_t)l * a.P + col] : 0;
                 }
         };
-        fetch(cls[c], item - first[c]);
+        fetch(c, cls[c], item - first[c]);
         while (item < end) {
             const EncodeDesc &a = cls[c];
+            const int64_t slice = f_slice;   // the item's block, fetched with its words
 #pragma unroll
             for (int l = 0; l < Q; ++l)
 #pragma unroll
@@ -305,8 +321,8 @@ __global__ __launch_bounds__(kWave *kEncodeWaves) void encode_desc_kernel(const 
             int c2 = c;
             int64_t next2 = next;
             while (nit >= next2 && nit < end) next2 = first[++c2 + 1];
-            if (nit < end) fetch(cls[c2], nit - first[c2]);
-            encode_bins<Q, EncodeDesc, false>(a, blk, t, tile, lane, 0);
+            if (nit < end) fetch(c2, cls[c2], nit - first[c2]);
+            encode_bins<Q, EncodeDesc, false>(a, blk, t, tile, lane, 0, slice);
             item = nit;
             c = c2;
             next = next2;
