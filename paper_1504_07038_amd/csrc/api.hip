@@ -331,7 +331,7 @@ int decode_setup(const int32_t *dirs, int32_t n, int32_t P, int32_t Q, A &a) {
     const int R = ring_length(sp, Q);
     if (R < 0) return MOJETTE_EINVAL;
     a.R = R;
-    a.ring_stride = R + 1;  // odd stride spreads the rows over the LDS banks
+    a.ring_stride = mj::ring_stride_of(Q, R);
     a.nb = default_blocks(Q, a.ring_stride);
     if (mj::decode_lds_bytes(Q, a.nb, a.ring_stride) > kLdsLimit) return MOJETTE_ENOTSUP;
     a.P = P;
@@ -346,7 +346,7 @@ int decode_setup(const int32_t *dirs, int32_t n, int32_t P, int32_t Q, A &a) {
 // per wavefront against 4.00 ms at 32 with the unaligned full-slot body).
 int pool_default_blocks(int Q, int ring_stride) {
     const int nb = default_blocks(Q, ring_stride);
-    if (Q != 4 || ring_stride != 2 * mj::kDecodeTile + 1) return nb;
+    if (Q != 4 || ring_stride != mj::ring_stride_of(Q, 2 * mj::kDecodeTile)) return nb;
     return std::min(nb, std::max(1, mj::decode_max_blocks_per_wave(Q) / 2));
 }
 
@@ -434,7 +434,7 @@ int plan_pool_whole(mj::DecodeArgs a, int Q, int nb_req, std::vector<mj::DecodeA
     a.ring_depth = common - mj::kDecodeTile - 1;
     mj::DecodeArgs m1 = a;
     m1.R = common;
-    m1.ring_stride = common + 1;
+    m1.ring_stride = mj::ring_stride_of(Q, common);
     m1.ring_mode = 1;
     pick_nb(m1);
     const int rc = add(m1);
@@ -899,7 +899,7 @@ int mojette_decode_batch_sys(uint64_t *images, const uint64_t *parity, const uin
     }
     if (rl.first < 0) return MOJETTE_EINVAL;
     a.R = rl.first;
-    a.ring_stride = rl.first + 1;
+    a.ring_stride = mj::ring_stride_of(Q, rl.first);
     a.sys_lead = rl.second;
     // the kernels are compiled for half the slots
     a.nb = std::min(default_blocks(Q, a.ring_stride),
@@ -1122,7 +1122,7 @@ int64_t mojette_decode_chunked_workspace(const mojette_chunk_plan *plan, int32_t
 static int chunked_launch(const mojette_chunk_plan *plan, int nchunks, mj::DecodeArgs &a, int Q,
                           bool gather, uint64_t *workspace, hipStream_t s) {
     a.R = std::max(a.R, plan->R);
-    a.ring_stride = a.R + 1;
+    a.ring_stride = mj::ring_stride_of(Q, a.R);
     // chunks are plentiful: half-full waves keep the sweep's registers and
     // LDS share small
     a.nb = std::max(1, mj::decode_max_blocks_per_wave(Q) / 2);
@@ -1224,7 +1224,7 @@ int mojette_decode_batch_two_corner(const uint64_t *projs, const uint16_t *erase
     const int Rn = ring_length(neg, Q);
     if (Rn < 0) return MOJETTE_EINVAL;
     a.R = std::max(a.R, Rn);
-    a.ring_stride = a.R + 1;
+    a.ring_stride = mj::ring_stride_of(Q, a.R);
     // two slots per block: the half-slot body, within the LDS share
     const int half = std::max(1, mj::decode_max_blocks_per_wave(Q) / 2);
     a.nb = blocks_per_wave > 0 ? std::min(blocks_per_wave, half) : default_blocks(Q, a.ring_stride);
@@ -1289,7 +1289,7 @@ static int main_ring_stride(const mj::DecodeArgs &a, int Q) {
     const int nb2 = pool_default_blocks(Q, a.ring_stride);
     const bool split =
         common > 0 && common < a.R && 1.0 - std::pow(1.0 - deep, nb2) <= 0.25;
-    return split ? common + 1 : a.ring_stride;
+    return split ? mj::ring_stride_of(Q, common) : a.ring_stride;
 }
 
 int32_t mojette_decode_max_blocks_per_wave(const int32_t *dirs, int32_t n, int32_t P,
@@ -1557,7 +1557,7 @@ static int decode_jobs_chunked_merged(const mojette_job *jobs, const std::vector
         if (rc != MOJETTE_OK) return rc;
         const mojette_chunk_plan *pl = j.plan;
         d.R = std::max(d.R, pl->R);
-        d.ring_stride = d.R + 1;
+        d.ring_stride = mj::ring_stride_of(j.Q, d.R);
         d.nb = std::max(1, mj::decode_max_blocks_per_wave(j.Q) / 2);
         while (d.nb > 0 && mj::decode_lds_bytes(j.Q, d.nb, d.ring_stride) > kLdsLimit) --d.nb;
         if (d.nb < 1) return MOJETTE_ENOTSUP;
@@ -1839,13 +1839,13 @@ int mojette_plan_create(const mojette_geom *geoms, int32_t ngeoms, const mojette
         const int tuned_nb = t ? t->decode_blocks_per_wave : 0;
         if (tuned_nb < 0) return MOJETTE_EINVAL;
         g.R = R;
-        g.nb = desc_blocks(Q, R + 1, tuned_nb);
-        if (mj::decode_lds_bytes(Q, g.nb, R + 1) > kLdsLimit) return MOJETTE_ENOTSUP;
+        g.nb = desc_blocks(Q, mj::ring_stride_of(Q, R), tuned_nb);
+        if (mj::decode_lds_bytes(Q, g.nb, mj::ring_stride_of(Q, R)) > kLdsLimit) return MOJETTE_ENOTSUP;
         const int split = t ? t->decode_ring_split : 0;
         if (split >= 0 && common > 0 && common < R) {
             g.R_short = common;
             g.depth_short = common - mj::kDecodeTile - 1;
-            g.nb_short = desc_blocks(Q, common + 1, tuned_nb);
+            g.nb_short = desc_blocks(Q, mj::ring_stride_of(Q, common), tuned_nb);
         }
         // rows decoded from both ends: their ring covers the survivor sets
         // of the negated directions too; two slots per block
@@ -1859,8 +1859,9 @@ int mojette_plan_create(const mojette_geom *geoms, int32_t ngeoms, const mojette
             const int Rn = ring_length(neg, Q);
             if (Rn < 0) return MOJETTE_EINVAL;
             g.R_two = std::max(R, Rn);
-            g.nb_two = desc_blocks(Q, g.R_two + 1, tuned_nb);
-            if (mj::decode_lds_bytes(Q, g.nb_two, g.R_two + 1) > kLdsLimit) return MOJETTE_ENOTSUP;
+            g.nb_two = desc_blocks(Q, mj::ring_stride_of(Q, g.R_two), tuned_nb);
+            if (mj::decode_lds_bytes(Q, g.nb_two, mj::ring_stride_of(Q, g.R_two)) > kLdsLimit)
+                return MOJETTE_ENOTSUP;
         }
         qmask |= 1u << Q;
         qmax = std::max(qmax, Q);
@@ -1966,12 +1967,12 @@ int mojette_decode_batched(const mojette_plan *plan, const mojette_block *blocks
                 if (g.Q != q) continue;
                 if (two) {
                     if (g.two_min_P > 0)
-                        lds = std::max(lds, mj::decode_lds_bytes(q, g.nb_two, g.R_two + 1));
+                        lds = std::max(lds, mj::decode_lds_bytes(q, g.nb_two, mj::ring_stride_of(q, g.R_two)));
                     continue;
                 }
-                lds = std::max(lds, mj::decode_lds_bytes(q, g.nb, g.R + 1));
+                lds = std::max(lds, mj::decode_lds_bytes(q, g.nb, mj::ring_stride_of(q, g.R)));
                 if (g.R_short > 0)
-                    lds = std::max(lds, mj::decode_lds_bytes(q, g.nb_short, g.R_short + 1));
+                    lds = std::max(lds, mj::decode_lds_bytes(q, g.nb_short, mj::ring_stride_of(q, g.R_short)));
             }
             if (lds == 0) continue;   // no code of this row count decodes from both ends
             const int grp = q + (two ? mj::kTwoGroup : 0);

@@ -307,7 +307,7 @@ __global__ __launch_bounds__(kLayoutThreads) void desc_layout_kernel(DescCall c)
             d.n = g.n;
             d.nb = nb;
             d.R = two_corner(c, g, P) ? g.R_two : ring ? g.R_short : g.R;
-            d.ring_stride = d.R + 1;
+            d.ring_stride = ring_stride_of(g.Q, d.R);
             d.mask_uniform = 0;
             d.bin_swap = g.pshift;
             for (int i = 0; i < kMaxDirs; ++i) {

@@ -29,9 +29,12 @@
 // picks R >= max(2 TW, TW + D + 1) over every survivor set, so a staged bin
 // never lands on a pixel that is still needed or not yet stored.  Columns
 // outside the image are written as zero and rings start zeroed, so
-// dependency reads are never bounds checked.  Block slots in LDS are an odd
-// number of words apart, so equal ring positions of different blocks fall on
-// different LDS banks.
+// dependency reads are never bounds checked.  Equal columns of different
+// rows and blocks fall on different LDS banks: for codes of 5 to 8 rows the
+// rings are aligned to their length (a slot's address is then the ring's
+// address OR'ed with the masked column offset) and the ring of row l in
+// block slot s is rotated by s*(Q+1) + l slots; for the others rings are
+// R + 1 words apart and block slots an odd number of words apart.
 //
 // Memory traffic.  A tile is TW columns per row.  After sweeping tile t the
 // wave (1) stores, for every row, the TW-aligned window of TW pixels that has
@@ -121,41 +124,61 @@ using PixT = typename std::conditional<W == 1, uint64_t, Pix128>::type;
 template <class T>
 __device__ __forceinline__ T pix_zero() { return T{}; }
 
-// Sweep state of one row of one lane (pixels of type T).
+// Sweep state of one row of one lane (pixels of type T).  Rings are aligned
+// to their length (R pixels), so the LDS byte address of a column's slot is
+// the ring's offset OR'ed with the masked byte offset of the column: one add
+// and one and-or per access.
 template <int Q, class T = uint64_t>
 struct RowState {
     static constexpr int QM = Q > 1 ? Q - 1 : 1;
-    T *ring;                 // this row's ring
-    T *dep[QM];              // rings of the other rows
-    int delta[QM];           // column offset (l - r) * p_r of each other row
+    uint32_t ring;           // LDS address of this row's ring
+    uint32_t dep[QM];        // LDS addresses of the other rows' rings
+    int rot;                 // this ring's rotation (slot of column c: c + rot mod R)
+    int delta[QM];           // column offset (l - r) * p_r of each other row, plus its ring's rotation
     int d;                   // first column of tile 0
     bool on;                 // a real row of a decodable block
 };
 
 // Reconstructs column k0 + i of one row: the bin staged in the row's slot
 // XOR the other rows' pixels on the same line, zero outside the image.
+// own / o[m]: byte offsets (before masking) of the row's and the other rows'
+// slots for i = 0; M = (R - 1) * sizeof(T).
 // EDGE: the column may lie outside the image (else the whole tile of every
 // row of the wavefront is inside it and nothing needs zeroing).
+template <class T>
+using LdsPtr = __attribute__((address_space(3))) T *;
+
+// The LDS address of a ring slot: the ring's address plus the masked byte
+// offset of the column; with aligned rings (a ring's address a multiple of
+// its byte length) the add is an OR, folded with the mask into one and-or.
+template <class T, bool ALN>
+__device__ __forceinline__ T *ring_slot(uint32_t ring, uint32_t off, uint32_t M) {
+    return (T *)(LdsPtr<T>)(uintptr_t)(ALN ? ring | (off & M) : ring + (off & M));
+}
+
 template <int Q, bool EDGE, class T>
-__device__ __forceinline__ void sweep_pixel(const RowState<Q, T> &s,
-                                            const int (&o)[RowState<Q, T>::QM], int k0, int i,
-                                            int Rmask, int P) {
+__device__ __forceinline__ void sweep_pixel(const RowState<Q, T> &s, uint32_t own,
+                                            const uint32_t (&o)[RowState<Q, T>::QM], int k0,
+                                            int i, uint32_t M, int P) {
     if (!s.on) return;
+    constexpr uint32_t E = sizeof(T);
+    constexpr bool ALN = ring_aligned(Q);
     const int k = k0 + i;
     T dv[RowState<Q, T>::QM];
-    const T own = s.ring[k & Rmask];
+    T *const slot = ring_slot<T, ALN>(s.ring, own + i * E, M);
+    const T own_v = *slot;
 #pragma unroll
-    for (int m = 0; m < Q - 1; ++m) dv[m] = s.dep[m][(o[m] + i) & Rmask];
+    for (int m = 0; m < Q - 1; ++m) dv[m] = *ring_slot<T, ALN>(s.dep[m], o[m] + i * E, M);
     // Tall codes: every read is issued before the first XOR waits for one
     // (the scheduler splits eight reads into two round trips to LDS
     // otherwise).  Measured: 8 KB (12,8) decode 902 -> 964 GB/s, 1 MB
     // (12,4) 25.0 -> 21.7 ms; 4-row codes 2-5% slower with it, so not there.
     if constexpr (Q > 4) __builtin_amdgcn_sched_barrier(0);
-    T v = own;
+    T v = own_v;
 #pragma unroll
     for (int m = 0; m < Q - 1; ++m) v ^= dv[m];
     if (EDGE && (unsigned)k >= (unsigned)P) v = pix_zero<T>();
-    s.ring[k & Rmask] = v;
+    *slot = v;
 }
 
 // Row window owned by one lane in store/load iteration `it`: segment
@@ -163,6 +186,7 @@ __device__ __forceinline__ void sweep_pixel(const RowState<Q, T> &s,
 // and q + TW/2), q = lane % LPS.  Offsets count pixels (words when W = 1).
 struct SegParam {
     int ring;      // LDS index of the segment's ring row (valid slots only)
+    int rot;       // its ring's rotation (column c at slot c + rot mod R)
     int gbin;      // pool: offset (in the wave's pool slice) of column 0's bin;
                    // systematic code, known line: of its column 0 in the image slice
                    // pointer mode: bin index of column 0 (jbase)
@@ -289,9 +313,21 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch,
     const bool mir = CHUNK == kTwoCorner && (item - blk * per) == 1;
     const int64_t blk_lo = gathered ? gather_lo : batch * NB / per;
     const int rel = (int)(blk - blk_lo);
+    // Rings (ring_stride_of): aligned to their length R for ring_aligned(Q),
+    // else R + 1 words apart in block slots of an odd number of words.
+    constexpr bool ALN = ring_aligned(Q);
     const int RS = a.ring_stride;
-    const int SS = Q * RS + 1;              // pixels per block slot (odd)
+    const int SS = Q * RS + (ALN ? 0 : 1);  // pixels per block slot
     const int Rmask = a.R - 1;
+    // Aligned rings: column c of row l of block slot sl at slot
+    // (c + rot(sl, l)) mod R.  The rotation spreads equal columns of
+    // different rows and slots over the LDS banks as the odd strides do.
+    auto rot_of = [&](int sl, int l) { return ALN ? (sl * (Q + 1) + l) & Rmask : 0; };
+    if (RS != ring_stride_of(Q, a.R)) {
+        // anything but the host's layout would break the slot addresses
+        if (lane == 0 && a.status) a.status[0] = MOJETTE_EINVAL;
+        return;
+    }
     const int P = a.P;
     // descriptor classes of 128-bit pixels: word bin j stored at word j ^ 1.
     // Read once: the class table is global memory that the loop's stores
@@ -300,6 +336,14 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch,
     int bswap = 0;
     if constexpr (kIsDesc<Args>) bswap = __builtin_amdgcn_readfirstlane(a.bin_swap);
     T *slot_base = lds + (size_t)(lane_used ? slot : 0) * SS;
+    const uint32_t RM = (uint32_t)Rmask * sizeof(T);   // byte mask of a ring
+    // LDS address of the dynamic array (0 in these kernels, which declare no
+    // other LDS): rings are aligned to their byte length within it
+    const uint32_t lds_at = (uint32_t)(uintptr_t)(LdsPtr<T>)lds;
+    if (ALN && (lds_at & (RM | (sizeof(T) - 1))) != 0) {
+        if (lane == 0 && a.status) a.status[0] = MOJETTE_EINVAL;
+        return;
+    }
     const int r0 = 2 * j, r1 = 2 * j + 1;   // this lane's rows
     const int q = lane % LPS;
     const int QP = Q * P;
@@ -475,15 +519,19 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch,
             const int Ax = r0_is_x ? A0 : A1, Ay = r0_is_x ? A1 : A0;
             X.on = valid && (r0_is_x ? sw0 : sw1);
             Y.on = valid && (r0_is_x ? sw1 : sw0);
-            X.ring = slot_base + (rx < Q ? rx : 0) * RS;
-            Y.ring = slot_base + (ry < Q ? ry : 0) * RS;
+            const uint32_t sb = lds_at + (uint32_t)((slot_base - lds) * sizeof(T));   // slot's address
+            const int ss = lane_used ? slot : 0;
+            X.ring = sb + (uint32_t)((rx < Q ? rx : 0) * RS * sizeof(T));
+            Y.ring = sb + (uint32_t)((ry < Q ? ry : 0) * RS * sizeof(T));
+            X.rot = rot_of(ss, rx < Q ? rx : 0);
+            Y.rot = rot_of(ss, ry < Q ? ry : 0);
 #pragma unroll
             for (int m = 0; m < Q - 1; ++m) {
                 const int lx = m + (m >= rx ? 1 : 0), ly = m + (m >= ry ? 1 : 0);
-                X.dep[m] = slot_base + (lx < Q ? lx : 0) * RS;
-                Y.dep[m] = slot_base + (ly < Q ? ly : 0) * RS;
-                X.delta[m] = (lx - rx) * px;
-                Y.delta[m] = (ly - ry) * py;
+                X.dep[m] = sb + (uint32_t)((lx < Q ? lx : 0) * RS * sizeof(T));
+                Y.dep[m] = sb + (uint32_t)((ly < Q ? ly : 0) * RS * sizeof(T));
+                X.delta[m] = (lx - rx) * px + rot_of(ss, lx < Q ? lx : 0);
+                Y.delta[m] = (ly - ry) * py + rot_of(ss, ly < Q ? ly : 0);
             }
             X.d = X.on ? -((A_max - Ax) >> 1) : 0;       // (Ax - A_max)/2, exact
             Y.d = Y.on ? -((A_max - Ay - 1) >> 1) : 0;   // (Ay - A_max + 1)/2, exact
@@ -597,6 +645,7 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch,
                     s.last = ntiles_wave * TW + dd - 1;
                 }
                 s.ring = (sslot < NB ? sslot : 0) * SS + srow * RS;
+                s.rot = rot_of(sslot < NB ? sslot : 0, srow);
                 s.gbin = odd ? og1 : og0;
                 s.bins = nullptr;
                 s.dst = nullptr;
@@ -732,15 +781,16 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch,
                     // previous tile's, from `prev`, goes in instead)
                     const bool held = AL && q < s.mis;
                     const u32x4 v0 = held ? prev[AL ? it : 0] : buf[it * W];
-                    row[(c - (held ? TW : 0)) & Rmask] = Pix128{lo64(v0), hi64(v0)};
-                    row[(c - LPS) & Rmask] = Pix128{lo64(buf[it * W + 1]), hi64(buf[it * W + 1])};
+                    row[(c - (held ? TW : 0) + s.rot) & Rmask] = Pix128{lo64(v0), hi64(v0)};
+                    row[(c - LPS + s.rot) & Rmask] =
+                        Pix128{lo64(buf[it * W + 1]), hi64(buf[it * W + 1])};
                 } else if constexpr (AL) {
                     const int c = t * TW + s.col0 + s.mis;   // column of this line's word 2q
                     const bool h0 = 2 * q < s.mis, h1 = 2 * q + 1 < s.mis;
-                    row[(c - (h0 ? TW : 0)) & Rmask] = h0 ? lo64(prev[it]) : lo64(buf[it]);
-                    row[(c - 1 - (h1 ? TW : 0)) & Rmask] = h1 ? hi64(prev[it]) : hi64(buf[it]);
+                    row[(c - (h0 ? TW : 0) + s.rot) & Rmask] = h0 ? lo64(prev[it]) : lo64(buf[it]);
+                    row[(c - 1 - (h1 ? TW : 0) + s.rot) & Rmask] = h1 ? hi64(prev[it]) : hi64(buf[it]);
                 } else {
-                    const int c = t * TW + s.col0;
+                    const int c = t * TW + s.col0 + s.rot;
                     row[c & Rmask] = lo64(buf[it]);
                     row[(c - 1) & Rmask] = hi64(buf[it]);
                 }
@@ -759,7 +809,7 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch,
 #pragma unroll
                     for (int h = 0; h < 2; ++h) {
                         const int ch = c + h * LPS;
-                        const Pix128 v = row[ch & Rmask];
+                        const Pix128 v = row[(ch + s.rot) & Rmask];
                         const bool in = s.on && (unsigned)ch < (unsigned)P;
                         const uint32_t off = in ? (uint32_t)(s.img + ch) * 16u : kOffNone;
                         __builtin_amdgcn_raw_buffer_store_b128(
@@ -768,7 +818,7 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch,
                             rout, off, 0, STPOL);
                     }
                 } else {
-                    const uint64_t w0 = row[c & Rmask], w1 = row[(c + 1) & Rmask];
+                    const uint64_t w0 = row[(c + s.rot) & Rmask], w1 = row[(c + 1 + s.rot) & Rmask];
                     bool in_chunk = true;
                     if constexpr (CHUNK == kChunkA || CHUNK == kChunkC)
                         in_chunk = ((t < a.chunk.tiles ? store_in : store_past) >> it) & 1u;
@@ -842,8 +892,10 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch,
                 const uint64_t *st =
                     a.chunk.ws + (blk * per + (chunk - 1)) * (int64_t)(Q * a.chunk.max_cols);
                 for (int e = 0; e < E; ++e) {
-                    if (r0 < Q) slot_base[r0 * RS + ((shift + dr0 - E + e) & Rmask)] = st[r0 * E + e];
-                    if (r1 < Q) slot_base[r1 * RS + ((shift + dr1 - E + e) & Rmask)] = st[r1 * E + e];
+                    if (r0 < Q)
+                        slot_base[r0 * RS + ((shift + dr0 - E + e + rot_of(slot, r0)) & Rmask)] = st[r0 * E + e];
+                    if (r1 < Q)
+                        slot_base[r1 * RS + ((shift + dr1 - E + e + rot_of(slot, r1)) & Rmask)] = st[r1 * E + e];
                 }
             }
         }
@@ -883,11 +935,16 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch,
         // Sweeps tile t and stores the rows' completed windows.
         auto sweep_tile = [&](int t) {
             const int kx = t * TW + X.d, ky = t * TW + Y.d;
-            int ox[QM], oy[QM];
+            // byte offsets (before masking) of this tile's first column in
+            // each ring: the multiple of the pixel size keeps the offset
+            // modulo the ring's bytes right for negative columns too
+            constexpr uint32_t PB = sizeof(T);
+            const uint32_t ownx = (uint32_t)(kx + X.rot) * PB, owny = (uint32_t)(ky + Y.rot) * PB;
+            uint32_t ox[QM], oy[QM];
 #pragma unroll
             for (int m = 0; m < Q - 1; ++m) {
-                ox[m] = kx + X.delta[m];
-                oy[m] = ky + Y.delta[m];
+                ox[m] = (uint32_t)(kx + X.delta[m]) * PB;
+                oy[m] = (uint32_t)(ky + Y.delta[m]) * PB;
             }
             // a tile inside the image for every row of the wavefront (most
             // tiles of a long row) zeroes nothing
@@ -896,17 +953,17 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch,
             if (__all(in_x && in_y)) {
 #pragma unroll
                 for (int i = 0; i < TW; ++i) {
-                    sweep_pixel<Q, false>(X, ox, kx, i, Rmask, P);
+                    sweep_pixel<Q, false>(X, ownx, ox, kx, i, RM, P);
                     wave_sync();
-                    sweep_pixel<Q, false>(Y, oy, ky, i, Rmask, P);
+                    sweep_pixel<Q, false>(Y, owny, oy, ky, i, RM, P);
                     wave_sync();
                 }
             } else {
 #pragma unroll
                 for (int i = 0; i < TW; ++i) {
-                    sweep_pixel<Q, true>(X, ox, kx, i, Rmask, P);
+                    sweep_pixel<Q, true>(X, ownx, ox, kx, i, RM, P);
                     wave_sync();
-                    sweep_pixel<Q, true>(Y, oy, ky, i, Rmask, P);
+                    sweep_pixel<Q, true>(Y, owny, oy, ky, i, RM, P);
                     wave_sync();
                 }
             }
@@ -953,8 +1010,10 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch,
                 uint64_t *st = a.chunk.ws + (blk * per + chunk) * (int64_t)(Q * a.chunk.max_cols);
                 const int end = shift + a.chunk.tiles * TW;
                 for (int e = 0; e < E; ++e) {
-                    if (r0 < Q) st[r0 * E + e] = slot_base[r0 * RS + ((end + dr0 - E + e) & Rmask)];
-                    if (r1 < Q) st[r1 * E + e] = slot_base[r1 * RS + ((end + dr1 - E + e) & Rmask)];
+                    if (r0 < Q)
+                        st[r0 * E + e] = slot_base[r0 * RS + ((end + dr0 - E + e + rot_of(slot, r0)) & Rmask)];
+                    if (r1 < Q)
+                        st[r1 * E + e] = slot_base[r1 * RS + ((end + dr1 - E + e + rot_of(slot, r1)) & Rmask)];
                 }
             }
         }

@@ -14,6 +14,17 @@ constexpr int kMaxDirs = MOJETTE_MAX_DIRS;
 constexpr int kMaxRows = MOJETTE_MAX_ROWS;
 constexpr int kWave = 64;          // CDNA wavefront width
 constexpr int kDecodeTile = 16;    // columns per row per decode tile
+// Decode rings (decode_body.h) of codes of 5 to 8 rows are aligned to their
+// length R (a power of two): a slot's LDS address is then one add and one
+// and-or from the tile's offset, and rotations spread the rows over the
+// banks.  Other row counts keep rings R + 1 words apart (odd strides spread
+// them): with 4 rows the one more register per row window costs the
+// whole-line body its second wavefront per SIMD, and the descriptor body of
+// 12 rows likewise (measured 4 KB (6,4) decode 1.7x, 1 MB (12,4) descriptor
+// decode 1.5x slower aligned; 8 KB (12,8) unchanged, 1 MB (8,4) 10% faster).
+__host__ __device__ constexpr bool ring_aligned(int Q) { return Q >= 5 && Q <= 8; }
+// LDS words between the rings of two rows of a block slot.
+__host__ __device__ constexpr int ring_stride_of(int Q, int R) { return ring_aligned(Q) ? R : R + 1; }
 constexpr int kEncodeWaves = 4;    // most waves per encode workgroup
 
 // Orders LDS traffic between the lanes of one wavefront.  The LDS
