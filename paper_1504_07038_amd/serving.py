@@ -145,22 +145,30 @@ class SlotStore:
 
     def take_write_slots(self, want: int) -> np.ndarray:
         """Up to `want` slots: free ones first, then the oldest resident
-        objects in ring order up to the first one an in-flight read holds."""
+        objects in ring order that no in-flight read holds; a held object
+        met on the way goes to the young end of the ring (a second chance)
+        instead of stopping the eviction there."""
         take = min(want, self.nfree)
         got = self.free[self.nfree - take:self.nfree][::-1].copy()
         self.nfree -= take
         want -= take
         if want > 0 and self.count > 0:
-            c = min(want, self.count)
-            idx = (self.head + np.arange(c)) % self.slots
+            idx = (self.head + np.arange(self.count)) % self.slots
             cand = self.ring[idx]
-            busy = np.flatnonzero(self.refs[cand] != 0)
-            ev = c if len(busy) == 0 else int(busy[0])
-            if ev:
-                self.head = (self.head + ev) % self.slots
-                self.count -= ev
-                self.source[cand[:ev]] = -1
-                got = np.concatenate([got, cand[:ev]])
+            idle = np.flatnonzero(self.refs[cand] == 0)
+            k = min(want, len(idle))
+            if k:
+                scanned = int(idle[k - 1]) + 1          # objects looked at, oldest first
+                held = cand[:scanned][self.refs[cand[:scanned]] != 0]
+                ev = cand[idle[:k]]
+                self.head = (self.head + scanned) % self.slots
+                self.count -= scanned
+                self.source[ev] = -1
+                if len(held):
+                    back = (self.head + self.count + np.arange(len(held))) % self.slots
+                    self.ring[back] = held
+                    self.count += len(held)
+                got = np.concatenate([got, ev])
         return got
 
     def pick_resident(self, k: int, rng) -> np.ndarray:

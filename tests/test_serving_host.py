@@ -74,13 +74,47 @@ def test_slot_store_free_then_oldest_idle(sv):
     assert sorted(b[:2]) == [4, 5] and b[2] == a[0]
     assert st.count == 3 and st.source[a[0]] == -1
     st.push_resident(b, np.arange(10, 13))
-    # an in-flight read of the oldest object blocks eviction past it
-    oldest = st.resident()[0]
-    st.refs[oldest] = 1
-    assert len(st.take_write_slots(2)) == 0
-    st.refs[oldest] = 0
+    # an in-flight read of the oldest object: it is skipped and moves to
+    # the young end; the next oldest idle objects are evicted
+    res0 = list(st.resident())
+    st.refs[res0[0]] = 1
     c = st.take_write_slots(2)
-    assert list(c) == list(st.ring[[(st.head - 2) % 6, (st.head - 1) % 6]])
-    assert st.count + st.nfree + 2 + 3 == 6 + 3   # 2 in flight, ring holds the rest
+    assert list(c) == res0[1:3]
+    assert list(st.resident()) == res0[3:] + [res0[0]]
+    assert st.count == len(res0) - 2
+    st.refs[res0[0]] = 0
     res = st.resident()
     assert len(set(res)) == len(res) and not set(res) & set(c)
+    # every resident object held: nothing to evict
+    st.refs[st.resident()] = 1
+    assert len(st.take_write_slots(1)) == 0 and list(st.resident()) == list(res)
+    st.refs[:] = 0
+
+
+def test_slot_store_random_operations_keep_slots_unique(sv):
+    """Random writes, reads and releases: every slot is free, resident or in a
+    write that has not completed, never two of these; held objects are never
+    evicted."""
+    st = sv.SlotStore(40)
+    rng = np.random.default_rng(5)
+    pending_writes, held = [], []
+    for _ in range(3000):
+        op = rng.integers(0, 4)
+        if op == 0:
+            got = st.take_write_slots(int(rng.integers(1, 8)))
+            assert not set(got.tolist()) & set(np.concatenate(held).tolist() if held else [])
+            pending_writes.append(got)
+        elif op == 1 and pending_writes:
+            w = pending_writes.pop(0)
+            st.push_resident(w, np.arange(len(w)))
+        elif op == 2 and st.count:
+            held.append(st.pick_resident(int(rng.integers(1, 6)), rng))
+        elif op == 3 and held:
+            st.release(held.pop(0))
+        res = st.resident().tolist()
+        free = st.free[:st.nfree].tolist()
+        inw = np.concatenate(pending_writes).tolist() if pending_writes else []
+        assert len(set(res)) == len(res)
+        assert not set(res) & set(free) and not set(res) & set(inw) and not set(free) & set(inw)
+        assert len(res) + len(free) + len(inw) == st.slots
+        assert (st.refs >= 0).all()
