@@ -177,6 +177,23 @@ int mojette_decode_batch_wide(const uint64_t *projs, const uint16_t *erased, int
                               uint64_t *images, int32_t *status, void *stream);
 
 /*
+ * ONE block of 128-bit pixels (Section 3.1): mojette_encode and
+ * mojette_decode for a P x Q image of 16-byte pixels.
+ *   image, image_out  device, Q*P pixels of two words (pixel (k,l) at words
+ *                     2*(l*P+k) and 2*(l*P+k)+1).
+ *   proj_out[i], proj[t]  device, 2*mojette_proj_size(p, P, Q) words: the
+ *                     bins of that direction, two words each, bin j's words
+ *                     in the order of a pixel's.
+ * Other arguments, flags (MOJETTE_VERIFY) and return codes as for the 64-bit
+ * one-block calls; P may be up to 2^23 and |p| up to 2^15.
+ */
+int mojette_encode_wide(const uint64_t *image, int32_t P, int32_t Q, const int32_t *dirs,
+                        int32_t n, uint64_t *const *proj_out, void *stream);
+int mojette_decode_wide(const uint64_t *const *proj, const int32_t *proj_ids, int32_t m,
+                        const int32_t *dirs, int32_t n, int32_t P, int32_t Q,
+                        uint64_t *image_out, uint32_t flags, void *stream);
+
+/*
  * Never-used bins left out (Section 2.3 notes that some bins are used by no
  * reconstruction, whatever the projections at hand).  For this library's
  * reconstruction path (of the survivors the Q with the smallest p are used,

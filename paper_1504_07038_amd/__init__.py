@@ -173,6 +173,9 @@ def lib() -> ctypes.CDLL:
         "mojette_decode_ring": ([vp, i32, i32, i32], i32),
         "mojette_encode": ([vp, i32, i32, vp, i32, vp, vp], ctypes.c_int),
         "mojette_decode": ([vp, vp, i32, vp, i32, i32, i32, vp, ctypes.c_uint32, vp], ctypes.c_int),
+        "mojette_encode_wide": ([vp, i32, i32, vp, i32, vp, vp], ctypes.c_int),
+        "mojette_decode_wide": ([vp, vp, i32, vp, i32, i32, i32, vp, ctypes.c_uint32, vp],
+                                ctypes.c_int),
         "mojette_encode_batch": ([vp, i64, i32, i32, vp, i32, vp, vp], ctypes.c_int),
         "mojette_decode_batch": ([vp, vp, i64, i32, i32, vp, i32, vp, vp, vp], ctypes.c_int),
         "mojette_encode_batch_wide": ([vp, i64, i32, i32, vp, i32, vp, vp], ctypes.c_int),
@@ -248,7 +251,8 @@ def exported_symbols() -> list[str]:
         "mojette_strerror", "mojette_last_hip_error", "mojette_proj_size",
         "mojette_bin_offset", "mojette_block_words", "mojette_decode_ring", "mojette_encode",
         "mojette_decode", "mojette_encode_batch", "mojette_decode_batch",
-        "mojette_encode_batch_wide", "mojette_decode_batch_wide", "mojette_verify_batch",
+        "mojette_encode_batch_wide", "mojette_decode_batch_wide", "mojette_encode_wide",
+        "mojette_decode_wide", "mojette_verify_batch",
         "mojette_trimmed_layout", "mojette_trimmed_path", "mojette_encode_batch_trimmed",
         "mojette_decode_batch_trimmed",
         "mojette_encode_batch_sys", "mojette_sys_workspace", "mojette_decode_batch_sys",
@@ -346,12 +350,36 @@ def mojette_decode(proj, proj_ids, dirs, P: int, Q: int, image_out, stream=None,
     """One block from m >= Q projections; verify=True sets MOJETTE_VERIFY (the
     call then checks every given projection against the decoded image and
     waits for the verdict)."""
+    return _decode_one("mojette_decode", proj, proj_ids, dirs, P, Q, image_out, stream,
+                       check, verify)
+
+
+def mojette_encode_wide(image, P: int, Q: int, dirs, proj_out, stream=None,
+                        check: bool = True) -> int:
+    """mojette_encode for 16-byte pixels: image of Q*P pixels of two words,
+    proj_out[i] of 2*B_i words."""
+    arr, n = _i32_array(dirs)
+    ptrs = (ctypes.c_void_p * max(1, len(proj_out)))(
+        *[_word_tensor(t, "proj_out") for t in proj_out])
+    rc = lib().mojette_encode_wide(_word_tensor(image, "image"), P, Q, arr, n, ptrs,
+                                   _stream(stream))
+    return _check(rc, "mojette_encode_wide", check)
+
+
+def mojette_decode_wide(proj, proj_ids, dirs, P: int, Q: int, image_out, stream=None,
+                        check: bool = True, verify: bool = False) -> int:
+    """mojette_decode for 16-byte pixels (layouts as mojette_encode_wide)."""
+    return _decode_one("mojette_decode_wide", proj, proj_ids, dirs, P, Q, image_out, stream,
+                       check, verify)
+
+
+def _decode_one(name, proj, proj_ids, dirs, P, Q, image_out, stream, check, verify):
     arr, n = _i32_array(dirs)
     ids, m = _i32_array(proj_ids)
     ptrs = (ctypes.c_void_p * max(1, len(proj)))(*[_word_tensor(t, "proj") for t in proj])
-    rc = lib().mojette_decode(ptrs, ids, m, arr, n, P, Q, _word_tensor(image_out, "image_out"),
+    rc = getattr(lib(), name)(ptrs, ids, m, arr, n, P, Q, _word_tensor(image_out, "image_out"),
                               MOJETTE_VERIFY if verify else 0, _stream(stream))
-    return _check(rc, "mojette_decode", check)
+    return _check(rc, name, check)
 
 
 def mojette_encode_batch(images, nblocks: int, P: int, Q: int, dirs, projs, stream=None,

@@ -91,7 +91,7 @@ __device__ __forceinline__ void encode_bins(const A &a, int64_t blk, int t, cons
 #pragma unroll
             for (int l = 0; l < Q; ++l) v ^= tile[l * rstride + base - b];
             if constexpr (VERIFY) {
-                if (v != src[b - bmin]) *a.status = MOJETTE_EINCONSISTENT;
+                if (v != src[(b - bmin) ^ a.bin_swap]) *a.status = MOJETTE_EINCONSISTENT;
                 continue;
             }
             dst[(b - bmin) ^ a.bin_swap] = v;

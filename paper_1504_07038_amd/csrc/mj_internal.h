@@ -209,6 +209,7 @@ struct DecodeArgs {
     int32_t align;                   // whole-block pool sweeps: whole-line loads where compiled
     int32_t gather_range;            // ring_mode 2: blocks scanned per wavefront for members of
                                      // the class (a multiple of 64), 0: every block in batches
+    int32_t bin_swap;                // pointer mode: 1 reads word bin j at word j ^ 1 (128-bit pixels)
     __device__ const uint64_t *proj_base(int64_t blk, int id) const {
         return pool ? pool + slots[blk] * proj_stride + off[id] : in[id];
     }

@@ -110,3 +110,65 @@ def test_wide_argument_checks(mj):
                                         check=False) == mj.MOJETTE_EINVAL
     assert mj.mojette_encode_batch_wide(d, -1, 8, 2, [0, 1], d,
                                         check=False) == mj.MOJETTE_EINVAL
+
+
+@pytest.mark.parametrize("P,Q,n,m", [
+    (64, 4, 6, 4),      # 4 KB block of the (6,4) code in the paper's pixels
+    (37, 3, 5, 5),      # odd row length, every projection given (Q of them used)
+    (1, 1, 2, 1),
+    (700, 2, 4, 3),     # rows over several tiles, a ragged last one
+])
+def test_wide_one_block(mj, P, Q, n, m):
+    """mojette_encode_wide / mojette_decode_wide: one block, projections at
+    separate pointers, against the oracle's wide transform; the decode reads
+    m of them (erased ones overwritten) and restores the image."""
+    dirs = synth.centered_dirs(n)
+    say(f"wide one block P={P} Q={Q} n={n} m={m}")
+    img = wide_images(500 + P + n, 1, P, Q)
+    want = oracle.encode_blocks_wide(img, P, Q, dirs)[0]
+    sizes = [oracle.proj_size(p, 1, P, Q) for p in dirs]
+    off = np.cumsum([0] + sizes)
+    outs = [torch.full((2 * s,), -1, dtype=torch.int64, device="cuda") for s in sizes]
+    assert mj.mojette_encode_wide(to_dev(img), P, Q, dirs, outs) == 0
+    torch.cuda.synchronize()
+    for i in range(n):
+        assert np.array_equal(to_np(outs[i]).reshape(-1, 2), want[off[i]:off[i + 1]]), i
+    ids = sorted(np.random.default_rng(P + m).choice(n, m, replace=False).tolist())
+    for i in set(range(n)) - set(ids):
+        outs[i].fill_(int(POISON.astype(np.int64)))
+    d_out = torch.full((Q * P * 2,), -1, dtype=torch.int64, device="cuda")
+    assert mj.mojette_decode_wide([outs[i] for i in ids], ids, dirs, P, Q, d_out,
+                                  verify=True) == 0
+    torch.cuda.synchronize()
+    assert np.array_equal(to_np(d_out).reshape(Q, P, 2), img[0])
+
+
+def test_wide_one_block_verify_finds_a_flipped_word(mj):
+    """One flipped word of one 16-byte bin (either half): with every
+    projection given the verified decode reports MOJETTE_EINCONSISTENT."""
+    P, Q, n = 64, 4, 6
+    dirs = synth.centered_dirs(n)
+    img = wide_images(31, 1, P, Q)
+    want = oracle.encode_blocks_wide(img, P, Q, dirs)[0]
+    off = np.cumsum([0] + [oracle.proj_size(p, 1, P, Q) for p in dirs])
+    rng = np.random.default_rng(8)
+    for trial in range(4):
+        i = int(rng.integers(0, n))
+        bins = want[off[i]:off[i + 1]].copy()
+        bins[int(rng.integers(0, len(bins))), trial % 2] ^= np.uint64(1 << int(rng.integers(64)))
+        proj = [to_dev(want[off[t]:off[t + 1]]) for t in range(n)]
+        proj[i] = to_dev(bins)
+        d_out = torch.empty(Q * P * 2, dtype=torch.int64, device="cuda")
+        rc = mj.mojette_decode_wide(proj, list(range(n)), dirs, P, Q, d_out, verify=True,
+                                    check=False)
+        assert rc == mj.MOJETTE_EINCONSISTENT, (trial, i)
+
+
+def test_wide_one_block_argument_checks(mj):
+    d = torch.zeros(16, dtype=torch.int64, device="cuda")
+    assert mj.mojette_encode_wide(d, (1 << 23) + 1, 1, [0, 1], [d, d],
+                                  check=False) == mj.MOJETTE_EINVAL
+    assert mj.mojette_decode_wide([d, d], [0, 1], [0, 1 << 15 | 1], 8, 2, d,
+                                  check=False) == mj.MOJETTE_EINVAL
+    assert mj.mojette_decode_wide([d], [0], [0, 1], 8, 2, d,
+                                  check=False) == mj.MOJETTE_ENOTRECON
