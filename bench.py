@@ -49,14 +49,19 @@ def parse():
                     help="mixed workload: device memory for the projections of one chunk")
     ap.add_argument("--mixed-blocks", type=int, default=500000,
                     help="blocks of the mixed workload (16 size x code classes)")
-    ap.add_argument("--qps", default="10000,20000,50000,100000,200000,500000,1000000,2000000",
+    ap.add_argument("--qps",
+                    default="10000,20000,50000,100000,200000,500000,1000000,2000000,3000000",
                     help="serving: comma-separated arrival rates (requests/s)")
     ap.add_argument("--serve-seconds", type=float, default=2.0,
                     help="serving: arrival window per rate")
     ap.add_argument("--serve-long-reads", default="chunked", choices=["chunked", "both_ends"],
                     help="serving: how reads of long rows are decoded")
-    ap.add_argument("--serve-budget-gib", type=float, default=64.0,
+    ap.add_argument("--serve-budget-gib", type=float, default=96.0,
                     help="serving: HBM budget of the store (arenas, payloads, outputs)")
+    ap.add_argument("--serve-depth", type=int, default=3,
+                    help="serving: iterations in flight")
+    ap.add_argument("--serve-iter-mib", type=int, default=128,
+                    help="serving: image MiB per class and kind in one iteration")
     ap.add_argument("--plain-blocks", type=int, default=1024)
     ap.add_argument("--cpu-sample", type=int, default=1 << 19)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -946,8 +951,9 @@ def run_serving(args):
 
     geos = serving.geometries()
     t_setup = time.perf_counter()
-    srv = serving.Server(budget_bytes=int(args.serve_budget_gib * (1 << 30)), depth=3,
-                         seed=synth.SEED_DATA, geos=geos, prefill=0.5, per_iter_bytes=64 << 20,
+    srv = serving.Server(budget_bytes=int(args.serve_budget_gib * (1 << 30)),
+                         depth=args.serve_depth, seed=synth.SEED_DATA, geos=geos, prefill=0.5,
+                         per_iter_bytes=args.serve_iter_mib << 20,
                          long_reads=args.serve_long_reads)
     setup_s = time.perf_counter() - t_setup
     # warm-up: a short run at a low rate (first launches of every kernel variant)
@@ -975,8 +981,9 @@ def run_serving(args):
         "config": {"workload": "serving: Poisson arrivals, 70% degraded reads (0..m erasures) / "
                                "30% writes, sizes 2^U[12,20] B rounded to 8k, codes (4,2)/(8,4), "
                                f"{len(geos)} size x code classes, {args.serve_budget_gib:g} GiB "
-                               "HBM budget, up to 3 iterations in flight, long-row reads "
-                               f"{args.serve_long_reads}",
+                               f"HBM budget, up to {args.serve_depth} iterations in flight "
+                               f"of up to {args.serve_iter_mib} MiB per class and kind, "
+                               f"long-row reads {args.serve_long_reads}",
                    "parallelism": "single GPU"},
         "best_point": {k: best[k] for k in ("qps", "p50_us", "p99_us", "GBps")},
         "sweep": sweep, "setup_s": round(setup_s, 2), "status_ok": ok,

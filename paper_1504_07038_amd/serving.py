@@ -239,11 +239,15 @@ class Server:
         #                side stream with a completion event of its own: the
         #                sweep work once, and the iteration's writes and
         #                short reads complete without waiting for it.
-        # Measured (64 GiB, 66 classes): chunked keeps pace up to 1M req/s
-        # (p99 10.6 ms, 186 GB/s) and moves 310 GB/s at 2M with a growing
-        # queue; both ends peaks at 126 GB/s: an iteration's long reads
-        # take ~25 ms to sweep (chains of up to 16k columns), and the
-        # iterations waiting on them hold the in-flight window.
+        # Measured (66 classes, 3 iterations in flight): with 64 MiB per
+        # class and kind in an iteration, chunked keeps pace up to 1M req/s
+        # and moves 322 GB/s at 2M with a growing queue (every iteration
+        # full); with 128 MiB (96 GiB budget) it keeps pace at 2M (374 GB/s,
+        # p99 22 ms).  Both ends at 3 in flight peaks at 126 GB/s: an
+        # iteration's long reads take ~25 ms to sweep (chains of up to 16k
+        # columns), and the iterations waiting on them hold the in-flight
+        # window; with 6 in flight and 128 MiB it also keeps pace at 2M, at
+        # a p99 of 38 ms (37 ms already at 1M).
         if long_reads not in ("chunked", "both_ends"):
             raise ValueError("long_reads is 'chunked' or 'both_ends'")
         self.long_reads = long_reads
