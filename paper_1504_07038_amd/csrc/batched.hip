@@ -26,7 +26,12 @@ namespace mj {
 
 namespace {
 
-constexpr int kLayoutThreads = 1024;
+// The layout is one workgroup per call, launched while other streams may
+// fill the chip: four wavefronts and 2 KB of LDS find a compute unit where
+// sixteen wavefronts and 40 KB waited for one (its sort keys live in the
+// workspace).  Serving trace, 1M requests/s: 85 us average per call with
+// 1,024 threads and the keys in LDS (p99 375 us), 34 us like this (p99 74).
+constexpr int kLayoutThreads = 256;
 
 __device__ __forceinline__ uint64_t class_key(int geom, int ring, uint32_t P) {
     return ((uint64_t)(geom + 1) << 32) | ((uint64_t)ring << 31) | P;   // never 0
@@ -170,9 +175,11 @@ __device__ __forceinline__ int64_t class_weight_items(const DescCall &c, const G
 }
 
 __global__ __launch_bounds__(kLayoutThreads) void desc_layout_kernel(DescCall c) {
-    __shared__ uint64_t order[kDescSlots];   // sort keys: group, longest rows first, slot
     __shared__ int64_t scan[kLayoutThreads];
     __shared__ int nclasses;
+    // sort keys: group, longest rows first, slot (global memory: the
+    // workgroup's own writes, ordered by its barriers)
+    uint64_t *order = reinterpret_cast<uint64_t *>(c.ws + DescWorkspace::kOrder);
     const uint64_t *keys = reinterpret_cast<const uint64_t *>(c.ws + DescWorkspace::kKeys);
     const uint32_t *counts = reinterpret_cast<const uint32_t *>(c.ws + DescWorkspace::kCounts);
     int32_t *slot_class = reinterpret_cast<int32_t *>(c.ws + DescWorkspace::kSlotClass);
@@ -231,57 +238,52 @@ __global__ __launch_bounds__(kLayoutThreads) void desc_layout_kernel(DescCall c)
             __syncthreads();
         }
     }
-    // 3. per class (sorted): blocks and work items, scanned in order
-    constexpr int CPT = kDescSlots / kLayoutThreads;   // classes per thread, consecutive
-    int64_t my_blocks[CPT], my_items[CPT];
-    int64_t tb = 0, ti = 0;
-    for (int k = 0; k < CPT; ++k) {
-        const int ci = tid * CPT + k;
-        my_blocks[k] = my_items[k] = 0;
-        if (ci >= nc) continue;
-        const int s = (int)(order[ci] & (kDescSlots - 1));
-        const uint64_t key = keys[s];
-        const int geom = (int)(key >> 32) - 1;
-        const int ring = (int)((key >> 31) & 1);
-        const int P = (int)(key & 0x7FFFFFFFu);
-        int nb = 1, W = 1;
-        my_blocks[k] = counts[s];
-        my_items[k] = class_weight_items(c, c.geoms[geom], ring, P, counts[s], nb, W);
-        tb += my_blocks[k];
-        ti += my_items[k];
-    }
-    // exclusive scans of blocks and items over threads (two passes of one buffer)
-    int64_t blocks_before = 0, items_before = 0;
-    for (int pass = 0; pass < 2; ++pass) {
-        scan[tid] = pass == 0 ? tb : ti;
-        __syncthreads();
-        for (int off = 1; off < kLayoutThreads; off <<= 1) {
-            const int64_t v = tid >= off ? scan[tid - off] : 0;
+    // 3. per class (sorted): blocks and work items, scanned in order; rounds
+    // of one class per thread (one round for up to kLayoutThreads classes)
+    int32_t *idx = reinterpret_cast<int32_t *>(c.ws + DescWorkspace::idx_at(c.nblocks));
+    int64_t run_blocks = 0, run_items = 0;   // totals of the earlier rounds
+    for (int base = 0; base < nc; base += kLayoutThreads) {
+        const int ci = base + tid;
+        int64_t my_blocks = 0, my_items = 0;
+        int s = 0, geom = 0, ring = 0, P = 0, nb = 1, W = 1;
+        if (ci < nc) {
+            s = (int)(order[ci] & (kDescSlots - 1));
+            const uint64_t key = keys[s];
+            geom = (int)(key >> 32) - 1;
+            ring = (int)((key >> 31) & 1);
+            P = (int)(key & 0x7FFFFFFFu);
+            my_blocks = counts[s];
+            my_items = class_weight_items(c, c.geoms[geom], ring, P, counts[s], nb, W);
+        }
+        // exclusive scans of blocks and items over the round (two passes of one buffer)
+        int64_t blocks_before = 0, items_before = 0, tot_blocks = 0, tot_items = 0;
+        for (int pass = 0; pass < 2; ++pass) {
+            const int64_t mine = pass == 0 ? my_blocks : my_items;
+            scan[tid] = mine;
             __syncthreads();
-            scan[tid] += v;
+            for (int off = 1; off < kLayoutThreads; off <<= 1) {
+                const int64_t v = tid >= off ? scan[tid - off] : 0;
+                __syncthreads();
+                scan[tid] += v;
+                __syncthreads();
+            }
+            const int64_t excl = scan[tid] - mine, tot = scan[kLayoutThreads - 1];
+            if (pass == 0) {
+                blocks_before = run_blocks + excl;
+                tot_blocks = tot;
+            } else {
+                items_before = run_items + excl;
+                tot_items = tot;
+            }
             __syncthreads();
         }
-        const int64_t excl = scan[tid] - (pass == 0 ? tb : ti);
-        if (pass == 0) blocks_before = excl; else items_before = excl;
-        if (pass == 0 && tid == kLayoutThreads - 1) seg_start[nc] = scan[tid];
-        if (pass == 1 && tid == kLayoutThreads - 1) first_item[nc] = scan[tid];
-        __syncthreads();
-    }
-    int32_t *idx = reinterpret_cast<int32_t *>(c.ws + DescWorkspace::idx_at(c.nblocks));
-    for (int k = 0; k < CPT; ++k) {
-        const int ci = tid * CPT + k;
+        run_blocks += tot_blocks;
+        run_items += tot_items;
         if (ci >= nc) continue;
-        const int s = (int)(order[ci] & (kDescSlots - 1));
-        const uint64_t key = keys[s];
-        const int geom = (int)(key >> 32) - 1;
-        const int ring = (int)((key >> 31) & 1);
-        const int P = (int)(key & 0x7FFFFFFFu);
         const GeomDev &g = c.geoms[geom];
         slot_class[s] = ci;
         seg_start[ci] = blocks_before;
         first_item[ci] = items_before;
-        int nb = 1, W = 1;
-        class_weight_items(c, g, ring, P, counts[s], nb, W);
         // projection i's stored bins: Eq. 2's, or the kept ones
         int32_t off[kMaxDirs], kept[kMaxDirs];
         int32_t o = 0;
@@ -299,7 +301,7 @@ __global__ __launch_bounds__(kLayoutThreads) void desc_layout_kernel(DescCall c)
             d.images = nullptr;
             d.masks = nullptr;
             d.slots = nullptr;
-            d.nblocks = my_blocks[k];
+            d.nblocks = my_blocks;
             d.proj_stride = o;
             d.img_stride = (int64_t)P * g.Q;
             d.P = P;
@@ -321,7 +323,7 @@ __global__ __launch_bounds__(kLayoutThreads) void desc_layout_kernel(DescCall c)
             e.desc = (global_block *)c.desc;
             e.idx = (global_i32 *)(idx + blocks_before);
             e.pool = (global_u64 *)c.pool;
-            e.nblocks = my_blocks[k];
+            e.nblocks = my_blocks;
             e.P = P;
             e.Q = g.Q;
             e.n = g.n;
@@ -337,15 +339,17 @@ __global__ __launch_bounds__(kLayoutThreads) void desc_layout_kernel(DescCall c)
                 e.keep_n[i] = i < g.n ? kept[i] : 0;
             }
         }
-        blocks_before += my_blocks[k];
-        items_before += my_items[k];
         // launch groups: where the group of consecutive classes changes
         const int grp = (int)(order[ci] >> 58);
-        if (ci == 0 || (int)(order[ci - 1] >> 58) != grp) hd.range[2 * grp] = first_item[ci];
+        if (ci == 0 || (int)(order[ci - 1] >> 58) != grp) hd.range[2 * grp] = items_before;
         if (ci == nc - 1 || (int)(order[ci + 1] >> 58) != grp)
-            hd.range[2 * grp + 1] = first_item[ci] + my_items[k];
+            hd.range[2 * grp + 1] = items_before + my_items;
     }
-    if (tid == 0) hd.nclasses = nc;
+    if (tid == 0) {
+        seg_start[nc] = run_blocks;
+        first_item[nc] = run_items;
+        hd.nclasses = nc;
+    }
 }
 
 __global__ __launch_bounds__(256) void desc_scatter_kernel(DescCall c) {

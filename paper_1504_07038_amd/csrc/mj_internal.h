@@ -348,7 +348,8 @@ struct DescWorkspace {
     static constexpr size_t kSlotClass = kCounts + 4 * kDescSlots; // int32 per slot
     static constexpr size_t kSegStart = kSlotClass + 4 * kDescSlots;  // int64 per class + 1
     static constexpr size_t kFirstItem = kSegStart + 8 * (kDescSlots + 8); // int64 per class + 1
-    static constexpr size_t kClasses = kFirstItem + 8 * (kDescSlots + 8);
+    static constexpr size_t kOrder = kFirstItem + 8 * (kDescSlots + 8);    // uint64 sort keys
+    static constexpr size_t kClasses = kOrder + 8 * kDescSlots;
     static constexpr size_t kClassBytes =
         sizeof(DecodeDesc) > sizeof(EncodeDesc) ? sizeof(DecodeDesc) : sizeof(EncodeDesc);
     static constexpr size_t kSlotOf = (kClasses + kClassBytes * kDescSlots + 255) / 256 * 256;
