@@ -210,6 +210,10 @@ int mojette_decode_wide(const uint64_t *const *proj, const int32_t *proj_ids, in
  * mojette_encode_batch_trimmed / mojette_decode_batch_trimmed: as the
  *   batched calls, projections in the trimmed layout (block b's slice at
  *   word b * mojette_trimmed_layout()).
+ * mojette_encode_trimmed / mojette_decode_trimmed: as the one-block calls
+ *   mojette_encode / mojette_decode (flags: MOJETTE_VERIFY, which then
+ *   compares the kept bins), each projection buffer holding count[i] words:
+ *   its kept bins, from index first[i] on.
  *
  * The layout is tied to the reconstruction path above: another decoder
  * (another assignment of projections to rows) may need bins it leaves out.
@@ -226,6 +230,11 @@ int mojette_encode_batch_trimmed(const uint64_t *images, int64_t nblocks, int32_
 int mojette_decode_batch_trimmed(const uint64_t *projs, const uint16_t *erased, int64_t nblocks,
                                  int32_t P, int32_t Q, const int32_t *dirs, int32_t n,
                                  uint64_t *images, int32_t *status, void *stream);
+int mojette_encode_trimmed(const uint64_t *image, int32_t P, int32_t Q, const int32_t *dirs,
+                           int32_t n, uint64_t *const *proj_out, void *stream);
+int mojette_decode_trimmed(const uint64_t *const *proj, const int32_t *proj_ids, int32_t m,
+                           const int32_t *dirs, int32_t n, int32_t P, int32_t Q,
+                           uint64_t *image_out, uint32_t flags, void *stream);
 
 /*
  * Systematic code (Section 2.3 mentions a systematic version of the code as

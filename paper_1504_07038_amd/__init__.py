@@ -176,6 +176,9 @@ def lib() -> ctypes.CDLL:
         "mojette_encode_wide": ([vp, i32, i32, vp, i32, vp, vp], ctypes.c_int),
         "mojette_decode_wide": ([vp, vp, i32, vp, i32, i32, i32, vp, ctypes.c_uint32, vp],
                                 ctypes.c_int),
+        "mojette_encode_trimmed": ([vp, i32, i32, vp, i32, vp, vp], ctypes.c_int),
+        "mojette_decode_trimmed": ([vp, vp, i32, vp, i32, i32, i32, vp, ctypes.c_uint32, vp],
+                                   ctypes.c_int),
         "mojette_encode_batch": ([vp, i64, i32, i32, vp, i32, vp, vp], ctypes.c_int),
         "mojette_decode_batch": ([vp, vp, i64, i32, i32, vp, i32, vp, vp, vp], ctypes.c_int),
         "mojette_encode_batch_wide": ([vp, i64, i32, i32, vp, i32, vp, vp], ctypes.c_int),
@@ -252,7 +255,8 @@ def exported_symbols() -> list[str]:
         "mojette_bin_offset", "mojette_block_words", "mojette_decode_ring", "mojette_encode",
         "mojette_decode", "mojette_encode_batch", "mojette_decode_batch",
         "mojette_encode_batch_wide", "mojette_decode_batch_wide", "mojette_encode_wide",
-        "mojette_decode_wide", "mojette_verify_batch",
+        "mojette_decode_wide", "mojette_encode_trimmed", "mojette_decode_trimmed",
+        "mojette_verify_batch",
         "mojette_trimmed_layout", "mojette_trimmed_path", "mojette_encode_batch_trimmed",
         "mojette_decode_batch_trimmed",
         "mojette_encode_batch_sys", "mojette_sys_workspace", "mojette_decode_batch_sys",
@@ -358,12 +362,29 @@ def mojette_encode_wide(image, P: int, Q: int, dirs, proj_out, stream=None,
                         check: bool = True) -> int:
     """mojette_encode for 16-byte pixels: image of Q*P pixels of two words,
     proj_out[i] of 2*B_i words."""
+    return _encode_one("mojette_encode_wide", image, P, Q, dirs, proj_out, stream, check)
+
+
+def mojette_encode_trimmed(image, P: int, Q: int, dirs, proj_out, stream=None,
+                           check: bool = True) -> int:
+    """mojette_encode storing the kept bins only: proj_out[i] of count[i]
+    words (mojette_trimmed_layout)."""
+    return _encode_one("mojette_encode_trimmed", image, P, Q, dirs, proj_out, stream, check)
+
+
+def mojette_decode_trimmed(proj, proj_ids, dirs, P: int, Q: int, image_out, stream=None,
+                           check: bool = True, verify: bool = False) -> int:
+    """mojette_decode from projections in the trimmed layout."""
+    return _decode_one("mojette_decode_trimmed", proj, proj_ids, dirs, P, Q, image_out, stream,
+                       check, verify)
+
+
+def _encode_one(name, image, P, Q, dirs, proj_out, stream, check):
     arr, n = _i32_array(dirs)
     ptrs = (ctypes.c_void_p * max(1, len(proj_out)))(
         *[_word_tensor(t, "proj_out") for t in proj_out])
-    rc = lib().mojette_encode_wide(_word_tensor(image, "image"), P, Q, arr, n, ptrs,
-                                   _stream(stream))
-    return _check(rc, "mojette_encode_wide", check)
+    rc = getattr(lib(), name)(_word_tensor(image, "image"), P, Q, arr, n, ptrs, _stream(stream))
+    return _check(rc, name, check)
 
 
 def mojette_decode_wide(proj, proj_ids, dirs, P: int, Q: int, image_out, stream=None,

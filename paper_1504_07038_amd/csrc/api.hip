@@ -541,9 +541,12 @@ int32_t mojette_decode_ring(const int32_t *dirs, int32_t n, int32_t P, int32_t Q
     return ring_length(sp, Q);
 }
 
-// One block; bin_swap: 128-bit pixels as the word image of twice the width.
+// One block; bin_swap: 128-bit pixels as the word image of twice the width;
+// keep_first/keep_count: the stored bins of each projection (null: all).
 static int encode_one_impl(const uint64_t *image, int32_t P, int32_t Q, const int32_t *dirs,
-                           int32_t n, uint64_t *const *proj_out, void *stream, int bin_swap) {
+                           int32_t n, uint64_t *const *proj_out, void *stream, int bin_swap,
+                           const int32_t *keep_first = nullptr,
+                           const int32_t *keep_count = nullptr) {
     if (!image || !proj_out || !geometry_ok(dirs, n, P, Q)) return MOJETTE_EINVAL;
     for (int i = 0; i < n; ++i)
         if (!proj_out[i]) return MOJETTE_EINVAL;
@@ -551,7 +554,13 @@ static int encode_one_impl(const uint64_t *image, int32_t P, int32_t Q, const in
     if (!encode_tiling(dirs, n, P, Q, a)) return MOJETTE_ENOTSUP;
     a.images = image;
     a.bin_swap = bin_swap;
-    for (int i = 0; i < n; ++i) a.out[i] = proj_out[i];
+    for (int i = 0; i < n; ++i) {
+        a.out[i] = proj_out[i];
+        if (keep_first) {
+            a.keep_lo[i] = keep_first[i];
+            a.keep_n[i] = keep_count[i];
+        }
+    }
     a.proj_stride = 0;
     a.nblocks = 1;
     const int grid = (a.ntiles + a.waves - 1) / a.waves;
@@ -569,6 +578,13 @@ int mojette_encode_wide(const uint64_t *image, int32_t P, int32_t Q, const int32
     int32_t dirs2[kMaxDirs];
     if (!wide_geometry(dirs, n, P, Q, dirs2)) return MOJETTE_EINVAL;
     return encode_one_impl(image, 2 * P, Q, dirs2, n, proj_out, stream, 1);
+}
+
+int mojette_encode_trimmed(const uint64_t *image, int32_t P, int32_t Q, const int32_t *dirs,
+                           int32_t n, uint64_t *const *proj_out, void *stream) {
+    int32_t f[kMaxDirs], c[kMaxDirs];
+    if (!kept_layout(dirs, n, P, Q, f, c)) return MOJETTE_EINVAL;
+    return encode_one_impl(image, P, Q, dirs, n, proj_out, stream, 0, f, c);
 }
 
 // keep_first/keep_count: the stored bins of each projection (null: all).
@@ -666,12 +682,18 @@ static int32_t *verify_word_on_current_device() {
 // its bins (the consistency check of Section 2.2); waits for the result.
 static int verify_one_block(const uint64_t *const *proj, const int32_t *proj_ids, int32_t m,
                             const int32_t *dirs, int32_t n, int32_t P, int32_t Q,
-                            const uint64_t *image, hipStream_t stream, int bin_swap) {
+                            const uint64_t *image, hipStream_t stream, int bin_swap,
+                            const int32_t *keep_first, const int32_t *keep_count) {
     static std::mutex mu;
     std::lock_guard<std::mutex> g(mu);
     mj::VerifyArgs a{};
     if (!encode_tiling(dirs, n, P, Q, a)) return MOJETTE_ENOTSUP;
     a.bin_swap = bin_swap;
+    if (keep_first)
+        for (int i = 0; i < n; ++i) {
+            a.keep_lo[i] = keep_first[i];
+            a.keep_n[i] = keep_count[i];
+        }
     uint32_t have = 0;
     for (int t = 0; t < m; ++t) {
         a.par[proj_ids[t]] = proj[t];
@@ -699,10 +721,13 @@ static int verify_one_block(const uint64_t *const *proj, const int32_t *proj_ids
     return verdict;
 }
 
-// One block; bin_swap: 128-bit pixels as the word image of twice the width.
+// One block; bin_swap: 128-bit pixels as the word image of twice the width;
+// keep_first/keep_count: the stored bins of each projection (null: all).
 static int decode_one_impl(const uint64_t *const *proj, const int32_t *proj_ids, int32_t m,
                            const int32_t *dirs, int32_t n, int32_t P, int32_t Q,
-                           uint64_t *image_out, uint32_t flags, void *stream, int bin_swap) {
+                           uint64_t *image_out, uint32_t flags, void *stream, int bin_swap,
+                           const int32_t *keep_first = nullptr,
+                           const int32_t *keep_count = nullptr) {
     if (!image_out || !geometry_ok(dirs, n, P, Q) || m < 0 || m > n) return MOJETTE_EINVAL;
     if (flags & ~(uint32_t)MOJETTE_VERIFY) return MOJETTE_EINVAL;
     if (m > 0 && (!proj || !proj_ids)) return MOJETTE_EINVAL;
@@ -727,11 +752,13 @@ static int decode_one_impl(const uint64_t *const *proj, const int32_t *proj_ids,
     a.nblocks = 1;
     a.nb = 1;   // one block: one slot
     a.bin_swap = bin_swap;
+    if (keep_first)
+        for (int i = 0; i < n; ++i) a.keep_lo[i] = keep_first[i];
     clear_stale_error();
     const int st = status_of(mj::launch_decode(Q, mj::kLaunchPointers, a, 1, (hipStream_t)stream));
     if (st != MOJETTE_OK || !(flags & MOJETTE_VERIFY)) return st;
     return verify_one_block(proj, proj_ids, m, dirs, n, P, Q, image_out, (hipStream_t)stream,
-                            bin_swap);
+                            bin_swap, keep_first, keep_count);
 }
 
 int mojette_decode(const uint64_t *const *proj, const int32_t *proj_ids, int32_t m,
@@ -746,6 +773,14 @@ int mojette_decode_wide(const uint64_t *const *proj, const int32_t *proj_ids, in
     int32_t dirs2[kMaxDirs];
     if (!wide_geometry(dirs, n, P, Q, dirs2)) return MOJETTE_EINVAL;
     return decode_one_impl(proj, proj_ids, m, dirs2, n, 2 * P, Q, image_out, flags, stream, 1);
+}
+
+int mojette_decode_trimmed(const uint64_t *const *proj, const int32_t *proj_ids, int32_t m,
+                           const int32_t *dirs, int32_t n, int32_t P, int32_t Q,
+                           uint64_t *image_out, uint32_t flags, void *stream) {
+    int32_t f[kMaxDirs], c[kMaxDirs];
+    if (!kept_layout(dirs, n, P, Q, f, c)) return MOJETTE_EINVAL;
+    return decode_one_impl(proj, proj_ids, m, dirs, n, P, Q, image_out, flags, stream, 0, f, c);
 }
 
 static int decode_batch_impl(const uint64_t *projs, const uint16_t *erased, int64_t nblocks,

@@ -95,3 +95,59 @@ def test_trimmed_argument_checks(mj):
     assert mj.mojette_decode_batch_trimmed(d, None, -1, 8, 2, [0, 1], d,
                                            check=False) == mj.MOJETTE_EINVAL
     assert mj.mojette_encode_batch_trimmed(d, 0, 8, 2, [0, 1], d) == 0
+
+
+@pytest.mark.parametrize("P,Q,n,m", [
+    (128, 4, 6, 4),     # 4 KB (6,4)
+    (128, 8, 12, 9),    # 8 KB (8,4), more survivors than Q
+    (37, 3, 6, 3),      # odd row length
+    (300, 2, 4, 4),     # rows over several encode tiles, every projection given
+])
+def test_trimmed_one_block(mj, P, Q, n, m):
+    """mojette_encode_trimmed / mojette_decode_trimmed: one block, each
+    projection's kept bins at its own pointer, against the oracle's kept-bin
+    transform; the verified decode from m of them restores the image."""
+    dirs = synth.centered_dirs(n)
+    say(f"trimmed one block P={P} Q={Q} n={n} m={m}")
+    words, keep = mj.mojette_trimmed_layout(dirs, P, Q)
+    img = synth.block_images(700 + P + n, 0, 1, P, Q)
+    want = oracle.encode_blocks_kept(img, P, Q, dirs)[0]
+    offs = np.concatenate([[0], np.cumsum([c for _, c in keep])]).astype(int)
+    outs = [torch.full((c,), -1, dtype=torch.int64, device="cuda") for _, c in keep]
+    assert mj.mojette_encode_trimmed(to_dev(img), P, Q, dirs, outs) == 0
+    torch.cuda.synchronize()
+    for i in range(n):
+        assert np.array_equal(to_np(outs[i]), want[offs[i]:offs[i + 1]]), i
+    ids = sorted(np.random.default_rng(P + m).choice(n, m, replace=False).tolist())
+    for i in set(range(n)) - set(ids):
+        outs[i].fill_(int(POISON.astype(np.int64)))
+    d_out = torch.full((Q * P,), -1, dtype=torch.int64, device="cuda")
+    assert mj.mojette_decode_trimmed([outs[i] for i in ids], ids, dirs, P, Q, d_out,
+                                     verify=True) == 0
+    torch.cuda.synchronize()
+    assert np.array_equal(to_np(d_out).reshape(Q, P), img[0])
+
+
+def test_trimmed_one_block_verify_finds_a_flipped_bin(mj):
+    """A flipped kept bin of a projection the decode does not use (every
+    projection given; the Q of smallest p rebuild): the verified decode
+    reports MOJETTE_EINCONSISTENT."""
+    P, Q, n = 128, 4, 6
+    dirs = synth.centered_dirs(n)
+    _, keep = mj.mojette_trimmed_layout(dirs, P, Q)
+    img = synth.block_images(41, 0, 1, P, Q)
+    want = oracle.encode_blocks_kept(img, P, Q, dirs)[0]
+    offs = np.concatenate([[0], np.cumsum([c for _, c in keep])]).astype(int)
+    unused = np.argsort(dirs)[Q:]
+    rng = np.random.default_rng(9)
+    for trial in range(4):
+        i = int(unused[trial % len(unused)])
+        bins = want[offs[i]:offs[i + 1]].copy()
+        bins[int(rng.integers(0, len(bins)))] ^= np.uint64(1 << int(rng.integers(64)))
+        proj = [to_dev(want[offs[t]:offs[t + 1]]) for t in range(n)]
+        proj[i] = to_dev(bins)
+        d_out = torch.empty(Q * P, dtype=torch.int64, device="cuda")
+        rc = mj.mojette_decode_trimmed(proj, list(range(n)), dirs, P, Q, d_out, verify=True,
+                                       check=False)
+        assert rc == mj.MOJETTE_EINCONSISTENT, (trial, i)
+        assert np.array_equal(to_np(d_out).reshape(Q, P), img[0])
