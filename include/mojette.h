@@ -564,6 +564,17 @@ int mojette_decode_batch_chunked(const mojette_chunk_plan *plan, const uint64_t 
                                  void *stream);
 
 /*
+ * mojette_decode_batch_chunked for projections in the layout without
+ * never-used bins (block b's slice at word b * mojette_trimmed_layout(),
+ * see mojette_decode_batch_trimmed): the chunks read only bins that layout
+ * keeps.  Arguments, workspace and errors as mojette_decode_batch_chunked.
+ */
+int mojette_decode_batch_chunked_trimmed(const mojette_chunk_plan *plan, const uint64_t *projs,
+                                         const uint16_t *erased, int64_t nblocks, int32_t P,
+                                         uint64_t *images, int32_t *status,
+                                         uint64_t *workspace, void *stream);
+
+/*
  * mojette_decode_batch_chunked for callers that cannot allocate device
  * memory or pass a workspace (code under HIP graph capture, serving loops,
  * harnesses that forbid hipMalloc).  The workspace is a fixed array of

@@ -211,6 +211,8 @@ def lib() -> ctypes.CDLL:
         "mojette_chunk_matrix": ([vp, i32, i32, vp, vp, i64], i64),
         "mojette_decode_chunked_workspace": ([vp, i32, i64], i64),
         "mojette_decode_batch_chunked": ([vp, vp, vp, i64, i32, vp, vp, vp, vp], ctypes.c_int),
+        "mojette_decode_batch_chunked_trimmed": ([vp, vp, vp, i64, i32, vp, vp, vp, vp],
+                                                 ctypes.c_int),
         "mojette_plan_create": ([vp, i32, vp, vp], ctypes.c_int),
         "mojette_plan_destroy": ([vp], ctypes.c_int),
         "mojette_workspace_size": ([vp, i64], i64),
@@ -266,7 +268,8 @@ def exported_symbols() -> list[str]:
         "mojette_classes_layout", "mojette_encode_classes", "mojette_decode_classes",
         "mojette_encode_jobs", "mojette_decode_jobs", "mojette_chunk_plan_create",
         "mojette_chunk_plan_destroy", "mojette_chunk_matrix", "mojette_decode_chunked_workspace",
-        "mojette_decode_batch_chunked", "mojette_decode_batch_chunked_noalloc",
+        "mojette_decode_batch_chunked", "mojette_decode_batch_chunked_trimmed",
+        "mojette_decode_batch_chunked_noalloc",
         "mojette_plan_create", "mojette_plan_destroy", "mojette_workspace_size",
         "mojette_encode_batched", "mojette_decode_batched",
         "mojette_mlp_params", "mojette_mlp_forward",
@@ -681,7 +684,10 @@ def mojette_decode_chunked_workspace(plan: ChunkPlan, P: int, nblocks: int) -> i
 
 
 def mojette_decode_batch_chunked(plan: ChunkPlan, projs, erased, nblocks: int, P: int, images,
-                                 workspace, status=None, stream=None, check: bool = True) -> int:
+                                 workspace, status=None, stream=None, check: bool = True,
+                                 trimmed: bool = False) -> int:
+    """trimmed=True: projections in the layout without never-used bins
+    (mojette_decode_batch_chunked_trimmed)."""
     import torch
 
     if erased is not None and erased.dtype not in (torch.int16, torch.uint16):
@@ -694,11 +700,12 @@ def mojette_decode_batch_chunked(plan: ChunkPlan, projs, erased, nblocks: int, P
         if workspace is None or workspace.numel() < need:
             raise ValueError(f"workspace must hold {need} words")
         ws = _word_tensor(workspace, "workspace")
-    rc = lib().mojette_decode_batch_chunked(plan.handle, _word_tensor(projs, "projs"),
-                                            _dev_ptr(erased, "erased"), nblocks, P,
-                                            _word_tensor(images, "images"),
-                                            _dev_ptr(status, "status"), ws, _stream(stream))
-    return _check(rc, "mojette_decode_batch_chunked", check)
+    name = "mojette_decode_batch_chunked" + ("_trimmed" if trimmed else "")
+    rc = getattr(lib(), name)(plan.handle, _word_tensor(projs, "projs"),
+                              _dev_ptr(erased, "erased"), nblocks, P,
+                              _word_tensor(images, "images"), _dev_ptr(status, "status"), ws,
+                              _stream(stream))
+    return _check(rc, name, check)
 
 
 def mojette_decode_batch_chunked_noalloc(plan: ChunkPlan, projs, erased, nblocks: int, P: int,

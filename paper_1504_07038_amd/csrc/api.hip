@@ -1241,16 +1241,21 @@ static bool plan_matches(const mojette_chunk_plan *plan, const int32_t *dirs, in
     return true;
 }
 
-int mojette_decode_batch_chunked(const mojette_chunk_plan *plan, const uint64_t *projs,
-                                 const uint16_t *erased, int64_t nblocks, int32_t P,
-                                 uint64_t *images, int32_t *status, uint64_t *workspace,
-                                 void *stream) {
+// trimmed: projections in the layout without never-used bins.
+static int decode_chunked_impl(const mojette_chunk_plan *plan, const uint64_t *projs,
+                               const uint16_t *erased, int64_t nblocks, int32_t P,
+                               uint64_t *images, int32_t *status, uint64_t *workspace,
+                               void *stream, bool trimmed) {
     if (!plan || nblocks < 0 || P < 1 || P > kMaxP) return MOJETTE_EINVAL;
+    const int n = plan->n, Q = plan->Q;
+    int32_t kf[kMaxDirs], kc[kMaxDirs];
+    if (trimmed && !kept_layout(plan->dirs, n, P, Q, kf, kc)) return MOJETTE_EINVAL;
     const int nchunks = plan_chunks(plan, P);
     if (nchunks < 2)
-        return mojette_decode_batch(projs, erased, nblocks, P, plan->Q, plan->dirs, plan->n,
-                                    images, status, stream);
-    const int n = plan->n, Q = plan->Q;
+        return trimmed ? mojette_decode_batch_trimmed(projs, erased, nblocks, P, Q, plan->dirs, n,
+                                                      images, status, stream)
+                       : mojette_decode_batch(projs, erased, nblocks, P, Q, plan->dirs, n,
+                                              images, status, stream);
     if (!geometry_ok(plan->dirs, n, P, Q)) return MOJETTE_EINVAL;
     if (nblocks == 0) return MOJETTE_OK;
     if (!projs || !images || !workspace) return MOJETTE_EINVAL;
@@ -1260,7 +1265,12 @@ int mojette_decode_batch_chunked(const mojette_chunk_plan *plan, const uint64_t 
     int64_t off = 0;
     for (int i = 0; i < n; ++i) {
         a.off[i] = (int32_t)off;
-        off += mojette_proj_size(plan->dirs[i], P, Q);
+        if (trimmed) {
+            a.keep_lo[i] = kf[i];
+            off += kc[i];
+        } else {
+            off += mojette_proj_size(plan->dirs[i], P, Q);
+        }
     }
     a.pool = projs;
     a.slots = nullptr;
@@ -1272,6 +1282,22 @@ int mojette_decode_batch_chunked(const mojette_chunk_plan *plan, const uint64_t 
     a.status = status;
     a.nblocks = nblocks;
     return chunked_launch(plan, nchunks, a, Q, false, workspace, (hipStream_t)stream);
+}
+
+int mojette_decode_batch_chunked(const mojette_chunk_plan *plan, const uint64_t *projs,
+                                 const uint16_t *erased, int64_t nblocks, int32_t P,
+                                 uint64_t *images, int32_t *status, uint64_t *workspace,
+                                 void *stream) {
+    return decode_chunked_impl(plan, projs, erased, nblocks, P, images, status, workspace,
+                               stream, false);
+}
+
+int mojette_decode_batch_chunked_trimmed(const mojette_chunk_plan *plan, const uint64_t *projs,
+                                         const uint16_t *erased, int64_t nblocks, int32_t P,
+                                         uint64_t *images, int32_t *status,
+                                         uint64_t *workspace, void *stream) {
+    return decode_chunked_impl(plan, projs, erased, nblocks, P, images, status, workspace,
+                               stream, true);
 }
 
 int mojette_decode_batch_two_corner(const uint64_t *projs, const uint16_t *erased,
