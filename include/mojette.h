@@ -531,6 +531,14 @@ int mojette_decode_batched(const mojette_plan *plan, const mojette_block *blocks
  */
 int mojette_chunk_plan_create(const int32_t *dirs, int32_t n, int32_t Q, int32_t chunk_cols,
                               mojette_chunk_plan **plan);
+/* A plan for blocks of 128-bit pixels (Section 3.1; layouts as for
+ * mojette_decode_batch_wide): mojette_decode_batch_chunked and
+ * mojette_decode_chunked_workspace on such a plan take P in 16-byte pixels
+ * and the 128-bit layouts; chunk_cols counts 16-byte pixels.  |p| up to 2^14.
+ * Not for jobs (mojette_decode_jobs) or mojette_decode_batch_chunked_trimmed,
+ * which return MOJETTE_EINVAL on it. */
+int mojette_chunk_plan_create_wide(const int32_t *dirs, int32_t n, int32_t Q,
+                                   int32_t chunk_cols, mojette_chunk_plan **plan);
 int mojette_chunk_plan_destroy(mojette_chunk_plan *plan);
 
 /* Host only: the state width E (*state_cols) and transfer matrix of one

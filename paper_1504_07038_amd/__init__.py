@@ -213,6 +213,7 @@ def lib() -> ctypes.CDLL:
         "mojette_decode_batch_chunked": ([vp, vp, vp, i64, i32, vp, vp, vp, vp], ctypes.c_int),
         "mojette_decode_batch_chunked_trimmed": ([vp, vp, vp, i64, i32, vp, vp, vp, vp],
                                                  ctypes.c_int),
+        "mojette_chunk_plan_create_wide": ([vp, i32, i32, i32, vp], ctypes.c_int),
         "mojette_plan_create": ([vp, i32, vp, vp], ctypes.c_int),
         "mojette_plan_destroy": ([vp], ctypes.c_int),
         "mojette_workspace_size": ([vp, i64], i64),
@@ -268,6 +269,7 @@ def exported_symbols() -> list[str]:
         "mojette_classes_layout", "mojette_encode_classes", "mojette_decode_classes",
         "mojette_encode_jobs", "mojette_decode_jobs", "mojette_chunk_plan_create",
         "mojette_chunk_plan_destroy", "mojette_chunk_matrix", "mojette_decode_chunked_workspace",
+        "mojette_chunk_plan_create_wide",
         "mojette_decode_batch_chunked", "mojette_decode_batch_chunked_trimmed",
         "mojette_decode_batch_chunked_noalloc",
         "mojette_plan_create", "mojette_plan_destroy", "mojette_workspace_size",
@@ -636,13 +638,16 @@ class ChunkPlan:
     (directions, Q) and one chunk length.  Creating it allocates device memory
     and synchronises; ``close()`` (or garbage collection) frees it."""
 
-    def __init__(self, dirs, Q: int, chunk_cols: int):
+    def __init__(self, dirs, Q: int, chunk_cols: int, wide: bool = False):
+        """wide=True: a plan for 128-bit pixels (mojette_chunk_plan_create_wide)."""
         arr, n = _i32_array(dirs)
         h = ctypes.c_void_p(0)
-        rc = lib().mojette_chunk_plan_create(arr, n, Q, chunk_cols, ctypes.addressof(h))
-        _check(rc, "mojette_chunk_plan_create", True)
+        name = "mojette_chunk_plan_create" + ("_wide" if wide else "")
+        rc = getattr(lib(), name)(arr, n, Q, chunk_cols, ctypes.addressof(h))
+        _check(rc, name, True)
         self.handle = h.value
         self.dirs, self.Q, self.chunk_cols = [int(p) for p in dirs], int(Q), int(chunk_cols)
+        self.wide = bool(wide)
 
     def close(self) -> None:
         if self.handle:

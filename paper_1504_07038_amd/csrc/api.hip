@@ -1002,6 +1002,10 @@ struct mojette_chunk_plan {
     int32_t n, Q, tiles, max_cols, R, nsets;
     int32_t npow;            // matrices per set: T, T^2, ..., T^(2^(npow-1))
     int32_t dirs[MOJETTE_MAX_DIRS];
+    // 128-bit pixels: dirs (and tiles, max_cols, R) describe the word image
+    // of twice the width; dirs1 holds the caller's directions
+    int32_t wide;
+    int32_t dirs1[MOJETTE_MAX_DIRS];
     int32_t *lut;            // device, 2^n entries
     int32_t *state_cols;     // device, per set
     int64_t *tmat_off;       // device, per set
@@ -1017,8 +1021,8 @@ static void plan_free(mojette_chunk_plan *pl) {
     delete pl;
 }
 
-int mojette_chunk_plan_create(const int32_t *dirs, int32_t n, int32_t Q, int32_t chunk_cols,
-                        mojette_chunk_plan **plan) {
+static int chunk_plan_create_impl(const int32_t *dirs, int32_t n, int32_t Q, int32_t chunk_cols,
+                                  mojette_chunk_plan **plan) {
     if (!plan) return MOJETTE_EINVAL;
     *plan = nullptr;
     if (!geometry_ok(dirs, n, 1, Q) || n < Q || chunk_cols < 1) return MOJETTE_EINVAL;
@@ -1131,6 +1135,25 @@ int mojette_chunk_plan_create(const int32_t *dirs, int32_t n, int32_t Q, int32_t
     return MOJETTE_OK;
 }
 
+int mojette_chunk_plan_create(const int32_t *dirs, int32_t n, int32_t Q, int32_t chunk_cols,
+                              mojette_chunk_plan **plan) {
+    return chunk_plan_create_impl(dirs, n, Q, chunk_cols, plan);
+}
+
+int mojette_chunk_plan_create_wide(const int32_t *dirs, int32_t n, int32_t Q,
+                                   int32_t chunk_cols, mojette_chunk_plan **plan) {
+    if (!plan) return MOJETTE_EINVAL;
+    *plan = nullptr;
+    int32_t dirs2[kMaxDirs];
+    if (chunk_cols < 1 || chunk_cols > (1 << 29) || !wide_geometry(dirs, n, 1, Q, dirs2))
+        return MOJETTE_EINVAL;
+    const int rc = chunk_plan_create_impl(dirs2, n, Q, 2 * chunk_cols, plan);
+    if (rc != MOJETTE_OK) return rc;
+    (*plan)->wide = 1;
+    for (int i = 0; i < n; ++i) (*plan)->dirs1[i] = dirs[i];
+    return MOJETTE_OK;
+}
+
 int64_t mojette_chunk_matrix(const int32_t *p_sorted, int32_t Q, int32_t chunk_cols,
                              int32_t *state_cols, uint64_t *rows, int64_t cap_words) {
     if (!p_sorted || Q < 1 || Q > kMaxRows || chunk_cols < 1 || !state_cols) return -1;
@@ -1172,7 +1195,8 @@ static int scan_steps(const mojette_chunk_plan *pl, int per, int64_t nblocks) {
 }
 
 int64_t mojette_decode_chunked_workspace(const mojette_chunk_plan *plan, int32_t P, int64_t nblocks) {
-    if (!plan || P < 1 || P > kMaxP || nblocks < 0) return -1;
+    if (!plan || P < 1 || P > (plan->wide ? kMaxP / 2 : kMaxP) || nblocks < 0) return -1;
+    if (plan->wide) P *= 2;   // word columns
     const int nchunks = plan_chunks(plan, P);
     if (nchunks < 2) return 0;
     const int64_t one = nblocks * (nchunks - 1) * (int64_t)plan->Q * plan->max_cols;
@@ -1235,7 +1259,8 @@ static int chunked_launch(const mojette_chunk_plan *plan, int nchunks, mj::Decod
 }
 
 static bool plan_matches(const mojette_chunk_plan *plan, const int32_t *dirs, int32_t n, int32_t Q) {
-    if (!plan || plan->n != n || plan->Q != Q) return false;
+    // jobs take 64-bit pixels only
+    if (!plan || plan->wide || plan->n != n || plan->Q != Q) return false;
     for (int i = 0; i < n; ++i)
         if (plan->dirs[i] != dirs[i]) return false;
     return true;
@@ -1248,14 +1273,21 @@ static int decode_chunked_impl(const mojette_chunk_plan *plan, const uint64_t *p
                                void *stream, bool trimmed) {
     if (!plan || nblocks < 0 || P < 1 || P > kMaxP) return MOJETTE_EINVAL;
     const int n = plan->n, Q = plan->Q;
+    if (plan->wide && (trimmed || P > kMaxP / 2)) return MOJETTE_EINVAL;
     int32_t kf[kMaxDirs], kc[kMaxDirs];
     if (trimmed && !kept_layout(plan->dirs, n, P, Q, kf, kc)) return MOJETTE_EINVAL;
+    const int P1 = P;   // row length in the caller's pixels
+    if (plan->wide) P *= 2;   // 128-bit pixels: the word image of twice the width
     const int nchunks = plan_chunks(plan, P);
-    if (nchunks < 2)
+    if (nchunks < 2) {
+        if (plan->wide)
+            return mojette_decode_batch_wide(projs, erased, nblocks, P1, Q, plan->dirs1, n,
+                                             images, status, stream);
         return trimmed ? mojette_decode_batch_trimmed(projs, erased, nblocks, P, Q, plan->dirs, n,
                                                       images, status, stream)
                        : mojette_decode_batch(projs, erased, nblocks, P, Q, plan->dirs, n,
                                               images, status, stream);
+    }
     if (!geometry_ok(plan->dirs, n, P, Q)) return MOJETTE_EINVAL;
     if (nblocks == 0) return MOJETTE_OK;
     if (!projs || !images || !workspace) return MOJETTE_EINVAL;
@@ -1281,6 +1313,7 @@ static int decode_chunked_impl(const mojette_chunk_plan *plan, const uint64_t *p
     a.mask_uniform = 0;
     a.status = status;
     a.nblocks = nblocks;
+    a.bin_swap = plan->wide;
     return chunked_launch(plan, nchunks, a, Q, false, workspace, (hipStream_t)stream);
 }
 

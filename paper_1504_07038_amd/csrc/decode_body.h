@@ -329,14 +329,15 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch,
         return;
     }
     const int P = a.P;
-    // pointer mode, 128-bit pixels as the word image of twice the width:
-    // word bin j stored at word j ^ 1.  Read once: a class table is global
-    // memory that the loop's stores might alias, so a field read inside it
-    // is a vector load each time (and its wait would also wait for the bins
-    // loaded ahead).
+    // pointer mode and chunked sweeps, 128-bit pixels as the word image of
+    // twice the width: word bin j stored at word j ^ 1.  Read once: a class
+    // table is global memory that the loop's stores might alias, so a field
+    // read inside it is a vector load each time (and its wait would also
+    // wait for the bins loaded ahead).
     int bswap = 0;
     if constexpr (kIsDesc<Args> || kIsDecodeArgs<Args>)
-        if (!POOL) bswap = __builtin_amdgcn_readfirstlane(a.bin_swap);
+        if (!POOL || CHUNK == kChunkA || CHUNK == kChunkC)
+            bswap = __builtin_amdgcn_readfirstlane(a.bin_swap);
     T *slot_base = lds + (size_t)(lane_used ? slot : 0) * SS;
     const uint32_t RM = (uint32_t)Rmask * sizeof(T);   // byte mask of a ring
     // LDS address of the dynamic array (0 in these kernels, which declare no
@@ -731,6 +732,13 @@ __device__ __forceinline__ void decode_batch(const Args &a, const int64_t batch,
                             w = s.gbin + c;
                             wn = w - 1;
                         }
+                    }
+                    if constexpr (CHUNK == kChunkA || CHUNK == kChunkC) {
+                        // 128-bit pixels (the projections of the block's
+                        // slice have even lengths, so a word's pair
+                        // partner is in the same projection)
+                        w ^= bswap;
+                        wn ^= bswap;
                     }
                     const int cw = c + (AL ? s.mis : 0);     // column of word 2q
                     const bool in0 = s.on && (unsigned)cw < (unsigned)P;
