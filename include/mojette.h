@@ -488,7 +488,7 @@ int mojette_plan_create(const mojette_geom *geoms, int32_t ngeoms, const mojette
 int mojette_plan_destroy(mojette_plan *plan);
 
 /* Workspace bytes a call on up to nblocks blocks needs (non-decreasing in
- * nblocks), or -1 on bad arguments.  About 1.6 MB plus 12 bytes per block. */
+ * nblocks), or -1 on bad arguments.  About 1.7 MB plus 12 bytes per block. */
 int64_t mojette_workspace_size(const mojette_plan *plan, int64_t nblocks);
 
 /* Forward transform (Section 2.1, Eq. 1) of every described block: reads
