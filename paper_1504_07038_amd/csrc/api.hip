@@ -1951,6 +1951,13 @@ int mojette_plan_create(const mojette_geom *geoms, int32_t ngeoms, const mojette
         }
         // encode: tiles of at most enc_w columns beside the halo, within LDS
         g.H = (Q - 1) * maxabs;
+        int pmin = 0, pmax = 0;
+        for (int i = 0; i < n; ++i) {
+            pmin = std::min(pmin, dirs[i]);
+            pmax = std::max(pmax, dirs[i]);
+        }
+        g.plo = pmin;
+        g.pspan = pmax - pmin;
         int w = t && t->encode_tile_cols > 0 ? t->encode_tile_cols : kEncodeTileCols;
         if (w % 64 != 0) return MOJETTE_EINVAL;
         while (w > 64 && (size_t)Q * (w + 2 * g.H) * 8 > kLdsLimit) w -= 64;
@@ -2062,13 +2069,27 @@ int mojette_encode_batched(const mojette_plan *plan, const mojette_block *blocks
     // four wavefronts while their tiles take at most 48 KB
     for (int q = 1; q <= kMaxRows; ++q) {
         if (!((plan->qmask >> q) & 1u)) continue;
-        int tile_words = 0;
-        for (const mj::GeomDev &g : plan->geoms)
-            if (g.Q == q) tile_words = std::max(tile_words, q * (g.enc_w + 2 * g.H));
+        // tiles of every row the same width (tile and both halos), or for 9
+        // to 12 rows with register prefetch, row windows (the columns each
+        // row's bins cross: 8 KB (12,4) tiles of 128 columns take 20 KB of
+        // LDS instead of 29 KB, eight wavefronts per compute unit instead
+        // of five)
+        int tile_words = 0, max_row = 0, rw_words = 0, rw_row = 0;
+        for (const mj::GeomDev &g : plan->geoms) {
+            if (g.Q != q) continue;
+            tile_words = std::max(tile_words, q * (g.enc_w + 2 * g.H));
+            max_row = std::max(max_row, g.enc_w + 2 * g.H);
+            rw_words = std::max(rw_words, mj::row_window_off(q, g.enc_w, g.pspan));
+            rw_row = std::max(rw_row, g.enc_w + (q - 1) * g.pspan);
+        }
+        if (mj::encode_row_windows(q) && mj::encode_desc_prefetch(q, rw_row) > 0) {
+            tile_words = rw_words;
+            max_row = rw_row;
+        }
         const int waves = (size_t)mj::kEncodeWaves * tile_words * 8 <= 48 * 1024 ? mj::kEncodeWaves : 1;
         const int64_t want_waves = std::max<int64_t>(1, std::min<int64_t>(nblocks * 8, 1 << 16));
         const int grid = (int)((want_waves + waves - 1) / waves);
-        rc = status_of(mj::launch_encode_desc(q, c, q, waves, tile_words, grid, s));
+        rc = status_of(mj::launch_encode_desc(q, c, q, waves, tile_words, max_row, grid, s));
         if (rc != MOJETTE_OK) return rc;
     }
     return MOJETTE_OK;

@@ -330,6 +330,8 @@ __global__ __launch_bounds__(kLayoutThreads) void desc_layout_kernel(DescCall c)
             e.W = W;
             e.H = g.H;
             e.S = W + 2 * g.H;
+            e.plo = g.plo;
+            e.pspan = g.pspan;
             e.ntiles = (P + W - 1) / W;
             e.bin_swap = g.pshift;
             for (int i = 0; i < kMaxDirs; ++i) {

@@ -257,6 +257,10 @@ struct GeomDev {
     int32_t Q, n;
     int32_t sumabs;                  // sum of |p_i|: projection offsets are P-dependent
     int32_t H;                       // encode halo, (Q-1) * max |p|
+    // encode row windows (codes of 9 to 12 rows): row l of a tile at column
+    // x0 stages columns [x0 + l*plo, x0 + W + l*(plo + pspan)),
+    // plo = min(min p, 0), pspan = max(max p, 0) - plo
+    int32_t plo, pspan;
     int32_t enc_w;                   // encode tile width cap (columns)
     int32_t R, nb;                   // decode ring and blocks per wavefront, full ring
     int32_t R_short, nb_short;       // short-ring class (0: none)
@@ -320,6 +324,7 @@ struct EncodeDesc {
     global_u64 *pool;
     int64_t nblocks;
     int32_t P, Q, n, W, H, S, ntiles;
+    int32_t plo, pspan;              // row windows (see GeomDev)
     int32_t bin_swap;                // 1: word bin j stored at word j ^ 1 (128-bit pixels)
     int32_t off[kMaxDirs];
     int32_t p[kMaxDirs];             // 32-bit: read with scalar loads
@@ -387,8 +392,19 @@ hipError_t launch_desc_buckets(const DescCall &c, hipStream_t s);
 // (the classes of row count Q = g).
 hipError_t launch_decode_desc(int Q, bool two, const DescCall &c, int g, size_t lds, int grid,
                               hipStream_t s);
+// Descriptor encode of codes of 9 to 12 rows with register prefetch: each
+// row's LDS window holds only the columns its bins cross (see GeomDev.plo),
+// row l at word row_window_off(l, W, pspan) of the tile.
+constexpr bool encode_row_windows(int Q) { return Q >= 9 && Q <= 12; }
+__host__ __device__ constexpr int row_window_off(int l, int W, int pspan) {
+    return l * W + pspan * (l * (l - 1) / 2);
+}
+// Register prefetch chunks of a descriptor encode of Q rows whose widest
+// staged row has max_s columns (0: no prefetch).
+int encode_desc_prefetch(int Q, int max_s);
+// max_row: the widest staged row of the launch's tiles (words).
 hipError_t launch_encode_desc(int Q, const DescCall &c, int g, int waves, int tile_words,
-                              int grid, hipStream_t s);
+                              int max_row, int grid, hipStream_t s);
 
 // Status of a HIP call as a library status code; a failure is remembered for
 // mojette_last_hip_error() on the calling thread.

@@ -209,3 +209,31 @@ def test_wide_matches_the_batch_call(mj):
     got = to_np(d_pool)[nb * 2 * Q * P:]
     assert np.array_equal(got, to_np(d_batch))
     plan.close()
+
+
+def test_encode_row_windows_of_tall_codes(mj):
+    """Codes of 9 to 12 rows encode from LDS row windows (each row holds the
+    columns its bins cross): one-signed directions (the window's left or
+    right end at the tile's own column), a trimmed 12-row code, tiles at
+    the row's ends and in its middle; then codes whose windows exceed the
+    register prefetch (the 128-bit 12-row code, an 11-row code with |p| up
+    to 20), which keep the tile-and-halo layout.  Against the oracle."""
+    rw = [
+        (12, synth.centered_dirs(16), 0),
+        (12, synth.centered_dirs(16), mj.GEOM_TRIMMED),
+        (9, list(range(1, 11)), 0),
+        (10, list(range(-12, 0)), 0),
+        (4, synth.centered_dirs(6), 0),
+    ]
+    wide = [
+        (12, synth.centered_dirs(16), mj.GEOM_WIDE),
+        (11, [-3, 0, 1, 2, 4, 7, 9, 13, 20, -8, 5, 6], 0),
+    ]
+    for k, codes in enumerate((rw, wide)):
+        rng = np.random.default_rng(20 + k)
+        nb = 400
+        geom = rng.integers(0, len(codes), nb)
+        Ps = row_lengths(mj, codes, geom, [1, 2, 15, 16, 17, 64, 100, 128, 171, 300, 700], rng)
+        masks = masks_for(codes, geom, 3000 + 100 * k)
+        say(f"row windows: {nb} blocks, codes set {k}")
+        round_trip(mj, codes, geom, Ps, masks, 40 + k)
