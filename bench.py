@@ -50,17 +50,25 @@ def parse():
     ap.add_argument("--mixed-blocks", type=int, default=500000,
                     help="blocks of the mixed workload (16 size x code classes)")
     ap.add_argument("--qps",
-                    default="10000,20000,50000,100000,200000,500000,1000000,2000000,3000000",
+                    default="10000,20000,50000,100000,200000,500000,1000000,2000000,3000000,"
+                            "4000000",
                     help="serving: comma-separated arrival rates (requests/s)")
     ap.add_argument("--serve-seconds", type=float, default=2.0,
                     help="serving: arrival window per rate")
-    ap.add_argument("--serve-long-reads", default="chunked", choices=["chunked", "both_ends"],
+    ap.add_argument("--serve-long-reads", default="auto",
+                    choices=["chunked", "both_ends", "auto"],
                     help="serving: how reads of long rows are decoded")
-    ap.add_argument("--serve-budget-gib", type=float, default=96.0,
+    ap.add_argument("--serve-budget-gib", type=float, default=160.0,
                     help="serving: HBM budget of the store (arenas, payloads, outputs)")
     ap.add_argument("--serve-depth", type=int, default=3,
                     help="serving: iterations in flight")
-    ap.add_argument("--serve-iter-mib", type=int, default=128,
+    ap.add_argument("--serve-auto-backlog", type=int, default=50000,
+                    help="serving, long reads 'auto': waiting requests above which long "
+                         "rows decode from both ends")
+    ap.add_argument("--serve-auto-rate", type=float, default=1.5e6,
+                    help="serving, long reads 'auto': arrivals per second above which long "
+                         "rows decode from both ends")
+    ap.add_argument("--serve-iter-mib", type=int, default=384,
                     help="serving: image MiB per class and kind in one iteration")
     ap.add_argument("--plain-blocks", type=int, default=1024)
     ap.add_argument("--cpu-sample", type=int, default=1 << 19)
@@ -954,7 +962,9 @@ def run_serving(args):
     srv = serving.Server(budget_bytes=int(args.serve_budget_gib * (1 << 30)),
                          depth=args.serve_depth, seed=synth.SEED_DATA, geos=geos, prefill=0.5,
                          per_iter_bytes=args.serve_iter_mib << 20,
-                         long_reads=args.serve_long_reads)
+                         long_reads=args.serve_long_reads,
+                         auto_backlog=args.serve_auto_backlog,
+                         auto_rate=args.serve_auto_rate)
     setup_s = time.perf_counter() - t_setup
     # warm-up: a short run at a low rate (first launches of every kernel variant)
     srv.run(serving.make_trace(20000, 0.2, geos, seed=99), max_wall=60)
@@ -983,7 +993,10 @@ def run_serving(args):
                                f"{len(geos)} size x code classes, {args.serve_budget_gib:g} GiB "
                                f"HBM budget, up to {args.serve_depth} iterations in flight "
                                f"of up to {args.serve_iter_mib} MiB per class and kind, "
-                               f"long-row reads {args.serve_long_reads}",
+                               f"long-row reads {args.serve_long_reads}"
+                               + (f" (from both ends above {args.serve_auto_rate:g} arrivals/s "
+                                  f"or {args.serve_auto_backlog} waiting)"
+                                  if args.serve_long_reads == "auto" else ""),
                    "parallelism": "single GPU"},
         "best_point": {k: best[k] for k in ("qps", "p50_us", "p99_us", "GBps")},
         "sweep": sweep, "setup_s": round(setup_s, 2), "status_ok": ok,

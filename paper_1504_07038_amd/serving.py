@@ -22,7 +22,11 @@ image and its arena slot sit in the server's one word pool, its row length,
 code and erasure mask).  Reads of long rows either run as chunked decode
 jobs on side streams, joined into the iteration, or (long_reads="both_ends")
 as one more descriptor-driven decode on a side stream, every block swept
-from both ends, that completes on its own event.  Up to `depth` iterations
+from both ends, that completes on its own event; long_reads="auto" takes
+the chunked decode (short chains, twice the sweep work) at low load and the
+decode from both ends (the sweep work once, chains of half a row) once
+requests arrive faster than `auto_rate` per second (over the last 10 ms)
+or more than `auto_backlog` wait.  Up to `depth` iterations
 are in flight, so requests join while earlier ones are still running on the
 device.
 
@@ -216,7 +220,8 @@ class Server:
     def __init__(self, budget_bytes: int = 64 << 30, depth: int = 3, seed: int = 1,
                  geos=None, prefill: float = 0.5, per_iter_bytes: int = 16 << 20,
                  chunk_min_P: int = 1024, chunk_cols: int = 256, side_streams: int = 3,
-                 chunk_max_reads: int = 1 << 30, long_reads: str = "chunked"):
+                 chunk_max_reads: int = 1 << 30, long_reads: str = "chunked",
+                 auto_backlog: int = 50000, auto_rate: float = float("inf")):
         import torch
 
         self.torch = torch
@@ -229,7 +234,9 @@ class Server:
         self.L = mj.lib()
         caps = [int(max(4, min(4096, per_iter_bytes // (g.img_words * 8)))) for g in self.geos]
         stage_words = sum(2 * c + c // 4 + 1 for c in caps) + 64
-        # Reads of long rows (P >= chunk_min_P) take one of two paths:
+        # Reads of long rows (P >= chunk_min_P) take one of two paths (with
+        # "auto", per iteration: both ends while requests arrive faster than
+        # auto_rate per second or more than auto_backlog wait, else chunked):
         #   "chunked"    chunked decode jobs (one chunk plan per code, a
         #                workspace per class and in-flight iteration) on side
         #                streams, joined into the iteration: short chains,
@@ -247,16 +254,23 @@ class Server:
         # iteration's long reads take ~25 ms to sweep (chains of up to 16k
         # columns), and the iterations waiting on them hold the in-flight
         # window; with 6 in flight and 128 MiB it also keeps pace at 2M, at
-        # a p99 of 38 ms (37 ms already at 1M).
-        if long_reads not in ("chunked", "both_ends"):
-            raise ValueError("long_reads is 'chunked' or 'both_ends'")
+        # a p99 of 38 ms (37 ms already at 1M).  With 384 MiB iterations (160
+        # GiB budget, 3 in flight), "auto" switching at 1.5M arrivals/s keeps
+        # pace at 3M req/s (555 GB/s, p99 33 ms) with the chunked path's
+        # latency below (p50 0.9 ms at 10k req/s); switching on the backlog
+        # alone came too late (3M: p99 186 ms).
+        if long_reads not in ("chunked", "both_ends", "auto"):
+            raise ValueError("long_reads is 'chunked', 'both_ends' or 'auto'")
         self.long_reads = long_reads
+        self.auto_backlog = auto_backlog
+        self.auto_rate = auto_rate
+        self.busy = long_reads == "both_ends"   # this iteration's long reads from both ends
         self.chunk_min_P = chunk_min_P
         self.plans = {}
         ws_words = []
         for g, cap in zip(self.geos, caps):
             w = 0
-            if chunk_min_P and g.P >= chunk_min_P and long_reads == "chunked":
+            if chunk_min_P and g.P >= chunk_min_P and long_reads != "both_ends":
                 key = (tuple(g.dirs), g.Q)
                 if key not in self.plans:
                     self.plans[key] = mj.ChunkPlan(g.dirs, g.Q, chunk_cols)
@@ -279,7 +293,7 @@ class Server:
         stage_words += desc_words
         ws_bytes = self.plan.workspace_bytes(self.max_desc)
         # both ends: a descriptor-call workspace per side stream
-        n_side_ws = side_streams if long_reads == "both_ends" else 0
+        n_side_ws = side_streams if long_reads != "chunked" else 0
         fixed = sum((depth + 2) * c * g.img_words * 8 for c, g in zip(caps, self.geos))
         fixed += 2 * depth * stage_words * 8 + depth * 8 * sum(ws_words) + ws_bytes
         fixed += n_side_ws * ws_bytes
@@ -433,8 +447,8 @@ class Server:
             st = self.cs[c]
             img = st.payload_off + (row0 + np.arange(len(slots))) * st.geo.img_words
             wd.append((c, img, slots, None))
-        chunking = sum(len(r[2]) for r in reads) <= self.chunk_max_reads
-        both = self.long_reads == "both_ends"
+        both = self.busy
+        chunking = not both and sum(len(r[2]) for r in reads) <= self.chunk_max_reads
         for c, ids, slots in reads:
             st = self.cs[c]
             img = st.out_off + (ring * st.cap + np.arange(len(slots))) * st.geo.img_words
@@ -526,8 +540,10 @@ class Server:
         results = {}
         inflight = []
         seen = 0
-        stats = {"iterations": 0, "max_queued": 0, "admitted": 0, "blocked_writes": 0}
+        stats = {"iterations": 0, "max_queued": 0, "admitted": 0, "blocked_writes": 0,
+                 "both_ends_iterations": 0}
         gpu_ms = 0.0
+        rate_win = []   # (time, arrivals so far), about one a millisecond over 10 ms
         start = torch.cuda.Event(enable_timing=True)
         start.record(self.stream)
         start.synchronize()
@@ -553,6 +569,12 @@ class Server:
             if n_arr > seen:
                 arrived += np.bincount(qid[seen:n_arr], minlength=nq)
                 seen = n_arr
+            if not rate_win or now - rate_win[-1][0] >= 1e-3:
+                rate_win.append((now, seen))
+                # keep the newest sample at least 10 ms old (a wait on a
+                # completion event can leave no sample inside the window)
+                while len(rate_win) > 1 and now - rate_win[1][0] >= 10e-3:
+                    rate_win.pop(0)
             pending = arrived - heads
             stats["max_queued"] = max(stats["max_queued"], int(pending.sum()))
             writes, reads = [], []
@@ -577,6 +599,14 @@ class Server:
                 heads[q] = h + k
                 stats["admitted"] += k
             if writes or reads:
+                if self.long_reads == "auto":
+                    # the arrival rate over the last 10 ms, and the requests
+                    # still waiting once this iteration is admitted
+                    t_old, n_old = rate_win[0]
+                    rate = (seen - n_old) / (now - t_old) if now - t_old >= 1e-3 else 0.0
+                    self.busy = (rate > self.auto_rate or
+                                 int((arrived - heads).sum()) > self.auto_backlog)
+                    stats["both_ends_iterations"] += int(self.busy)
                 inflight.append((*self._launch(writes, reads, trace), writes, reads))
                 stats["iterations"] += 1
             elif seen == N and not inflight and (heads == arrived).all():
