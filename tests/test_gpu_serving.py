@@ -40,8 +40,8 @@ def alone_decode(mj, projs, mask, g):
                          [(3072, 0.5, 100000, 512, "chunked"), (640, 1.0, 200000, 512, "chunked"),
                           (3072, 0.5, 100000, 0, "chunked"),     # long rows never chunked
                           (3072, 0.5, 200000, 512, "both_ends"),
-                          # both paths by backlog (a low threshold so that the
-                          # decode from both ends is taken)
+                          # both paths by arrival rate and backlog (low
+                          # thresholds so that the decode from both ends is taken)
                           (3072, 0.5, 400000, 512, "auto")])
 def test_serving_mix_matches_alone_and_oracle(mj, orc, budget_mib, prefill, qps, chunk_max,
                                               long_reads):
@@ -53,7 +53,7 @@ def test_serving_mix_matches_alone_and_oracle(mj, orc, budget_mib, prefill, qps,
         f"chunked reads up to {chunk_max} per iteration, long reads {long_reads}")
     srv = serving.Server(budget_bytes=budget_mib << 20, depth=3, seed=seed, geos=geos,
                          prefill=prefill, per_iter_bytes=2 << 20, chunk_max_reads=chunk_max,
-                         long_reads=long_reads, auto_backlog=200)
+                         long_reads=long_reads, auto_backlog=200, auto_rate=3e5)
     assert srv.budget_used <= budget_mib << 20
     tr = serving.make_trace(qps, 0.05, geos, seed=3)
     N = len(tr.arrival)
