@@ -1896,6 +1896,45 @@ static int desc_blocks(int Q, int ring_stride, int tuned) {
     return std::min(nb, std::max(1, mj::decode_max_blocks_per_wave(Q) / 2));
 }
 
+// Streams of the descriptor decode's launch groups (one per row count and
+// the group decoded from both ends): each group runs on a stream of its own,
+// forked from the caller's stream after the bucketing and joined back to it
+// with events, so that a group bound by the chains of its long rows runs
+// beside the others instead of before them (a chunk of the mixed workload:
+// its 4-row group, 1 MB rows, takes 10 ms of which 7 ms are one chain, the
+// chip otherwise idle).  Created once per device, at plan creation (not
+// under graph capture); default priority.  The fork and join are recorded
+// under a lock so that calls from several threads do not mix their events.
+namespace {
+constexpr int kForkStreams = 4;
+struct ForkPool {
+    hipStream_t st[kForkStreams];
+    hipEvent_t fork, join[kForkStreams];
+    std::mutex mu;
+};
+
+ForkPool *fork_pool(int dev, bool create) {
+    static std::mutex mu;
+    static std::map<int, ForkPool *> pools;
+    std::lock_guard<std::mutex> g(mu);
+    auto it = pools.find(dev);
+    if (it != pools.end()) return it->second;
+    if (!create) return nullptr;
+    auto *fp = new (std::nothrow) ForkPool{};
+    if (!fp) return nullptr;
+    hipError_t e = hipEventCreateWithFlags(&fp->fork, hipEventDisableTiming);
+    for (int k = 0; k < kForkStreams && e == hipSuccess; ++k) {
+        e = hipStreamCreateWithFlags(&fp->st[k], hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&fp->join[k], hipEventDisableTiming);
+    }
+    if (e != hipSuccess) {
+        mj::hip_status(e);
+        return nullptr;   // the few handles made stay with the process
+    }
+    return pools[dev] = fp;
+}
+}  // namespace
+
 int mojette_plan_create(const mojette_geom *geoms, int32_t ngeoms, const mojette_tune *tune,
                         mojette_plan **plan) {
     if (!plan) return MOJETTE_EINVAL;
@@ -2009,6 +2048,7 @@ int mojette_plan_create(const mojette_geom *geoms, int32_t ngeoms, const mojette
     if (e == hipSuccess)
         e = hipMemcpy(pl->d_geoms, tab.data(), tab.size() * sizeof(mj::GeomDev),
                       hipMemcpyHostToDevice);
+    if (e == hipSuccess && !fork_pool(pl->dev, true)) e = hipErrorOutOfMemory;
     if (e != hipSuccess) {
         mj::hip_status(e);
         if (pl->d_geoms) (void)hipFree(pl->d_geoms);
@@ -2106,6 +2146,13 @@ int mojette_decode_batched(const mojette_plan *plan, const mojette_block *blocks
     if ((rc = status_of(mj::launch_desc_buckets(c, s))) != MOJETTE_OK) return rc;
     // at most two batches per block: a grid of that many (capped) loops over them
     const int grid = (int)std::min<int64_t>(kDecodeGridCap, 2 * nblocks);
+    ForkPool *fp = fork_pool(plan->dev, false);
+    if (!fp) return MOJETTE_EHIP;
+    std::lock_guard<std::mutex> fork_lock(fp->mu);
+    hipError_t fe = hipEventRecord(fp->fork, s);
+    if (fe != hipSuccess) return mj::hip_status(fe);
+    unsigned used = 0;   // fork streams that took a group
+    int ngroup = 0;
     for (int two = 0; two < 2; ++two) {
         for (int q = 1; q <= kMaxRows; ++q) {
             if (!((plan->qmask >> q) & 1u)) continue;
@@ -2123,11 +2170,29 @@ int mojette_decode_batched(const mojette_plan *plan, const mojette_block *blocks
             }
             if (lds == 0) continue;   // no code of this row count decodes from both ends
             const int grp = q + (two ? mj::kTwoGroup : 0);
-            rc = status_of(mj::launch_decode_desc(q, two != 0, c, grp, lds, grid, s));
-            if (rc != MOJETTE_OK) return rc;
+            const int k = ngroup++ % kForkStreams;
+            if (!((used >> k) & 1u)) {
+                fe = hipStreamWaitEvent(fp->st[k], fp->fork, 0);
+                if (fe != hipSuccess) {
+                    rc = mj::hip_status(fe);
+                    break;
+                }
+                used |= 1u << k;
+            }
+            rc = status_of(mj::launch_decode_desc(q, two != 0, c, grp, lds, grid, fp->st[k]));
+            if (rc != MOJETTE_OK) break;
         }
+        if (rc != MOJETTE_OK) break;
     }
-    return MOJETTE_OK;
+    // the caller's stream continues once every group is done (also after a
+    // failed launch: a captured fork must be joined)
+    for (int k = 0; k < kForkStreams; ++k) {
+        if (!((used >> k) & 1u)) continue;
+        fe = hipEventRecord(fp->join[k], fp->st[k]);
+        if (fe == hipSuccess) fe = hipStreamWaitEvent(s, fp->join[k], 0);
+        if (fe != hipSuccess && rc == MOJETTE_OK) rc = mj::hip_status(fe);
+    }
+    return rc;
 }
 
 }  // extern "C"
