@@ -446,20 +446,87 @@ int plan_pool_whole(mj::DecodeArgs a, int Q, int nb_req, std::vector<mj::DecodeA
     return add(a);
 }
 
+// Streams of the descriptor decode's launch groups (one per row count and
+// the group decoded from both ends; also the deep class of a split
+// whole-block pool decode): each group runs on a stream of its own,
+// forked from the caller's stream after the bucketing and joined back to it
+// with events, so that a group bound by the chains of its long rows runs
+// beside the others instead of before them (a chunk of the mixed workload:
+// its 4-row group, 1 MB rows, takes 10 ms of which 7 ms are one chain, the
+// chip otherwise idle).  Created once per device, at plan creation or at
+// the first pool decode that is not being captured; default priority.  The fork and join are recorded
+// under a lock so that calls from several threads do not mix their events.
+namespace {
+constexpr int kForkStreams = 4;
+struct ForkPool {
+    hipStream_t st[kForkStreams];
+    hipEvent_t fork, join[kForkStreams];
+    std::mutex mu;
+};
+
+ForkPool *fork_pool(int dev, bool create) {
+    static std::mutex mu;
+    static std::map<int, ForkPool *> pools;
+    std::lock_guard<std::mutex> g(mu);
+    auto it = pools.find(dev);
+    if (it != pools.end()) return it->second;
+    if (!create) return nullptr;
+    auto *fp = new (std::nothrow) ForkPool{};
+    if (!fp) return nullptr;
+    hipError_t e = hipEventCreateWithFlags(&fp->fork, hipEventDisableTiming);
+    for (int k = 0; k < kForkStreams && e == hipSuccess; ++k) {
+        e = hipStreamCreateWithFlags(&fp->st[k], hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&fp->join[k], hipEventDisableTiming);
+    }
+    if (e != hipSuccess) {
+        mj::hip_status(e);
+        return nullptr;   // the few handles made stay with the process
+    }
+    return pools[dev] = fp;
+}
+}  // namespace
+
 int launch_pool_whole(const mj::DecodeArgs &a, int Q, int nb_req, hipStream_t stream) {
     std::vector<mj::DecodeArgs> launches;
     const int rc = plan_pool_whole(a, Q, nb_req, launches);
     if (rc != MOJETTE_OK) return rc;
-    for (const mj::DecodeArgs &b : launches) {
+    // a split decode (short-ring class, then the deep sets): the deep launch
+    // on a fork stream beside the first (they write different blocks)
+    ForkPool *fp = nullptr;
+    if (launches.size() == 2) {
+        int dev = 0;
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipGetDevice(&dev) == hipSuccess) {
+            const bool capturing = hipStreamIsCapturing(stream, &cs) == hipSuccess &&
+                                   cs != hipStreamCaptureStatusNone;
+            fp = fork_pool(dev, !capturing);
+        }
+        (void)hipGetLastError();   // a failed lookup leaves the launches in order
+    }
+    std::unique_lock<std::mutex> fork_lock;
+    if (fp) {
+        fork_lock = std::unique_lock<std::mutex>(fp->mu);
+        hipError_t fe = hipEventRecord(fp->fork, stream);
+        if (fe == hipSuccess) fe = hipStreamWaitEvent(fp->st[0], fp->fork, 0);
+        if (fe != hipSuccess) return mj::hip_status(fe);
+    }
+    int rc2 = MOJETTE_OK;
+    for (size_t i = 0; i < launches.size() && rc2 == MOJETTE_OK; ++i) {
+        const mj::DecodeArgs &b = launches[i];
         // gathering launches: one wavefront per range of gather_range blocks
         const int64_t per_wave = b.gather_range > 0 ? b.gather_range : b.nb;
         const int64_t batches = (b.nblocks + per_wave - 1) / per_wave;
         const int grid = (int)std::min<int64_t>(batches, kDecodeGridCap);
         clear_stale_error();
-        const int st = status_of(mj::launch_decode(Q, mj::kLaunchPool, b, grid, stream));
-        if (st != MOJETTE_OK) return st;
+        rc2 = status_of(mj::launch_decode(Q, mj::kLaunchPool, b, grid,
+                                          fp && i == 1 ? fp->st[0] : stream));
     }
-    return MOJETTE_OK;
+    if (fp) {
+        hipError_t fe = hipEventRecord(fp->join[0], fp->st[0]);
+        if (fe == hipSuccess) fe = hipStreamWaitEvent(stream, fp->join[0], 0);
+        if (fe != hipSuccess && rc2 == MOJETTE_OK) rc2 = mj::hip_status(fe);
+    }
+    return rc2;
 }
 
 // Checks a class table and returns, per class, block words and pool offsets.
@@ -1896,44 +1963,6 @@ static int desc_blocks(int Q, int ring_stride, int tuned) {
     return std::min(nb, std::max(1, mj::decode_max_blocks_per_wave(Q) / 2));
 }
 
-// Streams of the descriptor decode's launch groups (one per row count and
-// the group decoded from both ends): each group runs on a stream of its own,
-// forked from the caller's stream after the bucketing and joined back to it
-// with events, so that a group bound by the chains of its long rows runs
-// beside the others instead of before them (a chunk of the mixed workload:
-// its 4-row group, 1 MB rows, takes 10 ms of which 7 ms are one chain, the
-// chip otherwise idle).  Created once per device, at plan creation (not
-// under graph capture); default priority.  The fork and join are recorded
-// under a lock so that calls from several threads do not mix their events.
-namespace {
-constexpr int kForkStreams = 4;
-struct ForkPool {
-    hipStream_t st[kForkStreams];
-    hipEvent_t fork, join[kForkStreams];
-    std::mutex mu;
-};
-
-ForkPool *fork_pool(int dev, bool create) {
-    static std::mutex mu;
-    static std::map<int, ForkPool *> pools;
-    std::lock_guard<std::mutex> g(mu);
-    auto it = pools.find(dev);
-    if (it != pools.end()) return it->second;
-    if (!create) return nullptr;
-    auto *fp = new (std::nothrow) ForkPool{};
-    if (!fp) return nullptr;
-    hipError_t e = hipEventCreateWithFlags(&fp->fork, hipEventDisableTiming);
-    for (int k = 0; k < kForkStreams && e == hipSuccess; ++k) {
-        e = hipStreamCreateWithFlags(&fp->st[k], hipStreamNonBlocking);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&fp->join[k], hipEventDisableTiming);
-    }
-    if (e != hipSuccess) {
-        mj::hip_status(e);
-        return nullptr;   // the few handles made stay with the process
-    }
-    return pools[dev] = fp;
-}
-}  // namespace
 
 int mojette_plan_create(const mojette_geom *geoms, int32_t ngeoms, const mojette_tune *tune,
                         mojette_plan **plan) {
