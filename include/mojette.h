@@ -122,7 +122,12 @@ int mojette_encode_batch(const uint64_t *images, int64_t nblocks, int32_t P, int
                          const int32_t *dirs, int32_t n, uint64_t *projs, void *stream);
 
 /*
- * Inverse transform of nblocks blocks of one geometry in one launch.
+ * Inverse transform of nblocks blocks of one geometry in one launch (two
+ * for large batches whose survivor sets need rings of two lengths: the
+ * deep sets then decode on a stream of the library's, forked from `stream`
+ * and joined back to it, so ordering on `stream` is as for one launch; under
+ * graph capture that stream must have been made by an earlier call or plan
+ * on the device, else the two launches run in order on `stream`).
  *   projs    device, pool laid out as for mojette_encode_batch.  Bins of
  *            erased projections are never read.
  *   erased   device, nblocks uint16 masks; bit i set = projection i of that
@@ -507,7 +512,11 @@ int mojette_encode_batched(const mojette_plan *plan, const mojette_block *blocks
  * projections its erasure mask leaves (bins of erased projections are never
  * read), writing its image.  A block with fewer than Q survivors is left
  * unwritten and MOJETTE_ENOTRECON is stored to *status.  Other arguments as
- * for mojette_encode_batched. */
+ * for mojette_encode_batched.  The launches of different row counts run on
+ * streams of the library's (created with the first plan on a device),
+ * forked from `stream` after its earlier work and joined back to it before
+ * its later work: ordering on `stream` is as for one launch, and the call
+ * stays safe to record into a HIP graph. */
 int mojette_decode_batched(const mojette_plan *plan, const mojette_block *blocks,
                            int64_t nblocks, uint64_t *pool, void *workspace, int32_t *status,
                            void *stream);
