@@ -512,8 +512,9 @@ int mojette_encode_batched(const mojette_plan *plan, const mojette_block *blocks
  * projections its erasure mask leaves (bins of erased projections are never
  * read), writing its image.  A block with fewer than Q survivors is left
  * unwritten and MOJETTE_ENOTRECON is stored to *status.  Other arguments as
- * for mojette_encode_batched.  The launches of different row counts run on
- * streams of the library's (created with the first plan on a device),
+ * for mojette_encode_batched.  In calls of 16,384 blocks or more the
+ * launches of different row counts run on streams of the library's (created
+ * with the first plan on a device),
  * forked from `stream` after its earlier work and joined back to it before
  * its later work: ordering on `stream` is as for one launch, and the call
  * stays safe to record into a HIP graph. */
